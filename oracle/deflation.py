@@ -1,0 +1,102 @@
+"""Deflation basis, coarse operator, projector and solution recovery (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Follows section "Subdomain deflation":
+* x = y + Z lambda with Z an n x m basis (eq. (2));
+* E = Z^T A Z, invertible when A is and Z has independent columns (eqs. (3),
+  (4) and the remark after them);
+* the deflated system P(A y) = P(b) with P = I - A Z E^{-1} Z^T (eqs. (6)-(7));
+* lambda recovered from the first block row of eq. (4).  The printed formula
+  for lambda is dimensionally inconsistent; the reading used is
+  lambda = E^{-1} Z^T (b - A y), which is what eq. (3) gives, so that
+  b - A x = P(b - A y);
+and section "Implementation": the projector applied matrix-free as
+t1 = Z^T r, t2 = E^{-1} t1, r* = r - (AZ) t2 with AZ and E formed explicitly,
+and E solved exactly (section "On precision of the coarse system solution").
+
+Z is given as its local blocks: row i of `Zloc` holds the ndv deflation
+vectors of the subdomain part[i] evaluated at unknown i; the full basis has
+column part[i]*ndv + k for the k-th vector (sections "Constant deflation",
+"Linear deflation").
+"""
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+class DeflationError(Exception):
+    pass
+
+
+def full_basis(part, nsub, Zloc):
+    """Sparse n x (nsub*ndv) basis Z from its local blocks."""
+    n, ndv = Zloc.shape
+    rows = np.repeat(np.arange(n), ndv)
+    cols = (np.asarray(part, dtype=np.int64)[:, None] * ndv
+            + np.arange(ndv)).ravel()
+    return sp.csr_matrix((Zloc.ravel(), (rows, cols)), shape=(n, nsub * ndv))
+
+
+def local_rank_check(part, nsub, Zloc, rtol=1e-12):
+    """Return the first subdomain whose local block has dependent columns
+    (numerical rank below ndv with tolerance rtol * largest singular value),
+    or -1 when every block has full column rank."""
+    ndv = Zloc.shape[1]
+    if ndv == 0:
+        return -1
+    order = np.argsort(part, kind="stable")
+    bounds = np.searchsorted(part[order], np.arange(nsub + 1))
+    for s in range(nsub):
+        Zs = Zloc[order[bounds[s]:bounds[s + 1]]]
+        if Zs.shape[0] < ndv:
+            return s
+        sv = np.linalg.svd(Zs, compute_uv=False)
+        if sv[0] == 0.0 or np.sum(sv > rtol * sv[0]) < ndv:
+            return s
+    return -1
+
+
+class Deflation:
+    """P = I - A Z E^{-1} Z^T with exact FP64 E solves."""
+
+    def __init__(self, A, part, nsub, Zloc, symmetric=True):
+        self.A = A
+        self.Z = full_basis(part, nsub, Zloc)
+        bad = local_rank_check(np.asarray(part), nsub, Zloc)
+        if bad >= 0:
+            raise DeflationError(f"deflation block of subdomain {bad} is rank deficient")
+        self.AZ = (A @ self.Z).tocsr()
+        self.E = (self.Z.T @ self.AZ).toarray()
+        self.symmetric = symmetric
+        self.m = self.E.shape[0]
+        if self.m == 0:              # no deflation vectors: P = I
+            self._fac = None
+            return
+        try:
+            if symmetric:
+                self._fac = sla.cho_factor(self.E, lower=True, check_finite=True)
+            else:
+                self._fac = sla.lu_factor(self.E, check_finite=True)
+                if np.any(np.diag(self._fac[0]) == 0.0):
+                    raise np.linalg.LinAlgError("singular E")
+        except np.linalg.LinAlgError as exc:
+            raise DeflationError(f"E = Z^T A Z is not factorizable: {exc}")
+
+    def solve_E(self, t1):
+        if self.m == 0:
+            return np.zeros(0)
+        if self.symmetric:
+            return sla.cho_solve(self._fac, t1)
+        return sla.lu_solve(self._fac, t1)
+
+    def project(self, v):
+        """P v = v - AZ E^{-1} Z^T v."""
+        t1 = self.Z.T @ v
+        t2 = self.solve_E(t1)
+        return v - self.AZ @ t2
+
+    def recover(self, b, y):
+        """x = y + Z E^{-1} Z^T (b - A y)."""
+        lam = self.solve_E(self.Z.T @ (b - self.A @ y))
+        return y + self.Z @ lam

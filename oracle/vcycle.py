@@ -1,0 +1,47 @@
+"""V(1,1) cycle and the block-diagonal local AMG preconditioner (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The preconditioner is block AMG without overlap: one AMG per subdomain, built
+on the square diagonal block of A, applied independently to the residual
+restricted to each subdomain (section "Implementation", last paragraphs).
+One application is one V-cycle with one pre- and one post-smoothing step of
+the diagonal smoother, starting from a zero guess on every level, and an exact
+solve on the coarsest level.
+"""
+import numpy as np
+import scipy.linalg as sla
+
+from .sa import build_hierarchy
+
+
+def vcycle(H, l, f):
+    """x = V(l, f) on hierarchy H."""
+    if l == H.nlevels - 1:
+        return sla.lu_solve(H.coarse_lu, f)
+    lvl = H.levels[l]
+    x = lvl.m * f                                   # pre-smooth from x = 0
+    r = f - lvl.A @ x
+    x = x + lvl.P @ vcycle(H, l + 1, lvl.R @ r)
+    x = x + lvl.m * (f - lvl.A @ x)                 # post-smooth
+    return x
+
+
+class BlockAMG:
+    """s = M^{-1} r, M^{-1} = blockdiag_s(V-cycle of A[S_s, S_s])."""
+
+    def __init__(self, A, part, nsub, **sa_params):
+        part = np.asarray(part)
+        self.sets = []
+        self.hierarchies = []
+        for s in range(nsub):
+            S = np.flatnonzero(part == s)            # ascending global index
+            self.sets.append(S)
+            A_ss = A[S][:, S].tocsr()
+            self.hierarchies.append(build_hierarchy(A_ss, **sa_params))
+
+    def apply(self, r):
+        out = np.zeros_like(r)
+        for S, H in zip(self.sets, self.hierarchies):
+            out[S] = vcycle(H, 0, r[S])
+        return out

@@ -1,0 +1,26 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This package only *builds inputs*: sparse matrices in CSR form, subdomain
+partitions, deflation vectors and right-hand sides.  It contains none of the
+solver's arithmetic (no projection, no multigrid, no Krylov recurrence), so
+both the CPU oracle and the GPU library can consume its output without sharing
+any solver code.
+
+Problems follow the paper's benchmark section: the 3D Poisson problem
+(-Laplace u = 1 on the unit cube, homogeneous Dirichlet conditions) discretised
+with the 7-point stencil, constant ("subdomain") and linear deflation vectors,
+and box partitions of the grid into subdomains.
+"""
+from .poisson import poisson7, grid_coords
+from .partition import box_partition, slab_partition
+from .deflation import constant_deflation, linear_deflation
+from .configs import (Problem, config_small_poisson, config_lognormal_poisson,
+                      config_batched, batched_recipe, concat_problems,
+                      make_problem, tiny_problem)
+
+__all__ = [
+    "poisson7", "grid_coords", "box_partition", "slab_partition",
+    "constant_deflation", "linear_deflation", "Problem",
+    "config_small_poisson", "config_lognormal_poisson", "config_batched",
+    "batched_recipe", "concat_problems", "make_problem", "tiny_problem",
+]
