@@ -1,0 +1,245 @@
+/*
+ * dfamg.h - C ABI of the MI355X subdomain-deflated local-AMG Krylov solver.
+ *
+ * The method is the one of Demidov & Rossi, "Subdomain deflation combined
+ * with local AMG" (arXiv:1710.03940):
+ *   - the solution is split as x = y + Z lambda with Z the subdomain
+ *     deflation basis (section "Subdomain deflation", eq. (2));
+ *   - a Krylov method solves the deflated system P(A y) = P(b) with the
+ *     projector P = I - A Z E^{-1} Z^T, E = Z^T A Z (eqs. (3)-(7)), applied
+ *     matrix-free as t1 = Z^T r, t2 = E^{-1} t1, r* = r - (AZ) t2 with AZ and
+ *     E formed explicitly (section "Implementation", projector equation);
+ *   - the preconditioner is block AMG without overlap: one smoothed-
+ *     aggregation V-cycle per subdomain, built on the square diagonal block
+ *     of A (section "Implementation");
+ *   - lambda = E^{-1} Z^T (b - A y) recovers x (eqs. (4)-(5)).
+ * Usage follows Listing 1: setup once from a CRS matrix and parameters, then
+ * solve(rhs, x) with x as the initial guess, returning iterations and the
+ * relative residual.
+ *
+ * Conventions for every entry point:
+ *   - every function returns a dfamg_status; no C++ exception crosses the ABI;
+ *   - on failure a message is available from dfamg_last_error(handle) (or
+ *     dfamg_last_error(NULL) when no handle exists yet);
+ *   - host pointers are read during the call only; the caller keeps
+ *     ownership;
+ *   - device pointers (rhs, x of the solve calls) are HIP device memory on the
+ *     device that was current at setup, borrowed for the duration of the call;
+ *   - a handle is not thread-safe; all of its GPU work is ordered on the
+ *     stream given at setup.
+ */
+#ifndef DFAMG_H
+#define DFAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DFAMG_OK = 0,
+    DFAMG_EINVAL = 1,      /* malformed input or parameters (nothing changed) */
+    DFAMG_ENOMEM = 2,      /* host or device allocation failed               */
+    DFAMG_ESINGULAR = 3,   /* E or a coarsest-level block is not invertible,
+                              or a local deflation block is rank deficient    */
+    DFAMG_ENOCONV = 4,     /* maxiter reached; outputs hold the last iterate  */
+    DFAMG_EBREAKDOWN = 5,  /* BiCGStab rho or omega became exactly zero       */
+    DFAMG_ENAN = 6,        /* a non-finite value appeared in the iteration    */
+    DFAMG_EHIP = 7,        /* a HIP runtime call failed                       */
+    DFAMG_ENOGPU = 8       /* no usable gfx950 device                         */
+} dfamg_status;
+
+enum { DFAMG_SOLVER_CG = 0, DFAMG_SOLVER_BICGSTAB = 1 };
+enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
+enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1 };
+enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2 };
+enum { DFAMG_PRECOND_AMG = 0, DFAMG_PRECOND_NONE = 1 };
+
+typedef struct {
+    int32_t solver;         /* DFAMG_SOLVER_*; CG needs a symmetric A          */
+    int32_t maxiter;        /* iteration limit (default 1000)                  */
+    double  rtol;           /* stop when ||r_k|| <= rtol ||b|| (default 1e-8)  */
+    int32_t precision;      /* DFAMG_PREC_FP64: whole path FP64; MIXED: AMG
+                               hierarchy, smoother and V-cycle vectors FP32,
+                               Krylov vectors, dots and deflation FP64        */
+    int32_t smoother;       /* DFAMG_SMOOTHER_SPAI0 (default) or _JACOBI       */
+    double  jacobi_omega;   /* damped Jacobi damping (default 0.8, Listing 1)  */
+    int32_t coarse_enough;  /* stop coarsening at <= this many unknowns (500)  */
+    double  eps_strong;     /* strength threshold on level 0 (0.08), halved
+                               on every coarser level                          */
+    int32_t max_levels;     /* hierarchy depth limit (20)                      */
+    int32_t block_size;     /* 1 (scalar) or 2..8 (point blocks, interleaved)  */
+    int32_t precond;        /* DFAMG_PRECOND_AMG (default) or _NONE (M = I)    */
+    int32_t spmv_format;    /* DFAMG_FORMAT_*: AUTO lets the setup autotuner
+                               time the candidates on the device              */
+    int32_t graph_iters;    /* Krylov iterations per captured HIP graph;
+                               0 launches kernels directly (default 16)       */
+    int32_t host_threads;   /* setup worker threads, 0 = hardware concurrency  */
+    int32_t verbose;        /* 1 prints setup/solve phase times to stderr      */
+} dfamg_params;
+
+/* Fill *p with the defaults listed above. */
+void dfamg_params_default(dfamg_params *p);
+
+typedef struct dfamg_handle_s *dfamg_handle;
+
+/*
+ * Build the solver on the current HIP device.
+ *   n          number of unknowns (rows of the square matrix), n >= 1
+ *   row_ptr    host, n+1 entries, 0-based CRS row pointers, monotone,
+ *              row_ptr[0] == 0
+ *   col        host, row_ptr[n] column indices in [0, n); no duplicates
+ *              within a row (any order)
+ *   val        host, row_ptr[n] finite FP64 values
+ *   part       host, n subdomain ids in [0, nsub); every subdomain non-empty;
+ *              with block_size b > 1 all b unknowns of a node (rows
+ *              b*k .. b*k+b-1) share one subdomain
+ *   nsub       number of subdomains (>= 1)
+ *   ndv        deflation vectors per subdomain (0..8); 0 disables deflation
+ *   Z          host, n x ndv row-major FP64: row i holds the ndv local
+ *              deflation vectors of subdomain part[i] at unknown i (sections
+ *              "Constant deflation", "Linear deflation"); may be NULL if
+ *              ndv == 0
+ *   stream     hipStream_t for all work of this handle (NULL = null stream)
+ *   out        receives the handle
+ * Errors: EINVAL (validation, before any device work), ESINGULAR (E, a
+ * coarsest block or a local Z block not invertible / of full rank, with the
+ * subdomain named in the message), ENOMEM, EHIP, ENOGPU.
+ */
+dfamg_status dfamg_setup(const dfamg_params *prm, int64_t n,
+                         const int64_t *row_ptr, const int32_t *col,
+                         const double *val, const int32_t *part, int32_t nsub,
+                         int32_t ndv, const double *Z, void *stream,
+                         dfamg_handle *out);
+
+/*
+ * Batched setup: nsys independent systems concatenated into one
+ * block-diagonal matrix.  sys_row_off (host, nsys+1 entries) gives the row
+ * range of every system; no matrix entry may couple two systems; subdomain
+ * ids are global across the batch and each subdomain lies inside one system.
+ * Every system gets its own deflation operator E, its own Krylov scalars and
+ * its own convergence test; all of them advance together in the same
+ * kernel launches.  Other arguments as in dfamg_setup.
+ */
+dfamg_status dfamg_setup_batched(const dfamg_params *prm, int32_t nsys,
+                                 const int64_t *sys_row_off, int64_t n,
+                                 const int64_t *row_ptr, const int32_t *col,
+                                 const double *val, const int32_t *part,
+                                 int32_t nsub, int32_t ndv, const double *Z,
+                                 void *stream, dfamg_handle *out);
+
+/*
+ * Solve A x = b (single-system handle).
+ *   rhs       device, n FP64 values (not modified)
+ *   x         device, n FP64 values: initial guess on entry, solution on exit
+ *   iters     host out: Krylov iterations performed
+ *   relres    host out: ||r_k|| / ||b|| of the recurrence residual at exit
+ *   relres_true host out: ||b - A x|| / ||b|| recomputed in FP64 at exit
+ *   history   host out (may be NULL): relative residual of iterations
+ *             0..iters, at most history_cap values written
+ * Returns after the stream has been synchronised.  b == 0 gives x = 0,
+ * iters = 0.  ENOCONV when maxiter is reached (x holds the recovered last
+ * iterate).  ENAN when a non-finite value appears.
+ */
+dfamg_status dfamg_solve(dfamg_handle h, const double *rhs, double *x,
+                         int32_t *iters, double *relres, double *relres_true,
+                         double *history, int32_t history_cap);
+
+/*
+ * Batched solve: rhs and x are the concatenated device vectors; iters,
+ * relres_true and status are host arrays of nsys entries (status may be
+ * NULL).  Returns DFAMG_OK when every system converged, else the first
+ * non-OK per-system status.
+ */
+dfamg_status dfamg_solve_batched(dfamg_handle h, const double *rhs, double *x,
+                                 int32_t *iters, double *relres_true,
+                                 int32_t *status);
+
+/* Single operators of the method on device vectors in the caller's
+ * (original) ordering, for checking them one at a time. */
+enum {
+    DFAMG_OP_SPMV = 0,      /* out = A in                                     */
+    DFAMG_OP_PROJECT = 1,   /* out = P in = in - AZ E^{-1} Z^T in             */
+    DFAMG_OP_PRECOND = 2,   /* out = M^{-1} in (one V-cycle per subdomain)    */
+    DFAMG_OP_RECOVER = 3    /* out = in + Z E^{-1} Z^T (b - A in), b = the
+                               right-hand side of the last solve             */
+};
+dfamg_status dfamg_apply(dfamg_handle h, int32_t op, const double *in,
+                         double *out);
+
+typedef struct {
+    int64_t n, nnz;
+    int32_t nsys, nsub, ndv, m_total;
+    int32_t nlevels_max;              /* deepest hierarchy over subdomains   */
+    int64_t level_rows[20];           /* packed unknowns per level           */
+    int64_t level_nnz[20];            /* packed nnz(A_l) per level           */
+    int64_t level_p_nnz[20];          /* packed nnz(P_l) per level           */
+    int32_t format_outer;             /* chosen DFAMG_FORMAT_* for A         */
+    int32_t format_level[20];         /* chosen format for A_l               */
+    int32_t lanes_level[20];          /* lanes per row for CSR formats       */
+    double  setup_host_s;             /* host setup (hierarchy, AZ, E) time  */
+    double  setup_device_s;           /* uploads, E inversion, tuning time   */
+    double  solve_s;                  /* wall time of the last solve call    */
+    int64_t device_bytes;             /* device memory owned by the handle   */
+    double  bytes_per_iter;           /* algorithmic HBM bytes per Krylov
+                                         iteration (whole batch)             */
+} dfamg_stats;
+
+dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *out);
+
+/* Release every resource of the handle (NULL is accepted). */
+dfamg_status dfamg_destroy(dfamg_handle h);
+
+/* Last error message of the handle, or of the calling thread's last failed
+ * setup when h is NULL.  The pointer stays valid until the next call. */
+const char *dfamg_last_error(dfamg_handle h);
+
+/*
+ * Host-only inspection of the setup (no device is touched): the same
+ * validation, permutation, hierarchy, AZ and E construction that dfamg_setup
+ * performs, kept on the host so that it can be compared with other
+ * implementations.
+ */
+typedef struct dfamg_plan_s *dfamg_plan;
+
+dfamg_status dfamg_plan_create(const dfamg_params *prm, int32_t nsys,
+                               const int64_t *sys_row_off, int64_t n,
+                               const int64_t *row_ptr, const int32_t *col,
+                               const double *val, const int32_t *part,
+                               int32_t nsub, int32_t ndv, const double *Z,
+                               dfamg_plan *out);
+
+/* Level sizes of subdomain `sub` (user id): writes up to cap entries into
+ * rows[l], nnz[l] (A_l) and p_nnz[l] (P_l, 0 on the coarsest), omega[l]
+ * (0 on the coarsest); *nlevels receives the hierarchy depth. */
+dfamg_status dfamg_plan_levels(dfamg_plan p, int32_t sub, int32_t cap,
+                               int32_t *nlevels, int64_t *rows, int64_t *nnz,
+                               int64_t *p_nnz, double *omega);
+
+/* Aggregate ids (-1 = in no aggregate) of level `level` of subdomain `sub`,
+ * in the subdomain's local order (ascending original index); *count gets the
+ * number of nodes; at most cap ids written. */
+dfamg_status dfamg_plan_aggregates(dfamg_plan p, int32_t sub, int32_t level,
+                                   int64_t cap, int32_t *agg, int64_t *count);
+
+/* CRS of matrix `which` (0 = A_l, 1 = P_l) of level `level` of subdomain
+ * `sub` in local numbering; pass NULL arrays to query sizes only. */
+dfamg_status dfamg_plan_level_matrix(dfamg_plan p, int32_t sub, int32_t level,
+                                     int32_t which, int64_t *nrows,
+                                     int64_t *ncols, int64_t *nnz,
+                                     int64_t *row_ptr, int32_t *col,
+                                     double *val);
+
+/* E of system `sys` as a dense m x m row-major array (m = ndv * subdomains of
+ * the system, columns ordered by user subdomain id then vector). */
+dfamg_status dfamg_plan_coarse_operator(dfamg_plan p, int32_t sys, int32_t *m,
+                                        double *E, int64_t cap);
+
+dfamg_status dfamg_plan_destroy(dfamg_plan p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFAMG_H */

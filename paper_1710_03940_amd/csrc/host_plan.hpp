@@ -1,0 +1,160 @@
+// Host-side setup of the deflated block-AMG solver: validation, subdomain
+// permutation, per-subdomain smoothed-aggregation hierarchies, AZ and E, and
+// the packed per-level layout that the device code consumes.  Nothing in this
+// header touches the GPU.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "dfamg.h"
+
+namespace dfamg {
+
+struct Error {
+    dfamg_status status;
+    std::string msg;
+};
+
+// Compressed sparse rows, 0-based, sorted column indices.
+struct Csr {
+    int64_t nrows = 0, ncols = 0;
+    std::vector<int64_t> ptr{0};
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int64_t nnz() const { return ptr.empty() ? 0 : ptr.back(); }
+};
+
+Csr transpose(const Csr &A);
+// C = A * B with exact-zero results dropped; rows of C sorted.
+Csr multiply(const Csr &A, const Csr &B);
+
+// One level of a subdomain hierarchy (local numbering).
+struct Level {
+    Csr A;                   // level operator
+    Csr P, R;                // prolongation (n_l x n_{l+1}) and R = P^T
+    std::vector<double> m;   // smoother diagonal
+    double eps = 0.0, omega = 0.0;
+    std::vector<int32_t> agg;  // node -> aggregate (-1: none)
+    int32_t nagg = 0;
+};
+
+struct Hierarchy {
+    std::vector<Level> lv;   // lv.back() is the coarsest level
+    int nlevels() const { return (int)lv.size(); }
+};
+
+struct SaParams {
+    double eps_strong = 0.08;
+    int coarse_enough = 500;
+    int max_levels = 20;
+    int smoother = DFAMG_SMOOTHER_SPAI0;
+    double jacobi_omega = 0.8;
+    int bs = 1;
+};
+
+Hierarchy build_hierarchy(Csr A, const SaParams &prm);
+
+// A row-tile of a packed level: up to `rows per tile` consecutive rows of one
+// subdomain.
+struct Tile {
+    int32_t row0;    // first packed row
+    int32_t nrows;
+    int32_t sub;     // internal subdomain index
+    int32_t slot;    // index of the tile's partial-sum slot
+};
+
+// Sliced ELLPACK with 64-row slices (one wavefront per slice, one row per
+// lane), entries stored slice-major so that a wavefront reads consecutive
+// addresses: entry j of lane l of slice s sits at off[s] + j*64 + l.
+struct HostSell {
+    std::vector<Tile> tiles;         // tile t covers slices 4t .. 4t+3
+    std::vector<int64_t> slice_off;  // 4 per tile
+    std::vector<int32_t> slice_w;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int64_t nnz = 0;                 // structural nonzeros (without padding)
+    int64_t nrows_covered = 0;
+};
+
+// CSR rows handled by `lanes` lanes each (a 256-thread block covers
+// 256/lanes rows).
+struct HostCsrv {
+    std::vector<Tile> tiles;
+    std::vector<int32_t> ptr;        // packed CSR over all rows of the level
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int lanes = 8;
+    int64_t nnz = 0;
+};
+
+struct HostMat {
+    int format = DFAMG_FORMAT_SELL;  // DFAMG_FORMAT_SELL or _CSR
+    int lanes = 1;
+    HostSell sell;
+    HostCsrv csr;
+    int64_t nrows = 0, ncols = 0;    // packed row / column spaces
+};
+
+// All subdomains at one level, packed in internal subdomain order.
+struct PackedLevel {
+    int64_t nrows = 0;                   // unknowns of all subdomains present
+    std::vector<int64_t> sub_off;        // nsub+1 style: offset or -1 when absent
+    std::vector<int32_t> sub_len;
+    Csr A, P, R;                         // packed (block-diagonal) matrices
+    std::vector<double> m;               // smoother diagonal (0 when inactive)
+    std::vector<int32_t> active_subs;    // subdomains smoothing on this level
+    std::vector<int32_t> coarse_subs;    // subdomains whose coarsest level is this
+};
+
+struct Plan {
+    dfamg_params prm{};
+    int64_t n = 0, nnz = 0;
+    int32_t nsys = 1, nsub = 0, ndv = 0, bs = 1;
+    // internal ordering
+    std::vector<int64_t> perm;          // internal row -> original row
+    std::vector<int64_t> sub_row_off;   // nsub+1
+    std::vector<int32_t> sub_sys;       // internal subdomain -> system
+    std::vector<int32_t> sub_user;      // internal subdomain -> user id
+    std::vector<int32_t> user_to_sub;   // user id -> internal subdomain
+    std::vector<int64_t> sys_row_off;   // nsys+1 (internal rows)
+    std::vector<int32_t> sys_sub_off;   // nsys+1 (internal subdomains)
+    Csr A;                              // permuted matrix
+    std::vector<double> Z;              // permuted n x ndv
+    std::vector<double> AZown;          // n x ndv, own-subdomain columns
+    Csr AZoff;                          // n rows; columns = global coarse index
+    std::vector<int32_t> sys_m;         // coarse size per system
+    std::vector<int64_t> sys_E_off;     // offset of each system's E block
+    std::vector<double> E;              // concatenated dense row-major blocks
+    std::vector<Hierarchy> hier;        // per internal subdomain
+    std::vector<PackedLevel> levels;
+    int nlevels_max = 0;
+    double host_seconds = 0.0;
+};
+
+// Validates, permutes and builds everything; throws Error.
+void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys,
+                const int64_t *sys_row_off, int64_t n, const int64_t *row_ptr,
+                const int32_t *col, const double *val, const int32_t *part,
+                int32_t nsub, int32_t ndv, const double *Z);
+
+// Device-ready layouts.  `ranges` lists, per subdomain covered by the
+// matrix, its first packed row and row count; tiles never straddle two
+// subdomains.  `slots` (optional) gives the partial-sum slot of the first tile
+// of each range; consecutive tiles of a range take consecutive slots.
+struct RowRange {
+    int64_t row0;
+    int32_t nrows;
+    int32_t sub;
+    int32_t slot0;
+};
+HostSell make_sell(const Csr &M, const std::vector<RowRange> &ranges);
+HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes);
+constexpr int kSellTileRows = 256;     // 4 wavefronts x 64 rows
+
+// Runs fn(i) for i in [0, count) on `threads` host threads.
+void parallel_for(int64_t count, int threads, const std::function<void(int64_t)> &fn);
+
+}  // namespace dfamg
