@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Time-to-solution benchmark of the deflated block-AMG CG solve on one MI355X.
+
+Workload: 150^3 7-point Poisson with log-normal cell coefficients (sigma = 2,
+seed 0), right-hand side U[-1,1] (seed 1), 64 box subdomains, linear deflation
+(4 vectors per subdomain), smoothed-aggregation AMG with SPAI-0, CG to
+rtol 1e-8.  One step = one complete solve through the C ABI (permutation in,
+initial projection, all Krylov iterations, solution recovery, true residual,
+permutation out) with inputs resident in HBM.
+
+The JSON line reports the FP64 path as `value` (seconds per solve), the
+mixed-precision path (FP32 hierarchy / FP64 Krylov and deflation) and, unless
+--no-batched, the 48-system batched solve next to it, the roofline of the
+dominant kernel (the outer SpMV with its fused epilogue) measured with HIP
+events inside the timed solves, and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "time-to-solution at rtol 1e-8 (FP64 vs mixed vs batched); SpMV HBM GB/s % peak"
+KERNEL_SOURCES = ["paper_1710_03940_amd/csrc/kernels.hpp", "paper_1710_03940_amd/csrc/device.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_lognormal150_traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# --------------------------------------------------------------------------
+# CPU baseline: the oracle, in a child process with one BLAS thread
+# --------------------------------------------------------------------------
+
+def cpu_baseline_worker(sample_iters):
+    import numpy as np
+    from workloads import config_lognormal_poisson
+    from oracle import OracleSolver
+    P = config_lognormal_poisson()
+    t0 = time.perf_counter()
+    S = OracleSolver(P.A, P.part, P.nsub, P.Z)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = S.solve(P.b, maxiter=sample_iters)
+    t_solve = time.perf_counter() - t0
+    print(json.dumps({"setup_s": t_setup, "sample_iters": r["iters"], "sample_s": t_solve,
+                      "numpy": np.__version__}), flush=True)
+
+
+def start_cpu_baseline(sample_iters):
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
+                             "--sample-iters", str(sample_iters)],
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, env=env, text=True)
+
+
+# --------------------------------------------------------------------------
+# GPU timing
+# --------------------------------------------------------------------------
+
+def time_solver(S, b, x, steps, warmup, log):
+    import torch
+    out = None
+    for _ in range(warmup):
+        x.zero_()
+        out = S.solve(b, x, history=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for _ in range(steps):
+        x.zero_()
+        out = S.solve(b, x, history=False)
+        iters.append(out["iters"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    log(f"  {steps} solves: {dt * 1e3:.2f} ms/solve, iterations {iters}, "
+        f"relres_true {out['relres_true']:.3e}")
+    return dt, out, iters
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--sample-iters", type=int, default=20)
+    ap.add_argument("--cpu-baseline-worker", action="store_true")
+    args = ap.parse_args()
+
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker(args.sample_iters)
+        return 0
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the deflated solve is not sharded across GPUs in this "
+              "build (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline(args.sample_iters)
+
+    import numpy as np
+    import torch
+    import paper_1710_03940_amd as dfamg
+    from workloads import config_lognormal_poisson
+
+    dev = torch.device("cuda:0")
+    log("generating the 150^3 log-normal Poisson problem")
+    P = config_lognormal_poisson()
+    b = torch.tensor(P.b, device=dev)
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+
+    log("setup FP64")
+    S64 = dfamg.Solver(P.A, P.part, P.nsub, P.Z, precision="fp64", profile=1)
+    st64 = S64.stats()
+    log(f"  host setup {st64['setup_host_s']:.2f} s, device setup {st64['setup_device_s']:.2f} s, "
+        f"levels {st64['level_rows']}")
+    log("timing FP64")
+    t64, out64, it64 = time_solver(S64, b, x, args.steps, args.warmup, log)
+    st64 = S64.stats()
+    x64 = x.clone()
+
+    result = {}
+    mixed = None
+    if not args.no_mixed:
+        log("setup mixed")
+        Sm = dfamg.Solver(P.A, P.part, P.nsub, P.Z, precision="mixed", profile=1)
+        log("timing mixed")
+        tm, outm, itm = time_solver(Sm, b, x, args.steps, args.warmup, log)
+        stm = Sm.stats()
+        diff = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        mixed = {"s_per_solve": tm, "iters": itm[-1], "relres_true": outm["relres_true"],
+                 "speedup_vs_fp64": t64 / tm, "rel_diff_vs_fp64_solution": diff,
+                 "bytes_per_iter": stm["bytes_per_iter"]}
+        Sm.close()
+
+    batched = None
+    if not args.no_batched:
+        try:
+            batched = bench_batched(args, log)
+        except Exception as exc:  # reported, never silently dropped
+            batched = {"error": str(exc)}
+
+    # roofline of the dominant kernel, from events recorded in the timed solves
+    k = st64["kernels"]["spmv"]
+    avg_s = k["ms"] / max(k["calls"], 1) * 1e-3
+    achieved = k["bytes"] / avg_s / 1e9 if avg_s > 0 else 0.0
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tf = json.load(fh)
+        if tf.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tf.get("bytes_per_launch")
+    kernels = {}
+    for name, kv in st64["kernels"].items():
+        if kv["calls"]:
+            a = kv["ms"] / kv["calls"]
+            kernels[name] = {"avg_us": a * 1e3, "GBps": (kv["bytes"] / (a * 1e-3) / 1e9) if kv["bytes"] else None}
+
+    cpu = None
+    if cpu_proc is not None:
+        log("waiting for the CPU oracle baseline")
+        outs, errs = cpu_proc.communicate(timeout=900)
+        try:
+            cb = json.loads(outs.strip().splitlines()[-1])
+            per_it = cb["sample_s"] / max(cb["sample_iters"], 1)
+            cpu = {"value": per_it * out64["iters"], "unit": "s", "cores": 1, "kind": "oracle",
+                   "sample": (f"oracle deflated CG on the full 150^3 problem for {cb['sample_iters']} "
+                              f"iterations ({cb['sample_s']:.1f} s, setup {cb['setup_s']:.1f} s "
+                              f"excluded), scaled to {out64['iters']} iterations"),
+                   "host_cores_available": len(os.sched_getaffinity(0))}
+        except Exception as exc:
+            cpu = {"error": f"{exc}: {errs[-400:]}"}
+
+    line = {
+        "metric": METRIC, "value": t64, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t64 * 1e3, "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "poisson150_lognormal2_boxes64_linear_cg",
+                   "n": P.n, "nnz": int(P.A.nnz), "subdomains": P.nsub, "deflation": "linear",
+                   "rtol": 1e-8, "smoother": "spai0", "solver": "cg"},
+        "iters": out64["iters"], "relres_true": out64["relres_true"],
+        "setup_s": {"host": st64["setup_host_s"], "device": st64["setup_device_s"]},
+        "bytes_per_iter": st64["bytes_per_iter"],
+        "effective_GBps": st64["bytes_per_iter"] * out64["iters"] / t64 / 1e9,
+        "mixed": mixed, "batched": batched,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_outer (outer SpMV + (p,q) + Z^T q epilogue)",
+                     "avg_us": avg_s * 1e6, "bytes_per_launch": k["bytes"],
+                     "events_in_graph": st64["profile_in_graph"]},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    S64.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_batched(args, log):
+    """48 independent systems in one handle vs the same systems one by one."""
+    import numpy as np
+    import torch
+    import paper_1710_03940_amd as dfamg
+    from workloads import config_batched, concat_problems
+    probs = config_batched()
+    A, part, nsub, Z, bvec, x0, off = concat_problems(probs)
+    dev = torch.device("cuda:0")
+    log(f"batched: {len(probs)} systems, {A.shape[0]} unknowns")
+    Sb = dfamg.BatchedSolver(A, part, nsub, Z, off, precision="mixed")
+    b = torch.tensor(bvec, device=dev)
+    x = torch.zeros(A.shape[0], dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        x.zero_()
+        Sb.solve(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.zero_()
+        outb = Sb.solve(b, x)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    Sb.close()
+    log(f"  batched mixed: {tb * 1e3:.2f} ms, iterations max {int(outb['iters'].max())}")
+    # plain FP64 path, one system after another
+    solvers = []
+    vecs = []
+    for p in probs:
+        solvers.append(dfamg.Solver(p.A, p.part, p.nsub, p.Z, precision="fp64"))
+        vecs.append((torch.tensor(p.b, device=dev), torch.zeros(p.n, dtype=torch.float64, device=dev)))
+    for S, (bb, xx) in zip(solvers, vecs):
+        xx.zero_()
+        S.solve(bb, xx, history=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(max(1, args.steps // 2)):
+        for S, (bb, xx) in zip(solvers, vecs):
+            xx.zero_()
+            its.append(S.solve(bb, xx, history=False)["iters"])
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / max(1, args.steps // 2)
+    for S in solvers:
+        S.close()
+    log(f"  sequential fp64: {ts * 1e3:.2f} ms")
+    return {"s_per_batch": tb, "sequential_fp64_s": ts, "speedup_vs_sequential_fp64": ts / tb,
+            "systems": len(probs), "unknowns": int(A.shape[0]),
+            "iters_max": int(outb["iters"].max()), "iters_min": int(outb["iters"].min()),
+            "relres_true_max": float(outb["relres_true"].max()),
+            "status": int(outb["status"])}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

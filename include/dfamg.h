@@ -78,6 +78,9 @@ typedef struct {
                                0 launches kernels directly (default 16)       */
     int32_t host_threads;   /* setup worker threads, 0 = hardware concurrency  */
     int32_t verbose;        /* 1 prints setup/solve phase times to stderr      */
+    int32_t profile;        /* 1 records HIP events around the hot kernels of
+                               every Krylov iteration (inside the captured
+                               graph as well); averages in dfamg_stats        */
 } dfamg_params;
 
 /* Fill *p with the defaults listed above. */
@@ -185,7 +188,27 @@ typedef struct {
     int64_t device_bytes;             /* device memory owned by the handle   */
     double  bytes_per_iter;           /* algorithmic HBM bytes per Krylov
                                          iteration (whole batch)             */
+    /* Per-kernel profile (params.profile = 1), indexed by DFAMG_KERNEL_*:
+       launches timed, total milliseconds and algorithmic bytes per launch. */
+    int64_t kernel_calls[16];
+    double  kernel_ms[16];
+    double  kernel_bytes[16];
+    int32_t profile_in_graph;         /* 1: events were replayed inside the
+                                         captured graphs; 0: the profiled
+                                         solves launched kernels directly   */
 } dfamg_stats;
+
+/* Kernel ids of the profile: the outer SpMV with its fused (p,q) and Z^T q
+ * epilogue, the per-system projection reduction (t1 sums, t2 = E^{-1} t1,
+ * alpha), the fused deflation-correction / Krylov update, the stopping test,
+ * the level-0 V-cycle kernels, everything on coarser levels (including the
+ * coarsest direct solves) as one span, and the (r,s) / direction update. */
+enum {
+    DFAMG_KERNEL_SPMV = 0, DFAMG_KERNEL_PROJECT = 1, DFAMG_KERNEL_UPDATE = 2,
+    DFAMG_KERNEL_TEST = 3, DFAMG_KERNEL_PRESMOOTH0 = 4, DFAMG_KERNEL_RESTRICT0 = 5,
+    DFAMG_KERNEL_COARSER = 6, DFAMG_KERNEL_PROLONG0 = 7, DFAMG_KERNEL_POSTSMOOTH0 = 8,
+    DFAMG_KERNEL_DIRECTION = 9, DFAMG_KERNEL_COUNT = 10
+};
 
 dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *out);
 

@@ -22,6 +22,8 @@ SMOOTHER_SPAI0, SMOOTHER_JACOBI = 0, 1
 FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL = 0, 1, 2
 PRECOND_AMG, PRECOND_NONE = 0, 1
 OP_SPMV, OP_PROJECT, OP_PRECOND, OP_RECOVER = 0, 1, 2, 3
+KERNEL_NAMES = ["spmv", "project", "update", "test", "presmooth0", "restrict0", "coarser",
+                "prolong0", "postsmooth0", "direction"]
 
 EXPORTED = [
     "dfamg_params_default", "dfamg_setup", "dfamg_setup_batched", "dfamg_solve",
@@ -47,7 +49,7 @@ class Params(ctypes.Structure):
         ("max_levels", ctypes.c_int32), ("block_size", ctypes.c_int32),
         ("precond", ctypes.c_int32), ("spmv_format", ctypes.c_int32),
         ("graph_iters", ctypes.c_int32), ("host_threads", ctypes.c_int32),
-        ("verbose", ctypes.c_int32),
+        ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
     ]
 
 
@@ -64,6 +66,8 @@ class Stats(ctypes.Structure):
         ("setup_host_s", ctypes.c_double), ("setup_device_s", ctypes.c_double),
         ("solve_s", ctypes.c_double), ("device_bytes", ctypes.c_int64),
         ("bytes_per_iter", ctypes.c_double),
+        ("kernel_calls", ctypes.c_int64 * 16), ("kernel_ms", ctypes.c_double * 16),
+        ("kernel_bytes", ctypes.c_double * 16), ("profile_in_graph", ctypes.c_int32),
     ]
 
 
@@ -212,7 +216,10 @@ def dfamg_get_stats(h):
             "lanes_level": list(s.lanes_level[:L]),
             "setup_host_s": s.setup_host_s, "setup_device_s": s.setup_device_s,
             "solve_s": s.solve_s, "device_bytes": s.device_bytes,
-            "bytes_per_iter": s.bytes_per_iter}
+            "bytes_per_iter": s.bytes_per_iter, "profile_in_graph": bool(s.profile_in_graph),
+            "kernels": {name: {"calls": int(s.kernel_calls[i]), "ms": float(s.kernel_ms[i]),
+                               "bytes": float(s.kernel_bytes[i])}
+                        for i, name in enumerate(KERNEL_NAMES)}}
 
 
 def dfamg_destroy(h):

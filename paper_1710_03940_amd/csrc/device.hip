@@ -171,6 +171,79 @@ int invert_on_device(DevArena &ar, hipStream_t s, const std::vector<const double
 
 }  // namespace
 
+// Event pairs around the hot kernels of each Krylov iteration (one set per
+// iteration slot of a chunk / captured graph).
+enum KernelId {
+    KID_SPMV = DFAMG_KERNEL_SPMV, KID_PROJECT = DFAMG_KERNEL_PROJECT, KID_UPDATE = DFAMG_KERNEL_UPDATE,
+    KID_TEST = DFAMG_KERNEL_TEST, KID_PRE0 = DFAMG_KERNEL_PRESMOOTH0, KID_RESTRICT0 = DFAMG_KERNEL_RESTRICT0,
+    KID_COARSER = DFAMG_KERNEL_COARSER, KID_PROLONG0 = DFAMG_KERNEL_PROLONG0, KID_POST0 = DFAMG_KERNEL_POSTSMOOTH0,
+    KID_DIR = DFAMG_KERNEL_DIRECTION, KID_N = DFAMG_KERNEL_COUNT
+};
+
+struct Prof {
+    bool on = false, capturing = false;
+    int slot = 0, nslots = 0;
+    std::vector<hipEvent_t> ev;          // [slot][kid][2]
+    std::vector<char> used;              // [slot][kid] recorded in this chunk / graph
+    double ms[KID_N] = {};
+    int64_t calls[KID_N] = {};
+    double bytes[KID_N] = {};
+    void init(int n) {
+        on = true;
+        nslots = n;
+        ev.resize((size_t)n * KID_N * 2);
+        used.assign((size_t)n * KID_N, 0);
+        for (auto &e : ev) HIP_CHECK(hipEventCreate(&e));
+    }
+    void mark(int kid, int which, hipStream_t st) {
+        if (!on) return;
+        hipEvent_t e = ev[((size_t)slot * KID_N + kid) * 2 + which];
+        if (capturing) HIP_CHECK(record_in_capture(e, st));
+        else HIP_CHECK(hipEventRecord(e, st));
+        used[(size_t)slot * KID_N + kid] = 1;
+    }
+    // Append an event-record node to the graph being captured on `st` and
+    // make it the capture's only dependency, so it sits between the kernels
+    // launched before and after it.
+    static hipError_t record_in_capture(hipEvent_t e, hipStream_t st) {
+        hipStreamCaptureStatus cs;
+        unsigned long long id = 0;
+        hipGraph_t g = nullptr;
+        const hipGraphNode_t *deps = nullptr;
+        size_t nd = 0;
+        hipError_t r = hipStreamGetCaptureInfo_v2(st, &cs, &id, &g, &deps, &nd);
+        if (r != hipSuccess) return r;
+        if (cs != hipStreamCaptureStatusActive) return hipErrorInvalidValue;
+        hipGraphNode_t node;
+        r = hipGraphAddEventRecordNode(&node, g, deps, nd, e);
+        if (r != hipSuccess) return r;
+        return hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies);
+    }
+    // Add the spans of the first `full` slots (all kernels) and of `partial`
+    // further slots (only kernels up to the stopping test, the rest of such an
+    // iteration exits early).
+    void collect(int full, int partial) {
+        if (!on) return;
+        for (int sl = 0; sl < std::min(nslots, full + partial); ++sl)
+            for (int k = 0; k < KID_N; ++k) {
+                if (!used[(size_t)sl * KID_N + k]) continue;
+                if (sl >= full && k > KID_TEST) continue;
+                float t = 0.f;
+                if (hipEventElapsedTime(&t, ev[((size_t)sl * KID_N + k) * 2], ev[((size_t)sl * KID_N + k) * 2 + 1]) ==
+                    hipSuccess) {
+                    ms[k] += t;
+                    calls[k] += 1;
+                }
+            }
+    }
+    void clear_used() {
+        if (!capturing) std::fill(used.begin(), used.end(), 0);
+    }
+    ~Prof() {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // preconditioner: packed hierarchy of every subdomain, one launch per step
 // ---------------------------------------------------------------------------
@@ -180,7 +253,8 @@ struct PrecondBase {
     // s = M^{-1} r with partial (r, s) per level-0 tile (part) and per
     // level-0 direct-solved subdomain (part_sub)
     virtual void apply(hipStream_t st, const double *r, double *s, double *part, double *part_sub,
-                       const SysState *states, const int32_t *sub_sys) = 0;
+                       const SysState *states, const int32_t *sub_sys, Prof *prof) = 0;
+    double kbytes[KID_N] = {};
     virtual const std::vector<int32_t> &sys_tile_off0() const = 0;
     virtual int32_t nslots0() const = 0;
     virtual double bytes_per_apply() const = 0;
@@ -241,6 +315,13 @@ struct Hierarchy_dev : PrecondBase {
                 if (l == 0) {
                     sto0 = D.A.sys_tile_off;
                     slots0 = D.A.ntiles;
+                    const double n0 = (double)PL.nrows, n1 = (double)plan.levels[1].nrows;
+                    const double ib = 4.0;
+                    // f = r is FP64 on level 0; m, res, z in VT; s written FP64
+                    kbytes[KID_PRE0] = D.A.nnz * (sv + ib) + n0 * (8.0 + 2.0 * sv);
+                    kbytes[KID_RESTRICT0] = D.R.nnz * (sv + ib) + n0 * sv + n1 * sv;
+                    kbytes[KID_PROLONG0] = D.P.nnz * (sv + ib) + n0 * (2.0 * sv + 8.0) + n1 * sv;
+                    kbytes[KID_POST0] = D.A.nnz * (sv + ib) + n0 * (2.0 * sv + 16.0);
                 }
                 // algorithmic bytes: A twice (pre/res and post), P, R, vectors
                 const double ib = 4.0;
@@ -287,19 +368,30 @@ struct Hierarchy_dev : PrecondBase {
     }
 
     void apply(hipStream_t st, const double *r, double *s, double *part, double *part_sub,
-               const SysState *states, const int32_t *sub_sys) override {
+               const SysState *states, const int32_t *sub_sys, Prof *prof) override {
         const int L = (int)lv.size();
+        auto mark = [&](int kid, int which) {
+            if (prof) prof->mark(kid, which, st);
+        };
         // downward: pre-smoothing residuals and restriction
         for (int l = 0; l + 1 < L; ++l) {
             Lvl &D = lv[l];
             if (!D.active) continue;
             const dim3 g(grid_for_tiles(D.A.ntiles)), b(kBlock);
-            if (l == 0)
+            if (l == 0) {
+                mark(KID_PRE0, 0);
                 hipLaunchKernelGGL((k_pre_res<VT, double>), g, b, 0, st, D.A.view(), D.m, r, D.res, states, sub_sys);
-            else
+                mark(KID_PRE0, 1);
+                mark(KID_RESTRICT0, 0);
+            } else {
                 hipLaunchKernelGGL((k_pre_res<VT, VT>), g, b, 0, st, D.A.view(), D.m, D.f, D.res, states, sub_sys);
+            }
             hipLaunchKernelGGL((k_spmv<VT>), dim3(grid_for_tiles(D.R.ntiles)), b, 0, st, D.R.view(), D.res,
                                lv[l + 1].f, states, sub_sys);
+            if (l == 0) {
+                mark(KID_RESTRICT0, 1);
+                mark(KID_COARSER, 0);
+            }
         }
         // direct solves on every subdomain's coarsest level
         for (int l = 0; l < L; ++l) {
@@ -319,10 +411,15 @@ struct Hierarchy_dev : PrecondBase {
             if (!D.active) continue;
             const dim3 g(grid_for_tiles(D.A.ntiles)), b(kBlock);
             if (l == 0) {
+                mark(KID_COARSER, 1);
+                mark(KID_PROLONG0, 0);
                 hipLaunchKernelGGL((k_prolong<VT, double>), g, b, 0, st, D.P.view(), D.m, r, lv[1].x, D.z, states,
                                    sub_sys);
+                mark(KID_PROLONG0, 1);
+                mark(KID_POST0, 0);
                 hipLaunchKernelGGL((k_post<VT, double, double, true>), g, b, 0, st, D.A.view(), D.m, r, D.z, s, part,
                                    states, sub_sys);
+                mark(KID_POST0, 1);
             } else {
                 hipLaunchKernelGGL((k_prolong<VT, VT>), g, b, 0, st, D.P.view(), D.m, D.f, lv[l + 1].x, D.z, states,
                                    sub_sys);
@@ -375,6 +472,9 @@ struct Handle {
     bool have_rhs = false;
     double setup_device_s = 0.0, solve_s = 0.0;
     double bytes_iter = 0.0;
+    Prof prof;
+    bool graph_profile_fallback = false;
+    bool probe_graph_events();
 
     ~Handle() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -390,7 +490,7 @@ struct Handle {
     void iteration(hipStream_t st);
     void initial(hipStream_t st);
     void finish(hipStream_t st);
-    void precond(hipStream_t st, const double *rin, double *sout);
+    void precond(hipStream_t st, const double *rin, double *sout, bool profiled = false);
     void launch_iterations(int k);
     dfamg_status run_solve(const double *rhs, double *xio);
     void apply_op(int op, const double *in, double *out);
@@ -497,6 +597,23 @@ void Handle::setup_device() {
         part_rs = ar.alloc<double>(nt);
         d_sto0 = d_sto_outer;
     }
+    if (prm.profile) {
+        prof.init(std::max(prm.graph_iters, 8));
+        if (prm.graph_iters > 0 && !probe_graph_events()) {
+            // event nodes cannot be captured here: profile with direct launches
+            prm.graph_iters = 0;
+            graph_profile_fallback = true;
+        }
+    }
+    {
+        const double nd = (double)n, nnzA = (double)P.nnz;
+        prof.bytes[KID_SPMV] = nnzA * 12.0 + 16.0 * nd + 8.0 * ndv * nd;
+        prof.bytes[KID_UPDATE] = 48.0 * nd + 8.0 * ndv * nd + (ndv ? 12.0 * (double)P.AZoff.nnz() + 4.0 * nd : 0.0);
+        prof.bytes[KID_PROJECT] = 8.0 * (double)P.sys_E_off[nsys] + 8.0 * (ndv + 1) * A.ntiles;
+        if (M)
+            for (int k = 0; k < KID_N; ++k)
+                if (M->kbytes[k] > 0) prof.bytes[k] = M->kbytes[k];
+    }
     // algorithmic bytes of one CG iteration
     {
         const double nnz = (double)P.nnz;
@@ -510,9 +627,43 @@ void Handle::setup_device() {
     setup_device_s = now_s() - t0;
 }
 
-void Handle::precond(hipStream_t st, const double *rin, double *sout) {
+__global__ void k_probe(double *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] += 1.0;
+}
+
+// True when event-record nodes can be placed inside a captured graph.
+bool Handle::probe_graph_events() {
+    double *buf = ar.alloc<double>(1);
+    HIP_CHECK(hipMemsetAsync(buf, 0, sizeof(double), stream));
+    HIP_CHECK(hipStreamSynchronize(stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    bool ok = false;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    if (hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+        bool rec = Prof::record_in_capture(e0, cap_stream) == hipSuccess;
+        hipLaunchKernelGGL(k_probe, dim3(1), dim3(64), 0, cap_stream, buf);
+        rec = rec && Prof::record_in_capture(e1, cap_stream) == hipSuccess;
+        const bool ended = hipStreamEndCapture(cap_stream, &g) == hipSuccess;
+        if (rec && ended && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess &&
+            hipGraphLaunch(ge, stream) == hipSuccess && hipStreamSynchronize(stream) == hipSuccess) {
+            float t = -1.f;
+            ok = hipEventElapsedTime(&t, e0, e1) == hipSuccess && t >= 0.f;
+        }
+    }
+    (void)hipGetLastError();
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ok;
+}
+
+void Handle::precond(hipStream_t st, const double *rin, double *sout, bool profiled) {
     if (M) {
-        M->apply(st, rin, sout, part_rs, part_rs_sub, states, d_sub_sys);
+        M->apply(st, rin, sout, part_rs, part_rs_sub, states, d_sub_sys, (profiled && prof.on) ? &prof : nullptr);
     } else {
         hipLaunchKernelGGL(k_identity, dim3(grid_for_tiles(A.ntiles)), dim3(kBlock), 0, st, A.tiles, A.ntiles, rin,
                            sout, part_rs, states, d_sub_sys);
@@ -525,19 +676,29 @@ void Handle::iteration(hipStream_t st) {
     const int nt = A.ntiles;
     const size_t red_shm = sizeof(double) * (4096 + 16);
 #define ITER_NDV(K)                                                                                             \
+    prof.mark(KID_SPMV, 0, st);                                                                                 \
     hipLaunchKernelGGL((k_outer<K, 0>), gt, b, 0, st, A.view(), p, nullptr, q, Z, part_outer, nt, states,        \
                        d_sub_sys);                                                                              \
+    prof.mark(KID_SPMV, 1, st);                                                                                 \
+    prof.mark(KID_PROJECT, 0, st);                                                                              \
     hipLaunchKernelGGL((k_project_reduce<K, 0>), dim3(nsys()), dim3(kReduceBlock), red_shm, st, part_outer, nt,  \
                        d_sto_outer, d_sub_tile_off, d_sys_sub_off, EinvT, d_sys_E_off, t2, states);             \
+    prof.mark(KID_PROJECT, 1, st);                                                                              \
+    prof.mark(KID_UPDATE, 0, st);                                                                               \
     hipLaunchKernelGGL((k_update<K, 0>), gt, b, 0, st, A.tiles, nt, p, q, y, r, AZown, AZoffp, AZoffc, AZoffv,  \
-                       t2, part_rr, states, d_sub_sys);
+                       t2, part_rr, states, d_sub_sys);                                                         \
+    prof.mark(KID_UPDATE, 1, st);
     DISPATCH_NDV(ndv(), ITER_NDV)
 #undef ITER_NDV
+    prof.mark(KID_TEST, 0, st);
     hipLaunchKernelGGL(k_residual_test<0>, dim3(nsys()), b, 0, st, part_rr, d_sto_outer, states, hist, hist_stride,
                        prm.rtol, prm.maxiter, nullptr);
-    precond(st, r, s);
+    prof.mark(KID_TEST, 1, st);
+    precond(st, r, s, true);
+    prof.mark(KID_DIR, 0, st);
     hipLaunchKernelGGL(k_rho<0>, dim3(nsys()), b, 0, st, part_rs, d_sto0, part_rs_sub, d_sys_sub_off, states);
     hipLaunchKernelGGL(k_cg_direction, gt, b, 0, st, A.tiles, nt, s, p, states, d_sub_sys);
+    prof.mark(KID_DIR, 1, st);
 }
 
 __global__ void k_zero_null_rhs(const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ y,
@@ -600,15 +761,24 @@ void Handle::finish(hipStream_t st) {
 
 void Handle::launch_iterations(int k) {
     if (prm.graph_iters <= 0) {
-        for (int i = 0; i < k; ++i) iteration(stream);
+        prof.clear_used();
+        for (int i = 0; i < k; ++i) {
+            prof.slot = i;
+            iteration(stream);
+        }
         return;
     }
     if (!graph_exec) {
+        prof.capturing = prof.on;
         HIP_CHECK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
-        for (int i = 0; i < prm.graph_iters; ++i) iteration(cap_stream);
+        for (int i = 0; i < prm.graph_iters; ++i) {
+            prof.slot = i;
+            iteration(cap_stream);
+        }
         HIP_CHECK(hipStreamEndCapture(cap_stream, &graph));
         HIP_CHECK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
         graph_k = prm.graph_iters;
+        prof.capturing = false;
     }
     for (int i = 0; i < k; i += graph_k) HIP_CHECK(hipGraphLaunch(graph_exec, stream));
 }
@@ -625,12 +795,30 @@ dfamg_status Handle::run_solve(const double *rhs, double *xio) {
     HIP_CHECK(hipGetLastError());
     const int chunk = prm.graph_iters > 0 ? prm.graph_iters : 8;
     int done_iters = 0;
+    std::vector<int32_t> it_before(nsys, 0);
+    bool first = true;
     for (;;) {
         HIP_CHECK(hipMemcpyAsync(h_states, states, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, stream));
         HIP_CHECK(hipStreamSynchronize(stream));
+        if (!first && prof.on) {
+            // iterations of this chunk that ran to the end, and the one that
+            // stopped at the test
+            int full = 0, partial = 0;
+            for (int i = 0; i < nsys; ++i) {
+                const int ran = h_states[i].iter - it_before[i];
+                const int f = h_states[i].done == kRunning ? ran : std::max(0, ran - 1);
+                full = std::max(full, f);
+                partial = std::max(partial, ran - f);
+            }
+            if (full > 0) partial = 0;
+            prof.collect(full, partial);
+        }
+        first = false;
         bool all = true;
-        for (int i = 0; i < nsys; ++i)
+        for (int i = 0; i < nsys; ++i) {
             if (h_states[i].done == kRunning) all = false;
+            it_before[i] = h_states[i].iter;
+        }
         if (all || done_iters > prm.maxiter + chunk) break;
         launch_iterations(chunk);
         HIP_CHECK(hipGetLastError());
@@ -945,6 +1133,12 @@ dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *o) {
     o->solve_s = H.solve_s;
     o->device_bytes = H.ar.bytes;
     o->bytes_per_iter = H.bytes_iter;
+    for (int k = 0; k < KID_N; ++k) {
+        o->kernel_calls[k] = H.prof.calls[k];
+        o->kernel_ms[k] = H.prof.ms[k];
+        o->kernel_bytes[k] = H.prof.bytes[k];
+    }
+    o->profile_in_graph = H.prof.on && H.prm.graph_iters > 0;
     return DFAMG_OK;
 }
 

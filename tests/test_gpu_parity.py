@@ -7,7 +7,8 @@ from workloads import (tiny_problem, config_small_poisson, make_problem)
 from oracle import OracleSolver, OracleParams
 
 torch = pytest.importorskip("torch")
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 
 def _dev():
@@ -105,3 +106,85 @@ def test_zero_rhs_and_maxiter():
     out = S.solve(_t(P.b), _t(np.zeros(P.n)))
     assert out["status"] == L._lib.ENOCONV and out["iters"] == 2
     S.close()
+
+
+def _mixed_bound(ref_iters):
+    # mixed precision must reach the same FP64 residual within +15 % iterations
+    return int(np.floor(ref_iters * 1.15)) + 1
+
+
+def test_small_poisson_mixed_reaches_fp64_residual():
+    P = config_small_poisson()
+    ref, out = _solve_pair(P, gpu_kw=dict(precision="mixed"))
+    print(f"mixed iters {out['iters']} oracle fp64 {ref['iters']}", flush=True)
+    assert out["status"] == 0
+    assert out["relres_true"] <= 1e-8
+    assert out["iters"] <= _mixed_bound(ref["iters"])
+    rel = np.linalg.norm(out["x"] - ref["x"]) / np.linalg.norm(ref["x"])
+    assert rel <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_equals_standalone(precision):
+    L = _lib()
+    from workloads import concat_problems
+    probs = [tiny_problem(N=n, pieces=pc, deflation="linear", sigma=1.0, seed=n)
+             for n, pc in [(9, (2, 1, 1)), (12, (2, 2, 1)), (7, (1, 1, 2)), (15, (3, 1, 1))]]
+    A, part, nsub, Z, b, x0, off = concat_problems(probs)
+    kw = dict(precision=precision, coarse_enough=30)
+    SB = L.BatchedSolver(A, part, nsub, Z, off, **kw)
+    xb = _t(np.zeros(A.shape[0]))
+    outb = SB.solve(_t(b), xb)
+    xb = xb.cpu().numpy()
+    SB.close()
+    assert outb["status"] == 0
+    for i, p in enumerate(probs):
+        S = L.Solver(p.A, p.part, p.nsub, p.Z, **kw)
+        x = _t(np.zeros(p.n))
+        o = S.solve(_t(p.b), x)
+        S.close()
+        assert o["iters"] == outb["iters"][i]
+        assert np.array_equal(x.cpu().numpy(), xb[off[i]:off[i + 1]])
+        assert outb["relres_true"][i] <= 1e-8
+
+
+def test_no_preconditioner_and_no_deflation():
+    # M = I with deflation: deflated CG; ndv = 0: plain AMG-PCG
+    P = tiny_problem(N=12, pieces=(2, 2, 1), deflation="linear", sigma=1.0, seed=4)
+    ref, out = _solve_pair(P, dict(precond="identity"), dict(precond="none"))
+    _assert_parity(ref, out)
+    Z0 = np.zeros((P.n, 0))
+    P0 = P.__class__(P.name, P.A, P.part, P.nsub, Z0, P.b, P.x0)
+    ref, out = _solve_pair(P0, dict(coarse_enough=30), dict(coarse_enough=30))
+    _assert_parity(ref, out)
+
+
+def test_jacobi_smoother_parity():
+    P = tiny_problem(N=13, pieces=(1, 2, 2), deflation="constant", sigma=1.0, seed=13)
+    ref, out = _solve_pair(P, dict(smoother="jacobi", coarse_enough=40),
+                           dict(smoother="jacobi", coarse_enough=40))
+    _assert_parity(ref, out)
+
+
+def test_nonzero_initial_guess():
+    P = tiny_problem(N=11, pieces=(2, 1, 1), deflation="linear", sigma=1.0, seed=2)
+    x0 = np.random.default_rng(3).standard_normal(P.n)
+    ref, out = _solve_pair(P, dict(coarse_enough=30), dict(coarse_enough=30), x0=x0)
+    _assert_parity(ref, out)
+
+
+def test_graph_and_direct_launch_agree():
+    L = _lib()
+    P = tiny_problem(N=12, pieces=(2, 2, 1), deflation="linear", sigma=1.0, seed=8)
+    res = []
+    for g in (0, 1, 16):
+        S = L.Solver(P.A, P.part, P.nsub, P.Z, coarse_enough=30, graph_iters=g)
+        x = _t(np.zeros(P.n))
+        for _ in range(3):             # repeated replays give identical results
+            x.zero_()
+            o = S.solve(_t(P.b), x)
+            res.append((o["iters"], x.cpu().numpy().copy()))
+        S.close()
+    for it, xv in res[1:]:
+        assert it == res[0][0]
+        assert np.array_equal(xv, res[0][1])

@@ -115,10 +115,16 @@ def concat_problems(problems):
     Returns (A, part, nsub_total, Z, b, x0, sys_row_off); subdomain ids are
     offset so that they are global across the batch.
     """
-    A = sp.block_diag([p.A for p in problems], format="csr")
-    A.sort_indices()
-    A.indptr = A.indptr.astype(np.int64)
-    A.indices = A.indices.astype(np.int32)
+    ptrs, cols, vals = [np.zeros(1, dtype=np.int64)], [], []
+    row0 = nz0 = 0
+    for p in problems:
+        ptrs.append(p.A.indptr[1:].astype(np.int64) + nz0)
+        cols.append(p.A.indices.astype(np.int64) + row0)
+        vals.append(p.A.data)
+        row0 += p.n
+        nz0 += p.A.nnz
+    A = sp.csr_matrix((np.concatenate(vals), np.concatenate(cols).astype(np.int32),
+                       np.concatenate(ptrs)), shape=(row0, row0))
     parts, off = [], 0
     for p in problems:
         parts.append(p.part + off)
