@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--sample-iters", type=int, default=20)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     args = ap.parse_args()
@@ -170,11 +171,7 @@ def main():
             tf = json.load(fh)
         if tf.get("kernel_source_hash") == kernel_source_hash():
             traffic = tf.get("bytes_per_launch")
-    kernels = {}
-    for name, kv in st64["kernels"].items():
-        if kv["calls"]:
-            a = kv["ms"] / kv["calls"]
-            kernels[name] = {"avg_us": a * 1e3, "GBps": (kv["bytes"] / (a * 1e-3) / 1e9) if kv["bytes"] else None}
+    kernels = kernel_breakdown(P, b, x, log) if not args.no_breakdown else None
 
     cpu = None
     if cpu_proc is not None:
@@ -214,6 +211,26 @@ def main():
     S64.close()
     print(json.dumps(line), flush=True)
     return 0
+
+
+def kernel_breakdown(P, b, x, log):
+    """Per-kernel spans of the FP64 path from a separate, untimed handle that
+    records an event pair around every kernel span of each iteration."""
+    import paper_1710_03940_amd as dfamg
+    S = dfamg.Solver(P.A, P.part, P.nsub, P.Z, precision="fp64", profile=2)
+    for _ in range(2):
+        x.zero_()
+        S.solve(b, x, history=False)
+    st = S.stats()
+    S.close()
+    out = {}
+    for name, kv in st["kernels"].items():
+        if kv["calls"]:
+            a = kv["ms"] / kv["calls"]
+            out[name] = {"avg_us": a * 1e3,
+                         "GBps": (kv["bytes"] / (a * 1e-3) / 1e9) if kv["bytes"] else None}
+    log("  per-kernel spans (us): " + ", ".join(f"{k} {v['avg_us']:.1f}" for k, v in out.items()))
+    return out
 
 
 def bench_batched(args, log):

@@ -74,13 +74,21 @@ typedef struct {
     int32_t precond;        /* DFAMG_PRECOND_AMG (default) or _NONE (M = I)    */
     int32_t spmv_format;    /* DFAMG_FORMAT_*: AUTO lets the setup autotuner
                                time the candidates on the device              */
+    int32_t autotune;       /* 1 (default): time the candidate layouts of every
+                               matrix at setup and keep the fastest; 0: one
+                               fixed layout (SELL, one row per lane, natural
+                               order, 32-bit columns; CSR with 8 lanes when
+                               spmv_format = CSR), so that two handles built
+                               from the same subdomains sum every dot product
+                               in the same order (bitwise-equal results)       */
     int32_t graph_iters;    /* Krylov iterations per captured HIP graph;
                                0 launches kernels directly (default 16)       */
     int32_t host_threads;   /* setup worker threads, 0 = hardware concurrency  */
     int32_t verbose;        /* 1 prints setup/solve phase times to stderr      */
-    int32_t profile;        /* 1 records HIP events around the hot kernels of
-                               every Krylov iteration (inside the captured
-                               graph as well); averages in dfamg_stats        */
+    int32_t profile;        /* 1 records HIP events around the outer SpMV of
+                               every Krylov iteration, 2 around every kernel
+                               span (inside the captured graph as well);
+                               averages in dfamg_stats                        */
 } dfamg_params;
 
 /* Fill *p with the defaults listed above. */

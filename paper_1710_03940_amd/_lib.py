@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
         ("coarse_enough", ctypes.c_int32), ("eps_strong", ctypes.c_double),
         ("max_levels", ctypes.c_int32), ("block_size", ctypes.c_int32),
         ("precond", ctypes.c_int32), ("spmv_format", ctypes.c_int32),
-        ("graph_iters", ctypes.c_int32), ("host_threads", ctypes.c_int32),
+        ("autotune", ctypes.c_int32), ("graph_iters", ctypes.c_int32), ("host_threads", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
     ]
 

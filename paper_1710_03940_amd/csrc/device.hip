@@ -1,8 +1,9 @@
-// Device side of the solver: uploads of the host plan, FP64 inversion of E
-// and of the coarsest blocks on the GPU, the Krylov driver (direct launches
-// or captured HIP graphs) and the C ABI.
+// Device side of the solver: uploads of the host plan with per-matrix layout
+// autotuning, FP64 inversion of E and of the coarsest blocks on the GPU, the
+// Krylov driver (direct launches or captured HIP graphs) and the C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -37,7 +38,7 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Owns every device allocation of a handle.
+// Owns device allocations.
 struct DevArena {
     std::vector<void *> ptrs;
     int64_t bytes = 0;
@@ -57,51 +58,239 @@ struct DevArena {
     template <class T>
     T *upload(const std::vector<T> &v, hipStream_t s) {
         T *p = alloc<T>(v.size());
-        if (!v.empty()) HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        if (!v.empty()) {
+            // sources are often temporaries: complete the copy before returning
+            HIP_CHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+        }
         return p;
+    }
+    void adopt(DevArena &o) {
+        ptrs.insert(ptrs.end(), o.ptrs.begin(), o.ptrs.end());
+        bytes += o.bytes;
+        o.ptrs.clear();
+        o.bytes = 0;
     }
     ~DevArena() {
         for (void *p : ptrs) (void)hipFree(p);
     }
 };
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// device matrices in one of the two layouts
+// ---------------------------------------------------------------------------
+
 template <class VT>
-struct DevSell {
+struct DevMat {
+    int fmt = DFAMG_FORMAT_SELL;  // DFAMG_FORMAT_SELL or DFAMG_FORMAT_CSR
+    int par = 1;                  // rows per lane (SELL) or lanes per row (CSR)
     DevTile *tiles = nullptr;
+    int32_t ntiles = 0;
+    bool idx16 = false, sorted = false;
     int64_t *soff = nullptr;
     int32_t *sw = nullptr;
+    int32_t *ptr = nullptr;
     int32_t *col = nullptr;
+    uint16_t *col16 = nullptr;
+    int32_t *cbase = nullptr;
+    int16_t *ridx = nullptr;
     VT *val = nullptr;
-    int32_t ntiles = 0;
     int64_t nnz = 0, stored = 0;
-    std::vector<int32_t> sys_tile_off;  // host copy: tiles per system
-    SellView<VT> view() const { return SellView<VT>{tiles, soff, sw, col, val, ntiles}; }
+    double tuned_us = 0.0;
+    std::vector<int32_t> sys_tile_off;  // host: tiles of each system
+    std::vector<int32_t> sub_tile_off;  // host: tiles of each subdomain
 };
+
+template <class VT, class Fn>
+void with_mat(const DevMat<VT> &M, Fn &&fn) {
+    if (M.fmt == DFAMG_FORMAT_SELL) {
+#define DFAMG_SELL_CASE(R)                                                                                  \
+    case R:                                                                                                 \
+        if (M.idx16) fn(SellM<VT, R, true>{M.tiles, M.soff, M.sw, M.col, M.col16, M.cbase, M.ridx, M.val, M.ntiles}); \
+        else fn(SellM<VT, R, false>{M.tiles, M.soff, M.sw, M.col, M.col16, M.cbase, M.ridx, M.val, M.ntiles});       \
+        return;
+        switch (M.par) {
+            DFAMG_SELL_CASE(1)
+            DFAMG_SELL_CASE(2)
+            DFAMG_SELL_CASE(4)
+        }
+#undef DFAMG_SELL_CASE
+    } else {
+        switch (M.par) {
+            case 4: fn(CsrM<VT, 4>{M.tiles, M.ptr, M.col, M.val, M.ntiles}); return;
+            case 8: fn(CsrM<VT, 8>{M.tiles, M.ptr, M.col, M.val, M.ntiles}); return;
+            case 16: fn(CsrM<VT, 16>{M.tiles, M.ptr, M.col, M.val, M.ntiles}); return;
+        }
+    }
+    throw Error{DFAMG_EINVAL, "unsupported matrix layout"};
+}
+
+// Compile-time bound on the deflation vectors per subdomain: kernels unroll
+// their Z / AZ loops to the bound (0, 1, 4 or 8) and skip the terms beyond
+// the run-time count.
+template <int N>
+struct NdvC {
+    static constexpr int value = N;
+};
+
+template <class Fn>
+void with_ndv(int ndv, Fn &&fn) {
+    if (ndv == 0) fn(NdvC<0>{});
+    else if (ndv == 1) fn(NdvC<1>{});
+    else if (ndv <= 4) fn(NdvC<4>{});
+    else if (ndv <= kMaxNdv) fn(NdvC<kMaxNdv>{});
+    else throw Error{DFAMG_EINVAL, "ndv out of range"};
+}
+
+namespace {
 
 std::vector<DevTile> to_dev_tiles(const std::vector<Tile> &t) {
     std::vector<DevTile> d(t.size());
-    for (size_t i = 0; i < t.size(); ++i) d[i] = DevTile{t[i].row0, t[i].nrows, t[i].sub, t[i].slot};
+    for (size_t i = 0; i < t.size(); ++i) d[i] = DevTile{t[i].row0, t[i].nrows, t[i].sub, (int32_t)i};
     return d;
 }
 
+void tile_offsets(const std::vector<Tile> &tiles, const std::vector<int32_t> &sub_sys, int nsys, int nsub,
+                  std::vector<int32_t> &sys_off, std::vector<int32_t> &sub_off) {
+    sys_off.assign(nsys + 1, 0);
+    sub_off.assign(nsub + 1, 0);
+    for (const Tile &t : tiles) {
+        sys_off[sub_sys[t.sub] + 1]++;
+        sub_off[t.sub + 1]++;
+    }
+    for (int i = 0; i < nsys; ++i) sys_off[i + 1] += sys_off[i];
+    for (int i = 0; i < nsub; ++i) sub_off[i + 1] += sub_off[i];
+}
+
+struct Layout {
+    int fmt, par;
+    bool sorted, idx16;
+};
+
+// Uploads matrix M in layout L; returns false (nothing uploaded) when the
+// layout cannot hold M (16-bit offsets that do not fit).
 template <class VT>
-DevSell<VT> upload_sell(DevArena &ar, const HostSell &S, hipStream_t s, const std::vector<int32_t> &sub_sys,
-                        int nsys) {
-    DevSell<VT> D;
-    D.tiles = ar.upload(to_dev_tiles(S.tiles), s);
-    D.soff = ar.upload(S.slice_off, s);
-    D.sw = ar.upload(S.slice_w, s);
-    D.col = ar.upload(S.col, s);
-    std::vector<VT> v(S.val.size());
-    for (size_t i = 0; i < v.size(); ++i) v[i] = (VT)S.val[i];
-    D.val = ar.upload(v, s);
-    D.ntiles = (int32_t)S.tiles.size();
-    D.nnz = S.nnz;
-    D.stored = (int64_t)S.val.size();
-    D.sys_tile_off.assign(nsys + 1, 0);
-    for (const Tile &t : S.tiles) D.sys_tile_off[sub_sys[t.sub] + 1]++;
-    for (int i = 0; i < nsys; ++i) D.sys_tile_off[i + 1] += D.sys_tile_off[i];
-    return D;
+bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, const Layout &L,
+                   hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys, int nsub, DevMat<VT> &D) {
+    D = DevMat<VT>{};
+    D.fmt = L.fmt;
+    D.par = L.par;
+    std::vector<Tile> tiles;
+    if (L.fmt == DFAMG_FORMAT_SELL) {
+        HostSell S;
+        if (!make_sell(M, ranges, L.par, L.sorted, L.idx16, S)) return false;
+        D.sorted = L.sorted;
+        D.idx16 = L.idx16;
+        tiles = S.tiles;
+        D.soff = ar.upload(S.slice_off, s);
+        D.sw = ar.upload(S.slice_w, s);
+        if (L.idx16) {
+            D.col16 = ar.upload(S.col16, s);
+            D.cbase = ar.upload(S.cbase, s);
+        } else {
+            D.col = ar.upload(S.col, s);
+        }
+        if (L.sorted) D.ridx = ar.upload(S.ridx, s);
+        std::vector<VT> v(S.val.size());
+        for (size_t i = 0; i < v.size(); ++i) v[i] = (VT)S.val[i];
+        D.val = ar.upload(v, s);
+        D.nnz = S.nnz;
+        D.stored = (int64_t)S.val.size();
+    } else {
+        HostCsrv C = make_csrv(M, ranges, L.par);
+        tiles = C.tiles;
+        D.ptr = ar.upload(C.ptr, s);
+        D.col = ar.upload(C.col, s);
+        std::vector<VT> v(C.val.size());
+        for (size_t i = 0; i < v.size(); ++i) v[i] = (VT)C.val[i];
+        D.val = ar.upload(v, s);
+        D.nnz = C.nnz;
+        D.stored = C.nnz;
+    }
+    D.tiles = ar.upload(to_dev_tiles(tiles), s);
+    D.ntiles = (int32_t)tiles.size();
+    tile_offsets(tiles, sub_sys, nsys, nsub, D.sys_tile_off, D.sub_tile_off);
+    return true;
+}
+
+// Plain y = M x timing (microseconds per launch).
+template <class VT>
+double time_spmv(const DevMat<VT> &M, const VT *x, VT *y, hipStream_t s) {
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    auto launch = [&]() {
+        with_mat(M, [&](auto m) {
+            hipLaunchKernelGGL((k_spmv<VT, decltype(m)>), dim3(grid_for_tiles(m.ntiles)), dim3(kBlock), 0, s, m, x,
+                               y, (const SysState *)nullptr, (const int32_t *)nullptr);
+        });
+    };
+    for (int i = 0; i < 2; ++i) launch();
+    const int reps = 8;
+    HIP_CHECK(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) launch();
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms * 1e3 / reps;
+}
+
+// Layout of one matrix: the fastest candidate of the family `format` (SELL,
+// CSR, or both with DFAMG_FORMAT_AUTO), timed on the device with a plain
+// product.  SELL candidates: 1, 2 or 4 rows per lane (more rows per lane only
+// while the tiles still fill the chip), rows in natural or length-sorted
+// order, 16-bit column offsets whenever they fit; CSR: 4, 8 or 16 lanes.
+template <class VT>
+DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, int format,
+                        bool autotune, hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys, int nsub) {
+    int64_t rows = 0;
+    for (auto &r : ranges) rows += r.nrows;
+    std::vector<Layout> cand;
+    if (!autotune) {
+        cand.push_back(format == DFAMG_FORMAT_CSR ? Layout{DFAMG_FORMAT_CSR, 8, false, false}
+                                                  : Layout{DFAMG_FORMAT_SELL, 1, false, false});
+    } else if (format == DFAMG_FORMAT_SELL || format == DFAMG_FORMAT_AUTO)
+        for (int r : {1, 2, 4})
+            if (r == 1 || rows / (256 * r) >= 512)
+                for (bool sorted : {false, true}) cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true});
+    if (autotune && (format == DFAMG_FORMAT_CSR || format == DFAMG_FORMAT_AUTO))
+        for (int l : {4, 8, 16}) cand.push_back(Layout{DFAMG_FORMAT_CSR, l, false, false});
+    DevArena scratch;
+    VT *x = scratch.alloc<VT>(std::max<int64_t>(1, M.ncols));
+    VT *y = scratch.alloc<VT>(std::max<int64_t>(1, M.nrows));
+    {
+        std::vector<VT> ones(std::max<int64_t>(1, M.ncols), (VT)1);
+        HIP_CHECK(hipMemcpyAsync(x, ones.data(), ones.size() * sizeof(VT), hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+    }
+    double best = 1e30;
+    DevMat<VT> bestM;
+    std::unique_ptr<DevArena> bestA;
+    for (Layout c : cand) {
+        auto A = std::make_unique<DevArena>();
+        DevMat<VT> D;
+        if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D)) {
+            if (c.fmt != DFAMG_FORMAT_SELL || !c.idx16) continue;
+            c.idx16 = false;   // columns too far apart for 16-bit offsets
+            A = std::make_unique<DevArena>();
+            if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D)) continue;
+        }
+        const double t = cand.size() > 1 ? time_spmv(D, x, y, s) : 0.0;
+        if (t < best) {
+            best = t;
+            bestM = D;
+            bestA = std::move(A);
+        }
+    }
+    if (!bestA) throw Error{DFAMG_EINVAL, "no sparse layout can hold a matrix"};
+    bestM.tuned_us = best;
+    ar.adopt(*bestA);
+    return bestM;
 }
 
 // Ranges of the packed rows of `subs` at a level.
@@ -111,21 +300,13 @@ std::vector<RowRange> ranges_of(const PackedLevel &L, const std::vector<int32_t>
     return r;
 }
 
-void assign_slots(std::vector<RowRange> &r, int rows_per_tile) {
-    int32_t slot = 0;
-    for (auto &x : r) {
-        x.slot0 = slot;
-        slot += (x.nrows + rows_per_tile - 1) / rows_per_tile;
-    }
-}
-
 // Batched FP64 Gauss-Jordan inversion on the device of the dense matrices
-// `mats` (row-major, sizes `ns`); returns the transposed inverses in type VT
-// concatenated at `out` (offsets `out_off`), and the index of the first
-// singular matrix or -1.
+// `mats` (row-major, sizes `ns`); writes the transposed inverses in type VT
+// at `out` (offsets `out_off`) and returns the index of the first singular
+// matrix or -1.
 template <class VT>
-int invert_on_device(DevArena &ar, hipStream_t s, const std::vector<const double *> &mats,
-                     const std::vector<int32_t> &ns, VT *out, const std::vector<int64_t> &out_off) {
+int invert_on_device(hipStream_t s, const std::vector<const double *> &mats, const std::vector<int32_t> &ns,
+                     VT *out, const std::vector<int64_t> &out_off, bool transposed) {
     const int nb = (int)mats.size();
     if (nb == 0) return -1;
     std::vector<InvJob> jobs(nb);
@@ -147,20 +328,20 @@ int invert_on_device(DevArena &ar, hipStream_t s, const std::vector<const double
             A[(int64_t)i * 2 * n + n + i] = 1.0;
         }
     }
-    // scratch of this call only
     DevArena tmp;
     double *d_aug = tmp.upload(aug, s);
     InvJob *d_jobs = tmp.upload(jobs, s);
     int64_t *d_coff = tmp.upload(col_off, s);
     double *d_colk = tmp.alloc<double>(col_off[nb]);
     int64_t *d_oof = tmp.upload(out_off, s);
-    int64_t maxel = (int64_t)nmax * 2 * nmax;
+    const int64_t maxel = (int64_t)nmax * 2 * nmax;
     const int gx = (int)std::min<int64_t>(1024, (maxel + kBlock - 1) / kBlock);
     for (int k = 0; k < nmax; ++k) {
         hipLaunchKernelGGL(k_gj_pivot, dim3(nb), dim3(kBlock), 0, s, d_jobs, d_aug, d_colk, d_coff, k);
         hipLaunchKernelGGL(k_gj_eliminate, dim3(gx, nb), dim3(kBlock), 0, s, d_jobs, d_aug, d_colk, d_coff, k);
     }
-    hipLaunchKernelGGL(k_gj_extract<VT>, dim3(gx, nb), dim3(kBlock), 0, s, d_jobs, d_aug, d_oof, out);
+    hipLaunchKernelGGL(k_gj_extract<VT>, dim3(gx, nb), dim3(kBlock), 0, s, d_jobs, d_aug, d_oof, out,
+                       transposed ? 1 : 0);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipMemcpyAsync(jobs.data(), d_jobs, nb * sizeof(InvJob), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -195,8 +376,9 @@ struct Prof {
         used.assign((size_t)n * KID_N, 0);
         for (auto &e : ev) HIP_CHECK(hipEventCreate(&e));
     }
+    int level = 1;                        // 1: outer SpMV only, 2: every span
     void mark(int kid, int which, hipStream_t st) {
-        if (!on) return;
+        if (!on || (level < 2 && kid != KID_SPMV)) return;
         hipEvent_t e = ev[((size_t)slot * KID_N + kid) * 2 + which];
         if (capturing) HIP_CHECK(record_in_capture(e, st));
         else HIP_CHECK(hipEventRecord(e, st));
@@ -220,7 +402,7 @@ struct Prof {
         return hipStreamUpdateCaptureDependencies(st, &node, 1, hipStreamSetCaptureDependencies);
     }
     // Add the spans of the first `full` slots (all kernels) and of `partial`
-    // further slots (only kernels up to the stopping test, the rest of such an
+    // further slots (only kernels up to the stopping test: the rest of such an
     // iteration exits early).
     void collect(int full, int partial) {
         if (!on) return;
@@ -251,13 +433,16 @@ struct Prof {
 struct PrecondBase {
     virtual ~PrecondBase() = default;
     // s = M^{-1} r with partial (r, s) per level-0 tile (part) and per
-    // level-0 direct-solved subdomain (part_sub)
-    virtual void apply(hipStream_t st, const double *r, double *s, double *part, double *part_sub,
+    // block of the level-0 direct solves (part_job)
+    virtual void apply(hipStream_t st, const double *r, double *s, double *part, double *part_job,
                        const SysState *states, const int32_t *sub_sys, Prof *prof) = 0;
-    double kbytes[KID_N] = {};
     virtual const std::vector<int32_t> &sys_tile_off0() const = 0;
     virtual int32_t nslots0() const = 0;
-    virtual double bytes_per_apply() const = 0;
+    std::vector<int32_t> sys_cjob_off0;  // level-0 direct-solve blocks per system
+    int32_t ncjobs0 = 0;
+    double bytes = 0.0;                 // algorithmic bytes per application
+    double kbytes[KID_N] = {};          // per profiled kernel
+    int fmt[20] = {}, par[20] = {};     // chosen layout of A_l
 };
 
 template <class VT>
@@ -265,27 +450,25 @@ struct Hierarchy_dev : PrecondBase {
     struct Lvl {
         int64_t nrows = 0;
         bool active = false;
-        DevSell<VT> A, P, R;
+        DevMat<VT> A, P, R;
         VT *m = nullptr;
         VT *f = nullptr, *res = nullptr, *z = nullptr, *x = nullptr;
         CoarseEntry *coarse = nullptr;
-        int32_t ncoarse = 0, coarse_nmax = 0;
+        CoarseJob *cjobs = nullptr;
+        int32_t ncoarse = 0, ncjobs = 0;
         VT *coarse_inv = nullptr;
-        int64_t coarse_elems = 0;
     };
     std::vector<Lvl> lv;
     std::vector<int32_t> sto0;
     int32_t slots0 = 0;
-    double bytes = 0.0;
 
     const std::vector<int32_t> &sys_tile_off0() const override { return sto0; }
     int32_t nslots0() const override { return slots0; }
-    double bytes_per_apply() const override { return bytes; }
 
-    void build(DevArena &ar, const Plan &plan, hipStream_t s) {
+    void build(DevArena &ar, const Plan &plan, hipStream_t s, int format, bool autotune) {
         const int L = plan.nlevels_max;
         lv.resize(L);
-        const double sv = sizeof(VT);
+        const double sv = sizeof(VT), ib = 4.0;
         for (int l = 0; l < L; ++l) {
             const PackedLevel &PL = plan.levels[l];
             Lvl &D = lv[l];
@@ -298,39 +481,44 @@ struct Hierarchy_dev : PrecondBase {
             if (D.active) {
                 D.res = ar.alloc<VT>(PL.nrows);
                 D.z = ar.alloc<VT>(PL.nrows);
-                auto rr = ranges_of(PL, PL.active_subs);
-                assign_slots(rr, kSellTileRows);
-                D.A = upload_sell<VT>(ar, make_sell(PL.A, rr), s, plan.sub_sys, plan.nsys);
-                D.P = upload_sell<VT>(ar, make_sell(PL.P, rr), s, plan.sub_sys, plan.nsys);
+                const auto rr = ranges_of(PL, PL.active_subs);
+                D.A = upload_tuned<VT>(ar, PL.A, rr, format, autotune, s, plan.sub_sys, plan.nsys, plan.nsub);
+                D.P = upload_tuned<VT>(ar, PL.P, rr, format, autotune, s, plan.sub_sys, plan.nsys, plan.nsub);
                 const PackedLevel &PN = plan.levels[l + 1];
                 std::vector<int32_t> next_subs;
                 for (int sub = 0; sub < plan.nsub; ++sub)
                     if (PN.sub_off[sub] >= 0) next_subs.push_back(sub);
-                auto rn = ranges_of(PN, next_subs);
-                assign_slots(rn, kSellTileRows);
-                D.R = upload_sell<VT>(ar, make_sell(PL.R, rn), s, plan.sub_sys, plan.nsys);
+                D.R = upload_tuned<VT>(ar, PL.R, ranges_of(PN, next_subs), format, autotune, s, plan.sub_sys,
+                                       plan.nsys, plan.nsub);
+                if (l < 20) {
+                    fmt[l] = D.A.fmt;
+                    par[l] = D.A.par;
+                }
                 std::vector<VT> m(PL.m.size());
                 for (size_t i = 0; i < m.size(); ++i) m[i] = (VT)PL.m[i];
                 D.m = ar.upload(m, s);
+                HIP_CHECK(hipStreamSynchronize(s));
+                const double n0 = (double)PL.nrows, n1 = (double)PN.nrows;
+                // the level's right-hand side is FP64 on level 0
+                const double fb = l == 0 ? 8.0 : sv;
+                const double kb_pre = D.A.nnz * (sv + ib) + n0 * (fb + 2.0 * sv);
+                const double kb_res = D.R.nnz * (sv + ib) + n0 * sv + n1 * sv;
+                const double kb_pro = D.P.nnz * (sv + ib) + n0 * (2.0 * sv + fb) + n1 * sv;
+                const double kb_post = D.A.nnz * (sv + ib) + n0 * (2.0 * sv + fb + (l == 0 ? 8.0 : sv));
                 if (l == 0) {
                     sto0 = D.A.sys_tile_off;
                     slots0 = D.A.ntiles;
-                    const double n0 = (double)PL.nrows, n1 = (double)plan.levels[1].nrows;
-                    const double ib = 4.0;
-                    // f = r is FP64 on level 0; m, res, z in VT; s written FP64
-                    kbytes[KID_PRE0] = D.A.nnz * (sv + ib) + n0 * (8.0 + 2.0 * sv);
-                    kbytes[KID_RESTRICT0] = D.R.nnz * (sv + ib) + n0 * sv + n1 * sv;
-                    kbytes[KID_PROLONG0] = D.P.nnz * (sv + ib) + n0 * (2.0 * sv + 8.0) + n1 * sv;
-                    kbytes[KID_POST0] = D.A.nnz * (sv + ib) + n0 * (2.0 * sv + 16.0);
+                    kbytes[KID_PRE0] = kb_pre;
+                    kbytes[KID_RESTRICT0] = kb_res;
+                    kbytes[KID_PROLONG0] = kb_pro;
+                    kbytes[KID_POST0] = kb_post;
+                } else {
+                    kbytes[KID_COARSER] += kb_pre + kb_res + kb_pro + kb_post;
                 }
-                // algorithmic bytes: A twice (pre/res and post), P, R, vectors
-                const double ib = 4.0;
-                bytes += 2.0 * (D.A.nnz * (sv + ib)) + (D.P.nnz + D.R.nnz) * (sv + ib) +
-                         (double)PL.nrows * sv * 10.0;
+                bytes += kb_pre + kb_res + kb_pro + kb_post;
             }
             if (!PL.coarse_subs.empty()) {
                 std::vector<CoarseEntry> ce;
-                std::vector<const double *> mats;
                 std::vector<std::vector<double>> dense;
                 std::vector<int32_t> ns;
                 std::vector<int64_t> off;
@@ -346,48 +534,75 @@ struct Hierarchy_dev : PrecondBase {
                     off.push_back(total);
                     ce.push_back(CoarseEntry{sub, n, PL.sub_off[sub], total});
                     total += (int64_t)n * n;
-                    D.coarse_nmax = std::max(D.coarse_nmax, n);
                 }
+                // one block per 4 rows of every coarsest matrix, in subdomain
+                // (hence system) order
+                std::vector<CoarseJob> cj;
+                std::vector<int32_t> sjo(plan.nsys + 1, 0);
+                for (size_t e = 0; e < ce.size(); ++e)
+                    for (int r0 = 0; r0 < ce[e].n; r0 += 4) {
+                        cj.push_back(CoarseJob{(int32_t)e, r0});
+                        sjo[plan.sub_sys[ce[e].sub] + 1]++;
+                    }
+                for (int i = 0; i < plan.nsys; ++i) sjo[i + 1] += sjo[i];
+                D.cjobs = ar.upload(cj, s);
+                D.ncjobs = (int32_t)cj.size();
+                if (l == 0) {
+                    sys_cjob_off0 = sjo;
+                    ncjobs0 = D.ncjobs;
+                }
+                std::vector<const double *> mats;
                 for (auto &d : dense) mats.push_back(d.data());
                 D.coarse_inv = ar.alloc<VT>(total);
-                D.coarse_elems = total;
-                const int bad = invert_on_device<VT>(ar, s, mats, ns, D.coarse_inv, off);
+                const int bad = invert_on_device<VT>(s, mats, ns, D.coarse_inv, off, false);
                 if (bad >= 0)
                     throw Error{DFAMG_ESINGULAR, "coarsest-level matrix of subdomain " +
                                                      std::to_string(plan.sub_user[PL.coarse_subs[bad]]) +
                                                      " is singular"};
                 D.coarse = ar.upload(ce, s);
                 D.ncoarse = (int32_t)ce.size();
-                bytes += total * sv + 2.0 * PL.nrows * sv;
+                HIP_CHECK(hipStreamSynchronize(s));
+                const double cb = total * sv + 2.0 * PL.nrows * sv;
+                bytes += cb;
+                if (l > 0) kbytes[KID_COARSER] += cb;
             }
         }
         if (L > 0 && !lv[0].active) {
             sto0.assign(plan.nsys + 1, 0);
             slots0 = 0;
         }
+        if (sys_cjob_off0.empty()) sys_cjob_off0.assign(plan.nsys + 1, 0);
     }
 
-    void apply(hipStream_t st, const double *r, double *s, double *part, double *part_sub,
+    void apply(hipStream_t st, const double *r, double *s, double *part, double *part_job,
                const SysState *states, const int32_t *sub_sys, Prof *prof) override {
         const int L = (int)lv.size();
         auto mark = [&](int kid, int which) {
             if (prof) prof->mark(kid, which, st);
         };
+        const dim3 b(kBlock);
         // downward: pre-smoothing residuals and restriction
         for (int l = 0; l + 1 < L; ++l) {
             Lvl &D = lv[l];
             if (!D.active) continue;
-            const dim3 g(grid_for_tiles(D.A.ntiles)), b(kBlock);
+            if (l == 0) mark(KID_PRE0, 0);
+            with_mat(D.A, [&](auto m) {
+                const dim3 g(grid_for_tiles(m.ntiles));
+                if (l == 0)
+                    hipLaunchKernelGGL((k_pre_res<VT, double, decltype(m)>), g, b, 0, st, m, D.m, r, D.res, states,
+                                       sub_sys);
+                else
+                    hipLaunchKernelGGL((k_pre_res<VT, VT, decltype(m)>), g, b, 0, st, m, D.m, D.f, D.res, states,
+                                       sub_sys);
+            });
             if (l == 0) {
-                mark(KID_PRE0, 0);
-                hipLaunchKernelGGL((k_pre_res<VT, double>), g, b, 0, st, D.A.view(), D.m, r, D.res, states, sub_sys);
                 mark(KID_PRE0, 1);
                 mark(KID_RESTRICT0, 0);
-            } else {
-                hipLaunchKernelGGL((k_pre_res<VT, VT>), g, b, 0, st, D.A.view(), D.m, D.f, D.res, states, sub_sys);
             }
-            hipLaunchKernelGGL((k_spmv<VT>), dim3(grid_for_tiles(D.R.ntiles)), b, 0, st, D.R.view(), D.res,
-                               lv[l + 1].f, states, sub_sys);
+            with_mat(D.R, [&](auto m) {
+                hipLaunchKernelGGL((k_spmv<VT, decltype(m)>), dim3(grid_for_tiles(m.ntiles)), b, 0, st, m, D.res,
+                                   lv[l + 1].f, states, sub_sys);
+            });
             if (l == 0) {
                 mark(KID_RESTRICT0, 1);
                 mark(KID_COARSER, 0);
@@ -397,35 +612,44 @@ struct Hierarchy_dev : PrecondBase {
         for (int l = 0; l < L; ++l) {
             Lvl &D = lv[l];
             if (!D.ncoarse) continue;
-            const size_t shm = (size_t)D.coarse_nmax * sizeof(VT);
             if (l == 0)
-                hipLaunchKernelGGL((k_coarse<VT, double, double, true>), dim3(D.ncoarse), dim3(kBlock), shm, st,
-                                   D.coarse, D.coarse_inv, r, s, part_sub, states, sub_sys);
+                hipLaunchKernelGGL((k_coarse<VT, double, double, true>), dim3(D.ncjobs), b, 0, st, D.cjobs, D.coarse,
+                                   D.coarse_inv, r, s, part_job, states, sub_sys);
             else
-                hipLaunchKernelGGL((k_coarse<VT, VT, VT, false>), dim3(D.ncoarse), dim3(kBlock), shm, st, D.coarse,
-                                   D.coarse_inv, D.f, D.x, part_sub, states, sub_sys);
+                hipLaunchKernelGGL((k_coarse<VT, VT, VT, false>), dim3(D.ncjobs), b, 0, st, D.cjobs, D.coarse,
+                                   D.coarse_inv, D.f, D.x, part_job, states, sub_sys);
         }
         // upward: coarse correction and post-smoothing
         for (int l = L - 2; l >= 0; --l) {
             Lvl &D = lv[l];
             if (!D.active) continue;
-            const dim3 g(grid_for_tiles(D.A.ntiles)), b(kBlock);
             if (l == 0) {
                 mark(KID_COARSER, 1);
                 mark(KID_PROLONG0, 0);
-                hipLaunchKernelGGL((k_prolong<VT, double>), g, b, 0, st, D.P.view(), D.m, r, lv[1].x, D.z, states,
-                                   sub_sys);
+            }
+            with_mat(D.P, [&](auto m) {
+                const dim3 g(grid_for_tiles(m.ntiles));
+                if (l == 0)
+                    hipLaunchKernelGGL((k_prolong<VT, double, decltype(m)>), g, b, 0, st, m, D.m, r, lv[1].x, D.z,
+                                       states, sub_sys);
+                else
+                    hipLaunchKernelGGL((k_prolong<VT, VT, decltype(m)>), g, b, 0, st, m, D.m, D.f, lv[l + 1].x, D.z,
+                                       states, sub_sys);
+            });
+            if (l == 0) {
                 mark(KID_PROLONG0, 1);
                 mark(KID_POST0, 0);
-                hipLaunchKernelGGL((k_post<VT, double, double, true>), g, b, 0, st, D.A.view(), D.m, r, D.z, s, part,
-                                   states, sub_sys);
-                mark(KID_POST0, 1);
-            } else {
-                hipLaunchKernelGGL((k_prolong<VT, VT>), g, b, 0, st, D.P.view(), D.m, D.f, lv[l + 1].x, D.z, states,
-                                   sub_sys);
-                hipLaunchKernelGGL((k_post<VT, VT, VT, false>), g, b, 0, st, D.A.view(), D.m, D.f, D.z, D.x, part,
-                                   states, sub_sys);
             }
+            with_mat(D.A, [&](auto m) {
+                const dim3 g(grid_for_tiles(m.ntiles));
+                if (l == 0)
+                    hipLaunchKernelGGL((k_post<VT, double, double, true, decltype(m)>), g, b, 0, st, m, D.m, r, D.z, s,
+                                       part, states, sub_sys);
+                else
+                    hipLaunchKernelGGL((k_post<VT, VT, VT, false, decltype(m)>), g, b, 0, st, m, D.m, D.f, D.z, D.x,
+                                       part, states, sub_sys);
+            });
+            if (l == 0) mark(KID_POST0, 1);
         }
     }
 };
@@ -442,22 +666,27 @@ struct Handle {
     int device = 0;
     DevArena ar;
     std::string err;
-    // outer operator and deflation
-    DevSell<double> A;
-    std::vector<int32_t> sto_outer;        // tiles per system (outer tiling)
-    int32_t *d_sto_outer = nullptr;
-    int32_t *d_sub_tile_off = nullptr;     // outer tiles per subdomain
-    int32_t *d_sub_sys = nullptr;
-    int32_t *d_sys_sub_off = nullptr;
+    // outer operator (its tiles carry the SpMV partials)
+    DevMat<double> A;
+    int32_t *d_sto_A = nullptr, *d_subto_A = nullptr;
+    // row tiles for the vector kernels (update, direction, expansion)
+    DevTile *rows = nullptr;
+    int32_t nrow_tiles = 0;
+    int32_t *d_sto_rows = nullptr, *d_subto_rows = nullptr;
+    int32_t *d_sub_sys = nullptr, *d_sys_sub_off = nullptr, *d_sys_job_off = nullptr;
     int64_t *d_perm = nullptr;
-    double *Z = nullptr, *AZown = nullptr, *AZoffv = nullptr, *EinvT = nullptr, *t2 = nullptr;
+    double *Z = nullptr, *AZown = nullptr, *AZoffv = nullptr, *t1 = nullptr, *t2 = nullptr;
+    double *EinvT = nullptr;               // row-major E^{-1} of every system
     int32_t *AZoffp = nullptr, *AZoffc = nullptr;
-    int64_t *d_sys_E_off = nullptr;
+    GemvJob *d_jobs = nullptr;
+    int32_t njobs = 0;
     // vectors
     double *b = nullptr, *y = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *w = nullptr,
            *x = nullptr;
     // partials and state
-    double *part_outer = nullptr, *part_rr = nullptr, *part_rs = nullptr, *part_rs_sub = nullptr;
+    double *part_A = nullptr, *part_rows = nullptr, *part_rs = nullptr, *part_rs_job = nullptr;
+    int32_t *d_sys_cjob_off0 = nullptr;
+    double *psub = nullptr, *tt_part = nullptr;
     int32_t *d_sto0 = nullptr;
     SysState *states = nullptr;
     SysState *h_states = nullptr;          // pinned
@@ -474,7 +703,6 @@ struct Handle {
     double bytes_iter = 0.0;
     Prof prof;
     bool graph_profile_fallback = false;
-    bool probe_graph_events();
 
     ~Handle() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -485,8 +713,13 @@ struct Handle {
 
     int nsys() const { return plan.nsys; }
     int ndv() const { return plan.ndv; }
+    SysRanges ranges() const { return SysRanges{d_sys_sub_off, d_sys_job_off}; }
 
     void setup_device();
+    bool probe_graph_events();
+    void outer(int mode, hipStream_t st, const double *xin, const double *bin, double *out, bool profiled = false);
+    void project_solve(hipStream_t st, bool in_loop, const int32_t *subto, double *part, int32_t nslots,
+                       int with_p0);
     void iteration(hipStream_t st);
     void initial(hipStream_t st);
     void finish(hipStream_t st);
@@ -495,20 +728,6 @@ struct Handle {
     dfamg_status run_solve(const double *rhs, double *xio);
     void apply_op(int op, const double *in, double *out);
 };
-
-#define DISPATCH_NDV(NDV_VALUE, FN)                                         \
-    switch (NDV_VALUE) {                                                    \
-        case 0: FN(0); break;                                               \
-        case 1: FN(1); break;                                               \
-        case 2: FN(2); break;                                               \
-        case 3: FN(3); break;                                               \
-        case 4: FN(4); break;                                               \
-        case 5: FN(5); break;                                               \
-        case 6: FN(6); break;                                               \
-        case 7: FN(7); break;                                               \
-        case 8: FN(8); break;                                               \
-        default: throw Error{DFAMG_EINVAL, "ndv out of range"};            \
-    }
 
 void Handle::setup_device() {
     const double t0 = now_s();
@@ -519,19 +738,28 @@ void Handle::setup_device() {
     for (int sy = 0; sy < nsys; ++sy)
         if (P.sys_m[sy] > 4096)
             throw Error{DFAMG_EINVAL, "coarse operator of a system exceeds 4096 unknowns (subdomains x vectors)"};
-    // outer matrix over all subdomains
     std::vector<RowRange> rr;
     for (int sub = 0; sub < nsub; ++sub)
         rr.push_back(RowRange{P.sub_row_off[sub], (int32_t)(P.sub_row_off[sub + 1] - P.sub_row_off[sub]), sub, 0});
-    assign_slots(rr, kSellTileRows);
-    HostSell outer = make_sell(P.A, rr);
-    A = upload_sell<double>(ar, outer, sm, P.sub_sys, nsys);
-    sto_outer = A.sys_tile_off;
-    d_sto_outer = ar.upload(sto_outer, sm);
-    std::vector<int32_t> sub_tile_off(nsub + 1, 0);
-    for (const Tile &t : outer.tiles) sub_tile_off[t.sub + 1]++;
-    for (int i = 0; i < nsub; ++i) sub_tile_off[i + 1] += sub_tile_off[i];
-    d_sub_tile_off = ar.upload(sub_tile_off, sm);
+    // outer matrix over all subdomains
+    A = upload_tuned<double>(ar, P.A, rr, prm.spmv_format, prm.autotune != 0, sm, P.sub_sys, nsys, nsub);
+    d_sto_A = ar.upload(A.sys_tile_off, sm);
+    d_subto_A = ar.upload(A.sub_tile_off, sm);
+    // row tiles of 256 rows: one row per thread in the vector kernels
+    {
+        const int tr = kBlock;
+        std::vector<Tile> tiles;
+        for (auto &g : rr)
+            for (int32_t r0 = 0; r0 < g.nrows; r0 += tr)
+                tiles.push_back(Tile{(int32_t)(g.row0 + r0), std::min(tr, g.nrows - r0), g.sub, 0});
+        rows = ar.upload(to_dev_tiles(tiles), sm);
+        nrow_tiles = (int32_t)tiles.size();
+        std::vector<int32_t> so, su;
+        tile_offsets(tiles, P.sub_sys, nsys, nsub, so, su);
+        d_sto_rows = ar.upload(so, sm);
+        d_subto_rows = ar.upload(su, sm);
+        HIP_CHECK(hipStreamSynchronize(sm));
+    }
     d_sub_sys = ar.upload(P.sub_sys, sm);
     d_sys_sub_off = ar.upload(P.sys_sub_off, sm);
     d_perm = ar.upload(P.perm, sm);
@@ -541,10 +769,24 @@ void Handle::setup_device() {
     AZoffp = ar.upload(offp, sm);
     AZoffc = ar.upload(P.AZoff.col, sm);
     AZoffv = ar.upload(P.AZoff.val, sm);
+    t1 = ar.alloc<double>((size_t)nsub * std::max(ndv, 1));
     t2 = ar.alloc<double>((size_t)nsub * std::max(ndv, 1));
+    psub = ar.alloc<double>(nsub);
+    // GEMV jobs of t2 = E^{-1} t1
+    std::vector<GemvJob> jobs;
+    std::vector<int32_t> joff(nsys + 1, 0);
+    for (int sy = 0; sy < nsys; ++sy) {
+        const int m = P.sys_m[sy];
+        for (int r0 = 0; r0 < m; r0 += kGemvRows)
+            jobs.push_back(GemvJob{sy, r0, m, P.sys_sub_off[sy] * ndv, P.sys_E_off[sy]});
+        joff[sy + 1] = (int32_t)jobs.size();
+    }
+    njobs = (int32_t)jobs.size();
+    d_jobs = ar.upload(jobs, sm);
+    d_sys_job_off = ar.upload(joff, sm);
+    tt_part = ar.alloc<double>(std::max(1, njobs));
+    HIP_CHECK(hipStreamSynchronize(sm));
     // E^{-1} per system (FP64, Gauss-Jordan on the device)
-    std::vector<int64_t> eoff(P.sys_E_off.begin(), P.sys_E_off.end());
-    d_sys_E_off = ar.upload(eoff, sm);
     EinvT = ar.alloc<double>(std::max<int64_t>(1, P.sys_E_off[nsys]));
     if (ndv > 0) {
         std::vector<const double *> mats;
@@ -555,11 +797,10 @@ void Handle::setup_device() {
             ns.push_back(P.sys_m[sy]);
             off.push_back(P.sys_E_off[sy]);
         }
-        const int bad = invert_on_device<double>(ar, sm, mats, ns, EinvT, off);
+        const int bad = invert_on_device<double>(sm, mats, ns, EinvT, off, false);
         if (bad >= 0)
             throw Error{DFAMG_ESINGULAR, "E = Z^T A Z of system " + std::to_string(bad) + " is singular"};
     }
-    // vectors
     b = ar.alloc<double>(n);
     y = ar.alloc<double>(n);
     r = ar.alloc<double>(n);
@@ -568,60 +809,57 @@ void Handle::setup_device() {
     s = ar.alloc<double>(n);
     w = ar.alloc<double>(n);
     x = ar.alloc<double>(n);
-    const int nt = A.ntiles;
-    part_outer = ar.alloc<double>((size_t)nt * (ndv + 1));
-    part_rr = ar.alloc<double>(nt);
-    part_rs_sub = ar.alloc<double>(nsub);
-    HIP_CHECK(hipMemsetAsync(part_rs_sub, 0, sizeof(double) * nsub, sm));
+    part_A = ar.alloc<double>((size_t)A.ntiles * (ndv + 1));
+    part_rows = ar.alloc<double>((size_t)nrow_tiles * (ndv + 1));
     states = ar.alloc<SysState>(nsys);
     HIP_CHECK(hipMemsetAsync(states, 0, sizeof(SysState) * nsys, sm));
     HIP_CHECK(hipHostMalloc((void **)&h_states, sizeof(SysState) * nsys, hipHostMallocDefault));
     hist_stride = prm.maxiter + 1;
     hist = ar.alloc<double>((size_t)nsys * hist_stride);
     relres_true = ar.alloc<double>(nsys);
-    // preconditioner
     if (prm.precond == DFAMG_PRECOND_AMG) {
         if (prm.precision == DFAMG_PREC_MIXED) {
             auto H = std::make_unique<Hierarchy_dev<float>>();
-            H->build(ar, P, sm);
+            H->build(ar, P, sm, prm.spmv_format, prm.autotune != 0);
             M = std::move(H);
         } else {
             auto H = std::make_unique<Hierarchy_dev<double>>();
-            H->build(ar, P, sm);
+            H->build(ar, P, sm, prm.spmv_format, prm.autotune != 0);
             M = std::move(H);
         }
         part_rs = ar.alloc<double>(std::max(1, M->nslots0()));
         HIP_CHECK(hipMemsetAsync(part_rs, 0, sizeof(double) * std::max(1, M->nslots0()), sm));
         d_sto0 = ar.upload(M->sys_tile_off0(), sm);
+        part_rs_job = ar.alloc<double>(std::max(1, M->ncjobs0));
+        HIP_CHECK(hipMemsetAsync(part_rs_job, 0, sizeof(double) * std::max(1, M->ncjobs0), sm));
+        d_sys_cjob_off0 = ar.upload(M->sys_cjob_off0, sm);
     } else {
-        part_rs = ar.alloc<double>(nt);
-        d_sto0 = d_sto_outer;
+        part_rs = ar.alloc<double>(nrow_tiles);
+        d_sto0 = d_sto_rows;
+        part_rs_job = ar.alloc<double>(1);
+        d_sys_cjob_off0 = ar.upload(std::vector<int32_t>(nsys + 1, 0), sm);
     }
     if (prm.profile) {
         prof.init(std::max(prm.graph_iters, 8));
+        prof.level = prm.profile;
         if (prm.graph_iters > 0 && !probe_graph_events()) {
             // event nodes cannot be captured here: profile with direct launches
             prm.graph_iters = 0;
             graph_profile_fallback = true;
         }
     }
+    // algorithmic bytes per launch of the profiled kernels and per iteration
     {
         const double nd = (double)n, nnzA = (double)P.nnz;
         prof.bytes[KID_SPMV] = nnzA * 12.0 + 16.0 * nd + 8.0 * ndv * nd;
         prof.bytes[KID_UPDATE] = 48.0 * nd + 8.0 * ndv * nd + (ndv ? 12.0 * (double)P.AZoff.nnz() + 4.0 * nd : 0.0);
         prof.bytes[KID_PROJECT] = 8.0 * (double)P.sys_E_off[nsys] + 8.0 * (ndv + 1) * A.ntiles;
+        prof.bytes[KID_DIR] = 24.0 * nd;
         if (M)
             for (int k = 0; k < KID_N; ++k)
                 if (M->kbytes[k] > 0) prof.bytes[k] = M->kbytes[k];
-    }
-    // algorithmic bytes of one CG iteration
-    {
-        const double nnz = (double)P.nnz;
-        bytes_iter = nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n;                  // SpMV: A, x, q
-        bytes_iter += 8.0 * ndv * n * 2.0 + 12.0 * (double)P.AZoff.nnz();   // Z, AZ
-        bytes_iter += 8.0 * (double)P.sys_E_off[nsys];                      // E^{-1}
-        bytes_iter += 8.0 * n * 8.0;                                        // y,r (rw), p,q read; s,p read, p write
-        if (M) bytes_iter += M->bytes_per_apply();
+        bytes_iter = prof.bytes[KID_SPMV] + prof.bytes[KID_UPDATE] + prof.bytes[KID_PROJECT] + prof.bytes[KID_DIR];
+        bytes_iter += M ? M->bytes : 16.0 * nd;
     }
     HIP_CHECK(hipStreamSynchronize(sm));
     setup_device_s = now_s() - t0;
@@ -661,102 +899,110 @@ bool Handle::probe_graph_events() {
     return ok;
 }
 
+// Outer SpMV launch with the epilogue of `mode` (see k_outer).
+void Handle::outer(int mode, hipStream_t st, const double *xin, const double *bin, double *out, bool profiled) {
+    if (profiled) prof.mark(KID_SPMV, 0, st);
+    with_mat(A, [&](auto m) {
+        with_ndv(ndv(), [&](auto nd_c) {
+            constexpr int ND = decltype(nd_c)::value;
+            const dim3 g(grid_for_tiles(m.ntiles)), bl(kBlock);
+            using MT = decltype(m);
+            const int nd = ndv();
+            switch (mode) {
+                case 0: hipLaunchKernelGGL((k_outer<0, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
+                case 1: hipLaunchKernelGGL((k_outer<1, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
+                case 2: hipLaunchKernelGGL((k_outer<2, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
+                case 3: hipLaunchKernelGGL((k_outer<3, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
+                default: hipLaunchKernelGGL((k_outer<4, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
+            }
+        });
+    });
+    if (profiled) prof.mark(KID_SPMV, 1, st);
+}
+
+// t1 per subdomain from tile partials, then t2 = E^{-1} t1 per system.
+void Handle::project_solve(hipStream_t st, bool in_loop, const int32_t *subto, double *part, int32_t nslots,
+                           int with_p0) {
+    const int nsub = plan.nsub;
+    if (in_loop)
+        hipLaunchKernelGGL(k_t1<true>, dim3(nsub), dim3(kBlock), 0, st, part, nslots, subto, ndv(), t1, psub, states,
+                           d_sub_sys, with_p0);
+    else
+        hipLaunchKernelGGL(k_t1<false>, dim3(nsub), dim3(kBlock), 0, st, part, nslots, subto, ndv(), t1, psub, states,
+                           d_sub_sys, with_p0);
+    if (ndv() > 0) {
+        if (in_loop)
+            hipLaunchKernelGGL(k_egemv<true>, dim3(njobs), dim3(kBlock), 0, st, d_jobs, EinvT, t1, t2, tt_part, states);
+        else
+            hipLaunchKernelGGL(k_egemv<false>, dim3(njobs), dim3(kBlock), 0, st, d_jobs, EinvT, t1, t2, tt_part,
+                               states);
+    }
+}
+
 void Handle::precond(hipStream_t st, const double *rin, double *sout, bool profiled) {
     if (M) {
-        M->apply(st, rin, sout, part_rs, part_rs_sub, states, d_sub_sys, (profiled && prof.on) ? &prof : nullptr);
+        M->apply(st, rin, sout, part_rs, part_rs_job, states, d_sub_sys, (profiled && prof.on) ? &prof : nullptr);
     } else {
-        hipLaunchKernelGGL(k_identity, dim3(grid_for_tiles(A.ntiles)), dim3(kBlock), 0, st, A.tiles, A.ntiles, rin,
+        hipLaunchKernelGGL(k_identity, dim3(grid_for_tiles(nrow_tiles)), dim3(kBlock), 0, st, rows, nrow_tiles, rin,
                            sout, part_rs, states, d_sub_sys);
     }
 }
 
 // One CG iteration on the deflated system (all systems at once).
 void Handle::iteration(hipStream_t st) {
-    const dim3 gt(grid_for_tiles(A.ntiles)), b(kBlock);
-    const int nt = A.ntiles;
-    const size_t red_shm = sizeof(double) * (4096 + 16);
-#define ITER_NDV(K)                                                                                             \
-    prof.mark(KID_SPMV, 0, st);                                                                                 \
-    hipLaunchKernelGGL((k_outer<K, 0>), gt, b, 0, st, A.view(), p, nullptr, q, Z, part_outer, nt, states,        \
-                       d_sub_sys);                                                                              \
-    prof.mark(KID_SPMV, 1, st);                                                                                 \
-    prof.mark(KID_PROJECT, 0, st);                                                                              \
-    hipLaunchKernelGGL((k_project_reduce<K, 0>), dim3(nsys()), dim3(kReduceBlock), red_shm, st, part_outer, nt,  \
-                       d_sto_outer, d_sub_tile_off, d_sys_sub_off, EinvT, d_sys_E_off, t2, states);             \
-    prof.mark(KID_PROJECT, 1, st);                                                                              \
-    prof.mark(KID_UPDATE, 0, st);                                                                               \
-    hipLaunchKernelGGL((k_update<K, 0>), gt, b, 0, st, A.tiles, nt, p, q, y, r, AZown, AZoffp, AZoffc, AZoffv,  \
-                       t2, part_rr, states, d_sub_sys);                                                         \
+    const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
+    outer(0, st, p, nullptr, q, true);
+    prof.mark(KID_PROJECT, 0, st);
+    project_solve(st, true, d_subto_A, part_A, A.ntiles, 1);
+    prof.mark(KID_PROJECT, 1, st);
+    prof.mark(KID_UPDATE, 0, st);
+    with_ndv(ndv(), [&](auto c) {
+        hipLaunchKernelGGL((k_update<0, decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, p, q, y, r, AZown, ndv(),
+                           AZoffp, AZoffc, AZoffv, t2, part_rows, states, d_sub_sys, psub, tt_part, ranges());
+    });
     prof.mark(KID_UPDATE, 1, st);
-    DISPATCH_NDV(ndv(), ITER_NDV)
-#undef ITER_NDV
     prof.mark(KID_TEST, 0, st);
-    hipLaunchKernelGGL(k_residual_test<0>, dim3(nsys()), b, 0, st, part_rr, d_sto_outer, states, hist, hist_stride,
-                       prm.rtol, prm.maxiter, nullptr);
+    hipLaunchKernelGGL(k_residual_test<0>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, d_sto_rows, states, hist,
+                       hist_stride, prm.rtol, prm.maxiter, nullptr, psub, ranges());
     prof.mark(KID_TEST, 1, st);
     precond(st, r, s, true);
     prof.mark(KID_DIR, 0, st);
-    hipLaunchKernelGGL(k_rho<0>, dim3(nsys()), b, 0, st, part_rs, d_sto0, part_rs_sub, d_sys_sub_off, states);
-    hipLaunchKernelGGL(k_cg_direction, gt, b, 0, st, A.tiles, nt, s, p, states, d_sub_sys);
+    hipLaunchKernelGGL(k_rho<0>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
+                       d_sys_cjob_off0, states);
+    hipLaunchKernelGGL(k_cg_direction<false>, gr, bl, 0, st, rows, nrow_tiles, s, p, states, d_sub_sys);
     prof.mark(KID_DIR, 1, st);
-}
-
-__global__ void k_zero_null_rhs(const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ y,
-                                const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
-    const int tile = tile_of_block(ntiles);
-    if (tile >= ntiles) return;
-    const DevTile T = tiles[tile];
-    if (st[sub_sys[T.sub]].bb != 0.0) return;
-    if ((int)threadIdx.x < T.nrows) y[T.row0 + threadIdx.x] = 0.0;
-}
-
-__global__ void k_copy_dir(const DevTile *__restrict__ tiles, int32_t ntiles, const double *__restrict__ s,
-                           double *__restrict__ p) {
-    const int tile = tile_of_block(ntiles);
-    if (tile >= ntiles) return;
-    const DevTile T = tiles[tile];
-    if ((int)threadIdx.x < T.nrows) p[T.row0 + threadIdx.x] = s[T.row0 + threadIdx.x];
 }
 
 // r0 = P(b - A y0), stopping test, s0 = M^{-1} r0, rho0, p0 = s0
 void Handle::initial(hipStream_t st) {
-    const dim3 gt(grid_for_tiles(A.ntiles)), b(kBlock);
-    const int nt = A.ntiles;
-    const size_t red_shm = sizeof(double) * (4096 + 16);
-#define INIT_NDV(K)                                                                                             \
-    hipLaunchKernelGGL((k_outer<K, 1>), gt, b, 0, st, A.view(), y, this->b, w, Z, part_outer, nt, states,       \
-                       d_sub_sys);                                                                              \
-    hipLaunchKernelGGL((k_project_reduce<K, 1>), dim3(nsys()), dim3(kReduceBlock), red_shm, st, part_outer, nt,  \
-                       d_sto_outer, d_sub_tile_off, d_sys_sub_off, EinvT, d_sys_E_off, t2, states);             \
-    hipLaunchKernelGGL((k_update<K, 1>), gt, b, 0, st, A.tiles, nt, nullptr, w, nullptr, r, AZown, AZoffp,       \
-                       AZoffc, AZoffv, t2, part_rr, states, d_sub_sys);
-    DISPATCH_NDV(ndv(), INIT_NDV)
-#undef INIT_NDV
-    hipLaunchKernelGGL(k_residual_test<1>, dim3(nsys()), b, 0, st, part_rr, d_sto_outer, states, hist, hist_stride,
-                       prm.rtol, prm.maxiter, nullptr);
-    hipLaunchKernelGGL(k_zero_null_rhs, gt, b, 0, st, A.tiles, nt, y, states, d_sub_sys);
+    const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
+    outer(1, st, y, b, w);
+    project_solve(st, false, d_subto_A, part_A, A.ntiles, 1);
+    with_ndv(ndv(), [&](auto c) {
+        hipLaunchKernelGGL((k_update<1, decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, nullptr, w, nullptr, r,
+                           AZown, ndv(), AZoffp, AZoffc, AZoffv, t2, part_rows, states, d_sub_sys, psub, tt_part,
+                           ranges());
+    });
+    hipLaunchKernelGGL(k_residual_test<1>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, d_sto_rows, states, hist,
+                       hist_stride, prm.rtol, prm.maxiter, nullptr, psub, ranges());
+    hipLaunchKernelGGL(k_zero_null_rhs, gr, bl, 0, st, rows, nrow_tiles, y, states, d_sub_sys);
     precond(st, r, s);
-    hipLaunchKernelGGL(k_rho<1>, dim3(nsys()), b, 0, st, part_rs, d_sto0, part_rs_sub, d_sys_sub_off, states);
-    hipLaunchKernelGGL(k_copy_dir, gt, b, 0, st, A.tiles, nt, s, p);
+    hipLaunchKernelGGL(k_rho<1>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
+                       d_sys_cjob_off0, states);
+    hipLaunchKernelGGL(k_cg_direction<true>, gr, bl, 0, st, rows, nrow_tiles, s, p, states, d_sub_sys);
 }
 
 // x = y + Z E^{-1} Z^T (b - A y), then ||b - A x|| / ||b||
 void Handle::finish(hipStream_t st) {
-    const dim3 gt(grid_for_tiles(A.ntiles)), b(kBlock);
-    const int nt = A.ntiles;
-    const size_t red_shm = sizeof(double) * (4096 + 16);
-#define FIN_NDV(K)                                                                                              \
-    hipLaunchKernelGGL((k_outer<K, 1>), gt, b, 0, st, A.view(), y, this->b, w, Z, part_outer, nt, states,       \
-                       d_sub_sys);                                                                              \
-    hipLaunchKernelGGL((k_project_reduce<K, 2>), dim3(nsys()), dim3(kReduceBlock), red_shm, st, part_outer, nt,  \
-                       d_sto_outer, d_sub_tile_off, d_sys_sub_off, EinvT, d_sys_E_off, t2, states);             \
-    hipLaunchKernelGGL((k_expand<K>), gt, b, 0, st, A.tiles, nt, y, Z, t2, x);                                   \
-    hipLaunchKernelGGL((k_outer<K, 2>), gt, b, 0, st, A.view(), x, this->b, w, Z, part_outer, nt, states,       \
-                       d_sub_sys);
-    DISPATCH_NDV(ndv(), FIN_NDV)
-#undef FIN_NDV
-    hipLaunchKernelGGL(k_residual_test<2>, dim3(nsys()), b, 0, st, part_outer, d_sto_outer, states, hist,
-                       hist_stride, prm.rtol, prm.maxiter, relres_true);
+    const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
+    outer(1, st, y, b, w);
+    project_solve(st, false, d_subto_A, part_A, A.ntiles, 0);
+    with_ndv(ndv(), [&](auto c) {
+        hipLaunchKernelGGL((k_expand<decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, y, Z, ndv(), t2, x);
+    });
+    outer(2, st, x, b, w);
+    hipLaunchKernelGGL(k_residual_test<2>, dim3(nsys()), dim3(kWideBlock), 0, st, part_A, d_sto_A, states, hist,
+                       hist_stride, prm.rtol, prm.maxiter, relres_true, psub, ranges());
 }
 
 void Handle::launch_iterations(int k) {
@@ -843,67 +1089,36 @@ dfamg_status Handle::run_solve(const double *rhs, double *xio) {
     return st;
 }
 
-__global__ void k_zt_partial(SellView<double> A, const double *__restrict__ v, const double *__restrict__ Z,
-                             double *__restrict__ part, int32_t nslots, int ndv) {
-    __shared__ double lds[4];
-    const int tile = tile_of_block(A.ntiles);
-    if (tile >= A.ntiles) return;
-    const DevTile T = A.tiles[tile];
-    for (int k = 0; k < ndv; ++k) {
-        double a = 0.0;
-        if ((int)threadIdx.x < T.nrows) {
-            const int row = T.row0 + threadIdx.x;
-            a = Z[(int64_t)row * ndv + k] * v[row];
-        }
-        const double sum = block_sum256(a, lds);
-        if (threadIdx.x == 0) part[(int64_t)(k + 1) * nslots + T.slot] = sum;
-    }
-}
-
-__global__ void k_plain_spmv(SellView<double> A, const double *__restrict__ x, double *__restrict__ y) {
-    const int tile = tile_of_block(A.ntiles);
-    if (tile >= A.ntiles) return;
-    const DevTile T = A.tiles[tile];
-    if ((int)threadIdx.x >= T.nrows) return;
-    y[T.row0 + threadIdx.x] = sell_row<double, double>(A, tile, threadIdx.x, [&](int c) { return x[c]; });
-}
-
 void Handle::apply_op(int op, const double *in, double *out) {
     const int64_t n = plan.n;
     const int nb = (int)((n + 255) / 256);
-    const dim3 gt(grid_for_tiles(A.ntiles)), b(kBlock);
-    const int nt = A.ntiles;
-    const size_t red_shm = sizeof(double) * (4096 + 16);
+    const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
     hipStream_t st = stream;
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, st, n, d_perm, in, w);
     HIP_CHECK(hipMemsetAsync(states, 0, sizeof(SysState) * plan.nsys, st));
     switch (op) {
         case DFAMG_OP_SPMV:
-            hipLaunchKernelGGL(k_plain_spmv, gt, b, 0, st, A.view(), w, x);
+            outer(4, st, w, nullptr, x);
             break;
         case DFAMG_OP_PROJECT:
-            hipLaunchKernelGGL(k_zt_partial, gt, b, 0, st, A.view(), w, Z, part_outer, nt, ndv());
-#define PROJ_NDV(K)                                                                                             \
-    hipLaunchKernelGGL((k_project_reduce<K, 2>), dim3(nsys()), dim3(kReduceBlock), red_shm, st, part_outer, nt,  \
-                       d_sto_outer, d_sub_tile_off, d_sys_sub_off, EinvT, d_sys_E_off, t2, states);             \
-    hipLaunchKernelGGL((k_update<K, 2>), gt, b, 0, st, A.tiles, nt, nullptr, w, nullptr, x, AZown, AZoffp,       \
-                       AZoffc, AZoffv, t2, part_rr, states, d_sub_sys);
-            DISPATCH_NDV(ndv(), PROJ_NDV)
-#undef PROJ_NDV
+            hipLaunchKernelGGL(k_zt_partial, gr, bl, 0, st, rows, nrow_tiles, w, Z, ndv(), part_rows, nrow_tiles);
+            project_solve(st, false, d_subto_rows, part_rows, nrow_tiles, 0);
+            with_ndv(ndv(), [&](auto c) {
+                hipLaunchKernelGGL((k_update<2, decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, nullptr, w,
+                                   nullptr, x, AZown, ndv(), AZoffp, AZoffc, AZoffv, t2, part_rows, states, d_sub_sys,
+                                   psub, tt_part, ranges());
+            });
             break;
         case DFAMG_OP_PRECOND:
             precond(st, w, x);
             break;
         case DFAMG_OP_RECOVER:
             if (!have_rhs) throw Error{DFAMG_EINVAL, "RECOVER needs a previous solve (for b)"};
-#define REC_NDV(K)                                                                                              \
-    hipLaunchKernelGGL((k_outer<K, 1>), gt, b, 0, st, A.view(), w, this->b, q, Z, part_outer, nt, states,       \
-                       d_sub_sys);                                                                              \
-    hipLaunchKernelGGL((k_project_reduce<K, 2>), dim3(nsys()), dim3(kReduceBlock), red_shm, st, part_outer, nt,  \
-                       d_sto_outer, d_sub_tile_off, d_sys_sub_off, EinvT, d_sys_E_off, t2, states);             \
-    hipLaunchKernelGGL((k_expand<K>), gt, b, 0, st, A.tiles, nt, w, Z, t2, x);
-            DISPATCH_NDV(ndv(), REC_NDV)
-#undef REC_NDV
+            outer(1, st, w, b, q);
+            project_solve(st, false, d_subto_A, part_A, A.ntiles, 0);
+            with_ndv(ndv(), [&](auto c) {
+                hipLaunchKernelGGL((k_expand<decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, w, Z, ndv(), t2, x);
+            });
             break;
         default:
             throw Error{DFAMG_EINVAL, "unknown operator"};
@@ -1011,9 +1226,11 @@ void dfamg_params_default(dfamg_params *p) {
     p->block_size = 1;
     p->precond = DFAMG_PRECOND_AMG;
     p->spmv_format = DFAMG_FORMAT_AUTO;
+    p->autotune = 1;
     p->graph_iters = 16;
     p->host_threads = 0;
     p->verbose = 0;
+    p->profile = 0;
 }
 
 dfamg_status dfamg_setup(const dfamg_params *prm, int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -1124,10 +1341,12 @@ dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *o) {
         o->level_rows[l] = P.levels[l].nrows;
         o->level_nnz[l] = P.levels[l].A.nnz();
         o->level_p_nnz[l] = P.levels[l].P.nnz();
-        o->format_level[l] = DFAMG_FORMAT_SELL;
-        o->lanes_level[l] = 1;
+        if (H.M) {
+            o->format_level[l] = H.M->fmt[l];
+            o->lanes_level[l] = H.M->par[l];
+        }
     }
-    o->format_outer = DFAMG_FORMAT_SELL;
+    o->format_outer = H.A.fmt;
     o->setup_host_s = P.host_seconds;
     o->setup_device_s = H.setup_device_s;
     o->solve_s = H.solve_s;

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdint>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -487,25 +488,41 @@ Hierarchy build_hierarchy(Csr A, const SaParams &prm) {
 // device layouts
 // ---------------------------------------------------------------------------
 
-HostSell make_sell(const Csr &M, const std::vector<RowRange> &ranges) {
-    HostSell S;
+bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool sorted, bool idx16,
+               HostSell &S) {
+    S = HostSell{};
+    S.rpl = rpl;
+    S.sorted = sorted;
+    S.idx16 = idx16;
+    const int tile_rows = sell_tile_rows(rpl), nsl = 4 * rpl;
     for (const RowRange &rg : ranges) {
         int32_t slot = rg.slot0;
-        for (int32_t r0 = 0; r0 < rg.nrows; r0 += kSellTileRows) {
-            Tile t{(int32_t)(rg.row0 + r0), std::min(kSellTileRows, rg.nrows - r0), rg.sub, slot++};
+        for (int32_t r0 = 0; r0 < rg.nrows; r0 += tile_rows) {
+            Tile t{(int32_t)(rg.row0 + r0), std::min(tile_rows, rg.nrows - r0), rg.sub, slot++};
             S.tiles.push_back(t);
         }
     }
+    auto len = [&](int64_t r) { return (int)(M.ptr[r + 1] - M.ptr[r]); };
+    // tile-local order of the rows (identity unless sorted)
+    std::vector<int16_t> order((size_t)S.tiles.size() * tile_rows, 0);
+    for (size_t ti = 0; ti < S.tiles.size(); ++ti) {
+        const Tile &t = S.tiles[ti];
+        int16_t *o = &order[ti * tile_rows];
+        for (int k = 0; k < t.nrows; ++k) o[k] = (int16_t)k;
+        if (sorted)
+            std::stable_sort(o, o + t.nrows, [&](int16_t a, int16_t b) { return len(t.row0 + a) > len(t.row0 + b); });
+    }
+    if (sorted) S.ridx = order;
     int64_t off = 0;
-    S.slice_off.reserve(S.tiles.size() * 4);
-    for (const Tile &t : S.tiles) {
-        for (int k = 0; k < 4; ++k) {
+    S.slice_off.reserve(S.tiles.size() * nsl);
+    for (size_t ti = 0; ti < S.tiles.size(); ++ti) {
+        const Tile &t = S.tiles[ti];
+        for (int k = 0; k < nsl; ++k) {
             int w = 0;
             for (int l = 0; l < 64; ++l) {
                 const int32_t lr = k * 64 + l;
                 if (lr >= t.nrows) break;
-                const int64_t r = t.row0 + lr;
-                w = std::max<int>(w, (int)(M.ptr[r + 1] - M.ptr[r]));
+                w = std::max(w, len(t.row0 + order[ti * tile_rows + lr]));
             }
             S.slice_off.push_back(off);
             S.slice_w.push_back(w);
@@ -513,40 +530,56 @@ HostSell make_sell(const Csr &M, const std::vector<RowRange> &ranges) {
         }
         S.nrows_covered += t.nrows;
     }
-    S.col.assign(off, 0);
+    if (idx16) {
+        S.col16.assign(off, 0);
+        S.cbase.assign(S.tiles.size(), 0);
+        for (size_t ti = 0; ti < S.tiles.size(); ++ti) {
+            const Tile &t = S.tiles[ti];
+            int64_t lo = INT64_MAX, hi = -1;
+            for (int64_t r = t.row0; r < t.row0 + t.nrows; ++r)
+                for (int64_t k = M.ptr[r]; k < M.ptr[r + 1]; ++k) {
+                    lo = std::min<int64_t>(lo, M.col[k]);
+                    hi = std::max<int64_t>(hi, M.col[k]);
+                }
+            if (hi < 0) lo = hi = std::min<int64_t>(t.row0, M.ncols - 1);
+            // padding of empty rows uses the base itself
+            if (hi - lo > 65535) return false;
+            S.cbase[ti] = (int32_t)lo;
+        }
+    } else {
+        S.col.assign(off, 0);
+    }
     S.val.assign(off, 0.0);
     for (size_t ti = 0; ti < S.tiles.size(); ++ti) {
         const Tile &t = S.tiles[ti];
-        for (int k = 0; k < 4; ++k) {
-            const int64_t base = S.slice_off[ti * 4 + k];
-            const int w = S.slice_w[ti * 4 + k];
+        for (int k = 0; k < nsl; ++k) {
+            const int64_t base = S.slice_off[ti * nsl + k];
+            const int w = S.slice_w[ti * nsl + k];
             for (int l = 0; l < 64; ++l) {
                 const int32_t lr = k * 64 + l;
                 if (lr >= t.nrows) break;
-                const int64_t r = t.row0 + lr;
-                const int64_t len = M.ptr[r + 1] - M.ptr[r];
-                const int32_t padc = len > 0 ? M.col[M.ptr[r + 1] - 1] : 0;
+                const int64_t r = t.row0 + order[ti * tile_rows + lr];
+                const int64_t n = len(r);
+                const int32_t padc = n > 0 ? M.col[M.ptr[r + 1] - 1]
+                                           : (idx16 ? S.cbase[ti] : (int32_t)std::min<int64_t>(r, M.ncols - 1));
                 for (int j = 0; j < w; ++j) {
                     const int64_t d = base + (int64_t)j * 64 + l;
-                    if (j < len) {
-                        S.col[d] = M.col[M.ptr[r] + j];
-                        S.val[d] = M.val[M.ptr[r] + j];
-                    } else {
-                        S.col[d] = padc;
-                        S.val[d] = 0.0;
-                    }
+                    const int32_t c = j < n ? M.col[M.ptr[r] + j] : padc;
+                    if (idx16) S.col16[d] = (uint16_t)(c - S.cbase[ti]);
+                    else S.col[d] = c;
+                    S.val[d] = j < n ? M.val[M.ptr[r] + j] : 0.0;
                 }
-                S.nnz += len;
+                S.nnz += n;
             }
         }
     }
-    return S;
+    return true;
 }
 
 HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes) {
     HostCsrv C;
     C.lanes = lanes;
-    const int rows_per_tile = 256 / lanes;
+    const int rows_per_tile = csr_tile_rows(lanes);
     for (const RowRange &rg : ranges) {
         int32_t slot = rg.slot0;
         for (int32_t r0 = 0; r0 < rg.nrows; r0 += rows_per_tile)

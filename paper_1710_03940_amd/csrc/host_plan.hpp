@@ -68,10 +68,18 @@ struct Tile {
 
 // Sliced ELLPACK with 64-row slices (one wavefront per slice, one row per
 // lane), entries stored slice-major so that a wavefront reads consecutive
-// addresses: entry j of lane l of slice s sits at off[s] + j*64 + l.
+// addresses: entry j of lane l of slice s sits at off[s] + j*64 + l.  A tile
+// of 256*rpl rows holds 4*rpl slices; wavefront w of the block walks slices
+// w*rpl .. w*rpl+rpl-1.
 struct HostSell {
-    std::vector<Tile> tiles;         // tile t covers slices 4t .. 4t+3
-    std::vector<int64_t> slice_off;  // 4 per tile
+    int rpl = 1;                     // rows per lane
+    bool sorted = false;             // rows of each tile ordered by length (SELL-sigma)
+    bool idx16 = false;              // columns stored as 16-bit offsets from a tile base
+    std::vector<int16_t> ridx;       // sorted: tile-local row of each slot
+    std::vector<uint16_t> col16;     // idx16: col - cbase[tile]
+    std::vector<int32_t> cbase;      // idx16: smallest column of each tile
+    std::vector<Tile> tiles;         // tile t covers slices 4*rpl*t ..
+    std::vector<int64_t> slice_off;  // 4*rpl per tile
     std::vector<int32_t> slice_w;
     std::vector<int32_t> col;
     std::vector<double> val;
@@ -79,8 +87,8 @@ struct HostSell {
     int64_t nrows_covered = 0;
 };
 
-// CSR rows handled by `lanes` lanes each (a 256-thread block covers
-// 256/lanes rows).
+// CSR rows handled by `lanes` lanes each; a 256-thread block covers a tile of
+// 256 rows, its 256/lanes lane groups striding over them.
 struct HostCsrv {
     std::vector<Tile> tiles;
     std::vector<int32_t> ptr;        // packed CSR over all rows of the level
@@ -150,9 +158,16 @@ struct RowRange {
     int32_t sub;
     int32_t slot0;
 };
-HostSell make_sell(const Csr &M, const std::vector<RowRange> &ranges);
+// `sorted` orders the rows of every tile by decreasing length (SELL-sigma
+// with sigma = tile); `idx16` stores columns as unsigned 16-bit offsets from
+// the smallest column of the tile and fails (returns false) when a tile's
+// columns span more than 65536 values.
+bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool sorted, bool idx16,
+               HostSell &S);
 HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes);
-constexpr int kSellTileRows = 256;     // 4 wavefronts x 64 rows
+// rows per block-sized tile of each layout
+inline int sell_tile_rows(int rpl) { return 256 * rpl; }
+inline int csr_tile_rows(int lanes) { return lanes > 0 ? 256 : 256; }
 
 // Runs fn(i) for i in [0, count) on `threads` host threads.
 void parallel_for(int64_t count, int threads, const std::function<void(int64_t)> &fn);

@@ -3,17 +3,21 @@
 // Layout conventions
 //   * every row-parallel kernel works on a list of row tiles; a tile lies
 //     inside one subdomain (hence one system), so per-tile partial sums are
-//     segmented by construction and the reductions are deterministic
-//     (fixed tile order, fixed wavefront/LDS reduction tree, no atomics);
-//   * block b is mapped to tile (b % 8) * per + b / 8 so that each of the 8
-//     XCDs (workgroups are dispatched round-robin over them) walks a
-//     contiguous range of tiles and its L2 sees the neighbouring rows;
-//   * sparse matrices are sliced ELLPACK with 64-row slices (one wavefront per
-//     slice, one row per lane, column-major inside the slice) or CSR with
-//     several lanes per row;
+//     segmented by construction and every reduction is deterministic (fixed
+//     tile order, fixed wavefront/LDS reduction tree, no atomics);
+//   * block b is mapped to tile (b % 8) * per + b / 8: workgroups are
+//     dispatched round-robin over the 8 XCDs, so each XCD walks a contiguous
+//     range of tiles and its L2 holds the neighbouring rows of its tiles;
+//   * sparse matrices come in two layouts, chosen per matrix by the setup
+//     autotuner: sliced ELLPACK (64-row slices, one row per lane, RPL rows per
+//     lane, slice-major storage so a wavefront streams consecutive addresses)
+//     or CSR with L lanes per row (for the long rows of Galerkin operators and
+//     of the restriction);
+//   * matrix entries are streamed with non-temporal loads so that the
+//     gathered vectors keep the caches;
 //   * Krylov scalars live on the device (SysState, one per system) and every
 //     in-loop kernel returns early once its system has stopped, so a fixed
-//     sequence of launches (or a captured graph) can run past convergence.
+//     launch sequence (or a captured graph) can run past convergence.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,7 +27,9 @@ namespace dfamg {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // 4 wavefronts
-constexpr int kReduceBlock = 1024;   // one block per system for reductions
+constexpr int kWideBlock = 1024;     // per-system reductions
+constexpr int kMaxNdv = 8;
+constexpr int kGemvRows = 4;         // rows of E^{-1} per GEMV block (one per wavefront)
 
 struct DevTile {
     int32_t row0, nrows, sub, slot;
@@ -32,11 +38,12 @@ struct DevTile {
 // Per-system Krylov state.
 struct SysState {
     double rho, alpha, beta, omega;  // CG / BiCGStab scalars
-    double pq;                       // (p, A p) or (r~, v)
+    double pq;                       // (p, P A p) of the last CG step
     double bb;                       // ||b||^2
     double rr;                       // ||r||^2
     double relres;                   // ||r|| / ||b|| of the last test
     double tt, ts;                   // BiCGStab (t,t), (t,s)
+    double rho_old, pad0;
     int32_t iter;
     int32_t done;                    // 0 running, 1 converged, 2 maxiter, 3 nan, 4 breakdown
     int32_t half;                    // BiCGStab: stopped on the half step
@@ -45,24 +52,33 @@ struct SysState {
 
 enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kNaN = 3, kBreakdown = 4 };
 
-template <class VT>
-struct SellView {
+// ---------------------------------------------------------------------------
+// matrix views
+// ---------------------------------------------------------------------------
+
+// SELL: I16 selects 16-bit column offsets from a per-tile base (cbase);
+// ridx (may be null) gives the tile-local row of each slot when the rows of
+// the tile are stored sorted by length.
+template <class VT, int RPL, bool I16>
+struct SellM {
     const DevTile *tiles;
     const int64_t *soff;
     const int32_t *sw;
     const int32_t *col;
+    const uint16_t *col16;
+    const int32_t *cbase;
+    const int16_t *ridx;
     const VT *val;
     int32_t ntiles;
 };
 
-template <class VT>
-struct CsrView {
+template <class VT, int L>
+struct CsrM {
     const DevTile *tiles;
     const int32_t *ptr;
     const int32_t *col;
     const VT *val;
     int32_t ntiles;
-    int32_t lanes;
 };
 
 __device__ __forceinline__ int tile_of_block(int ntiles) {
@@ -72,27 +88,100 @@ __device__ __forceinline__ int tile_of_block(int ntiles) {
 
 inline int grid_for_tiles(int ntiles) { return ((ntiles + 7) >> 3) * 8; }
 
+template <class T>
+__device__ __forceinline__ T stream_load(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+// sum_j val_j * x(col_j) over one SELL row (w entries, stride 64), loads
+// issued eight at a time
+template <class VT, class ACC, class CT, class XF>
+__device__ __forceinline__ ACC sell_dot(const CT *__restrict__ col, int cbase, const VT *__restrict__ val,
+                                        int64_t off, int w, XF x) {
+    ACC acc = 0;
+    for (int j0 = 0; j0 < w; j0 += 8) {
+        int c[8];
+        VT v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (j0 + u < w) {
+                c[u] = cbase + (int)stream_load(col + off + (int64_t)(j0 + u) * 64);
+                v[u] = stream_load(val + off + (int64_t)(j0 + u) * 64);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < w) acc += (ACC)v[u] * x(c[u]);
+    }
+    return acc;
+}
+
+// Calls f(row, sum_j a_rj x(c_j)) for every row of the tile owned by this
+// thread (exactly once per row over the block).
+template <class ACC, class VT, int RPL, bool I16, class XF, class F>
+__device__ __forceinline__ void for_rows(const SellM<VT, RPL, I16> &M, int tile, const DevTile &T, XF x, F f) {
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int cb = I16 ? M.cbase[tile] : 0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int sl = w * RPL + r;
+        const int lr = sl * 64 + lane;
+        if (lr < T.nrows) {
+            const int64_t si = (int64_t)tile * 4 * RPL + sl;
+            ACC acc;
+            if (I16) acc = sell_dot<VT, ACC>(M.col16, cb, M.val, M.soff[si] + lane, M.sw[si], x);
+            else acc = sell_dot<VT, ACC>(M.col, 0, M.val, M.soff[si] + lane, M.sw[si], x);
+            const int lrow = M.ridx ? (int)M.ridx[(int64_t)tile * 256 * RPL + lr] : lr;
+            f(T.row0 + lrow, acc);
+        }
+    }
+}
+
+// CSR: groups of L lanes share a row; the kBlock/L groups of the block walk
+// the tile's rows with stride kBlock/L (the trip count is uniform inside a
+// group, so the group's shuffles always see all of its lanes).
+template <class ACC, class VT, int L, class XF, class F>
+__device__ __forceinline__ void for_rows(const CsrM<VT, L> &M, int tile, const DevTile &T, XF x, F f) {
+    constexpr int G = kBlock / L;
+    const int t = threadIdx.x, g = t / L, lane = t % L;
+    for (int lr = g; lr < T.nrows; lr += G) {
+        const int row = T.row0 + lr;
+        const int k0 = M.ptr[row], k1 = M.ptr[row + 1];
+        ACC a0 = 0, a1 = 0;
+        int k = k0 + lane;
+        for (; k + L < k1; k += 2 * L) {
+            const int c0 = stream_load(M.col + k), c1 = stream_load(M.col + k + L);
+            const ACC v0 = (ACC)stream_load(M.val + k), v1 = (ACC)stream_load(M.val + k + L);
+            a0 += v0 * x(c0);
+            a1 += v1 * x(c1);
+        }
+        if (k < k1) a0 += (ACC)stream_load(M.val + k) * x(stream_load(M.col + k));
+        ACC acc = a0 + a1;
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+        if (lane == 0) f(row, acc);
+    }
+}
+
+// Rows of a tile for kernels without a matrix: thread t takes rows t, t+256, ..
+template <class F>
+__device__ __forceinline__ void for_tile_rows(const DevTile &T, F f) {
+#pragma unroll 4
+    for (int lr = threadIdx.x; lr < T.nrows; lr += kBlock) f(T.row0 + lr);
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
 }
 
-// Sum over a 256-thread block; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum256(double v, double *lds4) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) lds4[w] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
-    __syncthreads();
-    return r;
-}
-
-// Sum over a block of `nthreads` (multiple of 64, <= 1024); result valid in
-// every thread.
-__device__ __forceinline__ double block_sum_all(double v, double *lds, int nthreads) {
+// Sum over a block of `nthreads` (multiple of 64); result valid in every thread.
+__device__ __forceinline__ double block_sum(double v, double *lds, int nthreads) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) lds[w] = v;
@@ -104,220 +193,264 @@ __device__ __forceinline__ double block_sum_all(double v, double *lds, int nthre
     return r;
 }
 
-// Row-dot of one SELL row: sum_j a_j * x(c_j).
-template <class VT, class ACC, class XF>
-__device__ __forceinline__ ACC sell_row(const SellView<VT> &M, int tile, int t, XF x) {
-    const int k = t >> 6, lane = t & 63;
-    const int64_t off = M.soff[tile * 4 + k] + lane;
-    const int w = M.sw[tile * 4 + k];
-    ACC acc = 0;
-    int j = 0;
-    for (; j + 1 < w; j += 2) {
-        const int c0 = M.col[off + (int64_t)j * 64];
-        const int c1 = M.col[off + (int64_t)(j + 1) * 64];
-        const ACC a0 = (ACC)M.val[off + (int64_t)j * 64];
-        const ACC a1 = (ACC)M.val[off + (int64_t)(j + 1) * 64];
-        acc += a0 * x(c0);
-        acc += a1 * x(c1);
+// Deterministic sum of a[lo..hi) by one wavefront (all lanes get the result).
+__device__ __forceinline__ double wave_range_sum(const double *__restrict__ a, int lo, int hi) {
+    const int lane = threadIdx.x & 63;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = lo + lane;
+    for (; i + 192 < hi; i += 256) {
+        s0 += a[i];
+        s1 += a[i + 64];
+        s2 += a[i + 128];
+        s3 += a[i + 192];
     }
-    if (j < w) acc += (ACC)M.val[off + (int64_t)j * 64] * x(M.col[off + (int64_t)j * 64]);
-    return acc;
+    for (; i < hi; i += 64) s0 += a[i];
+    return wave_sum((s0 + s1) + (s2 + s3));
 }
 
 // ---------------------------------------------------------------------------
 // outer operator and deflation
 // ---------------------------------------------------------------------------
 
-// MODE 0: q = A p, partials (p,q), Z^T q           (CG operator product)
-// MODE 1: w = b - A y, partials (b,b), Z^T w       (initial / final residual)
-// MODE 2: w = b - A x, partial (w,w)               (true residual)
-// MODE 3: q = A p, partials Z^T q only             (BiCGStab operator product)
-template <int NDV, int MODE>
-__global__ void __launch_bounds__(kBlock) k_outer(SellView<double> A, const double *__restrict__ x,
-                                                  const double *__restrict__ b, double *__restrict__ out,
-                                                  const double *__restrict__ Z, double *__restrict__ part,
-                                                  int32_t nslots, const SysState *__restrict__ st,
-                                                  const int32_t *__restrict__ sub_sys) {
-    __shared__ double lds[4 * (NDV + 1)];
+// Epilogue partials per tile, slot-major: part[q * nslots + slot]
+//   MODE 0: q = A p;     partials (p,q), Z^T q              (CG operator product)
+//   MODE 1: w = b - A y; partials (b,b), Z^T w              (initial / final residual)
+//   MODE 2: w = b - A x; partial (w,w)                      (true residual)
+//   MODE 3: q = A p;     partials Z^T q, skip when stopped  (BiCGStab operator product)
+//   MODE 4: q = A p;     no partials, no stop check         (plain product)
+template <int MODE, int NDV, class MAT>
+__global__ void __launch_bounds__(kBlock) k_outer(MAT A, const double *__restrict__ x, const double *__restrict__ b,
+                                                  double *__restrict__ out, const double *__restrict__ Z, int ndv_rt,
+                                                  double *__restrict__ part, int32_t nslots,
+                                                  const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    __shared__ double lds[(kMaxNdv + 1) * 4];
+    const int ndv = ndv_rt;   // <= NDV, the unroll bound
     const int tile = tile_of_block(A.ntiles);
     if (tile >= A.ntiles) return;
     const DevTile T = A.tiles[tile];
     if ((MODE == 0 || MODE == 3) && st[sub_sys[T.sub]].done) return;
-    const int t = threadIdx.x;
-    const bool valid = t < T.nrows;
-    const int row = T.row0 + t;
-    double v = 0.0, d0 = 0.0;
+    double d0 = 0.0;
     double zq[NDV > 0 ? NDV : 1];
-    if (valid) {
-        const double ax = sell_row<double, double>(A, tile, t, [&](int c) { return x[c]; });
-        if (MODE == 0 || MODE == 3) {
+#pragma unroll
+    for (int k = 0; k < NDV; ++k) zq[k] = 0.0;
+    for_rows<double>(A, tile, T, [&](int c) { return x[c]; }, [&](int row, double ax) {
+        double v;
+        if (MODE == 0 || MODE == 3 || MODE == 4) {
             v = ax;
-            if (MODE == 0) d0 = x[row] * v;
+            if (MODE == 0) d0 += x[row] * v;
         } else {
             const double bi = b[row];
             v = bi - ax;
-            d0 = MODE == 1 ? bi * bi : v * v;
+            d0 += MODE == 1 ? bi * bi : v * v;
         }
         out[row] = v;
-    }
+        if (MODE == 0 || MODE == 1 || MODE == 3) {
 #pragma unroll
-    for (int k = 0; k < NDV; ++k) zq[k] = (valid && MODE != 2) ? Z[(int64_t)row * NDV + k] * v : 0.0;
-    // reduce d0 and zq over the block
-    const int w = t >> 6;
+            for (int k = 0; k < NDV; ++k)
+                if (k < ndv) zq[k] += Z[(int64_t)row * ndv + k] * v;
+        }
+    });
+    if (MODE == 4) return;
+    const int t = threadIdx.x, w = t >> 6;
+    const int nq = (MODE == 2) ? 1 : ndv + 1;
     d0 = wave_sum(d0);
+    if ((t & 63) == 0) lds[w] = d0;
 #pragma unroll
-    for (int k = 0; k < NDV; ++k) zq[k] = wave_sum(zq[k]);
-    if ((t & 63) == 0) {
-        lds[w] = d0;
-#pragma unroll
-        for (int k = 0; k < NDV; ++k) lds[4 * (k + 1) + w] = zq[k];
+    for (int k = 0; k < NDV; ++k) {
+        if (k < ndv && MODE != 2) {
+            const double s = wave_sum(zq[k]);
+            if ((t & 63) == 0) lds[4 * (k + 1) + w] = s;
+        }
     }
     __syncthreads();
-    if (t <= NDV && (MODE != 2 || t == 0)) {
+    if (t < nq && (MODE != 3 || t > 0)) {
         const double s = ((lds[4 * t] + lds[4 * t + 1]) + lds[4 * t + 2]) + lds[4 * t + 3];
         part[(int64_t)t * nslots + T.slot] = s;
     }
 }
 
-// One block per system: t1 = Z^T v per subdomain (sum of tile partials),
-// t2 = E^{-1} t1 (explicit FP64 inverse, stored transposed), then
-//   MODE 0 (CG):   alpha = rho / ((p,q) - t1.t2)        [(p, P A p) for symmetric A]
-//   MODE 1 (init): bb = sum of partial 0                 [(b,b)]
-//   MODE 2 (plain projection / recovery): t2 only
-//   MODE 3 (BiCGStab): t2 only, skipped when stopped
-template <int NDV, int MODE>
-__global__ void __launch_bounds__(kReduceBlock) k_project_reduce(
-    const double *__restrict__ part, int32_t nslots, const int32_t *__restrict__ sys_tile_off,
-    const int32_t *__restrict__ sub_tile_off, const int32_t *__restrict__ sys_sub_off,
-    const double *__restrict__ EinvT, const int64_t *__restrict__ sys_E_off,
-    double *__restrict__ t2, SysState *__restrict__ st) {
-    extern __shared__ double sh[];
-    double *t1 = sh;                 // m values
-    double *red = sh + 4096;         // 16 wave partials
-    const int sys = blockIdx.x;
-    SysState &S = st[sys];
-    if ((MODE == 0 || MODE == 3) && S.done) return;
-    const int s0 = sys_sub_off[sys], s1 = sys_sub_off[sys + 1];
-    const int m = (s1 - s0) * NDV;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int nw = kReduceBlock / 64;
-    // t1 per subdomain: one wavefront per (subdomain, vector)
-    for (int item = w; item < (s1 - s0) * NDV; item += nw) {
-        const int s = s0 + item / (NDV > 0 ? NDV : 1), k = item % (NDV > 0 ? NDV : 1);
-        double a = 0.0;
-        for (int tl = sub_tile_off[s] + lane; tl < sub_tile_off[s + 1]; tl += 64)
-            a += part[(int64_t)(k + 1) * nslots + tl];
-        a = wave_sum(a);
-        if (lane == 0) t1[item] = a;
-    }
-    double d0 = 0.0;
-    if (MODE == 0 || MODE == 1)
-        for (int tl = sys_tile_off[sys] + t; tl < sys_tile_off[sys + 1]; tl += kReduceBlock) d0 += part[tl];
-    __syncthreads();
-    const double D0 = block_sum_all(d0, red, kReduceBlock);
-    // t2 = E^{-1} t1
-    const double *Ei = EinvT + sys_E_off[sys];
-    double tt = 0.0;
-    for (int i = t; i < m; i += kReduceBlock) {
-        double a = 0.0;
-        for (int j = 0; j < m; ++j) a += Ei[(int64_t)j * m + i] * t1[j];
-        t2[(int64_t)s0 * NDV + i] = a;
-        tt += a * t1[i];
-    }
-    const double T12 = block_sum_all(tt, red, kReduceBlock);
-    if (t == 0) {
-        if (MODE == 0) {
-            S.pq = D0 - T12;
-            S.alpha = S.rho / S.pq;
-        } else if (MODE == 1) {
-            S.bb = D0;
+// One block per subdomain: sums of the subdomain's tile partials.
+//   t1[sub*ndv + k] = sum of partial k+1;  psub[sub] = sum of partial 0
+template <bool CHECK_DONE>
+__global__ void __launch_bounds__(kBlock) k_t1(const double *__restrict__ part, int32_t nslots,
+                                               const int32_t *__restrict__ sub_tile_off, int ndv,
+                                               double *__restrict__ t1, double *__restrict__ psub,
+                                               const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys,
+                                               int with_p0) {
+    const int sub = blockIdx.x;
+    if (CHECK_DONE && st[sub_sys[sub]].done) return;
+    const int w = threadIdx.x >> 6;
+    const int lo = sub_tile_off[sub], hi = sub_tile_off[sub + 1];
+    for (int q = w; q <= ndv; q += 4) {
+        if (q == 0 && !with_p0) continue;
+        const double s = wave_range_sum(part + (int64_t)q * nslots, lo, hi);
+        if ((threadIdx.x & 63) == 0) {
+            if (q == 0) psub[sub] = s;
+            else t1[(int64_t)sub * ndv + q - 1] = s;
         }
     }
 }
 
-// MODE 0 (CG): w = q - AZ t2; y += alpha p; r -= alpha w; partial (r,r)
+// t2 = E^{-1} t1: one wavefront per row of E^{-1} (row-major, lanes stride
+// the columns so every load is a contiguous 512-byte access), kGemvRows rows
+// per block; each block also leaves the partial sum_i t1_i t2_i of its rows.
+struct GemvJob {
+    int32_t sys, row0, m, coarse0;   // coarse0 = first coarse index of the system
+    int64_t e_off;
+};
+
+template <bool CHECK_DONE>
+__global__ void __launch_bounds__(kBlock) k_egemv(const GemvJob *__restrict__ jobs, const double *__restrict__ Einv,
+                                                  const double *__restrict__ t1, double *__restrict__ t2,
+                                                  double *__restrict__ tt_part, const SysState *__restrict__ st) {
+    __shared__ double red[kGemvRows];
+    const GemvJob J = jobs[blockIdx.x];
+    if (CHECK_DONE && st[J.sys].done) return;
+    const int m = J.m;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double *tl = t1 + J.coarse0;
+    double tt = 0.0;
+    const int i = J.row0 + w;
+    if (i < m) {
+        const double *row = Einv + J.e_off + (int64_t)i * m;
+        double a0 = 0.0, a1 = 0.0;
+        int j = lane;
+        for (; j + 64 < m; j += 128) {
+            a0 += row[j] * tl[j];
+            a1 += row[j + 64] * tl[j + 64];
+        }
+        if (j < m) a0 += row[j] * tl[j];
+        const double v = wave_sum(a0 + a1);
+        if (lane == 0) {
+            t2[J.coarse0 + i] = v;
+            tt = v * tl[i];
+        }
+    }
+    if (lane == 0) red[w] = tt;
+    __syncthreads();
+    if (threadIdx.x == 0) tt_part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Per-system offsets used by the fused scalar computations.
+struct SysRanges {
+    const int32_t *sub_off;   // subdomains of each system
+    const int32_t *job_off;   // GEMV jobs of each system
+};
+
+// (p, P A p) = (p, A p) - t1 . t2 for symmetric A, summed in a fixed order
+// by one wavefront.
+__device__ __forceinline__ double cg_curvature(const double *__restrict__ psub, const double *__restrict__ tt_part,
+                                               const SysRanges &R, int sys) {
+    const double pq = wave_range_sum(psub, R.sub_off[sys], R.sub_off[sys + 1]);
+    const double tt = wave_range_sum(tt_part, R.job_off[sys], R.job_off[sys + 1]);
+    return pq - tt;
+}
+
+// MODE 0 (CG): alpha = rho / (p,PAp); w = q - AZ t2; y += alpha p; r -= alpha w; partial (r,r)
 // MODE 1 (init): r = w - AZ t2; partial (r,r)
-// MODE 2 (project only): out = v - AZ t2
-template <int NDV, int MODE>
+// MODE 2 (projection only): out = v - AZ t2
+template <int MODE, int NDV>
 __global__ void __launch_bounds__(kBlock) k_update(
-    const DevTile *__restrict__ tiles, int32_t ntiles, const double *__restrict__ p,
-    const double *__restrict__ q, double *__restrict__ y, double *__restrict__ r,
-    const double *__restrict__ AZown, const int32_t *__restrict__ offp, const int32_t *__restrict__ offc,
-    const double *__restrict__ offv, const double *__restrict__ t2, double *__restrict__ part,
-    const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    const DevTile *__restrict__ tiles, int32_t ntiles, const double *__restrict__ p, const double *__restrict__ q,
+    double *__restrict__ y, double *__restrict__ r, const double *__restrict__ AZown, int ndv_rt,
+    const int32_t *__restrict__ offp, const int32_t *__restrict__ offc, const double *__restrict__ offv,
+    const double *__restrict__ t2, double *__restrict__ part, SysState *__restrict__ st,
+    const int32_t *__restrict__ sub_sys, const double *__restrict__ psub, const double *__restrict__ tt_part,
+    SysRanges R) {
     __shared__ double lds[4];
+    __shared__ double alpha_s;
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
     const DevTile T = tiles[tile];
-    const SysState &S = st[sub_sys[T.sub]];
+    const int sys = sub_sys[T.sub];
+    SysState &S = st[sys];
     if (MODE == 0 && S.done) return;
-    const int t = threadIdx.x;
+    if (MODE == 0) {
+        if (threadIdx.x < 64) {
+            const double pq = cg_curvature(psub, tt_part, R, sys);
+            if (threadIdx.x == 0) alpha_s = S.rho / pq;
+        }
+        __syncthreads();
+    }
+    const double a = MODE == 0 ? alpha_s : 0.0;
     double rr = 0.0;
-    if (t < T.nrows) {
-        const int row = T.row0 + t;
+    const int ndv = ndv_rt;   // <= NDV, the unroll bound
+    double t2s[NDV > 0 ? NDV : 1];
+#pragma unroll
+    for (int k = 0; k < NDV; ++k) t2s[k] = k < ndv ? t2[(int64_t)T.sub * ndv + k] : 0.0;
+    for_tile_rows(T, [&](int row) {
         double corr = 0.0;
 #pragma unroll
-        for (int k = 0; k < NDV; ++k) corr += AZown[(int64_t)row * NDV + k] * t2[(int64_t)T.sub * NDV + k];
-        if (NDV > 0)
+        for (int k = 0; k < NDV; ++k)
+            if (k < ndv) corr += AZown[(int64_t)row * ndv + k] * t2s[k];
+        if (ndv > 0)
             for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
         const double wv = q[row] - corr;
         if (MODE == 0) {
-            const double a = S.alpha;
             y[row] += a * p[row];
             const double rn = r[row] - a * wv;
             r[row] = rn;
-            rr = rn * rn;
+            rr += rn * rn;
         } else if (MODE == 1) {
             r[row] = wv;
-            rr = wv * wv;
+            rr += wv * wv;
         } else {
             r[row] = wv;
         }
-    }
+    });
     if (MODE == 2) return;
-    const double s = block_sum256(rr, lds);
-    if (t == 0) part[T.slot] = s;
+    const double s = block_sum(rr, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = s;
 }
 
 // x = y + Z t2 (solution recovery, x = y + Z lambda)
 template <int NDV>
 __global__ void __launch_bounds__(kBlock) k_expand(const DevTile *__restrict__ tiles, int32_t ntiles,
-                                                   const double *__restrict__ y, const double *__restrict__ Z,
+                                                   const double *__restrict__ y, const double *__restrict__ Z, int ndv_rt,
                                                    const double *__restrict__ t2, double *__restrict__ x) {
+    const int ndv = ndv_rt;   // <= NDV, the unroll bound
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
     const DevTile T = tiles[tile];
-    const int t = threadIdx.x;
-    if (t >= T.nrows) return;
-    const int row = T.row0 + t;
-    double v = y[row];
+    const double *t2s = t2 + (int64_t)T.sub * ndv;
+    for_tile_rows(T, [&](int row) {
+        double v = y[row];
 #pragma unroll
-    for (int k = 0; k < NDV; ++k) v += Z[(int64_t)row * NDV + k] * t2[(int64_t)T.sub * NDV + k];
-    x[row] = v;
+        for (int k = 0; k < NDV; ++k)
+            if (k < ndv) v += Z[(int64_t)row * ndv + k] * t2s[k];
+        x[row] = v;
+    });
 }
 
-// Per-system sum of tile partials into a SysState field and the stopping test.
-//   MODE 0 (CG loop): rr, iter++, history, stop test
-//   MODE 1 (initial residual): rr, iter = 0, history[0], stop test
-//   MODE 2 (true residual): relres = sqrt(sum / bb) written to out[sys]
+// Per-system sum of tile partials and the stopping test (1024 threads).
+//   MODE 0 (loop): rr, iter++, history, stop test; records alpha and (p,PAp)
+//   MODE 1 (initial residual): bb from the per-subdomain (b,b) sums, rr,
+//           iter = 0, history[0], stop test
+//   MODE 2 (true residual): out[sys] = sqrt(sum / bb)
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_residual_test(const double *__restrict__ part,
-                                                          const int32_t *__restrict__ sys_tile_off,
-                                                          SysState *__restrict__ st, double *__restrict__ hist,
-                                                          int32_t hist_stride, double rtol, int32_t maxiter,
-                                                          double *__restrict__ out) {
-    __shared__ double lds[4];
+__global__ void __launch_bounds__(kWideBlock) k_residual_test(const double *__restrict__ part,
+                                                              const int32_t *__restrict__ sys_tile_off,
+                                                              SysState *__restrict__ st, double *__restrict__ hist,
+                                                              int32_t hist_stride, double rtol, int32_t maxiter,
+                                                              double *__restrict__ out,
+                                                              const double *__restrict__ psub, SysRanges R) {
+    __shared__ double lds[16];
     const int sys = blockIdx.x;
     SysState &S = st[sys];
     if (MODE == 0 && S.done) return;
     double a = 0.0;
-    for (int tl = sys_tile_off[sys] + threadIdx.x; tl < sys_tile_off[sys + 1]; tl += kBlock) a += part[tl];
-    const double rr = block_sum256(a, lds);
+    for (int tl = sys_tile_off[sys] + threadIdx.x; tl < sys_tile_off[sys + 1]; tl += kWideBlock) a += part[tl];
+    const double rr = block_sum(a, lds, kWideBlock);
+    double bb = 0.0;
+    if (MODE == 1) {
+        if (threadIdx.x < 64) bb = wave_range_sum(psub, R.sub_off[sys], R.sub_off[sys + 1]);
+    }
     if (threadIdx.x != 0) return;
     if (MODE == 2) {
         out[sys] = S.bb > 0.0 ? sqrt(rr / S.bb) : 0.0;
         return;
     }
+    if (MODE == 1) S.bb = bb;
     S.rr = rr;
     const double h = S.bb > 0.0 ? sqrt(rr / S.bb) : 0.0;
     S.relres = h;
@@ -340,31 +473,29 @@ __global__ void __launch_bounds__(kBlock) k_residual_test(const double *__restri
 }
 
 // rho' = (r, s) from the tile partials of the preconditioner's last kernel
-// (and the per-subdomain partials of level-0 direct solves); CG beta.
+// (and the per-block partials of level-0 direct solves); CG beta.
 //   MODE 0: beta = rho'/rho, rho = rho'      MODE 1 (init): rho = rho', beta = 0
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_rho(const double *__restrict__ part, const int32_t *__restrict__ sys_tile_off,
-                                                const double *__restrict__ part_sub,
-                                                const int32_t *__restrict__ sys_sub_off, SysState *__restrict__ st) {
-    __shared__ double lds[4];
+__global__ void __launch_bounds__(kWideBlock) k_rho(const double *__restrict__ part,
+                                                    const int32_t *__restrict__ sys_tile_off,
+                                                    const double *__restrict__ part_job,
+                                                    const int32_t *__restrict__ sys_job_off, SysState *__restrict__ st) {
+    __shared__ double lds[16];
     const int sys = blockIdx.x;
     SysState &S = st[sys];
     if (S.done) return;
     double a = 0.0;
-    for (int tl = sys_tile_off[sys] + threadIdx.x; tl < sys_tile_off[sys + 1]; tl += kBlock) a += part[tl];
-    for (int s = sys_sub_off[sys] + threadIdx.x; s < sys_sub_off[sys + 1]; s += kBlock) a += part_sub[s];
-    const double rs = block_sum256(a, lds);
+    for (int tl = sys_tile_off[sys] + threadIdx.x; tl < sys_tile_off[sys + 1]; tl += kWideBlock) a += part[tl];
+    for (int j = sys_job_off[sys] + threadIdx.x; j < sys_job_off[sys + 1]; j += kWideBlock) a += part_job[j];
+    const double rs = block_sum(a, lds, kWideBlock);
     if (threadIdx.x == 0) {
-        if (MODE == 0) {
-            S.beta = rs / S.rho;
-        } else {
-            S.beta = 0.0;
-        }
+        S.beta = MODE == 0 ? rs / S.rho : 0.0;
         S.rho = rs;
     }
 }
 
-// p = s + beta p
+// p = s + beta p   (INIT: p = s)
+template <bool INIT>
 __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restrict__ tiles, int32_t ntiles,
                                                          const double *__restrict__ s, double *__restrict__ p,
                                                          const SysState *__restrict__ st,
@@ -373,11 +504,19 @@ __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restri
     if (tile >= ntiles) return;
     const DevTile T = tiles[tile];
     const SysState &S = st[sub_sys[T.sub]];
-    if (S.done) return;
-    const int t = threadIdx.x;
-    if (t >= T.nrows) return;
-    const int row = T.row0 + t;
-    p[row] = s[row] + S.beta * p[row];
+    if (!INIT && S.done) return;
+    const double beta = S.beta;
+    for_tile_rows(T, [&](int row) { p[row] = INIT ? s[row] : s[row] + beta * p[row]; });
+}
+
+// y = 0 for systems with b = 0
+__global__ void k_zero_null_rhs(const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ y,
+                                const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    if (st[sub_sys[T.sub]].bb != 0.0) return;
+    for_tile_rows(T, [&](int row) { y[row] = 0.0; });
 }
 
 // ---------------------------------------------------------------------------
@@ -386,109 +525,114 @@ __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restri
 // ---------------------------------------------------------------------------
 
 // res = f - A (m o f)        (pre-smoothing from a zero guess + residual)
-template <class VT, class FT>
-__global__ void __launch_bounds__(kBlock) k_pre_res(SellView<VT> A, const VT *__restrict__ m,
-                                                    const FT *__restrict__ f, VT *__restrict__ res,
-                                                    const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+template <class VT, class FT, class MAT>
+__global__ void __launch_bounds__(kBlock) k_pre_res(MAT A, const VT *__restrict__ m, const FT *__restrict__ f,
+                                                    VT *__restrict__ res, const SysState *__restrict__ st,
+                                                    const int32_t *__restrict__ sub_sys) {
     const int tile = tile_of_block(A.ntiles);
     if (tile >= A.ntiles) return;
     const DevTile T = A.tiles[tile];
     if (st[sub_sys[T.sub]].done) return;
-    const int t = threadIdx.x;
-    if (t >= T.nrows) return;
-    const int row = T.row0 + t;
-    const VT ax = sell_row<VT, VT>(A, tile, t, [&](int c) { return m[c] * (VT)f[c]; });
-    res[row] = (VT)f[row] - ax;
+    for_rows<VT>(A, tile, T, [&](int c) { return m[c] * (VT)f[c]; },
+                 [&](int row, VT ax) { res[row] = (VT)f[row] - ax; });
 }
 
-// y = M x (restriction)
-template <class VT>
-__global__ void __launch_bounds__(kBlock) k_spmv(SellView<VT> M, const VT *__restrict__ x, VT *__restrict__ y,
+// y = M x (restriction, or a plain product)
+template <class VT, class MAT>
+__global__ void __launch_bounds__(kBlock) k_spmv(MAT M, const VT *__restrict__ x, VT *__restrict__ y,
                                                  const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
     const int tile = tile_of_block(M.ntiles);
     if (tile >= M.ntiles) return;
     const DevTile T = M.tiles[tile];
-    if (st[sub_sys[T.sub]].done) return;
-    const int t = threadIdx.x;
-    if (t >= T.nrows) return;
-    y[T.row0 + t] = sell_row<VT, VT>(M, tile, t, [&](int c) { return x[c]; });
+    if (st && st[sub_sys[T.sub]].done) return;
+    for_rows<VT>(M, tile, T, [&](int c) { return x[c]; }, [&](int row, VT v) { y[row] = v; });
 }
 
 // z = m o f + P xc   (pre-smoothed iterate plus the coarse correction)
-template <class VT, class FT>
-__global__ void __launch_bounds__(kBlock) k_prolong(SellView<VT> P, const VT *__restrict__ m,
-                                                    const FT *__restrict__ f, const VT *__restrict__ xc,
-                                                    VT *__restrict__ z, const SysState *__restrict__ st,
-                                                    const int32_t *__restrict__ sub_sys) {
+template <class VT, class FT, class MAT>
+__global__ void __launch_bounds__(kBlock) k_prolong(MAT P, const VT *__restrict__ m, const FT *__restrict__ f,
+                                                    const VT *__restrict__ xc, VT *__restrict__ z,
+                                                    const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
     const int tile = tile_of_block(P.ntiles);
     if (tile >= P.ntiles) return;
     const DevTile T = P.tiles[tile];
     if (st[sub_sys[T.sub]].done) return;
-    const int t = threadIdx.x;
-    if (t >= T.nrows) return;
-    const int row = T.row0 + t;
-    z[row] = m[row] * (VT)f[row] + sell_row<VT, VT>(P, tile, t, [&](int c) { return xc[c]; });
+    for_rows<VT>(P, tile, T, [&](int c) { return xc[c]; },
+                 [&](int row, VT px) { z[row] = m[row] * (VT)f[row] + px; });
 }
 
 // x = z + m o (f - A z)   (post-smoothing); DOT: partial (f, x) per tile
-template <class VT, class FT, class OT, bool DOT>
-__global__ void __launch_bounds__(kBlock) k_post(SellView<VT> A, const VT *__restrict__ m,
-                                                 const FT *__restrict__ f, const VT *__restrict__ z,
-                                                 OT *__restrict__ x, double *__restrict__ part,
-                                                 const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+template <class VT, class FT, class OT, bool DOT, class MAT>
+__global__ void __launch_bounds__(kBlock) k_post(MAT A, const VT *__restrict__ m, const FT *__restrict__ f,
+                                                 const VT *__restrict__ z, OT *__restrict__ x,
+                                                 double *__restrict__ part, const SysState *__restrict__ st,
+                                                 const int32_t *__restrict__ sub_sys) {
     __shared__ double lds[4];
     const int tile = tile_of_block(A.ntiles);
     if (tile >= A.ntiles) return;
     const DevTile T = A.tiles[tile];
     if (st[sub_sys[T.sub]].done) return;
-    const int t = threadIdx.x;
     double d = 0.0;
-    if (t < T.nrows) {
-        const int row = T.row0 + t;
-        const VT az = sell_row<VT, VT>(A, tile, t, [&](int c) { return z[c]; });
+    for_rows<VT>(A, tile, T, [&](int c) { return z[c]; }, [&](int row, VT az) {
         const VT fr = (VT)f[row];
         const VT xv = z[row] + m[row] * (fr - az);
         x[row] = (OT)xv;
-        if (DOT) d = (double)f[row] * (double)(OT)xv;
-    }
+        if (DOT) d += (double)f[row] * (double)(OT)xv;
+    });
     if (!DOT) return;
-    const double s = block_sum256(d, lds);
-    if (t == 0) part[T.slot] = s;
+    const double s = block_sum(d, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = s;
 }
 
 // Dense direct solve on the coarsest level of each listed subdomain:
-// x = A_L^{-1} f with the inverse stored transposed.  DOT: partial (f, x)
-// per subdomain (level-0 coarsest subdomains only).
+// x = A_L^{-1} f with the inverse stored row-major, one wavefront per row
+// (lanes stride the columns), 4 rows per block.  DOT: partial (f, x) per
+// block, summed per subdomain by the (r, s) reduction.
 struct CoarseEntry {
     int32_t sub, n;
     int64_t off;      // first row in the level's packed vectors
-    int64_t inv_off;  // offset of the n x n transposed inverse
+    int64_t inv_off;  // offset of the n x n row-major inverse
+};
+
+struct CoarseJob {
+    int32_t entry;    // index into the CoarseEntry table
+    int32_t row0;     // first of the block's 4 rows
 };
 
 template <class VT, class FT, class OT, bool DOT>
-__global__ void __launch_bounds__(kBlock) k_coarse(const CoarseEntry *__restrict__ ent, const VT *__restrict__ invT,
-                                                   const FT *__restrict__ f, OT *__restrict__ x,
-                                                   double *__restrict__ part_sub, const SysState *__restrict__ st,
-                                                   const int32_t *__restrict__ sub_sys) {
-    extern __shared__ char smem[];
-    VT *fl = reinterpret_cast<VT *>(smem);
-    __shared__ double lds[4];
-    const CoarseEntry E = ent[blockIdx.x];
+__global__ void __launch_bounds__(kBlock) k_coarse(const CoarseJob *__restrict__ jobs, const CoarseEntry *__restrict__ ent,
+                                                   const VT *__restrict__ inv, const FT *__restrict__ f,
+                                                   OT *__restrict__ x, double *__restrict__ part_job,
+                                                   const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    __shared__ double red[4];
+    const CoarseJob J = jobs[blockIdx.x];
+    const CoarseEntry E = ent[J.entry];
     if (st[sub_sys[E.sub]].done) return;
-    const int n = E.n;
-    for (int i = threadIdx.x; i < n; i += kBlock) fl[i] = (VT)f[E.off + i];
-    __syncthreads();
-    const VT *Ai = invT + E.inv_off;
+    const int n = E.n, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = J.row0 + w;
     double d = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) {
-        VT a = 0;
-        for (int j = 0; j < n; ++j) a += Ai[(int64_t)j * n + i] * fl[j];
-        x[E.off + i] = (OT)a;
-        if (DOT) d += (double)f[E.off + i] * (double)(OT)a;
+    if (i < n) {
+        const VT *row = inv + E.inv_off + (int64_t)i * n;
+        const FT *fl = f + E.off;
+        VT a0 = 0, a1 = 0;
+        int j = lane;
+        for (; j + 64 < n; j += 128) {
+            a0 += row[j] * (VT)fl[j];
+            a1 += row[j + 64] * (VT)fl[j + 64];
+        }
+        if (j < n) a0 += row[j] * (VT)fl[j];
+        VT a = a0 + a1;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, kWave);
+        if (lane == 0) {
+            x[E.off + i] = (OT)a;
+            if (DOT) d = (double)fl[i] * (double)(OT)a;
+        }
     }
     if (!DOT) return;
-    const double s = block_sum256(d, lds);
-    if (threadIdx.x == 0) part_sub[E.sub] = s;
+    if (lane == 0) red[w] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) part_job[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // s = r (no preconditioner) with partial (r, s)
@@ -501,15 +645,30 @@ __global__ void __launch_bounds__(kBlock) k_identity(const DevTile *__restrict__
     if (tile >= ntiles) return;
     const DevTile T = tiles[tile];
     if (st[sub_sys[T.sub]].done) return;
-    const int t = threadIdx.x;
     double d = 0.0;
-    if (t < T.nrows) {
-        const double v = r[T.row0 + t];
-        s[T.row0 + t] = v;
-        d = v * v;
+    for_tile_rows(T, [&](int row) {
+        const double v = r[row];
+        s[row] = v;
+        d += v * v;
+    });
+    const double sum = block_sum(d, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = sum;
+}
+
+// Partials Z^T v per tile (for a stand-alone projection).
+__global__ void __launch_bounds__(kBlock) k_zt_partial(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                       const double *__restrict__ v, const double *__restrict__ Z,
+                                                       int ndv, double *__restrict__ part, int32_t nslots) {
+    __shared__ double lds[4];
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    for (int k = 0; k < ndv; ++k) {
+        double a = 0.0;
+        for_tile_rows(T, [&](int row) { a += Z[(int64_t)row * ndv + k] * v[row]; });
+        const double sum = block_sum(a, lds, kBlock);
+        if (threadIdx.x == 0) part[(int64_t)(k + 1) * nslots + T.slot] = sum;
     }
-    const double sum = block_sum256(d, lds);
-    if (t == 0) part[T.slot] = sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -526,11 +685,6 @@ __global__ void k_scatter(int64_t n, const int64_t *__restrict__ perm, const dou
                           double *__restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[perm[i]] = src[i];
-}
-
-__global__ void k_fill(int64_t n, double v, double *__restrict__ dst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -614,21 +768,23 @@ __global__ void __launch_bounds__(kBlock) k_gj_eliminate(const InvJob *__restric
         const int i = (int)(e / w2), j = (int)(e % w2);
         if (i == k || j < k) continue;
         const double f = ck[i];
-        if (f != 0.0) A[e] -= f * A[(int64_t)k * w2 + j];
+        if (f != 0.0) A[e] = (j == k) ? 0.0 : A[e] - f * A[(int64_t)k * w2 + j];
     }
 }
 
-// Copy the inverse (right half) out, transposed, in type VT.
+// Copy the inverse (right half) out in type VT, transposed or row-major.
 template <class VT>
 __global__ void k_gj_extract(const InvJob *__restrict__ jobs, const double *__restrict__ aug,
-                             const int64_t *__restrict__ out_off, VT *__restrict__ outT) {
+                             const int64_t *__restrict__ out_off, VT *__restrict__ out, int transposed) {
     const InvJob J = jobs[blockIdx.y];
     const int n = J.n;
     const double *A = aug + J.aug_off;
-    VT *O = outT + out_off[blockIdx.y];
+    VT *O = out + out_off[blockIdx.y];
     for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < (int64_t)n * n; e += (int64_t)gridDim.x * kBlock) {
         const int i = (int)(e / n), j = (int)(e % n);
-        O[(int64_t)j * n + i] = (VT)A[(int64_t)i * 2 * n + n + j];
+        const VT v = (VT)A[(int64_t)i * 2 * n + n + j];
+        if (transposed) O[(int64_t)j * n + i] = v;
+        else O[(int64_t)i * n + j] = v;
     }
 }
 

@@ -61,6 +61,37 @@ def test_small_poisson_fp64_parity():
     assert np.allclose(h[:k], ref["history"][:k], rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("fmt,tune", [("auto", 1), ("sell", 1), ("csr", 1), ("sell", 0), ("csr", 0)])
+def test_layouts_fp64_parity(fmt, tune):
+    P = tiny_problem(N=20, pieces=(2, 2, 2), deflation="linear", sigma=2.0, seed=20)
+    ref, out = _solve_pair(P, dict(coarse_enough=40),
+                           dict(coarse_enough=40, spmv_format=fmt, autotune=tune))
+    _assert_parity(ref, out)
+
+
+def test_autotuned_batched_matches_standalone_closely():
+    # independent autotuning may regroup partial sums: results agree to
+    # rounding, iteration counts exactly or within one
+    L = _lib()
+    from workloads import concat_problems
+    probs = [tiny_problem(N=n, pieces=pc, deflation="linear", sigma=1.0, seed=n)
+             for n, pc in [(16, (2, 2, 1)), (20, (2, 1, 2))]]
+    A, part, nsub, Z, b, x0, off = concat_problems(probs)
+    SB = L.BatchedSolver(A, part, nsub, Z, off, coarse_enough=30)
+    xb = _t(np.zeros(A.shape[0]))
+    outb = SB.solve(_t(b), xb)
+    xb = xb.cpu().numpy()
+    SB.close()
+    for i, p in enumerate(probs):
+        S = L.Solver(p.A, p.part, p.nsub, p.Z, coarse_enough=30)
+        x = _t(np.zeros(p.n))
+        o = S.solve(_t(p.b), x)
+        S.close()
+        assert abs(o["iters"] - outb["iters"][i]) <= 1
+        xs = x.cpu().numpy()
+        assert np.linalg.norm(xs - xb[off[i]:off[i + 1]]) <= 1e-9 * np.linalg.norm(xs)
+
+
 @pytest.mark.parametrize("case", [
     dict(N=10, pieces=(2, 1, 1), deflation="constant", sigma=1.0, ce=20),
     dict(N=13, pieces=(2, 2, 2), deflation="linear", sigma=2.0, ce=30),
@@ -131,7 +162,8 @@ def test_batched_equals_standalone(precision):
     probs = [tiny_problem(N=n, pieces=pc, deflation="linear", sigma=1.0, seed=n)
              for n, pc in [(9, (2, 1, 1)), (12, (2, 2, 1)), (7, (1, 1, 2)), (15, (3, 1, 1))]]
     A, part, nsub, Z, b, x0, off = concat_problems(probs)
-    kw = dict(precision=precision, coarse_enough=30)
+    # one layout family so that both handles sum every row in the same order
+    kw = dict(precision=precision, coarse_enough=30, autotune=0)
     SB = L.BatchedSolver(A, part, nsub, Z, off, **kw)
     xb = _t(np.zeros(A.shape[0]))
     outb = SB.solve(_t(b), xb)
@@ -178,7 +210,7 @@ def test_graph_and_direct_launch_agree():
     P = tiny_problem(N=12, pieces=(2, 2, 1), deflation="linear", sigma=1.0, seed=8)
     res = []
     for g in (0, 1, 16):
-        S = L.Solver(P.A, P.part, P.nsub, P.Z, coarse_enough=30, graph_iters=g)
+        S = L.Solver(P.A, P.part, P.nsub, P.Z, coarse_enough=30, graph_iters=g, autotune=0)
         x = _t(np.zeros(P.n))
         for _ in range(3):             # repeated replays give identical results
             x.zero_()
@@ -188,3 +220,13 @@ def test_graph_and_direct_launch_agree():
     for it, xv in res[1:]:
         assert it == res[0][0]
         assert np.array_equal(xv, res[0][1])
+
+
+@pytest.mark.parametrize("ndv", [2, 6])
+def test_other_deflation_counts(ndv):
+    # Z with ndv columns per subdomain: linear vectors plus bilinear ones
+    P = tiny_problem(N=12, pieces=(2, 2, 1), deflation="linear", sigma=1.0, seed=ndv)
+    Zx = np.column_stack([P.Z, P.Z[:, 1] * P.Z[:, 2], P.Z[:, 2] * P.Z[:, 3]])[:, :ndv]
+    P2 = P.__class__(P.name, P.A, P.part, P.nsub, np.ascontiguousarray(Zx), P.b, P.x0)
+    ref, out = _solve_pair(P2, dict(coarse_enough=30), dict(coarse_enough=30))
+    _assert_parity(ref, out)
