@@ -11,9 +11,15 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdfamg.so")
-SOURCES = ["host_plan.cpp", "device.hip"]
-HEADERS = ["host_plan.hpp", "kernels.hpp"]
-
+# (source, extra flags, object name)
+UNITS = [
+    ("host_plan.cpp", [], "host_plan.o"),
+    ("device.hip", [], "device.o"),
+    ("launch_outer.hip", [], "launch_outer.o"),
+    ("launch_vcycle.hip", ["-DDFAMG_VT_DOUBLE"], "launch_vcycle_f64.o"),
+    ("launch_vcycle.hip", [], "launch_vcycle_f32.o"),
+]
+HEADERS = ["host_plan.hpp", "kernels.hpp", "devmat.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -28,23 +34,32 @@ def _stale():
     if not os.path.exists(LIB):
         return True
     t = os.path.getmtime(LIB)
-    deps = [os.path.join(CSRC, f) for f in SOURCES + HEADERS]
+    deps = [os.path.join(CSRC, u[0]) for u in UNITS] + [os.path.join(CSRC, h) for h in HEADERS]
     deps.append(os.path.join(INCLUDE, "dfamg.h"))
     return any(os.path.getmtime(d) > t for d in deps)
 
 
-def build(force=True, verbose=True):
-    """Compile the library (always when force=True)."""
+def build(force=True, verbose=True, jobs=None):
+    """Compile the library (always when force=True); translation units are
+    compiled in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
     if not force and not _stale():
         return LIB
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
-        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", os.path.join(CSRC, src), "-o", obj]
+    jobs = jobs or min(len(UNITS), max(1, (os.cpu_count() or 4)))
+    cmds = []
+    for src, extra, objname in UNITS:
+        obj = os.path.join(CSRC, objname)
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append((cmd, obj))
+
+    def run(c):
         if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        objs.append(obj)
+            print(" ".join(c[0]), flush=True)
+        subprocess.check_call(c[0])
+        return c[1]
+
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(run, cmds))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     if verbose:

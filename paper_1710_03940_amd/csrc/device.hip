@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "dfamg.h"
+#include "devmat.hpp"
 #include "host_plan.hpp"
 #include "kernels.hpp"
 
@@ -78,55 +79,6 @@ struct DevArena {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// device matrices in one of the two layouts
-// ---------------------------------------------------------------------------
-
-template <class VT>
-struct DevMat {
-    int fmt = DFAMG_FORMAT_SELL;  // DFAMG_FORMAT_SELL or DFAMG_FORMAT_CSR
-    int par = 1;                  // rows per lane (SELL) or lanes per row (CSR)
-    DevTile *tiles = nullptr;
-    int32_t ntiles = 0;
-    bool idx16 = false, sorted = false;
-    int64_t *soff = nullptr;
-    int32_t *sw = nullptr;
-    int32_t *ptr = nullptr;
-    int32_t *col = nullptr;
-    uint16_t *col16 = nullptr;
-    int32_t *cbase = nullptr;
-    int16_t *ridx = nullptr;
-    VT *val = nullptr;
-    int64_t nnz = 0, stored = 0;
-    double tuned_us = 0.0;
-    std::vector<int32_t> sys_tile_off;  // host: tiles of each system
-    std::vector<int32_t> sub_tile_off;  // host: tiles of each subdomain
-};
-
-template <class VT, class Fn>
-void with_mat(const DevMat<VT> &M, Fn &&fn) {
-    if (M.fmt == DFAMG_FORMAT_SELL) {
-#define DFAMG_SELL_CASE(R)                                                                                  \
-    case R:                                                                                                 \
-        if (M.idx16) fn(SellM<VT, R, true>{M.tiles, M.soff, M.sw, M.col, M.col16, M.cbase, M.ridx, M.val, M.ntiles}); \
-        else fn(SellM<VT, R, false>{M.tiles, M.soff, M.sw, M.col, M.col16, M.cbase, M.ridx, M.val, M.ntiles});       \
-        return;
-        switch (M.par) {
-            DFAMG_SELL_CASE(1)
-            DFAMG_SELL_CASE(2)
-            DFAMG_SELL_CASE(4)
-        }
-#undef DFAMG_SELL_CASE
-    } else {
-        switch (M.par) {
-            case 4: fn(CsrM<VT, 4>{M.tiles, M.ptr, M.col, M.val, M.ntiles}); return;
-            case 8: fn(CsrM<VT, 8>{M.tiles, M.ptr, M.col, M.val, M.ntiles}); return;
-            case 16: fn(CsrM<VT, 16>{M.tiles, M.ptr, M.col, M.val, M.ntiles}); return;
-        }
-    }
-    throw Error{DFAMG_EINVAL, "unsupported matrix layout"};
-}
-
 // Compile-time bound on the deflation vectors per subdomain: kernels unroll
 // their Z / AZ loops to the bound (0, 1, 4 or 8) and skip the terms beyond
 // the run-time count.
@@ -164,13 +116,9 @@ void tile_offsets(const std::vector<Tile> &tiles, const std::vector<int32_t> &su
     for (int i = 0; i < nsub; ++i) sub_off[i + 1] += sub_off[i];
 }
 
-struct Layout {
-    int fmt, par;
-    bool sorted, idx16;
-};
-
-// Uploads matrix M in layout L; returns false (nothing uploaded) when the
-// layout cannot hold M (16-bit offsets that do not fit).
+// Uploads matrix M in layout L; returns false (nothing kept) when the layout
+// cannot hold M: 16-bit offsets that do not fit, or a staged column window
+// larger than the LDS budget.
 template <class VT>
 bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, const Layout &L,
                    hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys, int nsub, DevMat<VT> &D) {
@@ -180,15 +128,22 @@ bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &rang
     std::vector<Tile> tiles;
     if (L.fmt == DFAMG_FORMAT_SELL) {
         HostSell S;
-        if (!make_sell(M, ranges, L.par, L.sorted, L.idx16, S)) return false;
+        if (!make_sell(M, ranges, L.par, L.sorted, L.idx16 || L.stage, S)) return false;
+        if (L.stage) {
+            const int32_t mx = S.cspan.empty() ? 1 : *std::max_element(S.cspan.begin(), S.cspan.end());
+            if ((size_t)mx * sizeof(VT) > kMaxStageBytes) return false;
+            D.max_span = mx;
+        }
         D.sorted = L.sorted;
-        D.idx16 = L.idx16;
+        D.idx16 = L.idx16 || L.stage;
+        D.stage = L.stage;
         tiles = S.tiles;
         D.soff = ar.upload(S.slice_off, s);
         D.sw = ar.upload(S.slice_w, s);
-        if (L.idx16) {
+        if (D.idx16) {
             D.col16 = ar.upload(S.col16, s);
             D.cbase = ar.upload(S.cbase, s);
+            D.cspan = ar.upload(S.cspan, s);
         } else {
             D.col = ar.upload(S.col, s);
         }
@@ -200,9 +155,17 @@ bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &rang
         D.stored = (int64_t)S.val.size();
     } else {
         HostCsrv C = make_csrv(M, ranges, L.par);
+        if (L.stage) {
+            const int32_t mx = C.cspan.empty() ? 1 : *std::max_element(C.cspan.begin(), C.cspan.end());
+            if ((size_t)mx * sizeof(VT) > kMaxStageBytes) return false;
+            D.max_span = mx;
+            D.stage = true;
+        }
         tiles = C.tiles;
         D.ptr = ar.upload(C.ptr, s);
         D.col = ar.upload(C.col, s);
+        D.cbase = ar.upload(C.cbase, s);
+        D.cspan = ar.upload(C.cspan, s);
         std::vector<VT> v(C.val.size());
         for (size_t i = 0; i < v.size(); ++i) v[i] = (VT)C.val[i];
         D.val = ar.upload(v, s);
@@ -215,22 +178,42 @@ bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &rang
     return true;
 }
 
-// Plain y = M x timing (microseconds per launch).
+// What a matrix is used for, and so which kernel times its candidates.
+enum TuneKind { TUNE_OUTER, TUNE_SMOOTH, TUNE_RESTRICT, TUNE_PROLONG };
+
 template <class VT>
-double time_spmv(const DevMat<VT> &M, const VT *x, VT *y, hipStream_t s) {
+void launch_for_tuning(TuneKind kind, const DevMat<VT> &M, const VT *x, VT *y, hipStream_t s);
+
+template <>
+void launch_for_tuning<double>(TuneKind kind, const DevMat<double> &M, const double *x, double *y, hipStream_t s) {
+    switch (kind) {
+        case TUNE_OUTER: launch_outer_spmv_plain(M, x, y, s); break;
+        case TUNE_SMOOTH: launch_pre_res<double, double>(M, x, x, y, nullptr, nullptr, s); break;
+        case TUNE_RESTRICT: launch_spmv<double>(M, x, y, nullptr, nullptr, s); break;
+        case TUNE_PROLONG: launch_prolong<double, double>(M, x, y, x, y, nullptr, nullptr, s); break;
+    }
+}
+
+template <>
+void launch_for_tuning<float>(TuneKind kind, const DevMat<float> &M, const float *x, float *y, hipStream_t s) {
+    switch (kind) {
+        case TUNE_OUTER:
+        case TUNE_RESTRICT: launch_spmv<float>(M, x, y, nullptr, nullptr, s); break;
+        case TUNE_SMOOTH: launch_pre_res<float, float>(M, x, x, y, nullptr, nullptr, s); break;
+        case TUNE_PROLONG: launch_prolong<float, float>(M, x, y, x, y, nullptr, nullptr, s); break;
+    }
+}
+
+// Microseconds per launch of the kernel that will use M.
+template <class VT>
+double time_layout(TuneKind kind, const DevMat<VT> &M, const VT *x, VT *y, hipStream_t s) {
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
-    auto launch = [&]() {
-        with_mat(M, [&](auto m) {
-            hipLaunchKernelGGL((k_spmv<VT, decltype(m)>), dim3(grid_for_tiles(m.ntiles)), dim3(kBlock), 0, s, m, x,
-                               y, (const SysState *)nullptr, (const int32_t *)nullptr);
-        });
-    };
-    for (int i = 0; i < 2; ++i) launch();
+    for (int i = 0; i < 2; ++i) launch_for_tuning(kind, M, x, y, s);
     const int reps = 8;
     HIP_CHECK(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i) launch();
+    for (int i = 0; i < reps; ++i) launch_for_tuning(kind, M, x, y, s);
     HIP_CHECK(hipEventRecord(e1, s));
     HIP_CHECK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -241,30 +224,45 @@ double time_spmv(const DevMat<VT> &M, const VT *x, VT *y, hipStream_t s) {
 }
 
 // Layout of one matrix: the fastest candidate of the family `format` (SELL,
-// CSR, or both with DFAMG_FORMAT_AUTO), timed on the device with a plain
-// product.  SELL candidates: 1, 2 or 4 rows per lane (more rows per lane only
-// while the tiles still fill the chip), rows in natural or length-sorted
-// order, 16-bit column offsets whenever they fit; CSR: 4, 8 or 16 lanes.
+// CSR, or both with DFAMG_FORMAT_AUTO), timed on the device with the kernel
+// that will use the matrix.  SELL candidates: 1 or 2 rows per lane (2 only
+// while the tiles still fill the chip), natural or length-sorted rows,
+// 16-bit column offsets (32-bit when they do not fit), with or without an LDS
+// stage of the gathered vector; CSR: 4, 8 or 16 lanes per row, staged or
+// not, for rows of 10+ entries.  The global operator keeps unstaged SELL.
 template <class VT>
 DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, int format,
-                        bool autotune, hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys, int nsub) {
+                        bool autotune, TuneKind kind, hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys,
+                        int nsub) {
     int64_t rows = 0;
     for (auto &r : ranges) rows += r.nrows;
+    const double avg_len = rows ? (double)M.nnz() / (double)rows : 0.0;
     std::vector<Layout> cand;
+    const bool outer = kind == TUNE_OUTER;
     if (!autotune) {
-        cand.push_back(format == DFAMG_FORMAT_CSR ? Layout{DFAMG_FORMAT_CSR, 8, false, false}
-                                                  : Layout{DFAMG_FORMAT_SELL, 1, false, false});
-    } else if (format == DFAMG_FORMAT_SELL || format == DFAMG_FORMAT_AUTO)
-        for (int r : {1, 2, 4})
-            if (r == 1 || rows / (256 * r) >= 512)
-                for (bool sorted : {false, true}) cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true});
-    if (autotune && (format == DFAMG_FORMAT_CSR || format == DFAMG_FORMAT_AUTO))
-        for (int l : {4, 8, 16}) cand.push_back(Layout{DFAMG_FORMAT_CSR, l, false, false});
+        cand.push_back(format == DFAMG_FORMAT_CSR && !outer ? Layout{DFAMG_FORMAT_CSR, 8, false, false, false}
+                                                            : Layout{DFAMG_FORMAT_SELL, 1, false, false, false});
+    } else {
+        if (format == DFAMG_FORMAT_SELL || format == DFAMG_FORMAT_AUTO || outer) {
+            for (int r : outer ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2}) {
+                if (r > 1 && rows / (256 * r) < 512) continue;
+                for (bool sorted : {false, true}) {
+                    if (outer && sorted) continue;
+                    cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, false});
+                    if (!outer) cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, true});
+                }
+            }
+        }
+        if (!outer && (format == DFAMG_FORMAT_CSR || format == DFAMG_FORMAT_AUTO) &&
+            (avg_len >= 10.0 || format == DFAMG_FORMAT_CSR))
+            for (int l : {4, 8, 16})
+                for (bool stage : {false, true}) cand.push_back(Layout{DFAMG_FORMAT_CSR, l, false, false, stage});
+    }
     DevArena scratch;
-    VT *x = scratch.alloc<VT>(std::max<int64_t>(1, M.ncols));
-    VT *y = scratch.alloc<VT>(std::max<int64_t>(1, M.nrows));
-    {
-        std::vector<VT> ones(std::max<int64_t>(1, M.ncols), (VT)1);
+    VT *x = scratch.alloc<VT>(std::max<int64_t>(1, std::max(M.ncols, M.nrows)));
+    VT *y = scratch.alloc<VT>(std::max<int64_t>(1, std::max(M.ncols, M.nrows)));
+    if (cand.size() > 1) {
+        std::vector<VT> ones(std::max<int64_t>(1, std::max(M.ncols, M.nrows)), (VT)1);
         HIP_CHECK(hipMemcpyAsync(x, ones.data(), ones.size() * sizeof(VT), hipMemcpyHostToDevice, s));
         HIP_CHECK(hipStreamSynchronize(s));
     }
@@ -275,12 +273,13 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
         auto A = std::make_unique<DevArena>();
         DevMat<VT> D;
         if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D)) {
-            if (c.fmt != DFAMG_FORMAT_SELL || !c.idx16) continue;
-            c.idx16 = false;   // columns too far apart for 16-bit offsets
+            // 16-bit offsets that do not fit: fall back to 32-bit columns once
+            if (c.fmt != DFAMG_FORMAT_SELL || c.stage || !c.idx16) continue;
+            c.idx16 = false;
             A = std::make_unique<DevArena>();
             if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D)) continue;
         }
-        const double t = cand.size() > 1 ? time_spmv(D, x, y, s) : 0.0;
+        const double t = cand.size() > 1 ? time_layout(kind, D, x, y, s) : 0.0;
         if (t < best) {
             best = t;
             bestM = D;
@@ -482,14 +481,16 @@ struct Hierarchy_dev : PrecondBase {
                 D.res = ar.alloc<VT>(PL.nrows);
                 D.z = ar.alloc<VT>(PL.nrows);
                 const auto rr = ranges_of(PL, PL.active_subs);
-                D.A = upload_tuned<VT>(ar, PL.A, rr, format, autotune, s, plan.sub_sys, plan.nsys, plan.nsub);
-                D.P = upload_tuned<VT>(ar, PL.P, rr, format, autotune, s, plan.sub_sys, plan.nsys, plan.nsub);
+                D.A = upload_tuned<VT>(ar, PL.A, rr, format, autotune, TUNE_SMOOTH, s, plan.sub_sys, plan.nsys,
+                                       plan.nsub);
+                D.P = upload_tuned<VT>(ar, PL.P, rr, format, autotune, TUNE_PROLONG, s, plan.sub_sys, plan.nsys,
+                                       plan.nsub);
                 const PackedLevel &PN = plan.levels[l + 1];
                 std::vector<int32_t> next_subs;
                 for (int sub = 0; sub < plan.nsub; ++sub)
                     if (PN.sub_off[sub] >= 0) next_subs.push_back(sub);
-                D.R = upload_tuned<VT>(ar, PL.R, ranges_of(PN, next_subs), format, autotune, s, plan.sub_sys,
-                                       plan.nsys, plan.nsub);
+                D.R = upload_tuned<VT>(ar, PL.R, ranges_of(PN, next_subs), format, autotune, TUNE_RESTRICT, s,
+                                       plan.sub_sys, plan.nsys, plan.nsub);
                 if (l < 20) {
                     fmt[l] = D.A.fmt;
                     par[l] = D.A.par;
@@ -585,24 +586,15 @@ struct Hierarchy_dev : PrecondBase {
         for (int l = 0; l + 1 < L; ++l) {
             Lvl &D = lv[l];
             if (!D.active) continue;
-            if (l == 0) mark(KID_PRE0, 0);
-            with_mat(D.A, [&](auto m) {
-                const dim3 g(grid_for_tiles(m.ntiles));
-                if (l == 0)
-                    hipLaunchKernelGGL((k_pre_res<VT, double, decltype(m)>), g, b, 0, st, m, D.m, r, D.res, states,
-                                       sub_sys);
-                else
-                    hipLaunchKernelGGL((k_pre_res<VT, VT, decltype(m)>), g, b, 0, st, m, D.m, D.f, D.res, states,
-                                       sub_sys);
-            });
             if (l == 0) {
+                mark(KID_PRE0, 0);
+                launch_pre_res<VT, double>(D.A, D.m, r, D.res, states, sub_sys, st);
                 mark(KID_PRE0, 1);
                 mark(KID_RESTRICT0, 0);
+            } else {
+                launch_pre_res<VT, VT>(D.A, D.m, D.f, D.res, states, sub_sys, st);
             }
-            with_mat(D.R, [&](auto m) {
-                hipLaunchKernelGGL((k_spmv<VT, decltype(m)>), dim3(grid_for_tiles(m.ntiles)), b, 0, st, m, D.res,
-                                   lv[l + 1].f, states, sub_sys);
-            });
+            launch_spmv<VT>(D.R, D.res, lv[l + 1].f, states, sub_sys, st);
             if (l == 0) {
                 mark(KID_RESTRICT0, 1);
                 mark(KID_COARSER, 0);
@@ -626,30 +618,15 @@ struct Hierarchy_dev : PrecondBase {
             if (l == 0) {
                 mark(KID_COARSER, 1);
                 mark(KID_PROLONG0, 0);
-            }
-            with_mat(D.P, [&](auto m) {
-                const dim3 g(grid_for_tiles(m.ntiles));
-                if (l == 0)
-                    hipLaunchKernelGGL((k_prolong<VT, double, decltype(m)>), g, b, 0, st, m, D.m, r, lv[1].x, D.z,
-                                       states, sub_sys);
-                else
-                    hipLaunchKernelGGL((k_prolong<VT, VT, decltype(m)>), g, b, 0, st, m, D.m, D.f, lv[l + 1].x, D.z,
-                                       states, sub_sys);
-            });
-            if (l == 0) {
+                launch_prolong<VT, double>(D.P, D.m, r, lv[1].x, D.z, states, sub_sys, st);
                 mark(KID_PROLONG0, 1);
                 mark(KID_POST0, 0);
+                launch_post<VT, double, double, true>(D.A, D.m, r, D.z, s, part, states, sub_sys, st);
+                mark(KID_POST0, 1);
+            } else {
+                launch_prolong<VT, VT>(D.P, D.m, D.f, lv[l + 1].x, D.z, states, sub_sys, st);
+                launch_post<VT, VT, VT, false>(D.A, D.m, D.f, D.z, D.x, part, states, sub_sys, st);
             }
-            with_mat(D.A, [&](auto m) {
-                const dim3 g(grid_for_tiles(m.ntiles));
-                if (l == 0)
-                    hipLaunchKernelGGL((k_post<VT, double, double, true, decltype(m)>), g, b, 0, st, m, D.m, r, D.z, s,
-                                       part, states, sub_sys);
-                else
-                    hipLaunchKernelGGL((k_post<VT, VT, VT, false, decltype(m)>), g, b, 0, st, m, D.m, D.f, D.z, D.x,
-                                       part, states, sub_sys);
-            });
-            if (l == 0) mark(KID_POST0, 1);
         }
     }
 };
@@ -742,7 +719,8 @@ void Handle::setup_device() {
     for (int sub = 0; sub < nsub; ++sub)
         rr.push_back(RowRange{P.sub_row_off[sub], (int32_t)(P.sub_row_off[sub + 1] - P.sub_row_off[sub]), sub, 0});
     // outer matrix over all subdomains
-    A = upload_tuned<double>(ar, P.A, rr, prm.spmv_format, prm.autotune != 0, sm, P.sub_sys, nsys, nsub);
+    A = upload_tuned<double>(ar, P.A, rr, prm.spmv_format, prm.autotune != 0, TUNE_OUTER, sm, P.sub_sys, nsys,
+                             nsub);
     d_sto_A = ar.upload(A.sys_tile_off, sm);
     d_subto_A = ar.upload(A.sub_tile_off, sm);
     // row tiles of 256 rows: one row per thread in the vector kernels
@@ -902,21 +880,7 @@ bool Handle::probe_graph_events() {
 // Outer SpMV launch with the epilogue of `mode` (see k_outer).
 void Handle::outer(int mode, hipStream_t st, const double *xin, const double *bin, double *out, bool profiled) {
     if (profiled) prof.mark(KID_SPMV, 0, st);
-    with_mat(A, [&](auto m) {
-        with_ndv(ndv(), [&](auto nd_c) {
-            constexpr int ND = decltype(nd_c)::value;
-            const dim3 g(grid_for_tiles(m.ntiles)), bl(kBlock);
-            using MT = decltype(m);
-            const int nd = ndv();
-            switch (mode) {
-                case 0: hipLaunchKernelGGL((k_outer<0, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
-                case 1: hipLaunchKernelGGL((k_outer<1, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
-                case 2: hipLaunchKernelGGL((k_outer<2, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
-                case 3: hipLaunchKernelGGL((k_outer<3, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
-                default: hipLaunchKernelGGL((k_outer<4, ND, MT>), g, bl, 0, st, m, xin, bin, out, Z, nd, part_A, A.ntiles, states, d_sub_sys); break;
-            }
-        });
-    });
+    launch_outer(mode, ndv(), A, xin, bin, out, Z, part_A, states, d_sub_sys, st);
     if (profiled) prof.mark(KID_SPMV, 1, st);
 }
 

@@ -533,6 +533,7 @@ bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool 
     if (idx16) {
         S.col16.assign(off, 0);
         S.cbase.assign(S.tiles.size(), 0);
+        S.cspan.assign(S.tiles.size(), 1);
         for (size_t ti = 0; ti < S.tiles.size(); ++ti) {
             const Tile &t = S.tiles[ti];
             int64_t lo = INT64_MAX, hi = -1;
@@ -545,6 +546,7 @@ bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool 
             // padding of empty rows uses the base itself
             if (hi - lo > 65535) return false;
             S.cbase[ti] = (int32_t)lo;
+            S.cspan[ti] = (int32_t)(hi - lo + 1);
         }
     } else {
         S.col.assign(off, 0);
@@ -585,6 +587,21 @@ HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes)
         for (int32_t r0 = 0; r0 < rg.nrows; r0 += rows_per_tile)
             C.tiles.push_back(Tile{(int32_t)(rg.row0 + r0), std::min(rows_per_tile, rg.nrows - r0),
                                    rg.sub, slot++});
+    }
+    C.cbase.assign(C.tiles.size(), 0);
+    C.cspan.assign(C.tiles.size(), 1);
+    for (size_t ti = 0; ti < C.tiles.size(); ++ti) {
+        const Tile &t = C.tiles[ti];
+        int64_t lo = INT64_MAX, hi = -1;
+        for (int64_t r = t.row0; r < t.row0 + t.nrows; ++r)
+            for (int64_t k = M.ptr[r]; k < M.ptr[r + 1]; ++k) {
+                lo = std::min<int64_t>(lo, M.col[k]);
+                hi = std::max<int64_t>(hi, M.col[k]);
+            }
+        if (hi >= 0) {
+            C.cbase[ti] = (int32_t)lo;
+            C.cspan[ti] = (int32_t)(hi - lo + 1);
+        }
     }
     C.ptr.resize(M.nrows + 1);
     for (int64_t i = 0; i <= M.nrows; ++i) C.ptr[i] = (int32_t)M.ptr[i];

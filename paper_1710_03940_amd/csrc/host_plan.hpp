@@ -78,6 +78,7 @@ struct HostSell {
     std::vector<int16_t> ridx;       // sorted: tile-local row of each slot
     std::vector<uint16_t> col16;     // idx16: col - cbase[tile]
     std::vector<int32_t> cbase;      // idx16: smallest column of each tile
+    std::vector<int32_t> cspan;      // idx16: largest - smallest column + 1
     std::vector<Tile> tiles;         // tile t covers slices 4*rpl*t ..
     std::vector<int64_t> slice_off;  // 4*rpl per tile
     std::vector<int32_t> slice_w;
@@ -91,6 +92,7 @@ struct HostSell {
 // 256 rows, its 256/lanes lane groups striding over them.
 struct HostCsrv {
     std::vector<Tile> tiles;
+    std::vector<int32_t> cbase, cspan;   // column window of every tile
     std::vector<int32_t> ptr;        // packed CSR over all rows of the level
     std::vector<int32_t> col;
     std::vector<double> val;

@@ -58,8 +58,11 @@ enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kNaN = 3, kBreakdown = 4 };
 
 // SELL: I16 selects 16-bit column offsets from a per-tile base (cbase);
 // ridx (may be null) gives the tile-local row of each slot when the rows of
-// the tile are stored sorted by length.
-template <class VT, int RPL, bool I16>
+// the tile are stored sorted by length.  STAGE (requires I16) first copies
+// the tile's column window [cbase, cbase + cspan) of the gathered vector into
+// LDS, so the irregular gathers of Galerkin operators and transfer matrices
+// hit LDS instead of fetching a cache line per lane from L2.
+template <class VT, int RPL, bool I16, bool STAGE>
 struct SellM {
     const DevTile *tiles;
     const int64_t *soff;
@@ -67,16 +70,20 @@ struct SellM {
     const int32_t *col;
     const uint16_t *col16;
     const int32_t *cbase;
+    const int32_t *cspan;
     const int16_t *ridx;
     const VT *val;
     int32_t ntiles;
 };
 
-template <class VT, int L>
+// CSR with L lanes per row; STAGE as above (cbase/cspan per tile).
+template <class VT, int L, bool STAGE>
 struct CsrM {
     const DevTile *tiles;
     const int32_t *ptr;
     const int32_t *col;
+    const int32_t *cbase;
+    const int32_t *cspan;
     const VT *val;
     int32_t ntiles;
 };
@@ -93,10 +100,22 @@ __device__ __forceinline__ T stream_load(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
-// sum_j val_j * x(col_j) over one SELL row (w entries, stride 64), loads
-// issued eight at a time
+// Dynamic LDS of the staged layouts.
+extern __shared__ double dfamg_stage_lds[];
+
+// Copies src(cb + k), k < span, into LDS; every thread of the block calls it.
+template <class VT, class SRC>
+__device__ __forceinline__ VT *stage_window(int cb, int span, SRC src) {
+    VT *lds = reinterpret_cast<VT *>(dfamg_stage_lds);
+    for (int k = threadIdx.x; k < span; k += kBlock) lds[k] = (VT)src(cb + k);
+    __syncthreads();
+    return lds;
+}
+
+// sum_j val_j * x(cadd + col_j) over one SELL row (w entries, stride 64),
+// loads issued eight at a time
 template <class VT, class ACC, class CT, class XF>
-__device__ __forceinline__ ACC sell_dot(const CT *__restrict__ col, int cbase, const VT *__restrict__ val,
+__device__ __forceinline__ ACC sell_dot(const CT *__restrict__ col, int cadd, const VT *__restrict__ val,
                                         int64_t off, int w, XF x) {
     ACC acc = 0;
     for (int j0 = 0; j0 < w; j0 += 8) {
@@ -105,7 +124,7 @@ __device__ __forceinline__ ACC sell_dot(const CT *__restrict__ col, int cbase, c
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (j0 + u < w) {
-                c[u] = cbase + (int)stream_load(col + off + (int64_t)(j0 + u) * 64);
+                c[u] = cadd + (int)stream_load(col + off + (int64_t)(j0 + u) * 64);
                 v[u] = stream_load(val + off + (int64_t)(j0 + u) * 64);
             }
         }
@@ -116,12 +135,17 @@ __device__ __forceinline__ ACC sell_dot(const CT *__restrict__ col, int cbase, c
     return acc;
 }
 
-// Calls f(row, sum_j a_rj x(c_j)) for every row of the tile owned by this
-// thread (exactly once per row over the block).
-template <class ACC, class VT, int RPL, bool I16, class XF, class F>
-__device__ __forceinline__ void for_rows(const SellM<VT, RPL, I16> &M, int tile, const DevTile &T, XF x, F f) {
+// Calls f(row, sum_j a_rj src(c_j)) for every row of the tile owned by this
+// thread (exactly once per row over the block).  Every thread of the block
+// must call it (the staged layouts synchronise the block).
+template <class ACC, class VT, int RPL, bool I16, bool STAGE, class SRC, class F>
+__device__ __forceinline__ void for_rows(const SellM<VT, RPL, I16, STAGE> &M, int tile, const DevTile &T, SRC src,
+                                         F f) {
+    static_assert(!STAGE || I16, "staged SELL needs 16-bit column offsets");
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int cb = I16 ? M.cbase[tile] : 0;
+    const VT *lds = nullptr;
+    if (STAGE) lds = stage_window<VT>(cb, M.cspan[tile], src);
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int sl = w * RPL + r;
@@ -129,8 +153,9 @@ __device__ __forceinline__ void for_rows(const SellM<VT, RPL, I16> &M, int tile,
         if (lr < T.nrows) {
             const int64_t si = (int64_t)tile * 4 * RPL + sl;
             ACC acc;
-            if (I16) acc = sell_dot<VT, ACC>(M.col16, cb, M.val, M.soff[si] + lane, M.sw[si], x);
-            else acc = sell_dot<VT, ACC>(M.col, 0, M.val, M.soff[si] + lane, M.sw[si], x);
+            if (STAGE) acc = sell_dot<VT, ACC>(M.col16, 0, M.val, M.soff[si] + lane, M.sw[si], [&](int c) { return lds[c]; });
+            else if (I16) acc = sell_dot<VT, ACC>(M.col16, cb, M.val, M.soff[si] + lane, M.sw[si], src);
+            else acc = sell_dot<VT, ACC>(M.col, 0, M.val, M.soff[si] + lane, M.sw[si], src);
             const int lrow = M.ridx ? (int)M.ridx[(int64_t)tile * 256 * RPL + lr] : lr;
             f(T.row0 + lrow, acc);
         }
@@ -140,10 +165,20 @@ __device__ __forceinline__ void for_rows(const SellM<VT, RPL, I16> &M, int tile,
 // CSR: groups of L lanes share a row; the kBlock/L groups of the block walk
 // the tile's rows with stride kBlock/L (the trip count is uniform inside a
 // group, so the group's shuffles always see all of its lanes).
-template <class ACC, class VT, int L, class XF, class F>
-__device__ __forceinline__ void for_rows(const CsrM<VT, L> &M, int tile, const DevTile &T, XF x, F f) {
+template <class ACC, class VT, int L, bool STAGE, class SRC, class F>
+__device__ __forceinline__ void for_rows(const CsrM<VT, L, STAGE> &M, int tile, const DevTile &T, SRC src, F f) {
     constexpr int G = kBlock / L;
     const int t = threadIdx.x, g = t / L, lane = t % L;
+    int cb = 0;
+    const VT *lds = nullptr;
+    if (STAGE) {
+        cb = M.cbase[tile];
+        lds = stage_window<VT>(cb, M.cspan[tile], src);
+    }
+    auto x = [&](int c) -> VT {
+        if (STAGE) return lds[c - cb];
+        return (VT)src(c);
+    };
     for (int lr = g; lr < T.nrows; lr += G) {
         const int row = T.row0 + lr;
         const int k0 = M.ptr[row], k1 = M.ptr[row + 1];
@@ -510,7 +545,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restri
 }
 
 // y = 0 for systems with b = 0
-__global__ void k_zero_null_rhs(const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ y,
+static __global__ void k_zero_null_rhs(const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ y,
                                 const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
@@ -532,7 +567,7 @@ __global__ void __launch_bounds__(kBlock) k_pre_res(MAT A, const VT *__restrict_
     const int tile = tile_of_block(A.ntiles);
     if (tile >= A.ntiles) return;
     const DevTile T = A.tiles[tile];
-    if (st[sub_sys[T.sub]].done) return;
+    if (st && st[sub_sys[T.sub]].done) return;
     for_rows<VT>(A, tile, T, [&](int c) { return m[c] * (VT)f[c]; },
                  [&](int row, VT ax) { res[row] = (VT)f[row] - ax; });
 }
@@ -556,7 +591,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong(MAT P, const VT *__restrict_
     const int tile = tile_of_block(P.ntiles);
     if (tile >= P.ntiles) return;
     const DevTile T = P.tiles[tile];
-    if (st[sub_sys[T.sub]].done) return;
+    if (st && st[sub_sys[T.sub]].done) return;
     for_rows<VT>(P, tile, T, [&](int c) { return xc[c]; },
                  [&](int row, VT px) { z[row] = m[row] * (VT)f[row] + px; });
 }
@@ -571,7 +606,7 @@ __global__ void __launch_bounds__(kBlock) k_post(MAT A, const VT *__restrict__ m
     const int tile = tile_of_block(A.ntiles);
     if (tile >= A.ntiles) return;
     const DevTile T = A.tiles[tile];
-    if (st[sub_sys[T.sub]].done) return;
+    if (st && st[sub_sys[T.sub]].done) return;
     double d = 0.0;
     for_rows<VT>(A, tile, T, [&](int c) { return z[c]; }, [&](int row, VT az) {
         const VT fr = (VT)f[row];
@@ -636,7 +671,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse(const CoarseJob *__restrict__
 }
 
 // s = r (no preconditioner) with partial (r, s)
-__global__ void __launch_bounds__(kBlock) k_identity(const DevTile *__restrict__ tiles, int32_t ntiles,
+static __global__ void __launch_bounds__(kBlock) k_identity(const DevTile *__restrict__ tiles, int32_t ntiles,
                                                      const double *__restrict__ r, double *__restrict__ s,
                                                      double *__restrict__ part, const SysState *__restrict__ st,
                                                      const int32_t *__restrict__ sub_sys) {
@@ -656,7 +691,7 @@ __global__ void __launch_bounds__(kBlock) k_identity(const DevTile *__restrict__
 }
 
 // Partials Z^T v per tile (for a stand-alone projection).
-__global__ void __launch_bounds__(kBlock) k_zt_partial(const DevTile *__restrict__ tiles, int32_t ntiles,
+static __global__ void __launch_bounds__(kBlock) k_zt_partial(const DevTile *__restrict__ tiles, int32_t ntiles,
                                                        const double *__restrict__ v, const double *__restrict__ Z,
                                                        int ndv, double *__restrict__ part, int32_t nslots) {
     __shared__ double lds[4];
@@ -675,13 +710,13 @@ __global__ void __launch_bounds__(kBlock) k_zt_partial(const DevTile *__restrict
 // permutation
 // ---------------------------------------------------------------------------
 
-__global__ void k_gather(int64_t n, const int64_t *__restrict__ perm, const double *__restrict__ src,
+static __global__ void k_gather(int64_t n, const int64_t *__restrict__ perm, const double *__restrict__ src,
                          double *__restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[perm[i]];
 }
 
-__global__ void k_scatter(int64_t n, const int64_t *__restrict__ perm, const double *__restrict__ src,
+static __global__ void k_scatter(int64_t n, const int64_t *__restrict__ perm, const double *__restrict__ src,
                           double *__restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[perm[i]] = src[i];
@@ -701,7 +736,7 @@ struct InvJob {
 
 // Step k, part 1 (one block per matrix): pivot search, row swap, pivot row
 // scaling and a copy of column k for the elimination.
-__global__ void __launch_bounds__(kBlock) k_gj_pivot(InvJob *__restrict__ jobs, double *__restrict__ aug,
+static __global__ void __launch_bounds__(kBlock) k_gj_pivot(InvJob *__restrict__ jobs, double *__restrict__ aug,
                                                      double *__restrict__ colk, const int64_t *__restrict__ col_off,
                                                      int k) {
     __shared__ double bv[kBlock];
@@ -754,7 +789,7 @@ __global__ void __launch_bounds__(kBlock) k_gj_pivot(InvJob *__restrict__ jobs, 
 }
 
 // Step k, part 2: row_i -= a_ik row_k for every i != k; grid (row blocks, matrices)
-__global__ void __launch_bounds__(kBlock) k_gj_eliminate(const InvJob *__restrict__ jobs, double *__restrict__ aug,
+static __global__ void __launch_bounds__(kBlock) k_gj_eliminate(const InvJob *__restrict__ jobs, double *__restrict__ aug,
                                                          const double *__restrict__ colk,
                                                          const int64_t *__restrict__ col_off, int k) {
     const InvJob J = jobs[blockIdx.y];

@@ -1,0 +1,76 @@
+// Launchers of the V-cycle matrix kernels for one value type, chosen at
+// compile time with -DDFAMG_VT_DOUBLE (FP64 hierarchy) or without it (FP32
+// hierarchy of the mixed-precision path).
+#include "devmat.hpp"
+
+namespace dfamg {
+
+template <class VT, class FT>
+void launch_pre_res(const DevMat<VT> &A, const VT *m, const FT *f, VT *res, const SysState *st,
+                    const int32_t *sub_sys, hipStream_t s) {
+    with_mat<false>(A, [&](auto v) {
+        hipLaunchKernelGGL((k_pre_res<VT, FT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
+                           A.stage_bytes(), s, v, m, f, res, st, sub_sys);
+    });
+}
+
+template <class VT>
+void launch_spmv(const DevMat<VT> &M, const VT *x, VT *y, const SysState *st, const int32_t *sub_sys,
+                 hipStream_t s) {
+    with_mat<false>(M, [&](auto v) {
+        hipLaunchKernelGGL((k_spmv<VT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock), M.stage_bytes(),
+                           s, v, x, y, st, sub_sys);
+    });
+}
+
+template <class VT, class FT>
+void launch_prolong(const DevMat<VT> &P, const VT *m, const FT *f, const VT *xc, VT *z, const SysState *st,
+                    const int32_t *sub_sys, hipStream_t s) {
+    with_mat<false>(P, [&](auto v) {
+        hipLaunchKernelGGL((k_prolong<VT, FT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
+                           P.stage_bytes(), s, v, m, f, xc, z, st, sub_sys);
+    });
+}
+
+template <class VT, class FT, class OT, bool DOT>
+void launch_post(const DevMat<VT> &A, const VT *m, const FT *f, const VT *z, OT *x, double *part,
+                 const SysState *st, const int32_t *sub_sys, hipStream_t s) {
+    with_mat<false>(A, [&](auto v) {
+        hipLaunchKernelGGL((k_post<VT, FT, OT, DOT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
+                           A.stage_bytes(), s, v, m, f, z, x, part, st, sub_sys);
+    });
+}
+
+#ifdef DFAMG_VT_DOUBLE
+template void launch_pre_res<double, double>(const DevMat<double> &, const double *, const double *, double *,
+                                             const SysState *, const int32_t *, hipStream_t);
+template void launch_spmv<double>(const DevMat<double> &, const double *, double *, const SysState *,
+                                  const int32_t *, hipStream_t);
+template void launch_prolong<double, double>(const DevMat<double> &, const double *, const double *, const double *,
+                                             double *, const SysState *, const int32_t *, hipStream_t);
+template void launch_post<double, double, double, true>(const DevMat<double> &, const double *, const double *,
+                                                        const double *, double *, double *, const SysState *,
+                                                        const int32_t *, hipStream_t);
+template void launch_post<double, double, double, false>(const DevMat<double> &, const double *, const double *,
+                                                         const double *, double *, double *, const SysState *,
+                                                         const int32_t *, hipStream_t);
+#else
+template void launch_pre_res<float, float>(const DevMat<float> &, const float *, const float *, float *,
+                                           const SysState *, const int32_t *, hipStream_t);
+template void launch_pre_res<float, double>(const DevMat<float> &, const float *, const double *, float *,
+                                            const SysState *, const int32_t *, hipStream_t);
+template void launch_spmv<float>(const DevMat<float> &, const float *, float *, const SysState *, const int32_t *,
+                                 hipStream_t);
+template void launch_prolong<float, float>(const DevMat<float> &, const float *, const float *, const float *, float *,
+                                           const SysState *, const int32_t *, hipStream_t);
+template void launch_prolong<float, double>(const DevMat<float> &, const float *, const double *, const float *,
+                                            float *, const SysState *, const int32_t *, hipStream_t);
+template void launch_post<float, float, float, false>(const DevMat<float> &, const float *, const float *,
+                                                      const float *, float *, double *, const SysState *,
+                                                      const int32_t *, hipStream_t);
+template void launch_post<float, double, double, true>(const DevMat<float> &, const float *, const double *,
+                                                       const float *, double *, double *, const SysState *,
+                                                       const int32_t *, hipStream_t);
+#endif
+
+}  // namespace dfamg

@@ -1,0 +1,50 @@
+"""Writes the stored expected values of the full-size parity tests.
+
+Every value here comes from the CPU oracle (oracle/) on the seeded inputs of
+workloads/; nothing is taken from the GPU library.  Run from the repository
+root:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from workloads import config_lognormal_poisson, config_small_poisson  # noqa: E402
+from oracle import OracleSolver  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+NSAMPLE = 2000
+
+
+def record(name, P):
+    t0 = time.time()
+    S = OracleSolver(P.A, P.part, P.nsub, P.Z)
+    t1 = time.time()
+    r = S.solve(P.b)
+    t2 = time.time()
+    idx = np.sort(np.random.default_rng(12345).choice(P.n, size=min(NSAMPLE, P.n), replace=False))
+    out = {
+        "workload": P.name, "n": int(P.n), "nnz": int(P.A.nnz), "nsub": int(P.nsub),
+        "ndv": int(P.ndv), "rtol": 1e-8, "iters": int(r["iters"]),
+        "relres": float(r["relres"]), "relres_true": float(r["relres_true"]),
+        "history": [float(h) for h in r["history"]],
+        "x_norm": float(np.linalg.norm(r["x"])),
+        "sample_index": [int(i) for i in idx],
+        "sample_x": [float(v) for v in r["x"][idx]],
+        "hierarchy_sub0": [list(map(float, lv)) for lv in S.hierarchy_summary()[0]],
+        "oracle_setup_s": t1 - t0, "oracle_solve_s": t2 - t1,
+        "source": "oracle/ (CPU FP64) via tests/golden/make_golden.py",
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(name, out["iters"], out["relres_true"], f"setup {t1 - t0:.1f}s solve {t2 - t1:.1f}s")
+
+
+if __name__ == "__main__":
+    record("poisson32_slabs8_constant", config_small_poisson())
+    record("poisson150_lognormal2_boxes64_linear", config_lognormal_poisson())
