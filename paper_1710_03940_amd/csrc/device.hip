@@ -154,7 +154,7 @@ bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &rang
         D.nnz = S.nnz;
         D.stored = (int64_t)S.val.size();
     } else {
-        HostCsrv C = make_csrv(M, ranges, L.par);
+        HostCsrv C = make_csrv(M, ranges, L.par, L.rpg > 0 ? L.rpg * (kBlock / L.par) : kBlock);
         if (L.stage) {
             const int32_t mx = C.cspan.empty() ? 1 : *std::max_element(C.cspan.begin(), C.cspan.end());
             if ((size_t)mx * sizeof(VT) > kMaxStageBytes) return false;
@@ -240,23 +240,28 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     std::vector<Layout> cand;
     const bool outer = kind == TUNE_OUTER;
     if (!autotune) {
-        cand.push_back(format == DFAMG_FORMAT_CSR && !outer ? Layout{DFAMG_FORMAT_CSR, 8, false, false, false}
-                                                            : Layout{DFAMG_FORMAT_SELL, 1, false, false, false});
+        cand.push_back(format == DFAMG_FORMAT_CSR && !outer ? Layout{DFAMG_FORMAT_CSR, 8, false, false, false, 0}
+                                                            : Layout{DFAMG_FORMAT_SELL, 1, false, false, false, 0});
     } else {
         if (format == DFAMG_FORMAT_SELL || format == DFAMG_FORMAT_AUTO || outer) {
             for (int r : outer ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2}) {
                 if (r > 1 && rows / (256 * r) < 512) continue;
                 for (bool sorted : {false, true}) {
                     if (outer && sorted) continue;
-                    cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, false});
-                    if (!outer) cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, true});
+                    cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, false, 0});
+                    if (!outer) cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, true, 0});
                 }
             }
         }
         if (!outer && (format == DFAMG_FORMAT_CSR || format == DFAMG_FORMAT_AUTO) &&
             (avg_len >= 10.0 || format == DFAMG_FORMAT_CSR))
             for (int l : {4, 8, 16})
-                for (bool stage : {false, true}) cand.push_back(Layout{DFAMG_FORMAT_CSR, l, false, false, stage});
+                for (int rpg : {0, 1, 4}) {
+                    // smaller tiles only where 256-row tiles leave the chip idle
+                    if (rpg > 0 && rows / 256 >= 2048) continue;
+                    for (bool stage : {false, true})
+                        cand.push_back(Layout{DFAMG_FORMAT_CSR, l, false, false, stage, rpg});
+                }
     }
     DevArena scratch;
     VT *x = scratch.alloc<VT>(std::max<int64_t>(1, std::max(M.ncols, M.nrows)));

@@ -19,6 +19,7 @@ namespace dfamg {
 struct Layout {
     int fmt, par;
     bool sorted, idx16, stage;
+    int rpg = 0;   // CSR: rows per lane group in a tile (tile = rpg * 256 / lanes rows); 0 = 256-row tiles
 };
 
 template <class VT>
@@ -45,7 +46,7 @@ struct DevMat {
 };
 
 // Largest LDS window (bytes) a staged layout may use per block.
-constexpr size_t kMaxStageBytes = 32768;
+constexpr size_t kMaxStageBytes = 65536;
 
 // Calls fn(view) with the kernel view type of M.  OUTER restricts the set to
 // the unstaged SELL layouts (used for the global operator).

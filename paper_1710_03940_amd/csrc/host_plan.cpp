@@ -578,10 +578,10 @@ bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool 
     return true;
 }
 
-HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes) {
+HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes, int tile_rows) {
     HostCsrv C;
     C.lanes = lanes;
-    const int rows_per_tile = csr_tile_rows(lanes);
+    const int rows_per_tile = tile_rows;
     for (const RowRange &rg : ranges) {
         int32_t slot = rg.slot0;
         for (int32_t r0 = 0; r0 < rg.nrows; r0 += rows_per_tile)

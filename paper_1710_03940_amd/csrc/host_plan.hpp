@@ -166,7 +166,9 @@ struct RowRange {
 // columns span more than 65536 values.
 bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool sorted, bool idx16,
                HostSell &S);
-HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes);
+// tile_rows: rows per 256-thread block (the block's 256/lanes groups stride
+// over them)
+HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes, int tile_rows = 256);
 // rows per block-sized tile of each layout
 inline int sell_tile_rows(int rpl) { return 256 * rpl; }
 inline int csr_tile_rows(int lanes) { return lanes > 0 ? 256 : 256; }

@@ -95,6 +95,8 @@ __device__ __forceinline__ int tile_of_block(int ntiles) {
 
 inline int grid_for_tiles(int ntiles) { return ((ntiles + 7) >> 3) * 8; }
 
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 template <class T>
 __device__ __forceinline__ T stream_load(const T *p) {
     return __builtin_nontemporal_load(p);
@@ -415,12 +417,19 @@ __global__ void __launch_bounds__(kBlock) k_update(
     for (int k = 0; k < NDV; ++k) t2s[k] = k < ndv ? t2[(int64_t)T.sub * ndv + k] : 0.0;
     for_tile_rows(T, [&](int row) {
         double corr = 0.0;
+        if (NDV == 4 && ndv == 4) {
+            // one row of the own AZ block is 32 contiguous bytes
+            const f64x2 *az = reinterpret_cast<const f64x2 *>(AZown + (int64_t)row * 4);
+            const f64x2 a01 = stream_load(az), a23 = stream_load(az + 1);
+            corr = ((a01.x * t2s[0] + a01.y * t2s[1]) + a23.x * t2s[2]) + a23.y * t2s[3];
+        } else {
 #pragma unroll
-        for (int k = 0; k < NDV; ++k)
-            if (k < ndv) corr += AZown[(int64_t)row * ndv + k] * t2s[k];
+            for (int k = 0; k < NDV; ++k)
+                if (k < ndv) corr += stream_load(AZown + (int64_t)row * ndv + k) * t2s[k];
+        }
         if (ndv > 0)
             for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
-        const double wv = q[row] - corr;
+        const double wv = stream_load(q + row) - corr;
         if (MODE == 0) {
             y[row] += a * p[row];
             const double rn = r[row] - a * wv;

@@ -14,7 +14,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from workloads import config_lognormal_poisson, config_small_poisson  # noqa: E402
+from workloads import config_lognormal_poisson, config_small_poisson, config_batched  # noqa: E402
 from oracle import OracleSolver  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -45,6 +45,31 @@ def record(name, P):
     print(name, out["iters"], out["relres_true"], f"setup {t1 - t0:.1f}s solve {t2 - t1:.1f}s")
 
 
+BATCHED_SAMPLE_SYSTEMS = [2, 12, 19, 28, 31, 42, 44, 47]
+
+
+def record_batched():
+    """Oracle solves of a subset of the 48 batched systems, one by one."""
+    systems = {}
+    for s, P in zip(BATCHED_SAMPLE_SYSTEMS, config_batched(systems=BATCHED_SAMPLE_SYSTEMS)):
+        r = OracleSolver(P.A, P.part, P.nsub, P.Z).solve(P.b)
+        idx = np.sort(np.random.default_rng(100 + s).choice(P.n, size=min(500, P.n), replace=False))
+        systems[str(s)] = {"n": int(P.n), "nsub": int(P.nsub), "iters": int(r["iters"]),
+                           "relres_true": float(r["relres_true"]),
+                           "x_norm": float(np.linalg.norm(r["x"])),
+                           "sample_index": [int(i) for i in idx],
+                           "sample_x": [float(v) for v in r["x"][idx]]}
+        print("batched system", s, P.n, r["iters"])
+    with open(os.path.join(HERE, "batched48_sample.json"), "w") as fh:
+        json.dump({"workload": "batched48_lognormal1_linear", "systems": systems,
+                   "source": "oracle/ (CPU FP64) via tests/golden/make_golden.py"}, fh, indent=1)
+
+
 if __name__ == "__main__":
-    record("poisson32_slabs8_constant", config_small_poisson())
-    record("poisson150_lognormal2_boxes64_linear", config_lognormal_poisson())
+    which = sys.argv[1:] or ["small", "lognormal", "batched"]
+    if "small" in which:
+        record("poisson32_slabs8_constant", config_small_poisson())
+    if "lognormal" in which:
+        record("poisson150_lognormal2_boxes64_linear", config_lognormal_poisson())
+    if "batched" in which:
+        record_batched()

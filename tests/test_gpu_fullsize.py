@@ -1,0 +1,87 @@
+"""Full-size GPU parity on the 150^3 log-normal Poisson problem, in the launch
+configuration the benchmark times (autotuned layouts, captured graphs).  The
+oracle's result is stored in tests/golden (written by make_golden.py, which
+only calls oracle/): iteration count, residual history and 2000 sampled
+solution entries."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", name + ".json")) as fh:
+        return json.load(fh)
+
+
+@pytest.fixture(scope="module")
+def lognormal150():
+    from workloads import config_lognormal_poisson
+    return config_lognormal_poisson()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lognormal150_matches_oracle(lognormal150, precision):
+    import paper_1710_03940_amd as L
+    P = lognormal150
+    g = _golden("poisson150_lognormal2_boxes64_linear")
+    assert g["n"] == P.n and g["nnz"] == P.A.nnz
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, precision=precision)
+    dev = torch.device("cuda:0")
+    b = torch.tensor(P.b, device=dev)
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    out = S.solve(b, x)
+    S.close()
+    print(f"{precision}: gpu iters {out['iters']} oracle {g['iters']} relres_true "
+          f"{out['relres_true']:.3e}", flush=True)
+    assert out["status"] == 0
+    assert out["relres_true"] <= 1e-8
+    if precision == "fp64":
+        assert abs(out["iters"] - g["iters"]) <= 2
+        k = min(len(out["history"]), len(g["history"]))
+        assert np.allclose(out["history"][:k], g["history"][:k], rtol=1e-5, atol=0)
+    else:
+        assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
+    idx = np.array(g["sample_index"])
+    xs = x.cpu().numpy()[idx]
+    gs = np.array(g["sample_x"])
+    assert np.linalg.norm(xs - gs) <= 1e-6 * np.linalg.norm(gs)
+    # the whole solution has the oracle's norm
+    assert abs(np.linalg.norm(x.cpu().numpy()) - g["x_norm"]) <= 1e-6 * g["x_norm"]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batched48_matches_oracle_on_sampled_systems(precision):
+    import paper_1710_03940_amd as L
+    from workloads import config_batched, concat_problems
+    g = _golden("batched48_sample")["systems"]
+    probs = config_batched()
+    A, part, nsub, Z, b, x0, off = concat_problems(probs)
+    S = L.BatchedSolver(A, part, nsub, Z, off, precision=precision)
+    dev = torch.device("cuda:0")
+    x = torch.zeros(A.shape[0], dtype=torch.float64, device=dev)
+    out = S.solve(torch.tensor(b, device=dev), x)
+    S.close()
+    xs = x.cpu().numpy()
+    assert out["status"] == 0
+    assert np.all(out["relres_true"] <= 1e-8)
+    for key, gs in g.items():
+        s = int(key)
+        it = int(out["iters"][s])
+        print(f"{precision} system {s}: gpu iters {it} oracle {gs['iters']}", flush=True)
+        if precision == "fp64":
+            assert abs(it - gs["iters"]) <= 2
+        else:
+            assert it <= int(np.floor(1.15 * gs["iters"])) + 1
+        seg = xs[off[s]:off[s + 1]]
+        idx = np.array(gs["sample_index"])
+        ref = np.array(gs["sample_x"])
+        assert np.linalg.norm(seg[idx] - ref) <= 1e-6 * np.linalg.norm(ref)
+        assert abs(np.linalg.norm(seg) - gs["x_norm"]) <= 1e-6 * gs["x_norm"]
