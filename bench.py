@@ -104,7 +104,16 @@ def main():
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--sample-iters", type=int, default=20)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a 2 GiB device copy (streaming ceiling; reference for HBM counters)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("SPMV_FETCH", "SPMV_WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="rocprofv3 --pmc CSVs of FETCH_SIZE / WRITE_SIZE for bench and for --copy-calibration; "
+                         "writes the traffic file read by the roofline")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
+    if args.traffic_from:
+        return write_traffic(*args.traffic_from)
 
     if args.cpu_baseline_worker:
         cpu_baseline_worker(args.sample_iters)
@@ -210,6 +219,68 @@ def main():
     }
     S64.close()
     print(json.dumps(line), flush=True)
+    return 0
+
+
+COPY_BYTES = 1 << 31
+
+
+def copy_calibration():
+    """Plain device copy of COPY_BYTES: the streaming ceiling of the device,
+    and the known-size reference for the HBM traffic counters."""
+    import torch
+    n = COPY_BYTES // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes": COPY_BYTES, "s": dt,
+                      "GBps_read_plus_write": 2 * COPY_BYTES / dt / 1e9}), flush=True)
+    return 0
+
+
+def _pmc_kib(csv_path, name_part, counter):
+    """Per-dispatch counter values (KiB) of kernels whose name contains name_part."""
+    import csv
+    vals = []
+    with open(csv_path) as fh:
+        for row in csv.DictReader(fh):
+            if name_part in row.get("Kernel_Name", "") and row.get("Counter_Name", counter) == counter:
+                vals.append(float(row["Counter_Value"]))
+    return vals
+
+
+def write_traffic(spmv_fetch, spmv_write, copy_fetch, copy_write):
+    """HBM bytes per launch of the outer SpMV from FETCH_SIZE / WRITE_SIZE,
+    scaled by what the same counters read for the plain copy of COPY_BYTES."""
+    import statistics
+    cf = max(_pmc_kib(copy_fetch, "", "FETCH_SIZE"))
+    cw = max(_pmc_kib(copy_write, "", "WRITE_SIZE"))
+    fscale = (COPY_BYTES / 1024.0) / cf      # true KiB per counted KiB
+    wscale = (COPY_BYTES / 1024.0) / cw
+    # launches of the in-loop SpMV; skipped launches after convergence read ~nothing
+    f = [v for v in _pmc_kib(spmv_fetch, "k_outer<0", "FETCH_SIZE")]
+    w = [v for v in _pmc_kib(spmv_write, "k_outer<0", "WRITE_SIZE")]
+    fbig = [v for v in f if v > 0.5 * max(f)]
+    wbig = [v for v in w if v > 0.5 * max(w)]
+    fetch = statistics.median(fbig) * fscale * 1024.0
+    write = statistics.median(wbig) * wscale * 1024.0
+    out = {"kernel": "k_outer<0,...> (outer SpMV, 150^3 log-normal workload)",
+           "bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+           "copy_scale_fetch": fscale, "copy_scale_write": wscale,
+           "launches_counted": [len(fbig), len(wbig)],
+           "kernel_source_hash": kernel_source_hash()}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
     return 0
 
 

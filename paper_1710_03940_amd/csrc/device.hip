@@ -665,6 +665,9 @@ struct Handle {
     // vectors
     double *b = nullptr, *y = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *s = nullptr, *w = nullptr,
            *x = nullptr;
+    // BiCGStab: r~, v, p^, s^, s, t
+    double *rt = nullptr, *v = nullptr, *ph = nullptr, *sh = nullptr, *sv = nullptr, *tv = nullptr;
+    bool bicg() const { return prm.solver == DFAMG_SOLVER_BICGSTAB; }
     // partials and state
     double *part_A = nullptr, *part_rows = nullptr, *part_rs = nullptr, *part_rs_job = nullptr;
     int32_t *d_sys_cjob_off0 = nullptr;
@@ -703,6 +706,7 @@ struct Handle {
     void project_solve(hipStream_t st, bool in_loop, const int32_t *subto, double *part, int32_t nslots,
                        int with_p0);
     void iteration(hipStream_t st);
+    void iteration_bicg(hipStream_t st);
     void initial(hipStream_t st);
     void finish(hipStream_t st);
     void precond(hipStream_t st, const double *rin, double *sout, bool profiled = false);
@@ -792,8 +796,16 @@ void Handle::setup_device() {
     s = ar.alloc<double>(n);
     w = ar.alloc<double>(n);
     x = ar.alloc<double>(n);
+    if (prm.solver == DFAMG_SOLVER_BICGSTAB) {
+        rt = ar.alloc<double>(n);
+        v = ar.alloc<double>(n);
+        ph = ar.alloc<double>(n);
+        sh = ar.alloc<double>(n);
+        sv = ar.alloc<double>(n);
+        tv = ar.alloc<double>(n);
+    }
     part_A = ar.alloc<double>((size_t)A.ntiles * (ndv + 1));
-    part_rows = ar.alloc<double>((size_t)nrow_tiles * (ndv + 1));
+    part_rows = ar.alloc<double>((size_t)nrow_tiles * std::max(ndv + 1, 2));
     states = ar.alloc<SysState>(nsys);
     HIP_CHECK(hipMemsetAsync(states, 0, sizeof(SysState) * nsys, sm));
     HIP_CHECK(hipHostMalloc((void **)&h_states, sizeof(SysState) * nsys, hipHostMallocDefault));
@@ -942,6 +954,48 @@ void Handle::iteration(hipStream_t st) {
     prof.mark(KID_DIR, 1, st);
 }
 
+// One BiCGStab iteration on the deflated operator P A (all systems at once).
+void Handle::iteration_bicg(hipStream_t st) {
+    const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock), gs(nsys()), wb(kWideBlock);
+    const int nt = nrow_tiles;
+    hipLaunchKernelGGL(k_bicg_p, gr, bl, 0, st, rows, nt, r, v, p, states, d_sub_sys);
+    precond(st, p, ph, true);
+    // v = P A p^, alpha = rho / (r~, v)
+    outer(3, st, ph, nullptr, q, true);
+    prof.mark(KID_PROJECT, 0, st);
+    project_solve(st, true, d_subto_A, part_A, A.ntiles, 0);
+    prof.mark(KID_PROJECT, 1, st);
+    with_ndv(ndv(), [&](auto c) {
+        hipLaunchKernelGGL((k_bicg_proj<0, decltype(c)::value>), gr, bl, 0, st, rows, nt, q, v, rt, ndv(), AZown,
+                           AZoffp, AZoffc, AZoffv, t2, part_rows, nt, states, d_sub_sys);
+    });
+    hipLaunchKernelGGL(k_bicg_scalar<0>, gs, wb, 0, st, part_rows, nt, d_sto_rows, states, hist, hist_stride,
+                       prm.rtol, prm.maxiter);
+    // s = r - alpha v and the half-step test
+    hipLaunchKernelGGL(k_bicg_s, gr, bl, 0, st, rows, nt, r, v, sv, part_rows, states, d_sub_sys);
+    hipLaunchKernelGGL(k_bicg_scalar<1>, gs, wb, 0, st, part_rows, nt, d_sto_rows, states, hist, hist_stride,
+                       prm.rtol, prm.maxiter);
+    precond(st, sv, sh);
+    // t = P A s^, omega = (t, s) / (t, t)
+    outer(3, st, sh, nullptr, q);
+    project_solve(st, true, d_subto_A, part_A, A.ntiles, 0);
+    with_ndv(ndv(), [&](auto c) {
+        hipLaunchKernelGGL((k_bicg_proj<1, decltype(c)::value>), gr, bl, 0, st, rows, nt, q, tv, sv, ndv(), AZown,
+                           AZoffp, AZoffc, AZoffv, t2, part_rows, nt, states, d_sub_sys);
+    });
+    hipLaunchKernelGGL(k_bicg_scalar<2>, gs, wb, 0, st, part_rows, nt, d_sto_rows, states, hist, hist_stride,
+                       prm.rtol, prm.maxiter);
+    // y += alpha p^ + omega s^, r = s - omega t, test, rho
+    prof.mark(KID_UPDATE, 0, st);
+    hipLaunchKernelGGL(k_bicg_update, gr, bl, 0, st, rows, nt, y, r, ph, sh, sv, tv, rt, part_rows, nt, states,
+                       d_sub_sys);
+    prof.mark(KID_UPDATE, 1, st);
+    prof.mark(KID_TEST, 0, st);
+    hipLaunchKernelGGL(k_bicg_scalar<3>, gs, wb, 0, st, part_rows, nt, d_sto_rows, states, hist, hist_stride,
+                       prm.rtol, prm.maxiter);
+    prof.mark(KID_TEST, 1, st);
+}
+
 // r0 = P(b - A y0), stopping test, s0 = M^{-1} r0, rho0, p0 = s0
 void Handle::initial(hipStream_t st) {
     const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
@@ -955,6 +1009,15 @@ void Handle::initial(hipStream_t st) {
     hipLaunchKernelGGL(k_residual_test<1>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, d_sto_rows, states, hist,
                        hist_stride, prm.rtol, prm.maxiter, nullptr, psub, ranges());
     hipLaunchKernelGGL(k_zero_null_rhs, gr, bl, 0, st, rows, nrow_tiles, y, states, d_sub_sys);
+    if (bicg()) {
+        // r~ = r0, v = p = 0, rho = (r~, r0), rho_old = alpha = omega = 1
+        hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, r, rt);
+        hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, (const double *)nullptr, v);
+        hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, (const double *)nullptr, p);
+        hipLaunchKernelGGL(k_bicg_scalar<4>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, nrow_tiles,
+                           d_sto_rows, states, hist, hist_stride, prm.rtol, prm.maxiter);
+        return;
+    }
     precond(st, r, s);
     hipLaunchKernelGGL(k_rho<1>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
                        d_sys_cjob_off0, states);
@@ -964,6 +1027,7 @@ void Handle::initial(hipStream_t st) {
 // x = y + Z E^{-1} Z^T (b - A y), then ||b - A x|| / ||b||
 void Handle::finish(hipStream_t st) {
     const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
+    if (bicg()) hipLaunchKernelGGL(k_bicg_halffix, gr, bl, 0, st, rows, nrow_tiles, y, ph, states, d_sub_sys);
     outer(1, st, y, b, w);
     project_solve(st, false, d_subto_A, part_A, A.ntiles, 0);
     with_ndv(ndv(), [&](auto c) {
@@ -979,7 +1043,8 @@ void Handle::launch_iterations(int k) {
         prof.clear_used();
         for (int i = 0; i < k; ++i) {
             prof.slot = i;
-            iteration(stream);
+            if (bicg()) iteration_bicg(stream);
+            else iteration(stream);
         }
         return;
     }
@@ -988,7 +1053,8 @@ void Handle::launch_iterations(int k) {
         HIP_CHECK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
         for (int i = 0; i < prm.graph_iters; ++i) {
             prof.slot = i;
-            iteration(cap_stream);
+            if (bicg()) iteration_bicg(cap_stream);
+            else iteration(cap_stream);
         }
         HIP_CHECK(hipStreamEndCapture(cap_stream, &graph));
         HIP_CHECK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));

@@ -553,6 +553,218 @@ __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restri
     for_tile_rows(T, [&](int row) { p[row] = INIT ? s[row] : s[row] + beta * p[row]; });
 }
 
+// ---------------------------------------------------------------------------
+// BiCGStab (right-preconditioned, Templates form) on the deflated operator
+// ---------------------------------------------------------------------------
+
+// own-subdomain + off-subdomain AZ t2 of one row (NDV = unroll bound)
+template <int NDV>
+__device__ __forceinline__ double az_t2(int row, int sub, int ndv, const double *__restrict__ AZown,
+                                        const int32_t *__restrict__ offp, const int32_t *__restrict__ offc,
+                                        const double *__restrict__ offv, const double *__restrict__ t2) {
+    double corr = 0.0;
+#pragma unroll
+    for (int k = 0; k < NDV; ++k)
+        if (k < ndv) corr += AZown[(int64_t)row * ndv + k] * t2[(int64_t)sub * ndv + k];
+    if (ndv > 0)
+        for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
+    return corr;
+}
+
+// p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega)
+static __global__ void __launch_bounds__(kBlock) k_bicg_p(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                          const double *__restrict__ r, const double *__restrict__ v,
+                                                          double *__restrict__ p, const SysState *__restrict__ st,
+                                                          const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const SysState &S = st[sub_sys[T.sub]];
+    if (S.done) return;
+    const double beta = (S.rho / S.rho_old) * (S.alpha / S.omega), om = S.omega;
+    for_tile_rows(T, [&](int row) { p[row] = r[row] + beta * (p[row] - om * v[row]); });
+}
+
+// out = q - AZ t2 (the projected operator product) with partials
+//   MODE 0: (rt, out)              -> v and (r~, v)
+//   MODE 1: (out, s), (out, out)   -> t and (t, s), (t, t)
+template <int MODE, int NDV>
+__global__ void __launch_bounds__(kBlock) k_bicg_proj(
+    const DevTile *__restrict__ tiles, int32_t ntiles, const double *__restrict__ q, double *__restrict__ out,
+    const double *__restrict__ other, int ndv, const double *__restrict__ AZown, const int32_t *__restrict__ offp,
+    const int32_t *__restrict__ offc, const double *__restrict__ offv, const double *__restrict__ t2,
+    double *__restrict__ part, int32_t nslots, const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    __shared__ double lds[4];
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    if (st[sub_sys[T.sub]].done) return;
+    double d0 = 0.0, d1 = 0.0;
+    for_tile_rows(T, [&](int row) {
+        const double v = q[row] - az_t2<NDV>(row, T.sub, ndv, AZown, offp, offc, offv, t2);
+        out[row] = v;
+        d0 += other[row] * v;
+        if (MODE == 1) d1 += v * v;
+    });
+    const double s0 = block_sum(d0, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = s0;
+    if (MODE == 1) {
+        const double s1 = block_sum(d1, lds, kBlock);
+        if (threadIdx.x == 0) part[(int64_t)nslots + T.slot] = s1;
+    }
+}
+
+// s = r - alpha v, partial (s, s)
+static __global__ void __launch_bounds__(kBlock) k_bicg_s(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                          const double *__restrict__ r, const double *__restrict__ v,
+                                                          double *__restrict__ s, double *__restrict__ part,
+                                                          const SysState *__restrict__ st,
+                                                          const int32_t *__restrict__ sub_sys) {
+    __shared__ double lds[4];
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const SysState &S = st[sub_sys[T.sub]];
+    if (S.done) return;
+    const double a = S.alpha;
+    double d = 0.0;
+    for_tile_rows(T, [&](int row) {
+        const double sv = r[row] - a * v[row];
+        s[row] = sv;
+        d += sv * sv;
+    });
+    const double sum = block_sum(d, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = sum;
+}
+
+// y += alpha p^ + omega s^; r = s - omega t; partials (r, r), (r~, r)
+static __global__ void __launch_bounds__(kBlock) k_bicg_update(
+    const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ y, double *__restrict__ r,
+    const double *__restrict__ ph, const double *__restrict__ sh, const double *__restrict__ s,
+    const double *__restrict__ t, const double *__restrict__ rt, double *__restrict__ part, int32_t nslots,
+    const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    __shared__ double lds[4];
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const SysState &S = st[sub_sys[T.sub]];
+    if (S.done) return;
+    const double a = S.alpha, om = S.omega;
+    double d0 = 0.0, d1 = 0.0;
+    for_tile_rows(T, [&](int row) {
+        y[row] += a * ph[row] + om * sh[row];
+        const double rn = s[row] - om * t[row];
+        r[row] = rn;
+        d0 += rn * rn;
+        d1 += rt[row] * rn;
+    });
+    const double s0 = block_sum(d0, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = s0;
+    const double s1 = block_sum(d1, lds, kBlock);
+    if (threadIdx.x == 0) part[(int64_t)nslots + T.slot] = s1;
+}
+
+// Per-system scalar steps of BiCGStab (1024 threads, sums of tile partials)
+//   STEP 0 (alpha): alpha = rho / (r~, v)
+//   STEP 1 (half test): ||s|| / ||b|| <= rtol stops with the half step
+//   STEP 2 (omega): omega = (t, s) / (t, t)
+//   STEP 3 (test): ||r|| / ||b||, iteration count, history, stop test,
+//                  rho_old = rho, rho = (r~, r)
+//   STEP 4 (init): rho = (r~, r) = ||r0||^2, rho_old = alpha = omega = 1
+template <int STEP>
+__global__ void __launch_bounds__(kWideBlock) k_bicg_scalar(const double *__restrict__ part, int32_t nslots,
+                                                            const int32_t *__restrict__ sys_tile_off,
+                                                            SysState *__restrict__ st, double *__restrict__ hist,
+                                                            int32_t hist_stride, double rtol, int32_t maxiter) {
+    __shared__ double lds[16];
+    const int sys = blockIdx.x;
+    SysState &S = st[sys];
+    if (STEP != 4 && S.done) return;
+    double a0 = 0.0, a1 = 0.0;
+    for (int tl = sys_tile_off[sys] + threadIdx.x; tl < sys_tile_off[sys + 1]; tl += kWideBlock) {
+        a0 += part[tl];
+        if (STEP == 2 || STEP == 3) a1 += part[(int64_t)nslots + tl];
+    }
+    const double s0 = block_sum(a0, lds, kWideBlock);
+    double s1 = 0.0;
+    if (STEP == 2 || STEP == 3) s1 = block_sum(a1, lds, kWideBlock);
+    if (threadIdx.x != 0) return;
+    if (STEP == 4) {
+        S.rho = S.rr;
+        S.rho_old = S.alpha = S.omega = 1.0;
+        return;
+    }
+    if (STEP == 0) {
+        if (s0 == 0.0) {
+            S.done = kBreakdown;
+            return;
+        }
+        S.alpha = S.rho / s0;
+        return;
+    }
+    if (STEP == 1) {
+        const double h = sqrt(s0 / S.bb);
+        if (!isfinite(h)) {
+            S.done = kNaN;
+        } else if (h <= rtol) {
+            const int it = S.iter + 1;
+            S.iter = it;
+            S.relres = h;
+            S.half = 1;
+            if (it < hist_stride) hist[(int64_t)sys * hist_stride + it] = h;
+            S.done = kConverged;
+        }
+        return;
+    }
+    if (STEP == 2) {
+        const double om = s1 != 0.0 ? s0 / s1 : 0.0;
+        S.tt = s1;
+        S.ts = s0;
+        if (om == 0.0) {   // counted as a (failed) iteration, y keeps its value
+            S.iter = S.iter + 1;
+            S.done = kBreakdown;
+        }
+        S.omega = om;
+        return;
+    }
+    // STEP 3
+    const double h = sqrt(s0 / S.bb);
+    const int it = S.iter + 1;
+    S.iter = it;
+    S.rr = s0;
+    S.relres = h;
+    if (it < hist_stride) hist[(int64_t)sys * hist_stride + it] = h;
+    S.rho_old = S.rho;
+    S.rho = s1;
+    if (!isfinite(h)) S.done = kNaN;
+    else if (h <= rtol) S.done = kConverged;
+    else if (it >= maxiter) S.done = kMaxIter;
+    else if (s1 == 0.0) S.done = kBreakdown;
+}
+
+// After a half-step stop: y += alpha p^ for the systems that stopped there.
+static __global__ void __launch_bounds__(kBlock) k_bicg_halffix(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                                double *__restrict__ y, const double *__restrict__ ph,
+                                                                const SysState *__restrict__ st,
+                                                                const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const SysState &S = st[sub_sys[T.sub]];
+    if (!S.half) return;
+    const double a = S.alpha;
+    for_tile_rows(T, [&](int row) { y[row] += a * ph[row]; });
+}
+
+// dst = src (used for r~ = r0 and zero-filled vectors)
+static __global__ void __launch_bounds__(kBlock) k_copy(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                        const double *__restrict__ src, double *__restrict__ dst) {
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    for_tile_rows(T, [&](int row) { dst[row] = src ? src[row] : 0.0; });
+}
+
 // y = 0 for systems with b = 0
 static __global__ void k_zero_null_rhs(const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ y,
                                 const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {

@@ -13,6 +13,7 @@ import paper_1710_03940_amd as L
 from paper_1710_03940_amd import _lib
 from workloads import tiny_problem, config_small_poisson, concat_problems, make_problem
 from workloads.convdiff import convection_diffusion7
+from workloads import config_oseen
 from oracle import OracleSolver, OracleParams
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -36,7 +37,17 @@ def test_params_default():
     assert abs(p.jacobi_omega - 0.8) < 1e-15 and p.block_size == 1
 
 
-def _compare_hierarchy(P, prm_kw, oracle_kw, sys_row_off=None):
+def _significant(M, rel=1e-13):
+    """Sparsity pattern without entries at rounding level: products in which
+    the exact value cancels to zero leave a residue of about 1e-19 whose
+    presence depends on the summation order."""
+    M = sp.csr_matrix(M)
+    keep = np.abs(M.data) > rel * np.abs(M.data).max()
+    r = np.repeat(np.arange(M.shape[0]), np.diff(M.indptr))
+    return set(zip(r[keep].tolist(), M.indices[keep].tolist()))
+
+
+def _compare_hierarchy(P, prm_kw, oracle_kw, sys_row_off=None, exact_structure=True):
     plan = L.dfamg_plan_create(L.make_params(**prm_kw), P.A, P.part, P.nsub, P.Z,
                                sys_row_off=sys_row_off)
     try:
@@ -45,7 +56,10 @@ def _compare_hierarchy(P, prm_kw, oracle_kw, sys_row_off=None):
         for s in range(P.nsub):
             lv = L.dfamg_plan_levels(plan, s)
             o = summ[s]
-            assert [x[:3] for x in lv] == [tuple(x[:3]) for x in o], (s, lv, o)
+            if exact_structure:
+                assert [x[:3] for x in lv] == [tuple(x[:3]) for x in o], (s, lv, o)
+            else:
+                assert [x[0] for x in lv] == [x[0] for x in o], (s, lv, o)
             for l in range(len(lv) - 1):
                 assert lv[l][3] == pytest.approx(o[l][3], rel=1e-11)
                 agg = L.dfamg_plan_aggregates(plan, s, l)
@@ -54,6 +68,8 @@ def _compare_hierarchy(P, prm_kw, oracle_kw, sys_row_off=None):
                 Pm = sp.csr_matrix((val, col, ptr), shape=shape)
                 ref = ora.M.hierarchies[s].levels[l].P
                 assert abs(Pm - ref).max() <= 1e-12 * abs(ref).max()
+                if not exact_structure:
+                    assert _significant(Pm) == _significant(ref)
             ptr, col, val, shape = L.dfamg_plan_level_matrix(plan, s, len(lv) - 1, 0)
             Ac = sp.csr_matrix((val, col, ptr), shape=shape)
             ref = ora.M.hierarchies[s].levels[-1].A
@@ -87,6 +103,15 @@ def test_hierarchy_nonsymmetric_matches_oracle():
     P = base.__class__("cd", A, base.part, base.nsub, base.Z, base.b, base.x0)
     _compare_hierarchy(P, dict(coarse_enough=20, solver="bicgstab"),
                        dict(coarse_enough=20, solver="bicgstab"))
+
+
+@pytest.mark.parametrize("N,pieces,ce", [(8, (2, 2, 1), 500), (10, (1, 2, 1), 60)])
+def test_block_hierarchy_oseen_matches_oracle(N, pieces, ce):
+    """Point-block (4x4) aggregation on the nonsymmetric Q1 Oseen operator,
+    with the nonsymmetric per-field E."""
+    P = config_oseen(N=N, pieces=pieces)
+    kw = dict(coarse_enough=ce, solver="bicgstab", block_size=4)
+    _compare_hierarchy(P, kw, kw, exact_structure=False)
 
 
 def test_batched_plan_hierarchies_match_standalone():

@@ -8,7 +8,11 @@
 * batched: 48 independent log-normal (sigma = 1) Poisson systems with grid
   edges drawn uniformly from [16, 96] and 2..4 pieces per axis (seed 2),
   coefficients from seed 1000+s, right-hand sides from seed 2000+s, linear
-  deflation with isotropic spacing 1/(max edge + 1).
+  deflation with isotropic spacing 1/(max edge + 1);
+* Oseen: the stabilised equal-order Q1 Oseen operator on 64^3 interior nodes
+  (4 interleaved unknowns per node, 1,048,576 rows), convection from seed 3,
+  nu = 1e-2, right-hand side U[-1,1] from seed 4, 8x8x4 boxes of 8x8x16 nodes,
+  per-field constant deflation (4 vectors per subdomain).
 """
 from dataclasses import dataclass, field
 from typing import Optional
@@ -19,6 +23,7 @@ import scipy.sparse as sp
 from .poisson import poisson7, grid_coords
 from .partition import box_partition
 from .deflation import constant_deflation, linear_deflation
+from .oseen import oseen_q1, field_deflation
 
 
 @dataclass
@@ -147,3 +152,14 @@ def tiny_problem(N=6, pieces=(1, 1, 2), deflation="constant", sigma=0.0,
     return make_problem(f"tiny{dims}", dims, pieces, deflation=deflation,
                         sigma=sigma, coef_seed=seed, rhs=rhs,
                         rhs_seed=seed + 17)
+
+
+def config_oseen(N=64, pieces=(8, 8, 4), nu=1e-2, dt=None):
+    """Oseen Q1 system with per-field constant deflation (block size 4)."""
+    A, _ = oseen_q1(N, nu=nu, seed=3, dt=dt)
+    part, nsub, Z = field_deflation(N, pieces)
+    n = A.shape[0]
+    b = np.random.default_rng(4).uniform(-1.0, 1.0, n)
+    return Problem(f"oseen{N}_boxes{nsub}_field", A, part, nsub, Z, b,
+                   np.zeros(n), (N, N, N), tuple(pieces),
+                   {"nu": nu, "dt": dt, "block_size": 4, "deflation": "field"})
