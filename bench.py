@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-oseen", action="store_true")
     ap.add_argument("--sample-iters", type=int, default=20)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -163,6 +164,13 @@ def main():
                  "bytes_per_iter": stm["bytes_per_iter"]}
         Sm.close()
 
+    oseen = None
+    if not args.no_oseen:
+        try:
+            oseen = bench_oseen(args, log)
+        except Exception as exc:  # reported, never silently dropped
+            oseen = {"error": str(exc)}
+
     batched = None
     if not args.no_batched:
         try:
@@ -208,7 +216,7 @@ def main():
         "setup_s": {"host": st64["setup_host_s"], "device": st64["setup_device_s"]},
         "bytes_per_iter": st64["bytes_per_iter"],
         "effective_GBps": st64["bytes_per_iter"] * out64["iters"] / t64 / 1e9,
-        "mixed": mixed, "batched": batched,
+        "mixed": mixed, "batched": batched, "oseen": oseen,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_outer (outer SpMV + (p,q) + Z^T q epilogue)",
@@ -230,15 +238,17 @@ def copy_calibration():
     and the known-size reference for the HBM traffic counters."""
     import torch
     n = COPY_BYTES // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    # uninitialised on purpose: the only kernels of this run are the copies
+    # (b = -a, one ordinary elementwise kernel reading and writing COPY_BYTES)
+    a = torch.empty(n, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
     for _ in range(3):
-        b.copy_(a)
+        torch.neg(a, out=b)
     torch.cuda.synchronize()
     reps = 10
     t0 = time.perf_counter()
     for _ in range(reps):
-        b.copy_(a)
+        torch.neg(a, out=b)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     print(json.dumps({"copy_bytes": COPY_BYTES, "s": dt,
@@ -261,8 +271,8 @@ def write_traffic(spmv_fetch, spmv_write, copy_fetch, copy_write):
     """HBM bytes per launch of the outer SpMV from FETCH_SIZE / WRITE_SIZE,
     scaled by what the same counters read for the plain copy of COPY_BYTES."""
     import statistics
-    cf = max(_pmc_kib(copy_fetch, "", "FETCH_SIZE"))
-    cw = max(_pmc_kib(copy_write, "", "WRITE_SIZE"))
+    cf = statistics.median(_pmc_kib(copy_fetch, "elementwise", "FETCH_SIZE"))
+    cw = statistics.median(_pmc_kib(copy_write, "elementwise", "WRITE_SIZE"))
     fscale = (COPY_BYTES / 1024.0) / cf      # true KiB per counted KiB
     wscale = (COPY_BYTES / 1024.0) / cw
     # launches of the in-loop SpMV; skipped launches after convergence read ~nothing
@@ -301,6 +311,34 @@ def kernel_breakdown(P, b, x, log):
             out[name] = {"avg_us": a * 1e3,
                          "GBps": (kv["bytes"] / (a * 1e-3) / 1e9) if kv["bytes"] else None}
     log("  per-kernel spans (us): " + ", ".join(f"{k} {v['avg_us']:.1f}" for k, v in out.items()))
+    return out
+
+
+def bench_oseen(args, log):
+    """Q1 Oseen system (64^3 nodes x 4 fields, 256 subdomains, per-field
+    deflation): BiCGStab with the FP32 block-SA preconditioner, and the same
+    solve with an FP64 preconditioner for comparison."""
+    import torch
+    import paper_1710_03940_amd as dfamg
+    from workloads import config_oseen
+    log("generating the 64^3 Q1 Oseen problem")
+    P = config_oseen()
+    dev = torch.device("cuda:0")
+    b = torch.tensor(P.b, device=dev)
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    out = {"workload": P.name, "n": P.n, "nnz": int(P.A.nnz), "subdomains": P.nsub,
+           "deflation": "per-field constant (4 per subdomain)", "solver": "bicgstab",
+           "block_size": 4}
+    for prec in ("mixed", "fp64"):
+        S = dfamg.Solver(P.A, P.part, P.nsub, P.Z, solver="bicgstab", block_size=4, precision=prec)
+        t, o, its = time_solver(S, b, x, args.steps, args.warmup, log)
+        st = S.stats()
+        S.close()
+        out[prec] = {"s_per_solve": t, "iters": its[-1], "relres_true": o["relres_true"],
+                     "setup_host_s": st["setup_host_s"], "setup_device_s": st["setup_device_s"],
+                     "bytes_per_iter": st["bytes_per_iter"]}
+        log(f"  oseen {prec}: {t * 1e3:.1f} ms, {its[-1]} iterations, relres {o['relres_true']:.2e}")
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
     return out
 
 

@@ -14,16 +14,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from workloads import config_lognormal_poisson, config_small_poisson, config_batched  # noqa: E402
-from oracle import OracleSolver  # noqa: E402
+from workloads import (config_lognormal_poisson, config_small_poisson, config_batched,  # noqa: E402
+                       config_oseen)
+from oracle import OracleSolver, OracleParams  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 NSAMPLE = 2000
 
 
-def record(name, P):
+def record(name, P, prm=None):
     t0 = time.time()
-    S = OracleSolver(P.A, P.part, P.nsub, P.Z)
+    S = OracleSolver(P.A, P.part, P.nsub, P.Z, prm)
     t1 = time.time()
     r = S.solve(P.b)
     t2 = time.time()
@@ -31,6 +32,7 @@ def record(name, P):
     out = {
         "workload": P.name, "n": int(P.n), "nnz": int(P.A.nnz), "nsub": int(P.nsub),
         "ndv": int(P.ndv), "rtol": 1e-8, "iters": int(r["iters"]),
+        "params": dict(vars(S.prm)),
         "relres": float(r["relres"]), "relres_true": float(r["relres_true"]),
         "history": [float(h) for h in r["history"]],
         "x_norm": float(np.linalg.norm(r["x"])),
@@ -73,3 +75,6 @@ if __name__ == "__main__":
         record("poisson150_lognormal2_boxes64_linear", config_lognormal_poisson())
     if "batched" in which:
         record_batched()
+    if "oseen" in which:
+        record("oseen64_boxes256_field", config_oseen(),
+               OracleParams(solver="bicgstab", block_size=4))

@@ -85,3 +85,32 @@ def test_batched48_matches_oracle_on_sampled_systems(precision):
         ref = np.array(gs["sample_x"])
         assert np.linalg.norm(seg[idx] - ref) <= 1e-6 * np.linalg.norm(ref)
         assert abs(np.linalg.norm(seg) - gs["x_norm"]) <= 1e-6 * gs["x_norm"]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_oseen64_matches_oracle(precision):
+    """Q1 Oseen, 64^3 nodes x 4 fields, 256 subdomains, per-field deflation
+    (m = 1024, nonsymmetric E), 4x4 point-block SA, BiCGStab."""
+    import paper_1710_03940_amd as L
+    from workloads import config_oseen
+    g = _golden("oseen64_boxes256_field")
+    P = config_oseen()
+    assert g["n"] == P.n and g["nnz"] == P.A.nnz
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, solver="bicgstab", block_size=4, precision=precision)
+    dev = torch.device("cuda:0")
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    out = S.solve(torch.tensor(P.b, device=dev), x)
+    S.close()
+    print(f"oseen {precision}: gpu iters {out['iters']} oracle {g['iters']} relres_true "
+          f"{out['relres_true']:.3e}", flush=True)
+    assert out["status"] == 0
+    assert out["relres_true"] <= 1e-8
+    if precision == "fp64":
+        assert abs(out["iters"] - g["iters"]) <= 2
+    else:
+        assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
+    xs = x.cpu().numpy()
+    idx = np.array(g["sample_index"])
+    gs = np.array(g["sample_x"])
+    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+    assert abs(np.linalg.norm(xs) - g["x_norm"]) <= 1e-6 * g["x_norm"]
