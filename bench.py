@@ -145,6 +145,7 @@ def main():
     st64 = S64.stats()
     log(f"  host setup {st64['setup_host_s']:.2f} s, device setup {st64['setup_device_s']:.2f} s, "
         f"levels {st64['level_rows']}")
+    log(f"  layouts: {st64['layouts']}")
     log("timing FP64")
     t64, out64, it64 = time_solver(S64, b, x, args.steps, args.warmup, log)
     st64 = S64.stats()
@@ -334,6 +335,7 @@ def bench_oseen(args, log):
         t, o, its = time_solver(S, b, x, args.steps, args.warmup, log)
         st = S.stats()
         S.close()
+        log(f"  oseen {prec} layouts: {st['layouts']}")
         out[prec] = {"s_per_solve": t, "iters": its[-1], "relres_true": o["relres_true"],
                      "setup_host_s": st["setup_host_s"], "setup_device_s": st["setup_device_s"],
                      "bytes_per_iter": st["bytes_per_iter"]}

@@ -204,6 +204,8 @@ typedef struct {
     int32_t profile_in_graph;         /* 1: events were replayed inside the
                                          captured graphs; 0: the profiled
                                          solves launched kernels directly   */
+    char    layouts[1024];            /* text: the layout the autotuner chose
+                                         for every matrix, NUL-terminated    */
 } dfamg_stats;
 
 /* Kernel ids of the profile: the outer SpMV with its fused (p,q) and Z^T q

@@ -121,7 +121,8 @@ void tile_offsets(const std::vector<Tile> &tiles, const std::vector<int32_t> &su
 // larger than the LDS budget.
 template <class VT>
 bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, const Layout &L,
-                   hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys, int nsub, DevMat<VT> &D) {
+                   hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys, int nsub, DevMat<VT> &D,
+                   size_t stage_limit = kMaxStageBytes) {
     D = DevMat<VT>{};
     D.fmt = L.fmt;
     D.par = L.par;
@@ -131,7 +132,7 @@ bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &rang
         if (!make_sell(M, ranges, L.par, L.sorted, L.idx16 || L.stage, S)) return false;
         if (L.stage) {
             const int32_t mx = S.cspan.empty() ? 1 : *std::max_element(S.cspan.begin(), S.cspan.end());
-            if ((size_t)mx * sizeof(VT) > kMaxStageBytes) return false;
+            if ((size_t)mx * sizeof(VT) > stage_limit) return false;
             D.max_span = mx;
         }
         D.sorted = L.sorted;
@@ -157,7 +158,7 @@ bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &rang
         HostCsrv C = make_csrv(M, ranges, L.par, L.rpg > 0 ? L.rpg * (kBlock / L.par) : kBlock);
         if (L.stage) {
             const int32_t mx = C.cspan.empty() ? 1 : *std::max_element(C.cspan.begin(), C.cspan.end());
-            if ((size_t)mx * sizeof(VT) > kMaxStageBytes) return false;
+            if ((size_t)mx * sizeof(VT) > stage_limit) return false;
             D.max_span = mx;
             D.stage = true;
         }
@@ -172,11 +173,15 @@ bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &rang
         D.nnz = C.nnz;
         D.stored = C.nnz;
     }
-    D.tiles = ar.upload(to_dev_tiles(tiles), s);
+    D.host_tiles = to_dev_tiles(tiles);
+    D.tiles = ar.upload(D.host_tiles, s);
     D.ntiles = (int32_t)tiles.size();
     tile_offsets(tiles, sub_sys, nsys, nsub, D.sys_tile_off, D.sub_tile_off);
     return true;
 }
+
+template <class VT>
+std::string describe(const DevMat<VT> &D);
 
 // What a matrix is used for, and so which kernel times its candidates.
 enum TuneKind { TUNE_OUTER, TUNE_SMOOTH, TUNE_RESTRICT, TUNE_PROLONG };
@@ -204,16 +209,16 @@ void launch_for_tuning<float>(TuneKind kind, const DevMat<float> &M, const float
     }
 }
 
-// Microseconds per launch of the kernel that will use M.
-template <class VT>
-double time_layout(TuneKind kind, const DevMat<VT> &M, const VT *x, VT *y, hipStream_t s) {
+// Microseconds per call of `launch` (2 untimed calls, then 8 timed).
+template <class F>
+double time_launches(F &&launch, hipStream_t s) {
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
-    for (int i = 0; i < 2; ++i) launch_for_tuning(kind, M, x, y, s);
+    for (int i = 0; i < 2; ++i) launch();
     const int reps = 8;
     HIP_CHECK(hipEventRecord(e0, s));
-    for (int i = 0; i < reps; ++i) launch_for_tuning(kind, M, x, y, s);
+    for (int i = 0; i < reps; ++i) launch();
     HIP_CHECK(hipEventRecord(e1, s));
     HIP_CHECK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -223,42 +228,51 @@ double time_layout(TuneKind kind, const DevMat<VT> &M, const VT *x, VT *y, hipSt
     return ms * 1e3 / reps;
 }
 
+// Microseconds per launch of the kernel that will use M.
+template <class VT>
+double time_layout(TuneKind kind, const DevMat<VT> &M, const VT *x, VT *y, hipStream_t s) {
+    return time_launches([&] { launch_for_tuning(kind, M, x, y, s); }, s);
+}
+
 // Layout of one matrix: the fastest candidate of the family `format` (SELL,
 // CSR, or both with DFAMG_FORMAT_AUTO), timed on the device with the kernel
 // that will use the matrix.  SELL candidates: 1 or 2 rows per lane (2 only
 // while the tiles still fill the chip), natural or length-sorted rows,
 // 16-bit column offsets (32-bit when they do not fit), with or without an LDS
 // stage of the gathered vector; CSR: 4, 8 or 16 lanes per row, staged or
-// not, for rows of 10+ entries.  The global operator keeps unstaged SELL.
+// not, for rows of 10+ entries.  The block-diagonal part of the global
+// operator also tries 4 rows per lane and only 256-row CSR tiles.
+// `timer` (optional) replaces the default timing of a candidate; `verbose`
+// above 1 prints every candidate's time.
 template <class VT>
 DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, int format,
                         bool autotune, TuneKind kind, hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys,
-                        int nsub) {
+                        int nsub, const std::function<double(const DevMat<VT> &)> &timer = {}, int verbose = 0) {
     int64_t rows = 0;
     for (auto &r : ranges) rows += r.nrows;
     const double avg_len = rows ? (double)M.nnz() / (double)rows : 0.0;
     std::vector<Layout> cand;
     const bool outer = kind == TUNE_OUTER;
     if (!autotune) {
-        cand.push_back(format == DFAMG_FORMAT_CSR && !outer ? Layout{DFAMG_FORMAT_CSR, 8, false, false, false, 0}
-                                                            : Layout{DFAMG_FORMAT_SELL, 1, false, false, false, 0});
+        cand.push_back(format == DFAMG_FORMAT_CSR ? Layout{DFAMG_FORMAT_CSR, 8, false, false, false, 0}
+                                                  : Layout{DFAMG_FORMAT_SELL, 1, false, false, false, 0});
     } else {
-        if (format == DFAMG_FORMAT_SELL || format == DFAMG_FORMAT_AUTO || outer) {
+        if (format == DFAMG_FORMAT_SELL || format == DFAMG_FORMAT_AUTO) {
             for (int r : outer ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2}) {
                 if (r > 1 && rows / (256 * r) < 512) continue;
                 for (bool sorted : {false, true}) {
                     if (outer && sorted) continue;
                     cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, false, 0});
-                    if (!outer) cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, true, 0});
+                    if (r <= 2) cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, true, 0});
                 }
             }
         }
-        if (!outer && (format == DFAMG_FORMAT_CSR || format == DFAMG_FORMAT_AUTO) &&
+        if ((format == DFAMG_FORMAT_CSR || format == DFAMG_FORMAT_AUTO) &&
             (avg_len >= 10.0 || format == DFAMG_FORMAT_CSR))
-            for (int l : {4, 8, 16})
+            for (int l : outer ? std::vector<int>{8, 16} : std::vector<int>{4, 8, 16})
                 for (int rpg : {0, 1, 4}) {
                     // smaller tiles only where 256-row tiles leave the chip idle
-                    if (rpg > 0 && rows / 256 >= 2048) continue;
+                    if (rpg > 0 && (outer || rows / 256 >= 2048)) continue;
                     for (bool stage : {false, true})
                         cand.push_back(Layout{DFAMG_FORMAT_CSR, l, false, false, stage, rpg});
                 }
@@ -274,17 +288,22 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     double best = 1e30;
     DevMat<VT> bestM;
     std::unique_ptr<DevArena> bestA;
+    // the outer kernel also keeps its reduction slots in static LDS
+    const size_t stage_limit = outer ? kMaxStageBytes - 512 : kMaxStageBytes;
     for (Layout c : cand) {
         auto A = std::make_unique<DevArena>();
         DevMat<VT> D;
-        if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D)) {
+        if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D, stage_limit)) {
             // 16-bit offsets that do not fit: fall back to 32-bit columns once
             if (c.fmt != DFAMG_FORMAT_SELL || c.stage || !c.idx16) continue;
             c.idx16 = false;
             A = std::make_unique<DevArena>();
-            if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D)) continue;
+            if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D, stage_limit)) continue;
         }
-        const double t = cand.size() > 1 ? time_layout(kind, D, x, y, s) : 0.0;
+        const double t = cand.size() > 1 ? (timer ? timer(D) : time_layout(kind, D, x, y, s)) : 0.0;
+        if (verbose > 1)
+            std::fprintf(stderr, "[dfamg] tune kind %d rows %lld nnz %lld: %s %.2f us\n", (int)kind, (long long)rows,
+                         (long long)M.nnz(), describe(D).c_str(), t);
         if (t < best) {
             best = t;
             bestM = D;
@@ -295,6 +314,72 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     bestM.tuned_us = best;
     ar.adopt(*bestA);
     return bestM;
+}
+
+// Couplings between subdomains of the permuted global operator (host side of
+// OffM): CSR over all rows.
+struct HostOff {
+    std::vector<int32_t> ptr, col;
+    std::vector<double> val;
+};
+
+// Splits the permuted operator into its block-diagonal part (columns inside
+// the row's subdomain; same row and column numbering) and the couplings.
+void split_operator(const Plan &P, Csr &loc, HostOff &off) {
+    loc.nrows = loc.ncols = P.n;
+    loc.ptr.assign(P.n + 1, 0);
+    loc.col.clear();
+    loc.val.clear();
+    loc.col.reserve(P.A.col.size());
+    loc.val.reserve(P.A.val.size());
+    off.ptr.assign(P.n + 1, 0);
+    for (int sub = 0; sub < P.nsub; ++sub) {
+        const int64_t lo = P.sub_row_off[sub], hi = P.sub_row_off[sub + 1];
+        for (int64_t i = lo; i < hi; ++i) {
+            for (int64_t k = P.A.ptr[i]; k < P.A.ptr[i + 1]; ++k) {
+                const int32_t c = P.A.col[k];
+                if (c >= lo && c < hi) {
+                    loc.col.push_back(c);
+                    loc.val.push_back(P.A.val[k]);
+                } else {
+                    off.col.push_back(c);
+                    off.val.push_back(P.A.val[k]);
+                }
+            }
+            loc.ptr[i + 1] = (int64_t)loc.col.size();
+            if (off.col.size() > (size_t)INT32_MAX) throw Error{DFAMG_EINVAL, "too many couplings"};
+            off.ptr[i + 1] = (int32_t)off.col.size();
+        }
+    }
+}
+
+// Device OffM for the tiles of the block-diagonal layout D.
+OffM upload_off(DevArena &ar, const HostOff &off, const DevMat<double> &D, hipStream_t s) {
+    std::vector<int32_t> any(std::max<size_t>(1, D.host_tiles.size()), 0);
+    for (size_t t = 0; t < D.host_tiles.size(); ++t) {
+        const DevTile &T = D.host_tiles[t];
+        any[t] = off.ptr[T.row0 + T.nrows] > off.ptr[T.row0] ? 1 : 0;
+    }
+    OffM o{};
+    o.any = ar.upload(any, s);
+    o.ptr = ar.upload(off.ptr, s);
+    o.col = ar.upload(off.col.empty() ? std::vector<int32_t>{0} : off.col, s);
+    o.val = ar.upload(off.val.empty() ? std::vector<double>{0.0} : off.val, s);
+    return o;
+}
+
+// Short text of a chosen layout, e.g. "sell2/i16/stage" or "csr8/t64".
+template <class VT>
+std::string describe(const DevMat<VT> &D) {
+    std::string t = D.fmt == DFAMG_FORMAT_SELL ? "sell" + std::to_string(D.par) : "csr" + std::to_string(D.par);
+    if (D.fmt == DFAMG_FORMAT_SELL) {
+        t += D.idx16 ? "/i16" : "/i32";
+        if (D.sorted) t += "/sorted";
+    } else if (!D.host_tiles.empty()) {
+        t += "/t" + std::to_string(D.host_tiles[0].nrows);
+    }
+    if (D.stage) t += "/stage";
+    return t;
 }
 
 // Ranges of the packed rows of `subs` at a level.
@@ -447,6 +532,7 @@ struct PrecondBase {
     double bytes = 0.0;                 // algorithmic bytes per application
     double kbytes[KID_N] = {};          // per profiled kernel
     int fmt[20] = {}, par[20] = {};     // chosen layout of A_l
+    std::string layouts;                // chosen layouts, as text
 };
 
 template <class VT>
@@ -500,6 +586,8 @@ struct Hierarchy_dev : PrecondBase {
                     fmt[l] = D.A.fmt;
                     par[l] = D.A.par;
                 }
+                layouts += " L" + std::to_string(l) + "{A " + describe(D.A) + ", R " + describe(D.R) + ", P " +
+                           describe(D.P) + "}";
                 std::vector<VT> m(PL.m.size());
                 for (size_t i = 0; i < m.size(); ++i) m[i] = (VT)PL.m[i];
                 D.m = ar.upload(m, s);
@@ -648,8 +736,11 @@ struct Handle {
     int device = 0;
     DevArena ar;
     std::string err;
-    // outer operator (its tiles carry the SpMV partials)
+    // outer operator: block-diagonal part (its tiles carry the SpMV partials)
+    // and the couplings between subdomains
     DevMat<double> A;
+    OffM offA{};
+    bool outer_split = false;
     int32_t *d_sto_A = nullptr, *d_subto_A = nullptr;
     // row tiles for the vector kernels (update, direction, expansion)
     DevTile *rows = nullptr;
@@ -727,9 +818,50 @@ void Handle::setup_device() {
     std::vector<RowRange> rr;
     for (int sub = 0; sub < nsub; ++sub)
         rr.push_back(RowRange{P.sub_row_off[sub], (int32_t)(P.sub_row_off[sub + 1] - P.sub_row_off[sub]), sub, 0});
-    // outer matrix over all subdomains
-    A = upload_tuned<double>(ar, P.A, rr, prm.spmv_format, prm.autotune != 0, TUNE_OUTER, sm, P.sub_sys, nsys,
-                             nsub);
+    d_sub_sys = ar.upload(P.sub_sys, sm);
+    Z = ar.upload(P.Z, sm);
+    states = ar.alloc<SysState>(nsys);
+    HIP_CHECK(hipMemsetAsync(states, 0, sizeof(SysState) * nsys, sm));
+    // outer matrix over all subdomains, either whole or as block-diagonal part
+    // plus couplings (which lets the layouts use 16-bit columns and LDS
+    // staging); every candidate is timed with the in-loop kernel (couplings
+    // and deflation epilogue included) and the faster form is kept
+    {
+        Csr loc;
+        HostOff off, none;
+        split_operator(P, loc, off);
+        none.ptr.assign(n + 1, 0);
+        DevArena vecs;
+        double *tx = vecs.alloc<double>(n), *ty = vecs.alloc<double>(n);
+        HIP_CHECK(hipMemsetAsync(tx, 0, sizeof(double) * n, sm));
+        auto make_timer = [&](const HostOff &o_) {
+            return std::function<double(const DevMat<double> &)>([&, po = &o_](const DevMat<double> &D) {
+                DevArena tmp;
+                const OffM o = upload_off(tmp, *po, D, sm);
+                double *tp = tmp.alloc<double>((size_t)D.ntiles * (ndv + 1));
+                const double t = time_launches(
+                    [&] { launch_outer(0, ndv, D, o, tx, nullptr, ty, Z, tp, states, d_sub_sys, sm); }, sm);
+                HIP_CHECK(hipStreamSynchronize(sm));
+                return t;
+            });
+        };
+        const bool tune = prm.autotune != 0;
+        DevArena arF, arS;
+        const DevMat<double> AF = upload_tuned<double>(arF, P.A, rr, prm.spmv_format, tune, TUNE_OUTER, sm,
+                                                       P.sub_sys, nsys, nsub, make_timer(none), prm.verbose);
+        bool split = false;
+        DevMat<double> AS;
+        if (tune && !off.col.empty()) {
+            AS = upload_tuned<double>(arS, loc, rr, prm.spmv_format, tune, TUNE_OUTER, sm, P.sub_sys, nsys, nsub,
+                                      make_timer(off), prm.verbose);
+            split = AS.tuned_us < AF.tuned_us;
+        }
+        ar.adopt(split ? arS : arF);
+        A = split ? AS : AF;
+        offA = upload_off(ar, split ? off : none, A, sm);
+        outer_split = split;
+        HIP_CHECK(hipStreamSynchronize(sm));
+    }
     d_sto_A = ar.upload(A.sys_tile_off, sm);
     d_subto_A = ar.upload(A.sub_tile_off, sm);
     // row tiles of 256 rows: one row per thread in the vector kernels
@@ -747,10 +879,8 @@ void Handle::setup_device() {
         d_subto_rows = ar.upload(su, sm);
         HIP_CHECK(hipStreamSynchronize(sm));
     }
-    d_sub_sys = ar.upload(P.sub_sys, sm);
     d_sys_sub_off = ar.upload(P.sys_sub_off, sm);
     d_perm = ar.upload(P.perm, sm);
-    Z = ar.upload(P.Z, sm);
     AZown = ar.upload(P.AZown, sm);
     std::vector<int32_t> offp(P.AZoff.ptr.begin(), P.AZoff.ptr.end());
     AZoffp = ar.upload(offp, sm);
@@ -806,8 +936,6 @@ void Handle::setup_device() {
     }
     part_A = ar.alloc<double>((size_t)A.ntiles * (ndv + 1));
     part_rows = ar.alloc<double>((size_t)nrow_tiles * std::max(ndv + 1, 2));
-    states = ar.alloc<SysState>(nsys);
-    HIP_CHECK(hipMemsetAsync(states, 0, sizeof(SysState) * nsys, sm));
     HIP_CHECK(hipHostMalloc((void **)&h_states, sizeof(SysState) * nsys, hipHostMallocDefault));
     hist_stride = prm.maxiter + 1;
     hist = ar.alloc<double>((size_t)nsys * hist_stride);
@@ -897,7 +1025,7 @@ bool Handle::probe_graph_events() {
 // Outer SpMV launch with the epilogue of `mode` (see k_outer).
 void Handle::outer(int mode, hipStream_t st, const double *xin, const double *bin, double *out, bool profiled) {
     if (profiled) prof.mark(KID_SPMV, 0, st);
-    launch_outer(mode, ndv(), A, xin, bin, out, Z, part_A, states, d_sub_sys, st);
+    launch_outer(mode, ndv(), A, offA, xin, bin, out, Z, part_A, states, d_sub_sys, st);
     if (profiled) prof.mark(KID_SPMV, 1, st);
 }
 
@@ -1382,6 +1510,11 @@ dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *o) {
         }
     }
     o->format_outer = H.A.fmt;
+    {
+        const std::string t = "outer " + describe(H.A) + (H.outer_split ? "+couplings" : "") +
+                              (H.M ? ";" + H.M->layouts : std::string());
+        std::snprintf(o->layouts, sizeof(o->layouts), "%s", t.c_str());
+    }
     o->setup_host_s = P.host_seconds;
     o->setup_device_s = H.setup_device_s;
     o->solve_s = H.solve_s;

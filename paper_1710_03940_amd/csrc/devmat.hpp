@@ -42,21 +42,21 @@ struct DevMat {
     double tuned_us = 0.0;
     std::vector<int32_t> sys_tile_off;  // host: tiles of each system
     std::vector<int32_t> sub_tile_off;  // host: tiles of each subdomain
+    std::vector<DevTile> host_tiles;    // host copy of `tiles`
     size_t stage_bytes() const { return stage ? (size_t)max_span * sizeof(VT) : 0; }
 };
 
 // Largest LDS window (bytes) a staged layout may use per block.
 constexpr size_t kMaxStageBytes = 65536;
 
-// Calls fn(view) with the kernel view type of M.  OUTER restricts the set to
-// the unstaged SELL layouts (used for the global operator).
-template <bool OUTER, class VT, class Fn>
+// Calls fn(view) with the kernel view type of M.
+template <class VT, class Fn>
 void with_mat(const DevMat<VT> &M, Fn &&fn) {
 #define DFAMG_SELL(R, I, S) \
     fn(SellM<VT, R, I, S>{M.tiles, M.soff, M.sw, M.col, M.col16, M.cbase, M.cspan, M.ridx, M.val, M.ntiles})
 #define DFAMG_CSR(L, S) fn(CsrM<VT, L, S>{M.tiles, M.ptr, M.col, M.cbase, M.cspan, M.val, M.ntiles})
     if (M.fmt == DFAMG_FORMAT_SELL) {
-        if (OUTER || !M.stage) {
+        if (!M.stage) {
             if (M.idx16) {
                 switch (M.par) {
                     case 1: DFAMG_SELL(1, true, false); return;
@@ -70,13 +70,13 @@ void with_mat(const DevMat<VT> &M, Fn &&fn) {
                     case 4: DFAMG_SELL(4, false, false); return;
                 }
             }
-        } else if constexpr (!OUTER) {
+        } else {
             switch (M.par) {
                 case 1: DFAMG_SELL(1, true, true); return;
                 case 2: DFAMG_SELL(2, true, true); return;
             }
         }
-    } else if constexpr (!OUTER) {
+    } else {
         if (M.stage) {
             switch (M.par) {
                 case 4: DFAMG_CSR(4, true); return;
@@ -112,8 +112,10 @@ void launch_post(const DevMat<VT> &A, const VT *m, const FT *f, const VT *z, OT 
                  const SysState *st, const int32_t *sub_sys, hipStream_t s);
 
 // ---- outer operator (launch_outer.hip) -----------------------------------
-void launch_outer(int mode, int ndv, const DevMat<double> &A, const double *x, const double *b, double *out,
-                  const double *Z, double *part, const SysState *st, const int32_t *sub_sys, hipStream_t s);
+// A: block-diagonal part, off: couplings between subdomains (see OffM).
+void launch_outer(int mode, int ndv, const DevMat<double> &A, const OffM &off, const double *x, const double *b,
+                  double *out, const double *Z, double *part, const SysState *st, const int32_t *sub_sys,
+                  hipStream_t s);
 void launch_outer_spmv_plain(const DevMat<double> &A, const double *x, double *y, hipStream_t s);
 
 }  // namespace dfamg

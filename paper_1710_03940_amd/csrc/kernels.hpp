@@ -249,17 +249,32 @@ __device__ __forceinline__ double wave_range_sum(const double *__restrict__ a, i
 // outer operator and deflation
 // ---------------------------------------------------------------------------
 
+// The global operator is stored as its block-diagonal part (columns inside
+// the row's subdomain, held in one of the layouts above, which can then use
+// 16-bit column offsets and LDS staging) plus the couplings between
+// subdomains in CSR over all rows (ptr has n + 1 entries); any[t] is nonzero
+// when tile t of the block-diagonal layout has a coupled row, so the other
+// tiles skip the pointer reads.
+struct OffM {
+    const int32_t *any;
+    const int32_t *ptr;
+    const int32_t *col;
+    const double *val;
+};
+
 // Epilogue partials per tile, slot-major: part[q * nslots + slot]
 //   MODE 0: q = A p;     partials (p,q), Z^T q              (CG operator product)
 //   MODE 1: w = b - A y; partials (b,b), Z^T w              (initial / final residual)
 //   MODE 2: w = b - A x; partial (w,w)                      (true residual)
 //   MODE 3: q = A p;     partials Z^T q, skip when stopped  (BiCGStab operator product)
 //   MODE 4: q = A p;     no partials, no stop check         (plain product)
+// The thread that forms a row's block-diagonal sum adds the row's couplings.
 template <int MODE, int NDV, class MAT>
-__global__ void __launch_bounds__(kBlock) k_outer(MAT A, const double *__restrict__ x, const double *__restrict__ b,
-                                                  double *__restrict__ out, const double *__restrict__ Z, int ndv_rt,
-                                                  double *__restrict__ part, int32_t nslots,
-                                                  const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+__global__ void __launch_bounds__(kBlock) k_outer(MAT A, OffM off, const double *__restrict__ x,
+                                                  const double *__restrict__ b, double *__restrict__ out,
+                                                  const double *__restrict__ Z, int ndv_rt, double *__restrict__ part,
+                                                  int32_t nslots, const SysState *__restrict__ st,
+                                                  const int32_t *__restrict__ sub_sys) {
     __shared__ double lds[(kMaxNdv + 1) * 4];
     const int ndv = ndv_rt;   // <= NDV, the unroll bound
     const int tile = tile_of_block(A.ntiles);
@@ -270,7 +285,24 @@ __global__ void __launch_bounds__(kBlock) k_outer(MAT A, const double *__restric
     double zq[NDV > 0 ? NDV : 1];
 #pragma unroll
     for (int k = 0; k < NDV; ++k) zq[k] = 0.0;
-    for_rows<double>(A, tile, T, [&](int c) { return x[c]; }, [&](int row, double ax) {
+    const bool coupled = off.any[tile] != 0;
+    auto finish_row = [&](int row, double ax) {
+        if (coupled) {
+            int e = off.ptr[row];
+            const int e1 = off.ptr[row + 1];
+            for (; e + 4 <= e1; e += 4) {   // four independent gathers in flight
+                int c[4];
+                double v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    c[u] = off.col[e + u];
+                    v[u] = off.val[e + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) ax += v[u] * x[c[u]];
+            }
+            for (; e < e1; ++e) ax += off.val[e] * x[off.col[e]];
+        }
         double v;
         if (MODE == 0 || MODE == 3 || MODE == 4) {
             v = ax;
@@ -286,7 +318,8 @@ __global__ void __launch_bounds__(kBlock) k_outer(MAT A, const double *__restric
             for (int k = 0; k < NDV; ++k)
                 if (k < ndv) zq[k] += Z[(int64_t)row * ndv + k] * v;
         }
-    });
+    };
+    for_rows<double>(A, tile, T, [&](int c) { return x[c]; }, finish_row);
     if (MODE == 4) return;
     const int t = threadIdx.x, w = t >> 6;
     const int nq = (MODE == 2) ? 1 : ndv + 1;

@@ -8,7 +8,7 @@ namespace dfamg {
 template <class VT, class FT>
 void launch_pre_res(const DevMat<VT> &A, const VT *m, const FT *f, VT *res, const SysState *st,
                     const int32_t *sub_sys, hipStream_t s) {
-    with_mat<false>(A, [&](auto v) {
+    with_mat(A, [&](auto v) {
         hipLaunchKernelGGL((k_pre_res<VT, FT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
                            A.stage_bytes(), s, v, m, f, res, st, sub_sys);
     });
@@ -17,7 +17,7 @@ void launch_pre_res(const DevMat<VT> &A, const VT *m, const FT *f, VT *res, cons
 template <class VT>
 void launch_spmv(const DevMat<VT> &M, const VT *x, VT *y, const SysState *st, const int32_t *sub_sys,
                  hipStream_t s) {
-    with_mat<false>(M, [&](auto v) {
+    with_mat(M, [&](auto v) {
         hipLaunchKernelGGL((k_spmv<VT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock), M.stage_bytes(),
                            s, v, x, y, st, sub_sys);
     });
@@ -26,7 +26,7 @@ void launch_spmv(const DevMat<VT> &M, const VT *x, VT *y, const SysState *st, co
 template <class VT, class FT>
 void launch_prolong(const DevMat<VT> &P, const VT *m, const FT *f, const VT *xc, VT *z, const SysState *st,
                     const int32_t *sub_sys, hipStream_t s) {
-    with_mat<false>(P, [&](auto v) {
+    with_mat(P, [&](auto v) {
         hipLaunchKernelGGL((k_prolong<VT, FT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
                            P.stage_bytes(), s, v, m, f, xc, z, st, sub_sys);
     });
@@ -35,7 +35,7 @@ void launch_prolong(const DevMat<VT> &P, const VT *m, const FT *f, const VT *xc,
 template <class VT, class FT, class OT, bool DOT>
 void launch_post(const DevMat<VT> &A, const VT *m, const FT *f, const VT *z, OT *x, double *part,
                  const SysState *st, const int32_t *sub_sys, hipStream_t s) {
-    with_mat<false>(A, [&](auto v) {
+    with_mat(A, [&](auto v) {
         hipLaunchKernelGGL((k_post<VT, FT, OT, DOT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
                            A.stage_bytes(), s, v, m, f, z, x, part, st, sub_sys);
     });
