@@ -9,8 +9,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "dfamg.h"
@@ -242,6 +246,44 @@ double time_layout(TuneKind kind, const DevMat<VT> &M, const VT *x, VT *y, hipSt
 // stage of the gathered vector; CSR: 4, 8 or 16 lanes per row, staged or
 // not, for rows of 10+ entries.  The block-diagonal part of the global
 // operator also tries 4 rows per lane and only 256-row CSR tiles.
+// Process-wide record of tuned layouts.
+struct TuneKey {
+    int kind, vt, format;
+    uint64_t hash;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(kind, vt, format, hash) < std::tie(o.kind, o.vt, o.format, o.hash);
+    }
+};
+std::map<TuneKey, std::pair<Layout, double>> &tune_cache() {
+    static std::map<TuneKey, std::pair<Layout, double>> c;
+    return c;
+}
+std::mutex &tune_cache_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+// Hash of the row ranges, row lengths and columns of the rows covered
+// (64-bit multiply-xorshift per word).
+uint64_t structure_hash(const Csr &M, const std::vector<RowRange> &ranges) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        h = (h ^ v) * 0x9e3779b97f4a7c15ull;
+        h ^= h >> 29;
+    };
+    mix((uint64_t)M.nrows);
+    mix((uint64_t)M.ncols);
+    for (const RowRange &r : ranges) {
+        mix((uint64_t)r.row0);
+        mix((uint64_t)r.nrows);
+        for (int64_t i = r.row0; i < r.row0 + r.nrows; ++i) {
+            mix((uint64_t)(M.ptr[i + 1] - M.ptr[i]));
+            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) mix((uint64_t)(uint32_t)M.col[k]);
+        }
+    }
+    return h;
+}
+
 // `timer` (optional) replaces the default timing of a candidate; `verbose`
 // above 1 prints every candidate's time.
 template <class VT>
@@ -261,7 +303,6 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
             for (int r : outer ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2}) {
                 if (r > 1 && rows / (256 * r) < 512) continue;
                 for (bool sorted : {false, true}) {
-                    if (outer && sorted) continue;
                     cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, false, 0});
                     if (r <= 2) cand.push_back(Layout{DFAMG_FORMAT_SELL, r, sorted, true, true, 0});
                 }
@@ -271,11 +312,24 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
             (avg_len >= 10.0 || format == DFAMG_FORMAT_CSR))
             for (int l : outer ? std::vector<int>{8, 16} : std::vector<int>{4, 8, 16})
                 for (int rpg : {0, 1, 4}) {
-                    // smaller tiles only where 256-row tiles leave the chip idle
-                    if (rpg > 0 && (outer || rows / 256 >= 2048)) continue;
+                    // smaller tiles where 256-row tiles leave the chip idle, and
+                    // for restrictions (long rows gathering from a wide window)
+                    if (rpg > 0 && (outer || (rows / 256 >= 2048 && kind != TUNE_RESTRICT))) continue;
                     for (bool stage : {false, true})
                         cand.push_back(Layout{DFAMG_FORMAT_CSR, l, false, false, stage, rpg});
                 }
+    }
+    // a matrix tuned before in this process (same kind, value type, family and
+    // structure) gets the layout chosen then, without timing
+    const TuneKey key{(int)kind, (int)sizeof(VT), format, structure_hash(M, ranges)};
+    double cached_us = -1.0;
+    if (cand.size() > 1) {
+        std::lock_guard<std::mutex> g(tune_cache_mutex());
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            cand.assign(1, it->second.first);
+            cached_us = it->second.second;
+        }
     }
     DevArena scratch;
     VT *x = scratch.alloc<VT>(std::max<int64_t>(1, std::max(M.ncols, M.nrows)));
@@ -287,6 +341,7 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     }
     double best = 1e30;
     DevMat<VT> bestM;
+    Layout bestL{};
     std::unique_ptr<DevArena> bestA;
     // the outer kernel also keeps its reduction slots in static LDS
     const size_t stage_limit = outer ? kMaxStageBytes - 512 : kMaxStageBytes;
@@ -300,7 +355,9 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
             A = std::make_unique<DevArena>();
             if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D, stage_limit)) continue;
         }
-        const double t = cand.size() > 1 ? (timer ? timer(D) : time_layout(kind, D, x, y, s)) : 0.0;
+        const double t = cached_us >= 0.0 ? cached_us
+                         : cand.size() > 1 ? (timer ? timer(D) : time_layout(kind, D, x, y, s))
+                                           : 0.0;
         if (verbose > 1)
             std::fprintf(stderr, "[dfamg] tune kind %d rows %lld nnz %lld: %s %.2f us\n", (int)kind, (long long)rows,
                          (long long)M.nnz(), describe(D).c_str(), t);
@@ -308,7 +365,12 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
             best = t;
             bestM = D;
             bestA = std::move(A);
+            bestL = c;
         }
+    }
+    if (bestA && cand.size() > 1) {
+        std::lock_guard<std::mutex> g(tune_cache_mutex());
+        tune_cache()[key] = {bestL, best};
     }
     if (!bestA) throw Error{DFAMG_EINVAL, "no sparse layout can hold a matrix"};
     bestM.tuned_us = best;
