@@ -457,7 +457,7 @@ std::vector<RowRange> ranges_of(const PackedLevel &L, const std::vector<int32_t>
 // matrix or -1.
 template <class VT>
 int invert_on_device(hipStream_t s, const std::vector<const double *> &mats, const std::vector<int32_t> &ns,
-                     VT *out, const std::vector<int64_t> &out_off, bool transposed) {
+                     VT *out, const std::vector<int64_t> &out_off, const std::vector<int32_t> &out_ld) {
     const int nb = (int)mats.size();
     if (nb == 0) return -1;
     std::vector<InvJob> jobs(nb);
@@ -485,14 +485,14 @@ int invert_on_device(hipStream_t s, const std::vector<const double *> &mats, con
     int64_t *d_coff = tmp.upload(col_off, s);
     double *d_colk = tmp.alloc<double>(col_off[nb]);
     int64_t *d_oof = tmp.upload(out_off, s);
+    int32_t *d_old = tmp.upload(out_ld, s);
     const int64_t maxel = (int64_t)nmax * 2 * nmax;
     const int gx = (int)std::min<int64_t>(1024, (maxel + kBlock - 1) / kBlock);
     for (int k = 0; k < nmax; ++k) {
         hipLaunchKernelGGL(k_gj_pivot, dim3(nb), dim3(kBlock), 0, s, d_jobs, d_aug, d_colk, d_coff, k);
         hipLaunchKernelGGL(k_gj_eliminate, dim3(gx, nb), dim3(kBlock), 0, s, d_jobs, d_aug, d_colk, d_coff, k);
     }
-    hipLaunchKernelGGL(k_gj_extract<VT>, dim3(gx, nb), dim3(kBlock), 0, s, d_jobs, d_aug, d_oof, out,
-                       transposed ? 1 : 0);
+    hipLaunchKernelGGL(k_gj_extract<VT>, dim3(gx, nb), dim3(kBlock), 0, s, d_jobs, d_aug, d_oof, d_old, out);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipMemcpyAsync(jobs.data(), d_jobs, nb * sizeof(InvJob), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -676,27 +676,29 @@ struct Hierarchy_dev : PrecondBase {
             if (!PL.coarse_subs.empty()) {
                 std::vector<CoarseEntry> ce;
                 std::vector<std::vector<double>> dense;
-                std::vector<int32_t> ns;
+                std::vector<int32_t> ns, lds;
                 std::vector<int64_t> off;
                 int64_t total = 0;
+                constexpr int nv = 16 / (int)sizeof(VT);
                 for (int32_t sub : PL.coarse_subs) {
                     const Csr &M = plan.hier[sub].lv.back().A;
-                    const int n = (int)M.nrows;
+                    const int n = (int)M.nrows, ld = (n + nv - 1) / nv * nv;
                     std::vector<double> d((size_t)n * n, 0.0);
                     for (int i = 0; i < n; ++i)
                         for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) d[(size_t)i * n + M.col[k]] = M.val[k];
                     dense.push_back(std::move(d));
                     ns.push_back(n);
+                    lds.push_back(ld);
                     off.push_back(total);
-                    ce.push_back(CoarseEntry{sub, n, PL.sub_off[sub], total});
-                    total += (int64_t)n * n;
+                    ce.push_back(CoarseEntry{sub, n, PL.sub_off[sub], total, ld, 0});
+                    total += (int64_t)n * ld;
                 }
-                // one block per 4 rows of every coarsest matrix, in subdomain
-                // (hence system) order
+                // one block per kCoarseRows rows of every coarsest matrix, in
+                // subdomain (hence system) order
                 std::vector<CoarseJob> cj;
                 std::vector<int32_t> sjo(plan.nsys + 1, 0);
                 for (size_t e = 0; e < ce.size(); ++e)
-                    for (int r0 = 0; r0 < ce[e].n; r0 += 4) {
+                    for (int r0 = 0; r0 < ce[e].n; r0 += kCoarseRows) {
                         cj.push_back(CoarseJob{(int32_t)e, r0});
                         sjo[plan.sub_sys[ce[e].sub] + 1]++;
                     }
@@ -710,7 +712,7 @@ struct Hierarchy_dev : PrecondBase {
                 std::vector<const double *> mats;
                 for (auto &d : dense) mats.push_back(d.data());
                 D.coarse_inv = ar.alloc<VT>(total);
-                const int bad = invert_on_device<VT>(s, mats, ns, D.coarse_inv, off, false);
+                const int bad = invert_on_device<VT>(s, mats, ns, D.coarse_inv, off, lds);
                 if (bad >= 0)
                     throw Error{DFAMG_ESINGULAR, "coarsest-level matrix of subdomain " +
                                                      std::to_string(plan.sub_user[PL.coarse_subs[bad]]) +
@@ -718,7 +720,9 @@ struct Hierarchy_dev : PrecondBase {
                 D.coarse = ar.upload(ce, s);
                 D.ncoarse = (int32_t)ce.size();
                 HIP_CHECK(hipStreamSynchronize(s));
-                const double cb = total * sv + 2.0 * PL.nrows * sv;
+                double nsq = 0.0;
+                for (int nn : ns) nsq += (double)nn * nn;
+                const double cb = nsq * sv + 2.0 * PL.nrows * sv;
                 bytes += cb;
                 if (l > 0) kbytes[KID_COARSER] += cb;
             }
@@ -976,7 +980,7 @@ void Handle::setup_device() {
             ns.push_back(P.sys_m[sy]);
             off.push_back(P.sys_E_off[sy]);
         }
-        const int bad = invert_on_device<double>(sm, mats, ns, EinvT, off, false);
+        const int bad = invert_on_device<double>(sm, mats, ns, EinvT, off, ns);
         if (bad >= 0)
             throw Error{DFAMG_ESINGULAR, "E = Z^T A Z of system " + std::to_string(bad) + " is singular"};
     }

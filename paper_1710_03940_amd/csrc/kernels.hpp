@@ -880,42 +880,80 @@ __global__ void __launch_bounds__(kBlock) k_post(MAT A, const VT *__restrict__ m
 struct CoarseEntry {
     int32_t sub, n;
     int64_t off;      // first row in the level's packed vectors
-    int64_t inv_off;  // offset of the n x n row-major inverse
+    int64_t inv_off;  // offset of the row-major inverse (n rows of ld entries)
+    int32_t ld;       // row stride: n rounded up to a 16-byte multiple, zero padded
+    int32_t pad;
 };
+
+constexpr int kCoarseRowsPerWave = 4;
+constexpr int kCoarseRows = kCoarseRowsPerWave * (kBlock / kWave);   // rows per block
 
 struct CoarseJob {
     int32_t entry;    // index into the CoarseEntry table
-    int32_t row0;     // first of the block's 4 rows
+    int32_t row0;     // first of the block's kCoarseRows rows
 };
 
+template <class VT>
+struct Vec16;   // 16-byte vector of VT
+template <>
+struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int N = 4;
+};
+template <>
+struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int N = 2;
+};
+
+// x = A_c^{-1} f on the coarsest level of every listed subdomain: each
+// wavefront takes kCoarseRowsPerWave rows of the inverse and reads them as
+// 16-byte vectors (the lanes of a wavefront cover 1 KB of a row per step),
+// the right-hand side chunk being shared by the rows; DOT leaves the
+// partial (f, x) of the block's rows.
 template <class VT, class FT, class OT, bool DOT>
 __global__ void __launch_bounds__(kBlock) k_coarse(const CoarseJob *__restrict__ jobs, const CoarseEntry *__restrict__ ent,
                                                    const VT *__restrict__ inv, const FT *__restrict__ f,
                                                    OT *__restrict__ x, double *__restrict__ part_job,
                                                    const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    using V = typename Vec16<VT>::type;
+    constexpr int NV = Vec16<VT>::N;
+    constexpr int R = kCoarseRowsPerWave;
     __shared__ double red[4];
     const CoarseJob J = jobs[blockIdx.x];
     const CoarseEntry E = ent[J.entry];
     if (st[sub_sys[E.sub]].done) return;
-    const int n = E.n, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = J.row0 + w;
-    double d = 0.0;
-    if (i < n) {
-        const VT *row = inv + E.inv_off + (int64_t)i * n;
-        const FT *fl = f + E.off;
-        VT a0 = 0, a1 = 0;
-        int j = lane;
-        for (; j + 64 < n; j += 128) {
-            a0 += row[j] * (VT)fl[j];
-            a1 += row[j + 64] * (VT)fl[j + 64];
+    const int n = E.n, ld = E.ld, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i0 = J.row0 + w * R;
+    const FT *fl = f + E.off;
+    const V *rows[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        rows[r] = reinterpret_cast<const V *>(inv + E.inv_off + (int64_t)min(i0 + r, n - 1) * ld);
+    VT acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0;
+    for (int j = lane * NV; j < n; j += 64 * NV) {
+        VT fv[NV];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) fv[u] = j + u < n ? (VT)fl[j + u] : (VT)0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const V a = __builtin_nontemporal_load(rows[r] + j / NV);
+#pragma unroll
+            for (int u = 0; u < NV; ++u) acc[r] += a[u] * fv[u];
         }
-        if (j < n) a0 += row[j] * (VT)fl[j];
-        VT a = a0 + a1;
+    }
+    double d = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        VT a = acc[r];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, kWave);
-        if (lane == 0) {
+        const int i = i0 + r;
+        if (lane == 0 && i < n) {
             x[E.off + i] = (OT)a;
-            if (DOT) d = (double)fl[i] * (double)(OT)a;
+            if (DOT) d += (double)fl[i] * (double)(OT)a;
         }
     }
     if (!DOT) return;
@@ -1064,16 +1102,15 @@ static __global__ void __launch_bounds__(kBlock) k_gj_eliminate(const InvJob *__
 // Copy the inverse (right half) out in type VT, transposed or row-major.
 template <class VT>
 __global__ void k_gj_extract(const InvJob *__restrict__ jobs, const double *__restrict__ aug,
-                             const int64_t *__restrict__ out_off, VT *__restrict__ out, int transposed) {
+                             const int64_t *__restrict__ out_off, const int32_t *__restrict__ out_ld,
+                             VT *__restrict__ out) {
     const InvJob J = jobs[blockIdx.y];
-    const int n = J.n;
+    const int n = J.n, ld = out_ld[blockIdx.y];
     const double *A = aug + J.aug_off;
     VT *O = out + out_off[blockIdx.y];
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < (int64_t)n * n; e += (int64_t)gridDim.x * kBlock) {
-        const int i = (int)(e / n), j = (int)(e % n);
-        const VT v = (VT)A[(int64_t)i * 2 * n + n + j];
-        if (transposed) O[(int64_t)j * n + i] = v;
-        else O[(int64_t)i * n + j] = v;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < (int64_t)n * ld; e += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(e / ld), j = (int)(e % ld);
+        O[e] = j < n ? (VT)A[(int64_t)i * 2 * n + n + j] : (VT)0;
     }
 }
 
