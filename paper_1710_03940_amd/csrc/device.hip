@@ -15,6 +15,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <unordered_map>
 #include <vector>
 
 #include "dfamg.h"
@@ -415,6 +416,45 @@ void split_operator(const Plan &P, Csr &loc, HostOff &off) {
     }
 }
 
+// Dictionary coding of the deflation blocks (see ZView): per subdomain and
+// column the distinct values in first-appearance order and a byte per entry.
+struct ZCodes {
+    std::vector<uint8_t> code;
+    std::vector<double> tab;
+    std::vector<int32_t> tab_off;
+};
+
+bool code_deflation(const Plan &P, ZCodes &zc) {
+    const int ndv = P.ndv;
+    zc.code.assign((size_t)P.n * ndv, 0);
+    zc.tab_off.assign((size_t)P.nsub * ndv, 0);
+    for (int s = 0; s < P.nsub; ++s)
+        for (int k = 0; k < ndv; ++k) {
+            zc.tab_off[(size_t)s * ndv + k] = (int32_t)zc.tab.size();
+            std::vector<double> vals;
+            std::unordered_map<uint64_t, int> seen;   // keyed by the bit pattern (-0.0 != 0.0)
+            for (int64_t i = P.sub_row_off[s]; i < P.sub_row_off[s + 1]; ++i) {
+                const double v = P.Z[(size_t)i * ndv + k];
+                uint64_t bits;
+                std::memcpy(&bits, &v, sizeof bits);
+                auto it = seen.find(bits);
+                int c;
+                if (it == seen.end()) {
+                    if (vals.size() == 256) return false;
+                    c = (int)vals.size();
+                    seen.emplace(bits, c);
+                    vals.push_back(v);
+                } else {
+                    c = it->second;
+                }
+                zc.code[(size_t)i * ndv + k] = (uint8_t)c;
+            }
+            zc.tab.insert(zc.tab.end(), vals.begin(), vals.end());
+            if (zc.tab.size() > (size_t)INT32_MAX) return false;
+        }
+    return true;
+}
+
 // Device OffM for the tiles of the block-diagonal layout D.
 OffM upload_off(DevArena &ar, const HostOff &off, const DevMat<double> &D, hipStream_t s) {
     std::vector<int32_t> any(std::max<size_t>(1, D.host_tiles.size()), 0);
@@ -806,6 +846,7 @@ struct Handle {
     // and the couplings between subdomains
     DevMat<double> A;
     OffM offA{};
+    ZView zview{};                          // Z as the operator epilogue reads it
     bool outer_split = false;
     int32_t *d_sto_A = nullptr, *d_subto_A = nullptr;
     // row tiles for the vector kernels (update, direction, expansion)
@@ -886,6 +927,15 @@ void Handle::setup_device() {
         rr.push_back(RowRange{P.sub_row_off[sub], (int32_t)(P.sub_row_off[sub + 1] - P.sub_row_off[sub]), sub, 0});
     d_sub_sys = ar.upload(P.sub_sys, sm);
     Z = ar.upload(P.Z, sm);
+    zview = ZView{Z, nullptr, nullptr, nullptr};
+    {
+        ZCodes zc;
+        if (ndv > 0 && code_deflation(P, zc)) {
+            zview.code = ar.upload(zc.code, sm);
+            zview.tab = ar.upload(zc.tab, sm);
+            zview.tab_off = ar.upload(zc.tab_off, sm);
+        }
+    }
     states = ar.alloc<SysState>(nsys);
     HIP_CHECK(hipMemsetAsync(states, 0, sizeof(SysState) * nsys, sm));
     // outer matrix over all subdomains, either whole or as block-diagonal part
@@ -906,7 +956,7 @@ void Handle::setup_device() {
                 const OffM o = upload_off(tmp, *po, D, sm);
                 double *tp = tmp.alloc<double>((size_t)D.ntiles * (ndv + 1));
                 const double t = time_launches(
-                    [&] { launch_outer(0, ndv, D, o, tx, nullptr, ty, Z, tp, states, d_sub_sys, sm); }, sm);
+                    [&] { launch_outer(0, ndv, D, o, tx, nullptr, ty, zview, tp, states, d_sub_sys, sm); }, sm);
                 HIP_CHECK(hipStreamSynchronize(sm));
                 return t;
             });
@@ -1091,7 +1141,7 @@ bool Handle::probe_graph_events() {
 // Outer SpMV launch with the epilogue of `mode` (see k_outer).
 void Handle::outer(int mode, hipStream_t st, const double *xin, const double *bin, double *out, bool profiled) {
     if (profiled) prof.mark(KID_SPMV, 0, st);
-    launch_outer(mode, ndv(), A, offA, xin, bin, out, Z, part_A, states, d_sub_sys, st);
+    launch_outer(mode, ndv(), A, offA, xin, bin, out, zview, part_A, states, d_sub_sys, st);
     if (profiled) prof.mark(KID_SPMV, 1, st);
 }
 

@@ -114,7 +114,7 @@ void launch_post(const DevMat<VT> &A, const VT *m, const FT *f, const VT *z, OT 
 // ---- outer operator (launch_outer.hip) -----------------------------------
 // A: block-diagonal part, off: couplings between subdomains (see OffM).
 void launch_outer(int mode, int ndv, const DevMat<double> &A, const OffM &off, const double *x, const double *b,
-                  double *out, const double *Z, double *part, const SysState *st, const int32_t *sub_sys,
+                  double *out, const ZView &Z, double *part, const SysState *st, const int32_t *sub_sys,
                   hipStream_t s);
 void launch_outer_spmv_plain(const DevMat<double> &A, const double *x, double *y, hipStream_t s);
 

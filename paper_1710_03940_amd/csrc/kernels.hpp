@@ -269,10 +269,22 @@ struct OffM {
 //   MODE 3: q = A p;     partials Z^T q, skip when stopped  (BiCGStab operator product)
 //   MODE 4: q = A p;     no partials, no stop check         (plain product)
 // The thread that forms a row's block-diagonal sum adds the row's couplings.
+// Deflation vectors as the operator epilogue reads them: row-major FP64 (z),
+// or, when every column of every subdomain block takes at most 256 distinct
+// values (constant, linear and indicator vectors on structured grids), one
+// byte per entry that indexes the block's table of those values -- the same
+// FP64 numbers in an eighth of the bytes.
+struct ZView {
+    const double *z;
+    const uint8_t *code;      // null: read z
+    const double *tab;
+    const int32_t *tab_off;   // per (subdomain, column): first table entry
+};
+
 template <int MODE, int NDV, class MAT>
 __global__ void __launch_bounds__(kBlock) k_outer(MAT A, OffM off, const double *__restrict__ x,
                                                   const double *__restrict__ b, double *__restrict__ out,
-                                                  const double *__restrict__ Z, int ndv_rt, double *__restrict__ part,
+                                                  ZView Zv, int ndv_rt, double *__restrict__ part,
                                                   int32_t nslots, const SysState *__restrict__ st,
                                                   const int32_t *__restrict__ sub_sys) {
     __shared__ double lds[(kMaxNdv + 1) * 4];
@@ -283,8 +295,13 @@ __global__ void __launch_bounds__(kBlock) k_outer(MAT A, OffM off, const double 
     if ((MODE == 0 || MODE == 3) && st[sub_sys[T.sub]].done) return;
     double d0 = 0.0;
     double zq[NDV > 0 ? NDV : 1];
+    const double *ztab[NDV > 0 ? NDV : 1];
+    const bool coded = Zv.code != nullptr;
 #pragma unroll
-    for (int k = 0; k < NDV; ++k) zq[k] = 0.0;
+    for (int k = 0; k < NDV; ++k) {
+        zq[k] = 0.0;
+        ztab[k] = (coded && k < ndv) ? Zv.tab + Zv.tab_off[T.sub * ndv + k] : nullptr;
+    }
     const bool coupled = off.any[tile] != 0;
     auto finish_row = [&](int row, double ax) {
         if (coupled) {
@@ -314,9 +331,19 @@ __global__ void __launch_bounds__(kBlock) k_outer(MAT A, OffM off, const double 
         }
         out[row] = v;
         if (MODE == 0 || MODE == 1 || MODE == 3) {
+            if (coded && NDV == 4 && ndv == 4) {
+                const uint32_t c4 = *reinterpret_cast<const uint32_t *>(Zv.code + (int64_t)row * 4);
 #pragma unroll
-            for (int k = 0; k < NDV; ++k)
-                if (k < ndv) zq[k] += Z[(int64_t)row * ndv + k] * v;
+                for (int k = 0; k < NDV; ++k) zq[k] += ztab[k][(c4 >> (8 * k)) & 0xff] * v;
+            } else if (coded) {
+#pragma unroll
+                for (int k = 0; k < NDV; ++k)
+                    if (k < ndv) zq[k] += ztab[k][Zv.code[(int64_t)row * ndv + k]] * v;
+            } else {
+#pragma unroll
+                for (int k = 0; k < NDV; ++k)
+                    if (k < ndv) zq[k] += Zv.z[(int64_t)row * ndv + k] * v;
+            }
         }
     };
     for_rows<double>(A, tile, T, [&](int c) { return x[c]; }, finish_row);

@@ -27,7 +27,7 @@ void with_ndv(int ndv, Fn &&fn) {
 }  // namespace
 
 void launch_outer(int mode, int ndv, const DevMat<double> &A, const OffM &off, const double *x, const double *b,
-                  double *out, const double *Z, double *part, const SysState *st, const int32_t *sub_sys,
+                  double *out, const ZView &Z, double *part, const SysState *st, const int32_t *sub_sys,
                   hipStream_t s) {
     with_mat(A, [&](auto v) {
         with_ndv(ndv, [&](auto nd_c) {

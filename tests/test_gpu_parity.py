@@ -230,3 +230,16 @@ def test_other_deflation_counts(ndv):
     P2 = P.__class__(P.name, P.A, P.part, P.nsub, np.ascontiguousarray(Zx), P.b, P.x0)
     ref, out = _solve_pair(P2, dict(coarse_enough=30), dict(coarse_enough=30))
     _assert_parity(ref, out)
+
+
+def test_general_deflation_vectors():
+    # deflation columns with more than 256 distinct values per subdomain
+    # (the operator epilogue then reads Z as plain FP64 rather than as
+    # per-subdomain value tables)
+    P = tiny_problem(N=12, pieces=(2, 2, 1), deflation="constant", sigma=1.0, seed=31)
+    g = np.random.default_rng(5).standard_normal((P.n, 2))
+    Zx = np.column_stack([P.Z[:, 0], g[:, 0], g[:, 1]])
+    P2 = P.__class__(P.name, P.A, P.part, P.nsub, np.ascontiguousarray(Zx), P.b, P.x0)
+    assert min(len(np.unique(Zx[P.part == s, 1])) for s in range(P.nsub)) > 256
+    ref, out = _solve_pair(P2, dict(coarse_enough=30), dict(coarse_enough=30))
+    _assert_parity(ref, out)
