@@ -29,7 +29,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "time-to-solution at rtol 1e-8 (FP64 vs mixed vs batched); SpMV HBM GB/s % peak"
-KERNEL_SOURCES = ["paper_1710_03940_amd/csrc/kernels.hpp", "paper_1710_03940_amd/csrc/device.hip"]
+# device code of the outer-operator kernel (its launcher, views and body)
+KERNEL_SOURCES = ["paper_1710_03940_amd/csrc/kernels.hpp", "paper_1710_03940_amd/csrc/launch_outer.hip",
+                  "paper_1710_03940_amd/csrc/devmat.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_lognormal150_traffic.json")
 
 
@@ -235,6 +237,8 @@ def main():
                      "kernel": "k_outer (outer SpMV + (p,q) + Z^T q epilogue)",
                      "avg_us": avg_s * 1e6, "bytes_per_launch": k["bytes"],
                      "copy_ceiling": copy_gbps, "frac_of_copy": achieved / copy_gbps,
+                     "layout_bytes_per_launch": st64["outer_layout_bytes"],
+                     "layout_GBps": st64["outer_layout_bytes"] / avg_s / 1e9 if avg_s > 0 else 0.0,
                      "events_in_graph": st64["profile_in_graph"]},
         "kernels": kernels,
         "cpu_baseline": cpu,
@@ -288,15 +292,22 @@ def copy_calibration():
     return 0
 
 
-def _pmc_kib(csv_path, name_part, counter):
-    """Per-dispatch counter values (KiB) of kernels whose name contains name_part."""
+def _pmc_kib(csv_path, name_part, counter, most_frequent=False):
+    """Per-dispatch counter values (KiB) of kernels whose name contains
+    name_part; with most_frequent, only those of the most often dispatched
+    such kernel (the in-loop instance, not the layouts timed at setup)."""
+    import collections
     import csv
-    vals = []
+    by = collections.defaultdict(list)
     with open(csv_path) as fh:
         for row in csv.DictReader(fh):
             if name_part in row.get("Kernel_Name", "") and row.get("Counter_Name", counter) == counter:
-                vals.append(float(row["Counter_Value"]))
-    return vals
+                by[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+    if not by:
+        return []
+    if most_frequent:
+        return max(by.values(), key=len)
+    return [v for vals in by.values() for v in vals]
 
 
 def write_traffic(spmv_fetch, spmv_write, copy_fetch, copy_write):
@@ -308,8 +319,8 @@ def write_traffic(spmv_fetch, spmv_write, copy_fetch, copy_write):
     fscale = (COPY_BYTES / 1024.0) / cf      # true KiB per counted KiB
     wscale = (COPY_BYTES / 1024.0) / cw
     # launches of the in-loop SpMV; skipped launches after convergence read ~nothing
-    f = [v for v in _pmc_kib(spmv_fetch, "k_outer<0", "FETCH_SIZE")]
-    w = [v for v in _pmc_kib(spmv_write, "k_outer<0", "WRITE_SIZE")]
+    f = _pmc_kib(spmv_fetch, "k_outer<0", "FETCH_SIZE", most_frequent=True)
+    w = _pmc_kib(spmv_write, "k_outer<0", "WRITE_SIZE", most_frequent=True)
     fbig = [v for v in f if v > 0.5 * max(f)]
     wbig = [v for v in w if v > 0.5 * max(w)]
     fetch = statistics.median(fbig) * fscale * 1024.0

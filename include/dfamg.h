@@ -206,6 +206,12 @@ typedef struct {
                                          solves launched kernels directly   */
     char    layouts[1024];            /* text: the layout the autotuner chose
                                          for every matrix, NUL-terminated    */
+    double  outer_layout_bytes;       /* bytes one outer-operator launch
+                                         moves in its chosen layout (stored
+                                         entries incl. padding and index
+                                         width, couplings, vectors, Z as
+                                         stored); the algorithmic figure is
+                                         kernel_bytes[DFAMG_KERNEL_SPMV]     */
 } dfamg_stats;
 
 /* Kernel ids of the profile: the outer SpMV with its fused (p,q) and Z^T q

@@ -68,7 +68,7 @@ class Stats(ctypes.Structure):
         ("bytes_per_iter", ctypes.c_double),
         ("kernel_calls", ctypes.c_int64 * 16), ("kernel_ms", ctypes.c_double * 16),
         ("kernel_bytes", ctypes.c_double * 16), ("profile_in_graph", ctypes.c_int32),
-        ("layouts", ctypes.c_char * 1024),
+        ("layouts", ctypes.c_char * 1024), ("outer_layout_bytes", ctypes.c_double),
     ]
 
 
@@ -218,7 +218,7 @@ def dfamg_get_stats(h):
             "setup_host_s": s.setup_host_s, "setup_device_s": s.setup_device_s,
             "solve_s": s.solve_s, "device_bytes": s.device_bytes,
             "bytes_per_iter": s.bytes_per_iter, "profile_in_graph": bool(s.profile_in_graph),
-            "layouts": s.layouts.decode(),
+            "layouts": s.layouts.decode(), "outer_layout_bytes": s.outer_layout_bytes,
             "kernels": {name: {"calls": int(s.kernel_calls[i]), "ms": float(s.kernel_ms[i]),
                                "bytes": float(s.kernel_bytes[i])}
                         for i, name in enumerate(KERNEL_NAMES)}}

@@ -848,6 +848,8 @@ struct Handle {
     OffM offA{};
     ZView zview{};                          // Z as the operator epilogue reads it
     bool outer_split = false;
+    int64_t outer_off_nnz = 0;              // couplings stored apart (split form)
+    double outer_layout_bytes = 0.0;
     int32_t *d_sto_A = nullptr, *d_subto_A = nullptr;
     // row tiles for the vector kernels (update, direction, expansion)
     DevTile *rows = nullptr;
@@ -976,6 +978,7 @@ void Handle::setup_device() {
         A = split ? AS : AF;
         offA = upload_off(ar, split ? off : none, A, sm);
         outer_split = split;
+        outer_off_nnz = split ? (int64_t)off.col.size() : 0;
         HIP_CHECK(hipStreamSynchronize(sm));
     }
     d_sto_A = ar.upload(A.sys_tile_off, sm);
@@ -1091,6 +1094,15 @@ void Handle::setup_device() {
     {
         const double nd = (double)n, nnzA = (double)P.nnz;
         prof.bytes[KID_SPMV] = nnzA * 12.0 + 16.0 * nd + 8.0 * ndv * nd;
+        {
+            const double ib = A.fmt == DFAMG_FORMAT_SELL ? (A.idx16 ? 2.0 : 4.0) : 4.0;
+            double b = (double)A.stored * (8.0 + ib) + 16.0 * nd;
+            if (A.fmt == DFAMG_FORMAT_CSR) b += 4.0 * nd;
+            if (A.sorted) b += 2.0 * nd;
+            if (outer_split) b += 12.0 * (double)outer_off_nnz + 4.0 * nd;
+            b += (zview.code ? 1.0 : 8.0) * ndv * nd;
+            outer_layout_bytes = b;
+        }
         prof.bytes[KID_UPDATE] = 48.0 * nd + 8.0 * ndv * nd + (ndv ? 12.0 * (double)P.AZoff.nnz() + 4.0 * nd : 0.0);
         prof.bytes[KID_PROJECT] = 8.0 * (double)P.sys_E_off[nsys] + 8.0 * (ndv + 1) * A.ntiles;
         prof.bytes[KID_DIR] = 24.0 * nd;
@@ -1626,6 +1638,7 @@ dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *o) {
         }
     }
     o->format_outer = H.A.fmt;
+    o->outer_layout_bytes = H.outer_layout_bytes;
     {
         const std::string t = "outer " + describe(H.A) + (H.outer_split ? "+couplings" : "") +
                               (H.M ? ";" + H.M->layouts : std::string());
