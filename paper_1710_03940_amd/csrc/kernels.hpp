@@ -476,6 +476,19 @@ __global__ void __launch_bounds__(kBlock) k_update(
 #pragma unroll
     for (int k = 0; k < NDV; ++k) t2s[k] = k < ndv ? t2[(int64_t)T.sub * ndv + k] : 0.0;
     for_tile_rows(T, [&](int row) {
+        // every load that does not depend on another is issued first
+        const double qv = stream_load(q + row);
+        double pv = 0.0, yv = 0.0, rv = 0.0;
+        if (MODE == 0) {
+            pv = stream_load(p + row);
+            yv = y[row];
+            rv = r[row];
+        }
+        int e = 0, e1 = 0;
+        if (ndv > 0) {
+            e = offp[row];
+            e1 = offp[row + 1];
+        }
         double corr = 0.0;
         if (NDV == 4 && ndv == 4) {
             // one row of the own AZ block is 32 contiguous bytes
@@ -487,12 +500,23 @@ __global__ void __launch_bounds__(kBlock) k_update(
             for (int k = 0; k < NDV; ++k)
                 if (k < ndv) corr += stream_load(AZown + (int64_t)row * ndv + k) * t2s[k];
         }
-        if (ndv > 0)
-            for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
-        const double wv = stream_load(q + row) - corr;
+        // couplings to other subdomains: groups of four independent gathers
+        for (; e + 4 <= e1; e += 4) {
+            int c[4];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = offc[e + u];
+                v[u] = offv[e + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) corr += v[u] * t2[c[u]];
+        }
+        for (; e < e1; ++e) corr += offv[e] * t2[offc[e]];
+        const double wv = qv - corr;
         if (MODE == 0) {
-            y[row] += a * p[row];
-            const double rn = r[row] - a * wv;
+            y[row] = yv + a * pv;
+            const double rn = rv - a * wv;
             r[row] = rn;
             rr += rn * rn;
         } else if (MODE == 1) {
@@ -617,20 +641,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restri
 // BiCGStab (right-preconditioned, Templates form) on the deflated operator
 // ---------------------------------------------------------------------------
 
-// own-subdomain + off-subdomain AZ t2 of one row (NDV = unroll bound)
-template <int NDV>
-__device__ __forceinline__ double az_t2(int row, int sub, int ndv, const double *__restrict__ AZown,
-                                        const int32_t *__restrict__ offp, const int32_t *__restrict__ offc,
-                                        const double *__restrict__ offv, const double *__restrict__ t2) {
-    double corr = 0.0;
-#pragma unroll
-    for (int k = 0; k < NDV; ++k)
-        if (k < ndv) corr += AZown[(int64_t)row * ndv + k] * t2[(int64_t)sub * ndv + k];
-    if (ndv > 0)
-        for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
-    return corr;
-}
-
 // p = r + beta (p - omega v), beta = (rho / rho_old) (alpha / omega)
 static __global__ void __launch_bounds__(kBlock) k_bicg_p(const DevTile *__restrict__ tiles, int32_t ntiles,
                                                           const double *__restrict__ r, const double *__restrict__ v,
@@ -660,10 +670,42 @@ __global__ void __launch_bounds__(kBlock) k_bicg_proj(
     const DevTile T = tiles[tile];
     if (st[sub_sys[T.sub]].done) return;
     double d0 = 0.0, d1 = 0.0;
+    double t2s[NDV > 0 ? NDV : 1];
+#pragma unroll
+    for (int k = 0; k < NDV; ++k) t2s[k] = k < ndv ? t2[(int64_t)T.sub * ndv + k] : 0.0;
     for_tile_rows(T, [&](int row) {
-        const double v = q[row] - az_t2<NDV>(row, T.sub, ndv, AZown, offp, offc, offv, t2);
+        // independent loads first, then the couplings in groups of four gathers
+        const double qv = q[row], ov = other[row];
+        int e = 0, e1 = 0;
+        if (ndv > 0) {
+            e = offp[row];
+            e1 = offp[row + 1];
+        }
+        double corr = 0.0;
+        if (NDV == 4 && ndv == 4) {
+            const f64x2 *az = reinterpret_cast<const f64x2 *>(AZown + (int64_t)row * 4);
+            const f64x2 a01 = stream_load(az), a23 = stream_load(az + 1);
+            corr = ((a01.x * t2s[0] + a01.y * t2s[1]) + a23.x * t2s[2]) + a23.y * t2s[3];
+        } else {
+#pragma unroll
+            for (int k = 0; k < NDV; ++k)
+                if (k < ndv) corr += stream_load(AZown + (int64_t)row * ndv + k) * t2s[k];
+        }
+        for (; e + 4 <= e1; e += 4) {
+            int c[4];
+            double w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = offc[e + u];
+                w[u] = offv[e + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) corr += w[u] * t2[c[u]];
+        }
+        for (; e < e1; ++e) corr += offv[e] * t2[offc[e]];
+        const double v = qv - corr;
         out[row] = v;
-        d0 += other[row] * v;
+        d0 += ov * v;
         if (MODE == 1) d1 += v * v;
     });
     const double s0 = block_sum(d0, lds, kBlock);
