@@ -159,6 +159,9 @@ def main():
     t64, out64, it64 = time_solver(S64, b, x, args.steps, args.warmup, log)
     st64 = S64.stats()
     x64 = x.clone()
+    golden = load_golden("poisson150_lognormal2_boxes64_linear")
+    err64 = error_vs_oracle(x64, golden)
+    log(f"  FP64 error against the stored oracle solution (sampled): {err64:.2e}")
 
     result = {}
     mixed = None
@@ -172,6 +175,7 @@ def main():
         mixed = {"s_per_solve": tm, "median_s": outm["median_s"], "iters": itm[-1],
                  "relres_true": outm["relres_true"],
                  "speedup_vs_fp64": t64 / tm, "rel_diff_vs_fp64_solution": diff,
+                 "rel_error_vs_oracle_sampled": error_vs_oracle(x, golden),
                  "bytes_per_iter": stm["bytes_per_iter"]}
         Sm.close()
 
@@ -228,6 +232,7 @@ def main():
                    "n": P.n, "nnz": int(P.A.nnz), "subdomains": P.nsub, "deflation": "linear",
                    "rtol": 1e-8, "smoother": "spai0", "solver": "cg"},
         "iters": out64["iters"], "relres_true": out64["relres_true"], "median_s": out64["median_s"],
+        "oracle_iters": golden["iters"], "rel_error_vs_oracle_sampled": err64,
         "setup_s": {"host": st64["setup_host_s"], "device": st64["setup_device_s"]},
         "bytes_per_iter": st64["bytes_per_iter"],
         "effective_GBps": st64["bytes_per_iter"] * out64["iters"] / t64 / 1e9,
@@ -249,6 +254,21 @@ def main():
 
 
 COPY_BYTES = 1 << 31
+
+
+def load_golden(name):
+    """Stored oracle result of a workload (written by tests/golden/make_golden.py)."""
+    with open(os.path.join(ROOT, "tests", "golden", name + ".json")) as fh:
+        return json.load(fh)
+
+
+def error_vs_oracle(x, golden):
+    """||x - x_oracle|| / ||x_oracle|| over the oracle's stored sample entries."""
+    import numpy as np
+    idx = np.array(golden["sample_index"])
+    xs = x.cpu().numpy()[idx]
+    gs = np.array(golden["sample_x"])
+    return float(np.linalg.norm(xs - gs) / np.linalg.norm(gs))
 
 
 def copy_ceiling_gbps(nbytes=1 << 30, reps=10):
@@ -372,13 +392,17 @@ def bench_oseen(args, log):
     out = {"workload": P.name, "n": P.n, "nnz": int(P.A.nnz), "subdomains": P.nsub,
            "deflation": "per-field constant (4 per subdomain)", "solver": "bicgstab",
            "block_size": 4}
+    golden = load_golden("oseen64_boxes256_field")
+    out["oracle_iters"] = golden["iters"]
     for prec in ("mixed", "fp64"):
         S = dfamg.Solver(P.A, P.part, P.nsub, P.Z, solver="bicgstab", block_size=4, precision=prec)
         t, o, its = time_solver(S, b, x, args.steps, args.warmup, log)
+        o["rel_error_vs_oracle_sampled"] = error_vs_oracle(x, golden)
         st = S.stats()
         S.close()
         log(f"  oseen {prec} layouts: {st['layouts']}")
         out[prec] = {"s_per_solve": t, "iters": its[-1], "relres_true": o["relres_true"],
+                     "rel_error_vs_oracle_sampled": o["rel_error_vs_oracle_sampled"],
                      "setup_host_s": st["setup_host_s"], "setup_device_s": st["setup_device_s"],
                      "bytes_per_iter": st["bytes_per_iter"]}
         log(f"  oseen {prec}: {t * 1e3:.1f} ms, {its[-1]} iterations, relres {o['relres_true']:.2e}")
@@ -411,6 +435,15 @@ def bench_batched(args, log):
     tb = (time.perf_counter() - t0) / args.steps
     Sb.close()
     log(f"  batched mixed: {tb * 1e3:.2f} ms, iterations max {int(outb['iters'].max())}")
+    # error against the oracle on the systems whose oracle solutions are stored
+    gsys = load_golden("batched48_sample")["systems"]
+    xs_all = x.cpu().numpy()
+    errs = {}
+    for key, gs in gsys.items():
+        sidx = int(key)
+        xs = xs_all[off[sidx] + np.array(gs["sample_index"])]
+        ref = np.array(gs["sample_x"])
+        errs[key] = float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))
     # plain FP64 path, one system after another
     solvers = []
     vecs = []
@@ -436,6 +469,8 @@ def bench_batched(args, log):
             "systems": len(probs), "unknowns": int(A.shape[0]),
             "iters_max": int(outb["iters"].max()), "iters_min": int(outb["iters"].min()),
             "relres_true_max": float(outb["relres_true"].max()),
+            "rel_error_vs_oracle_sampled_max": max(errs.values()),
+            "oracle_sampled_systems": sorted(int(k) for k in errs),
             "status": int(outb["status"])}
 
 

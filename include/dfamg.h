@@ -218,7 +218,10 @@ typedef struct {
  * epilogue, the per-system projection reduction (t1 sums, t2 = E^{-1} t1,
  * alpha), the fused deflation-correction / Krylov update, the stopping test,
  * the level-0 V-cycle kernels, everything on coarser levels (including the
- * coarsest direct solves) as one span, and the (r,s) / direction update. */
+ * coarsest direct solves) as one span, and the (r,s) / direction update.
+ * PRESMOOTH0 is the single level-0 kernel that applies the pre-smoothing
+ * sweep, the residual and the restriction as one operator; RESTRICT0 is kept
+ * for numbering and records no launches. */
 enum {
     DFAMG_KERNEL_SPMV = 0, DFAMG_KERNEL_PROJECT = 1, DFAMG_KERNEL_UPDATE = 2,
     DFAMG_KERNEL_TEST = 3, DFAMG_KERNEL_PRESMOOTH0 = 4, DFAMG_KERNEL_RESTRICT0 = 5,
@@ -263,8 +266,10 @@ dfamg_status dfamg_plan_levels(dfamg_plan p, int32_t sub, int32_t cap,
 dfamg_status dfamg_plan_aggregates(dfamg_plan p, int32_t sub, int32_t level,
                                    int64_t cap, int32_t *agg, int64_t *count);
 
-/* CRS of matrix `which` (0 = A_l, 1 = P_l) of level `level` of subdomain
- * `sub` in local numbering; pass NULL arrays to query sizes only. */
+/* CRS of matrix `which` (0 = A_l, 1 = P_l, 2 = B_l = R_l (I - A_l diag(m_l)),
+ * the operator the solve applies for pre-smoothing from a zero guess,
+ * residual and restriction together) of level `level` of subdomain `sub` in
+ * local numbering; pass NULL arrays to query sizes only. */
 dfamg_status dfamg_plan_level_matrix(dfamg_plan p, int32_t sub, int32_t level,
                                      int32_t which, int64_t *nrows,
                                      int64_t *ncols, int64_t *nnz,

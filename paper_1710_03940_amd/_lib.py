@@ -276,7 +276,8 @@ def dfamg_plan_aggregates(p, sub, level):
 
 
 def dfamg_plan_level_matrix(p, sub, level, which):
-    """Returns (row_ptr, col, val, shape) of A_l (which=0) or P_l (which=1)."""
+    """Returns (row_ptr, col, val, shape) of A_l (which=0), P_l (which=1) or
+    B_l = R_l (I - A_l diag(m_l)) (which=2)."""
     lib = load()
     nr, nc, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(lib.dfamg_plan_level_matrix(ctypes.c_void_p(p), sub, level, which, ctypes.byref(nr),

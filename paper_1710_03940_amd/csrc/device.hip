@@ -642,9 +642,9 @@ struct Hierarchy_dev : PrecondBase {
     struct Lvl {
         int64_t nrows = 0;
         bool active = false;
-        DevMat<VT> A, P, R;
+        DevMat<VT> A, P, B;   // B = R (I - A diag(m)), see k_restrict
         VT *m = nullptr;
-        VT *f = nullptr, *res = nullptr, *z = nullptr, *x = nullptr;
+        VT *f = nullptr, *z = nullptr, *x = nullptr;
         CoarseEntry *coarse = nullptr;
         CoarseJob *cjobs = nullptr;
         int32_t ncoarse = 0, ncjobs = 0;
@@ -657,7 +657,7 @@ struct Hierarchy_dev : PrecondBase {
     const std::vector<int32_t> &sys_tile_off0() const override { return sto0; }
     int32_t nslots0() const override { return slots0; }
 
-    void build(DevArena &ar, const Plan &plan, hipStream_t s, int format, bool autotune) {
+    void build(DevArena &ar, const Plan &plan, hipStream_t s, int format, bool autotune, int verbose) {
         const int L = plan.nlevels_max;
         lv.resize(L);
         const double sv = sizeof(VT), ib = 4.0;
@@ -671,24 +671,23 @@ struct Hierarchy_dev : PrecondBase {
                 D.x = ar.alloc<VT>(PL.nrows);
             }
             if (D.active) {
-                D.res = ar.alloc<VT>(PL.nrows);
                 D.z = ar.alloc<VT>(PL.nrows);
                 const auto rr = ranges_of(PL, PL.active_subs);
                 D.A = upload_tuned<VT>(ar, PL.A, rr, format, autotune, TUNE_SMOOTH, s, plan.sub_sys, plan.nsys,
-                                       plan.nsub);
+                                       plan.nsub, {}, verbose);
                 D.P = upload_tuned<VT>(ar, PL.P, rr, format, autotune, TUNE_PROLONG, s, plan.sub_sys, plan.nsys,
-                                       plan.nsub);
+                                       plan.nsub, {}, verbose);
                 const PackedLevel &PN = plan.levels[l + 1];
                 std::vector<int32_t> next_subs;
                 for (int sub = 0; sub < plan.nsub; ++sub)
                     if (PN.sub_off[sub] >= 0) next_subs.push_back(sub);
-                D.R = upload_tuned<VT>(ar, PL.R, ranges_of(PN, next_subs), format, autotune, TUNE_RESTRICT, s,
-                                       plan.sub_sys, plan.nsys, plan.nsub);
+                D.B = upload_tuned<VT>(ar, PL.B, ranges_of(PN, next_subs), format, autotune, TUNE_RESTRICT, s,
+                                       plan.sub_sys, plan.nsys, plan.nsub, {}, verbose);
                 if (l < 20) {
                     fmt[l] = D.A.fmt;
                     par[l] = D.A.par;
                 }
-                layouts += " L" + std::to_string(l) + "{A " + describe(D.A) + ", R " + describe(D.R) + ", P " +
+                layouts += " L" + std::to_string(l) + "{A " + describe(D.A) + ", B " + describe(D.B) + ", P " +
                            describe(D.P) + "}";
                 std::vector<VT> m(PL.m.size());
                 for (size_t i = 0; i < m.size(); ++i) m[i] = (VT)PL.m[i];
@@ -697,21 +696,20 @@ struct Hierarchy_dev : PrecondBase {
                 const double n0 = (double)PL.nrows, n1 = (double)PN.nrows;
                 // the level's right-hand side is FP64 on level 0
                 const double fb = l == 0 ? 8.0 : sv;
-                const double kb_pre = D.A.nnz * (sv + ib) + n0 * (fb + 2.0 * sv);
-                const double kb_res = D.R.nnz * (sv + ib) + n0 * sv + n1 * sv;
+                // pre-smoothing, residual and restriction as one operator B
+                const double kb_pre = D.B.nnz * (sv + ib) + n0 * fb + n1 * sv;
                 const double kb_pro = D.P.nnz * (sv + ib) + n0 * (2.0 * sv + fb) + n1 * sv;
                 const double kb_post = D.A.nnz * (sv + ib) + n0 * (2.0 * sv + fb + (l == 0 ? 8.0 : sv));
                 if (l == 0) {
                     sto0 = D.A.sys_tile_off;
                     slots0 = D.A.ntiles;
                     kbytes[KID_PRE0] = kb_pre;
-                    kbytes[KID_RESTRICT0] = kb_res;
                     kbytes[KID_PROLONG0] = kb_pro;
                     kbytes[KID_POST0] = kb_post;
                 } else {
-                    kbytes[KID_COARSER] += kb_pre + kb_res + kb_pro + kb_post;
+                    kbytes[KID_COARSER] += kb_pre + kb_pro + kb_post;
                 }
-                bytes += kb_pre + kb_res + kb_pro + kb_post;
+                bytes += kb_pre + kb_pro + kb_post;
             }
             if (!PL.coarse_subs.empty()) {
                 std::vector<CoarseEntry> ce;
@@ -787,16 +785,11 @@ struct Hierarchy_dev : PrecondBase {
             if (!D.active) continue;
             if (l == 0) {
                 mark(KID_PRE0, 0);
-                launch_pre_res<VT, double>(D.A, D.m, r, D.res, states, sub_sys, st);
+                launch_restrict<VT, double>(D.B, r, lv[1].f, states, sub_sys, st);
                 mark(KID_PRE0, 1);
-                mark(KID_RESTRICT0, 0);
-            } else {
-                launch_pre_res<VT, VT>(D.A, D.m, D.f, D.res, states, sub_sys, st);
-            }
-            launch_spmv<VT>(D.R, D.res, lv[l + 1].f, states, sub_sys, st);
-            if (l == 0) {
-                mark(KID_RESTRICT0, 1);
                 mark(KID_COARSER, 0);
+            } else {
+                launch_restrict<VT, VT>(D.B, D.f, lv[l + 1].f, states, sub_sys, st);
             }
         }
         // direct solves on every subdomain's coarsest level
@@ -1062,11 +1055,11 @@ void Handle::setup_device() {
     if (prm.precond == DFAMG_PRECOND_AMG) {
         if (prm.precision == DFAMG_PREC_MIXED) {
             auto H = std::make_unique<Hierarchy_dev<float>>();
-            H->build(ar, P, sm, prm.spmv_format, prm.autotune != 0);
+            H->build(ar, P, sm, prm.spmv_format, prm.autotune != 0, prm.verbose);
             M = std::move(H);
         } else {
             auto H = std::make_unique<Hierarchy_dev<double>>();
-            H->build(ar, P, sm, prm.spmv_format, prm.autotune != 0);
+            H->build(ar, P, sm, prm.spmv_format, prm.autotune != 0, prm.verbose);
             M = std::move(H);
         }
         part_rs = ar.alloc<double>(std::max(1, M->nslots0()));
@@ -1734,12 +1727,12 @@ dfamg_status dfamg_plan_aggregates(dfamg_plan p, int32_t sub, int32_t level, int
 dfamg_status dfamg_plan_level_matrix(dfamg_plan p, int32_t sub, int32_t level, int32_t which, int64_t *nrows,
                                      int64_t *ncols, int64_t *nnz, int64_t *row_ptr, int32_t *col, double *val) {
     const Hierarchy *H = plan_hier(p, sub);
-    if (!H || level < 0 || level >= H->nlevels() || (which == 1 && level + 1 >= H->nlevels()) || which < 0 ||
-        which > 1) {
+    if (!H || level < 0 || level >= H->nlevels() || (which >= 1 && level + 1 >= H->nlevels()) || which < 0 ||
+        which > 2) {
         g_last_error = "bad plan, subdomain, level or matrix";
         return DFAMG_EINVAL;
     }
-    const Csr &M = which == 0 ? H->lv[level].A : H->lv[level].P;
+    const Csr &M = which == 0 ? H->lv[level].A : which == 1 ? H->lv[level].P : H->lv[level].B;
     if (nrows) *nrows = M.nrows;
     if (ncols) *ncols = M.ncols;
     if (nnz) *nnz = M.nnz();

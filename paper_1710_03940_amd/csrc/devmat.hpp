@@ -104,6 +104,10 @@ void launch_pre_res(const DevMat<VT> &A, const VT *m, const FT *f, VT *res, cons
 template <class VT>
 void launch_spmv(const DevMat<VT> &M, const VT *x, VT *y, const SysState *st, const int32_t *sub_sys,
                  hipStream_t s);
+// fc = B f (see k_restrict)
+template <class VT, class FT>
+void launch_restrict(const DevMat<VT> &B, const FT *f, VT *fc, const SysState *st, const int32_t *sub_sys,
+                     hipStream_t s);
 template <class VT, class FT>
 void launch_prolong(const DevMat<VT> &P, const VT *m, const FT *f, const VT *xc, VT *z, const SysState *st,
                     const int32_t *sub_sys, hipStream_t s);

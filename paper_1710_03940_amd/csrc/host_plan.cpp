@@ -446,6 +446,40 @@ void smoothed_prolongation(const Csr &AF, const std::vector<int32_t> &agg, int32
 
 }  // namespace
 
+// B = R - (R A) diag(m), rows merged column by column; exact zeros dropped.
+// With one pre-smoothing sweep from a zero guess, x = m o f and the level's
+// restricted residual is R (f - A x) = B f.
+Csr restricted_residual_map(const Csr &R, const Csr &RA, const std::vector<double> &m) {
+    Csr B;
+    B.nrows = R.nrows;
+    B.ncols = R.ncols;
+    B.ptr.assign(R.nrows + 1, 0);
+    for (int64_t k = 0; k < R.nrows; ++k) {
+        int64_t a = R.ptr[k], b = RA.ptr[k];
+        const int64_t ae = R.ptr[k + 1], be = RA.ptr[k + 1];
+        while (a < ae || b < be) {
+            int32_t c;
+            double v;
+            if (b >= be || (a < ae && R.col[a] < RA.col[b])) {
+                c = R.col[a];
+                v = R.val[a++];
+            } else if (a >= ae || RA.col[b] < R.col[a]) {
+                c = RA.col[b];
+                v = -RA.val[b++] * m[c];
+            } else {
+                c = R.col[a];
+                v = R.val[a++] - RA.val[b++] * m[c];
+            }
+            if (v != 0.0) {
+                B.col.push_back(c);
+                B.val.push_back(v);
+            }
+        }
+        B.ptr[k + 1] = (int64_t)B.col.size();
+    }
+    return B;
+}
+
 Hierarchy build_hierarchy(Csr A, const SaParams &prm) {
     Hierarchy H;
     double eps = prm.eps_strong;
@@ -478,7 +512,9 @@ Hierarchy build_hierarchy(Csr A, const SaParams &prm) {
             }
             L.m[i] = prm.smoother == DFAMG_SMOOTHER_JACOBI ? prm.jacobi_omega / d : d / s;
         }
-        A = multiply(multiply(L.R, L.A), L.P);
+        const Csr RA = multiply(L.R, L.A);
+        L.B = restricted_residual_map(L.R, RA, L.m);
+        A = multiply(RA, L.P);
         eps *= 0.5;
     }
     return H;
@@ -971,6 +1007,33 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
             }
         }
         PL.R = transpose(PL.P);
+        // B packed like R: rows of the next level's packed order, this level's columns
+        PL.B.nrows = ncoarse;
+        PL.B.ncols = PL.nrows;
+        PL.B.ptr.assign(ncoarse + 1, 0);
+        if (has_next) {
+            for (int s = 0; s < nsub; ++s) {
+                if (PL.sub_off[s] < 0 || plan.hier[s].nlevels() - 1 <= l) continue;
+                const Csr &Bs = plan.hier[s].lv[l].B;
+                const int64_t oc = plan.levels[l + 1].sub_off[s];
+                for (int64_t k = 0; k < Bs.nrows; ++k) PL.B.ptr[oc + k + 1] = Bs.ptr[k + 1] - Bs.ptr[k];
+            }
+            for (int64_t k = 0; k < ncoarse; ++k) PL.B.ptr[k + 1] += PL.B.ptr[k];
+            PL.B.col.resize(PL.B.ptr[ncoarse]);
+            PL.B.val.resize(PL.B.ptr[ncoarse]);
+            for (int s = 0; s < nsub; ++s) {
+                if (PL.sub_off[s] < 0 || plan.hier[s].nlevels() - 1 <= l) continue;
+                const Csr &Bs = plan.hier[s].lv[l].B;
+                const int64_t o = PL.sub_off[s], oc = plan.levels[l + 1].sub_off[s];
+                for (int64_t k = 0; k < Bs.nrows; ++k) {
+                    int64_t d = PL.B.ptr[oc + k];
+                    for (int64_t e = Bs.ptr[k]; e < Bs.ptr[k + 1]; ++e, ++d) {
+                        PL.B.col[d] = (int32_t)(Bs.col[e] + o);
+                        PL.B.val[d] = Bs.val[e];
+                    }
+                }
+            }
+        }
     }
     plan.host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }

@@ -35,6 +35,8 @@ Csr multiply(const Csr &A, const Csr &B);
 struct Level {
     Csr A;                   // level operator
     Csr P, R;                // prolongation (n_l x n_{l+1}) and R = P^T
+    Csr B;                   // R (I - A diag(m)): the restricted residual of the
+                             // pre-smoothed iterate (zero initial guess) as one map
     std::vector<double> m;   // smoother diagonal
     double eps = 0.0, omega = 0.0;
     std::vector<int32_t> agg;  // node -> aggregate (-1: none)
@@ -113,7 +115,7 @@ struct PackedLevel {
     int64_t nrows = 0;                   // unknowns of all subdomains present
     std::vector<int64_t> sub_off;        // nsub+1 style: offset or -1 when absent
     std::vector<int32_t> sub_len;
-    Csr A, P, R;                         // packed (block-diagonal) matrices
+    Csr A, P, R, B;                      // packed (block-diagonal) matrices
     std::vector<double> m;               // smoother diagonal (0 when inactive)
     std::vector<int32_t> active_subs;    // subdomains smoothing on this level
     std::vector<int32_t> coarse_subs;    // subdomains whose coarsest level is this

@@ -906,6 +906,19 @@ __global__ void __launch_bounds__(kBlock) k_spmv(MAT M, const VT *__restrict__ x
     for_rows<VT>(M, tile, T, [&](int c) { return x[c]; }, [&](int row, VT v) { y[row] = v; });
 }
 
+// f_c = B f with B = R (I - A diag(m)): pre-smoothing from a zero guess,
+// residual and restriction of one level in a single operator
+template <class VT, class FT, class MAT>
+__global__ void __launch_bounds__(kBlock) k_restrict(MAT B, const FT *__restrict__ f, VT *__restrict__ fc,
+                                                     const SysState *__restrict__ st,
+                                                     const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(B.ntiles);
+    if (tile >= B.ntiles) return;
+    const DevTile T = B.tiles[tile];
+    if (st && st[sub_sys[T.sub]].done) return;
+    for_rows<VT>(B, tile, T, [&](int c) { return (VT)f[c]; }, [&](int row, VT v) { fc[row] = v; });
+}
+
 // z = m o f + P xc   (pre-smoothed iterate plus the coarse correction)
 template <class VT, class FT, class MAT>
 __global__ void __launch_bounds__(kBlock) k_prolong(MAT P, const VT *__restrict__ m, const FT *__restrict__ f,

@@ -24,6 +24,15 @@ void launch_spmv(const DevMat<VT> &M, const VT *x, VT *y, const SysState *st, co
 }
 
 template <class VT, class FT>
+void launch_restrict(const DevMat<VT> &B, const FT *f, VT *fc, const SysState *st, const int32_t *sub_sys,
+                     hipStream_t s) {
+    with_mat(B, [&](auto v) {
+        hipLaunchKernelGGL((k_restrict<VT, FT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
+                           B.stage_bytes(), s, v, f, fc, st, sub_sys);
+    });
+}
+
+template <class VT, class FT>
 void launch_prolong(const DevMat<VT> &P, const VT *m, const FT *f, const VT *xc, VT *z, const SysState *st,
                     const int32_t *sub_sys, hipStream_t s) {
     with_mat(P, [&](auto v) {
@@ -44,6 +53,8 @@ void launch_post(const DevMat<VT> &A, const VT *m, const FT *f, const VT *z, OT 
 #ifdef DFAMG_VT_DOUBLE
 template void launch_pre_res<double, double>(const DevMat<double> &, const double *, const double *, double *,
                                              const SysState *, const int32_t *, hipStream_t);
+template void launch_restrict<double, double>(const DevMat<double> &, const double *, double *, const SysState *,
+                                              const int32_t *, hipStream_t);
 template void launch_spmv<double>(const DevMat<double> &, const double *, double *, const SysState *,
                                   const int32_t *, hipStream_t);
 template void launch_prolong<double, double>(const DevMat<double> &, const double *, const double *, const double *,
@@ -61,6 +72,10 @@ template void launch_pre_res<float, double>(const DevMat<float> &, const float *
                                             const SysState *, const int32_t *, hipStream_t);
 template void launch_spmv<float>(const DevMat<float> &, const float *, float *, const SysState *, const int32_t *,
                                  hipStream_t);
+template void launch_restrict<float, float>(const DevMat<float> &, const float *, float *, const SysState *,
+                                            const int32_t *, hipStream_t);
+template void launch_restrict<float, double>(const DevMat<float> &, const double *, float *, const SysState *,
+                                             const int32_t *, hipStream_t);
 template void launch_prolong<float, float>(const DevMat<float> &, const float *, const float *, const float *, float *,
                                            const SysState *, const int32_t *, hipStream_t);
 template void launch_prolong<float, double>(const DevMat<float> &, const float *, const double *, const float *,

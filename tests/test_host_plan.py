@@ -114,6 +114,45 @@ def test_block_hierarchy_oseen_matches_oracle(N, pieces, ce):
     _compare_hierarchy(P, kw, kw, exact_structure=False)
 
 
+@pytest.mark.parametrize("N,pieces,ce,smoother,bs", [
+    (12, (2, 2, 1), 20, "spai0", 1),
+    (14, (1, 3, 1), 30, "jacobi", 1),
+    (8, (2, 1, 1), 60, "spai0", 4),
+])
+def test_fused_restriction_operator_matches_oracle_steps(N, pieces, ce, smoother, bs):
+    """The solve applies pre-smoothing (zero guess), residual and restriction
+    of a level as one operator B = R (I - A diag(m)); it must equal the
+    oracle's three steps composed."""
+    if bs == 4:
+        P = config_oseen(N=N, pieces=pieces)
+        kw = dict(coarse_enough=ce, smoother=smoother, solver="bicgstab", block_size=4)
+    else:
+        P = tiny_problem(N=N, pieces=pieces, deflation="linear", sigma=2.0, seed=N)
+        kw = dict(coarse_enough=ce, smoother=smoother)
+    plan = L.dfamg_plan_create(L.make_params(**kw), P.A, P.part, P.nsub, P.Z)
+    try:
+        ora = OracleSolver(P.A, P.part, P.nsub, P.Z, OracleParams(**kw))
+        checked = 0
+        for s in range(P.nsub):
+            levels = ora.M.hierarchies[s].levels
+            for l in range(len(levels) - 1):
+                lv = levels[l]
+                ref = (lv.R @ (sp.eye(lv.A.shape[0]) - lv.A @ sp.diags(lv.m))).tocsr()
+                ptr, col, val, shape = L.dfamg_plan_level_matrix(plan, s, l, 2)
+                Bm = sp.csr_matrix((val, col, ptr), shape=shape)
+                assert Bm.shape == ref.shape
+                assert abs(Bm - ref).max() <= 1e-12 * abs(ref).max()
+                # the reference applied to a vector, step by step
+                f = np.random.default_rng(l).standard_normal(lv.A.shape[0])
+                x = lv.m * f
+                step = lv.R @ (f - lv.A @ x)
+                assert np.linalg.norm(Bm @ f - step) <= 1e-12 * np.linalg.norm(step)
+                checked += 1
+        assert checked > 0
+    finally:
+        L.dfamg_plan_destroy(plan)
+
+
 def test_batched_plan_hierarchies_match_standalone():
     probs = [tiny_problem(N=n, pieces=pc, deflation="linear", sigma=1.0, seed=n)
              for n, pc in [(9, (2, 1, 1)), (12, (2, 2, 1))]]
