@@ -219,9 +219,9 @@ typedef struct {
  * alpha), the fused deflation-correction / Krylov update, the stopping test,
  * the level-0 V-cycle kernels, everything on coarser levels (including the
  * coarsest direct solves) as one span, and the (r,s) / direction update.
- * PRESMOOTH0 is the single level-0 kernel that applies the pre-smoothing
- * sweep, the residual and the restriction as one operator; RESTRICT0 is kept
- * for numbering and records no launches. */
+ * When level 0 applies the pre-smoothing sweep, the residual and the
+ * restriction as one operator (chosen at setup when it is faster), that
+ * kernel is PRESMOOTH0 and RESTRICT0 records no launches. */
 enum {
     DFAMG_KERNEL_SPMV = 0, DFAMG_KERNEL_PROJECT = 1, DFAMG_KERNEL_UPDATE = 2,
     DFAMG_KERNEL_TEST = 3, DFAMG_KERNEL_PRESMOOTH0 = 4, DFAMG_KERNEL_RESTRICT0 = 5,

@@ -642,9 +642,10 @@ struct Hierarchy_dev : PrecondBase {
     struct Lvl {
         int64_t nrows = 0;
         bool active = false;
-        DevMat<VT> A, P, B;   // B = R (I - A diag(m)), see k_restrict
+        DevMat<VT> A, P, R, B;   // B = R (I - A diag(m)), see k_restrict
+        bool fused = false;      // restrict with B, else pre-smoothing residual then R
         VT *m = nullptr;
-        VT *f = nullptr, *z = nullptr, *x = nullptr;
+        VT *f = nullptr, *res = nullptr, *z = nullptr, *x = nullptr;
         CoarseEntry *coarse = nullptr;
         CoarseJob *cjobs = nullptr;
         int32_t ncoarse = 0, ncjobs = 0;
@@ -681,14 +682,34 @@ struct Hierarchy_dev : PrecondBase {
                 std::vector<int32_t> next_subs;
                 for (int sub = 0; sub < plan.nsub; ++sub)
                     if (PN.sub_off[sub] >= 0) next_subs.push_back(sub);
-                D.B = upload_tuned<VT>(ar, PL.B, ranges_of(PN, next_subs), format, autotune, TUNE_RESTRICT, s,
-                                       plan.sub_sys, plan.nsys, plan.nsub, {}, verbose);
+                // the level's restricted residual either through B in one launch or
+                // as pre-smoothing residual (A) plus restriction (R): the faster by
+                // the tuner's timings (R without tuning)
+                {
+                    const auto rn = ranges_of(PN, next_subs);
+                    DevArena arR, arB;
+                    D.R = upload_tuned<VT>(arR, PL.R, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys, plan.nsys,
+                                           plan.nsub, {}, verbose);
+                    if (autotune) {
+                        D.B = upload_tuned<VT>(arB, PL.B, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
+                                               plan.nsys, plan.nsub, {}, verbose);
+                        D.fused = D.B.tuned_us < D.A.tuned_us + D.R.tuned_us;
+                    }
+                    if (D.fused) {
+                        ar.adopt(arB);
+                        D.R = DevMat<VT>{};
+                    } else {
+                        ar.adopt(arR);
+                        D.B = DevMat<VT>{};
+                        D.res = ar.alloc<VT>(PL.nrows);
+                    }
+                }
                 if (l < 20) {
                     fmt[l] = D.A.fmt;
                     par[l] = D.A.par;
                 }
-                layouts += " L" + std::to_string(l) + "{A " + describe(D.A) + ", B " + describe(D.B) + ", P " +
-                           describe(D.P) + "}";
+                layouts += " L" + std::to_string(l) + "{A " + describe(D.A) +
+                           (D.fused ? ", B " + describe(D.B) : ", R " + describe(D.R)) + ", P " + describe(D.P) + "}";
                 std::vector<VT> m(PL.m.size());
                 for (size_t i = 0; i < m.size(); ++i) m[i] = (VT)PL.m[i];
                 D.m = ar.upload(m, s);
@@ -696,20 +717,23 @@ struct Hierarchy_dev : PrecondBase {
                 const double n0 = (double)PL.nrows, n1 = (double)PN.nrows;
                 // the level's right-hand side is FP64 on level 0
                 const double fb = l == 0 ? 8.0 : sv;
-                // pre-smoothing, residual and restriction as one operator B
-                const double kb_pre = D.B.nnz * (sv + ib) + n0 * fb + n1 * sv;
+                // pre-smoothing residual and restriction, or both as one operator B
+                const double kb_pre = D.fused ? D.B.nnz * (sv + ib) + n0 * fb + n1 * sv
+                                              : D.A.nnz * (sv + ib) + n0 * (fb + 2.0 * sv);
+                const double kb_res = D.fused ? 0.0 : D.R.nnz * (sv + ib) + n0 * sv + n1 * sv;
                 const double kb_pro = D.P.nnz * (sv + ib) + n0 * (2.0 * sv + fb) + n1 * sv;
                 const double kb_post = D.A.nnz * (sv + ib) + n0 * (2.0 * sv + fb + (l == 0 ? 8.0 : sv));
                 if (l == 0) {
                     sto0 = D.A.sys_tile_off;
                     slots0 = D.A.ntiles;
                     kbytes[KID_PRE0] = kb_pre;
+                    kbytes[KID_RESTRICT0] = kb_res;
                     kbytes[KID_PROLONG0] = kb_pro;
                     kbytes[KID_POST0] = kb_post;
                 } else {
-                    kbytes[KID_COARSER] += kb_pre + kb_pro + kb_post;
+                    kbytes[KID_COARSER] += kb_pre + kb_res + kb_pro + kb_post;
                 }
-                bytes += kb_pre + kb_pro + kb_post;
+                bytes += kb_pre + kb_res + kb_pro + kb_post;
             }
             if (!PL.coarse_subs.empty()) {
                 std::vector<CoarseEntry> ce;
@@ -785,11 +809,22 @@ struct Hierarchy_dev : PrecondBase {
             if (!D.active) continue;
             if (l == 0) {
                 mark(KID_PRE0, 0);
-                launch_restrict<VT, double>(D.B, r, lv[1].f, states, sub_sys, st);
-                mark(KID_PRE0, 1);
+                if (D.fused) {
+                    launch_restrict<VT, double>(D.B, r, lv[1].f, states, sub_sys, st);
+                    mark(KID_PRE0, 1);
+                } else {
+                    launch_pre_res<VT, double>(D.A, D.m, r, D.res, states, sub_sys, st);
+                    mark(KID_PRE0, 1);
+                    mark(KID_RESTRICT0, 0);
+                    launch_spmv<VT>(D.R, D.res, lv[1].f, states, sub_sys, st);
+                    mark(KID_RESTRICT0, 1);
+                }
                 mark(KID_COARSER, 0);
-            } else {
+            } else if (D.fused) {
                 launch_restrict<VT, VT>(D.B, D.f, lv[l + 1].f, states, sub_sys, st);
+            } else {
+                launch_pre_res<VT, VT>(D.A, D.m, D.f, D.res, states, sub_sys, st);
+                launch_spmv<VT>(D.R, D.res, lv[l + 1].f, states, sub_sys, st);
             }
         }
         // direct solves on every subdomain's coarsest level
