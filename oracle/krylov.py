@@ -99,3 +99,99 @@ def deflated_bicgstab(A, defl, precond, b, y0, rtol, maxiter):
             return y, k, hist, OK
         rho_old = rho
     return y, maxiter, hist, NOCONV
+
+
+def deflated_bicgstabl(A, defl, precond, b, y0, rtol, maxiter, ell=2, observe=None):
+    """BiCGStab(ell) of Sleijpen & Fokkema (1993) on the right-preconditioned
+    deflated operator K = P A M^{-1}; returns (y, iters, history, status).
+
+    This is the solver of the paper's Poisson runs.  Readings: the iteration
+    solves K d = r_0 from d = 0, r_0 = P(b - A y_0), and y = y_0 + M^{-1} d is
+    formed once at the end (M^{-1}, one V-cycle from a zero guess, is linear);
+    one iteration is one cycle (ell BiCG steps, then the minimal-residual
+    polynomial step over r_1 .. r_ell orthogonalised by modified Gram-Schmidt),
+    i.e. 2 ell operator products; the stopping test runs after each cycle;
+    r~ = r_0; exact zeros of rho, gamma or sigma are breakdowns.
+    `observe(k, r_before, r_after, rt)` (tests only) sees, per cycle, copies of
+    r^_0 .. r^_ell as the BiCG part leaves them and the cycle's new residual.
+    """
+    bnorm = np.linalg.norm(b)
+    y = y0.copy()
+    if bnorm == 0.0:
+        return np.zeros_like(b), 0, [0.0], OK
+
+    def K(v):
+        return defl.project(A @ precond(v))
+
+    r0 = defl.project(b - A @ y)
+    hist = [np.linalg.norm(r0) / bnorm]
+    if hist[0] <= rtol:
+        return y, 0, hist, OK
+    rt = r0.copy()
+    d = np.zeros_like(b)                 # the iterate of K d = r_0
+    r = [r0.copy()] + [None] * ell       # r^_0 .. r^_ell
+    u = [np.zeros_like(b)] + [None] * ell
+    rho0, alpha, omega = 1.0, 0.0, 1.0
+
+    def finish(status, k):
+        return y + precond(d), k, hist, status
+
+    for k in range(1, maxiter + 1):
+        rho0 = -omega * rho0
+        # BiCG part: ell steps, each extending the u and r sequences by one
+        for j in range(ell):
+            rho1 = r[j] @ rt
+            if rho0 == 0.0 or rho1 == 0.0:
+                return finish(BREAKDOWN, k - 1)
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = K(u[j])
+            gamma = u[j + 1] @ rt
+            if gamma == 0.0:
+                return finish(BREAKDOWN, k - 1)
+            alpha = rho0 / gamma
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = K(r[j])
+            d = d + alpha * u[0]
+        before = [v.copy() for v in r] if observe else None
+        # minimal-residual part: orthogonalise r_1 .. r_ell (modified
+        # Gram-Schmidt) and minimise ||r_0 - sum_j g_j r_j|| over g
+        tau = np.zeros((ell + 1, ell + 1))
+        sigma = np.zeros(ell + 1)
+        gp = np.zeros(ell + 1)           # gamma'
+        for j in range(1, ell + 1):
+            for i in range(1, j):
+                tau[i, j] = (r[j] @ r[i]) / sigma[i]
+                r[j] = r[j] - tau[i, j] * r[i]
+            sigma[j] = r[j] @ r[j]
+            if sigma[j] == 0.0:
+                return finish(BREAKDOWN, k)
+            gp[j] = (r[0] @ r[j]) / sigma[j]
+        g = np.zeros(ell + 1)            # gamma, by back substitution
+        g[ell] = gp[ell]
+        omega = g[ell]
+        for j in range(ell - 1, 0, -1):
+            g[j] = gp[j] - sum(tau[j, i] * g[i] for i in range(j + 1, ell + 1))
+        gpp = np.zeros(ell + 1)          # gamma''
+        for j in range(1, ell):
+            gpp[j] = g[j + 1] + sum(tau[j, i] * g[i + 1] for i in range(j + 1, ell))
+        d = d + g[1] * r[0]
+        r[0] = r[0] - gp[ell] * r[ell]
+        u[0] = u[0] - g[ell] * u[ell]
+        for j in range(1, ell):
+            u[0] = u[0] - g[j] * u[j]
+            d = d + gpp[j] * r[j]
+            r[0] = r[0] - gp[j] * r[j]
+        if observe:
+            observe(k, before, r[0].copy(), rt)
+        hist.append(np.linalg.norm(r[0]) / bnorm)
+        if not np.isfinite(hist[-1]):
+            return finish(BREAKDOWN, k)
+        if hist[-1] <= rtol:
+            return finish(OK, k)
+        if omega == 0.0:
+            return finish(BREAKDOWN, k)
+    return finish(NOCONV, maxiter)

@@ -14,7 +14,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .deflation import Deflation, DeflationError
-from .krylov import deflated_cg, deflated_bicgstab, OK, NOCONV, BREAKDOWN
+from .krylov import deflated_cg, deflated_bicgstab, deflated_bicgstabl, OK, NOCONV, BREAKDOWN
 from .vcycle import BlockAMG
 
 
@@ -24,7 +24,8 @@ class OracleError(Exception):
 
 @dataclass
 class OracleParams:
-    solver: str = "cg"              # "cg" or "bicgstab"
+    solver: str = "cg"              # "cg", "bicgstab" or "bicgstabl"
+    ell: int = 2                    # BiCGStab(ell)
     rtol: float = 1e-8
     maxiter: int = 1000
     smoother: str = "spai0"         # "spai0" or "jacobi"
@@ -92,6 +93,9 @@ class OracleSolver:
         elif prm.solver == "bicgstab":
             y, iters, hist, status = deflated_bicgstab(
                 self.A, self.defl, self.precond, b, y0, rtol, maxiter)
+        elif prm.solver == "bicgstabl":
+            y, iters, hist, status = deflated_bicgstabl(
+                self.A, self.defl, self.precond, b, y0, rtol, maxiter, ell=prm.ell)
         else:
             raise OracleError(prm.solver)
         bnorm = np.linalg.norm(b)

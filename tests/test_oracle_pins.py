@@ -381,6 +381,66 @@ def test_bicgstab_nonsymmetric_matches_dense_solve(pieces, defl):
     assert np.linalg.norm(res["x"] - xd) <= 1e-10 * np.linalg.norm(xd)
 
 
+@pytest.mark.parametrize("ell", [1, 2, 3])
+@pytest.mark.parametrize("pieces,defl", [((1, 1, 1), "constant"), ((2, 2, 1), "linear")])
+def test_bicgstabl_nonsymmetric_matches_dense_solve(ell, pieces, defl):
+    N = 8
+    A = convection_diffusion7(N, peclet=3.0)
+    base = tiny_problem(N=N, pieces=pieces, deflation=defl, seed=2)
+    S = OracleSolver(A, base.part, base.nsub, base.Z,
+                     OracleParams(solver="bicgstabl", ell=ell, rtol=1e-13, coarse_enough=10))
+    res = S.solve(base.b)
+    xd = np.linalg.solve(A.toarray(), base.b)
+    assert res["status"] == "ok"
+    assert np.linalg.norm(res["x"] - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+def test_bicgstabl_with_ell_1_is_bicgstab():
+    """BiCGStab(1) is BiCGStab: the same residual after every full step
+    (Sleijpen & Fokkema's construction reduces to van der Vorst's)."""
+    N = 10
+    A = convection_diffusion7(N, peclet=2.0)
+    base = tiny_problem(N=N, pieces=(2, 1, 1), deflation="linear", seed=3)
+    kw = dict(rtol=1e-11, coarse_enough=20)
+    r1 = OracleSolver(A, base.part, base.nsub, base.Z,
+                      OracleParams(solver="bicgstab", **kw)).solve(base.b)
+    rl = OracleSolver(A, base.part, base.nsub, base.Z,
+                      OracleParams(solver="bicgstabl", ell=1, **kw)).solve(base.b)
+    k = min(len(r1["history"]), len(rl["history"])) - 1   # the last may be a half step
+    assert k >= 5
+    assert np.allclose(rl["history"][:k], r1["history"][:k], rtol=1e-8, atol=0)
+    assert np.linalg.norm(rl["x"] - r1["x"]) <= 1e-8 * np.linalg.norm(r1["x"])
+
+
+@pytest.mark.parametrize("ell", [2, 3])
+def test_bicgstabl_cycle_properties(ell):
+    """Per cycle: the BiCG part leaves the last residual orthogonal to the
+    shadow vector, and the minimal-residual part returns the least-squares
+    residual of r_0 over r_1 .. r_ell (orthogonal to each of them, and equal
+    to the one numpy's lstsq gives)."""
+    from oracle.krylov import deflated_bicgstabl
+    N = 8
+    A = convection_diffusion7(N, peclet=4.0)
+    base = tiny_problem(N=N, pieces=(2, 1, 1), deflation="constant", seed=4)
+    S = OracleSolver(A, base.part, base.nsub, base.Z, OracleParams(coarse_enough=10))
+    seen = []
+
+    def observe(k, before, after, rt):
+        R = np.column_stack(before[1:])
+        g, *_ = np.linalg.lstsq(R, before[0], rcond=None)
+        ls = before[0] - R @ g
+        scale = np.linalg.norm(before[0])
+        assert np.linalg.norm(after - ls) <= 1e-9 * scale
+        for j in range(1, ell + 1):
+            assert abs(after @ before[j]) <= 1e-9 * scale * np.linalg.norm(before[j])
+        assert abs(before[ell - 1] @ rt) <= 1e-9 * np.linalg.norm(before[ell - 1]) * np.linalg.norm(rt)
+        seen.append(k)
+
+    deflated_bicgstabl(A, S.defl, S.precond, base.b, np.zeros(A.shape[0]), 1e-10, 50,
+                       ell=ell, observe=observe)
+    assert len(seen) >= 2
+
+
 def test_plain_cg_reduction_matches_scipy():
     # Z empty and M = I: textbook CG; scipy's cg counts the same iterations
     P = tiny_problem(N=12, pieces=(1, 1, 1), sigma=1.0, seed=9)
