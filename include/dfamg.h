@@ -51,14 +51,17 @@ typedef enum {
     DFAMG_ENOGPU = 8       /* no usable gfx950 device                         */
 } dfamg_status;
 
-enum { DFAMG_SOLVER_CG = 0, DFAMG_SOLVER_BICGSTAB = 1 };
+enum { DFAMG_SOLVER_CG = 0, DFAMG_SOLVER_BICGSTAB = 1, DFAMG_SOLVER_BICGSTAB2 = 2 };
 enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
 enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1 };
 enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2 };
 enum { DFAMG_PRECOND_AMG = 0, DFAMG_PRECOND_NONE = 1 };
 
 typedef struct {
-    int32_t solver;         /* DFAMG_SOLVER_*; CG needs a symmetric A          */
+    int32_t solver;         /* DFAMG_SOLVER_*; CG needs a symmetric A; one
+                               BiCGStab(2) iteration is one cycle of two BiCG
+                               steps and the minimal-residual step (four
+                               operator products)                             */
     int32_t maxiter;        /* iteration limit (default 1000)                  */
     double  rtol;           /* stop when ||r_k|| <= rtol ||b|| (default 1e-8)  */
     int32_t precision;      /* DFAMG_PREC_FP64: whole path FP64; MIXED: AMG

@@ -16,7 +16,7 @@ OK, EINVAL, ENOMEM, ESINGULAR, ENOCONV, EBREAKDOWN, ENAN, EHIP, ENOGPU = range(9
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESINGULAR: "ESINGULAR",
                 ENOCONV: "ENOCONV", EBREAKDOWN: "EBREAKDOWN", ENAN: "ENAN",
                 EHIP: "EHIP", ENOGPU: "ENOGPU"}
-SOLVER_CG, SOLVER_BICGSTAB = 0, 1
+SOLVER_CG, SOLVER_BICGSTAB, SOLVER_BICGSTAB2 = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 SMOOTHER_SPAI0, SMOOTHER_JACOBI = 0, 1
 FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL = 0, 1, 2

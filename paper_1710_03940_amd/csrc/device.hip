@@ -896,6 +896,12 @@ struct Handle {
     // BiCGStab: r~, v, p^, s^, s, t
     double *rt = nullptr, *v = nullptr, *ph = nullptr, *sh = nullptr, *sv = nullptr, *tv = nullptr;
     bool bicg() const { return prm.solver == DFAMG_SOLVER_BICGSTAB; }
+    // BiCGStab(2): r^_1, r^_2, u^_0 .. u^_2, the iterate d of K d = r_0, and
+    // the preconditioner's output (r^_0 is r, r~ is rt)
+    double *b2r1 = nullptr, *b2r2 = nullptr, *b2u0 = nullptr, *b2u1 = nullptr, *b2u2 = nullptr, *b2d = nullptr,
+           *b2tmp = nullptr;
+    SysState *states_running = nullptr;     // all running: for the final M^{-1} d
+    bool bicg2() const { return prm.solver == DFAMG_SOLVER_BICGSTAB2; }
     // partials and state
     double *part_A = nullptr, *part_rows = nullptr, *part_rs = nullptr, *part_rs_job = nullptr;
     int32_t *d_sys_cjob_off0 = nullptr;
@@ -935,6 +941,7 @@ struct Handle {
                        int with_p0);
     void iteration(hipStream_t st);
     void iteration_bicg(hipStream_t st);
+    void iteration_bicg2(hipStream_t st);
     void initial(hipStream_t st);
     void finish(hipStream_t st);
     void precond(hipStream_t st, const double *rin, double *sout, bool profiled = false);
@@ -1081,8 +1088,20 @@ void Handle::setup_device() {
         sv = ar.alloc<double>(n);
         tv = ar.alloc<double>(n);
     }
+    if (bicg2()) {
+        rt = ar.alloc<double>(n);
+        b2r1 = ar.alloc<double>(n);
+        b2r2 = ar.alloc<double>(n);
+        b2u0 = ar.alloc<double>(n);
+        b2u1 = ar.alloc<double>(n);
+        b2u2 = ar.alloc<double>(n);
+        b2d = ar.alloc<double>(n);
+        b2tmp = ar.alloc<double>(n);
+        states_running = ar.alloc<SysState>(nsys);
+        HIP_CHECK(hipMemsetAsync(states_running, 0, sizeof(SysState) * nsys, sm));
+    }
     part_A = ar.alloc<double>((size_t)A.ntiles * (ndv + 1));
-    part_rows = ar.alloc<double>((size_t)nrow_tiles * std::max(ndv + 1, 2));
+    part_rows = ar.alloc<double>((size_t)nrow_tiles * std::max(ndv + 1, 3));
     HIP_CHECK(hipHostMalloc((void **)&h_states, sizeof(SysState) * nsys, hipHostMallocDefault));
     hist_stride = prm.maxiter + 1;
     hist = ar.alloc<double>((size_t)nsys * hist_stride);
@@ -1280,6 +1299,57 @@ void Handle::iteration_bicg(hipStream_t st) {
     prof.mark(KID_TEST, 1, st);
 }
 
+// One BiCGStab(2) cycle on K = P A M^{-1} (see the kernels' comments)
+void Handle::iteration_bicg2(hipStream_t st) {
+    const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock), gs(nsys()), wb(kWideBlock);
+    const int nt = nrow_tiles;
+    double *r0 = r, *r1 = b2r1, *r2 = b2r2, *u0 = b2u0, *u1 = b2u1, *u2 = b2u2;
+    // out = K in, with the partial (other, out) in partial region `region`
+    auto K = [&](const double *in, double *out, const double *other, int region, bool profiled) {
+        precond(st, in, b2tmp, profiled);
+        outer(3, st, b2tmp, nullptr, q, profiled);
+        if (profiled) prof.mark(KID_PROJECT, 0, st);
+        project_solve(st, true, d_subto_A, part_A, A.ntiles, 0);
+        if (profiled) prof.mark(KID_PROJECT, 1, st);
+        with_ndv(ndv(), [&](auto c) {
+            hipLaunchKernelGGL((k_bicg_proj<0, decltype(c)::value>), gr, bl, 0, st, rows, nt, q, out, other, ndv(),
+                               AZown, AZoffp, AZoffc, AZoffv, t2, part_rows + (int64_t)region * nt, nt, states,
+                               d_sub_sys);
+        });
+    };
+    auto scalar = [&](auto kern) {
+        hipLaunchKernelGGL(kern, gs, wb, 0, st, part_rows, nt, d_sto_rows, states, hist, hist_stride, prm.rtol,
+                           prm.maxiter);
+    };
+    // first BiCG step
+    scalar(k_bl_scalar<0>);
+    hipLaunchKernelGGL(k_bl_u, gr, bl, 0, st, rows, nt, r0, u0, (const double *)nullptr, (double *)nullptr, states,
+                       d_sub_sys);
+    K(u0, u1, rt, 0, true);
+    scalar(k_bl_scalar<2>);
+    hipLaunchKernelGGL(k_bl_r, gr, bl, 0, st, rows, nt, r0, u1, (double *)nullptr, (const double *)nullptr, b2d, u0,
+                       part_rows, nt, states, d_sub_sys);
+    K(r0, r1, rt, 0, false);
+    // second BiCG step
+    scalar(k_bl_scalar<1>);
+    hipLaunchKernelGGL(k_bl_u, gr, bl, 0, st, rows, nt, r0, u0, r1, u1, states, d_sub_sys);
+    K(u1, u2, rt, 0, false);
+    scalar(k_bl_scalar<2>);
+    hipLaunchKernelGGL(k_bl_r, gr, bl, 0, st, rows, nt, r0, u1, r1, u2, b2d, u0, part_rows, nt, states, d_sub_sys);
+    K(r1, r2, r1, 2, false);
+    // minimal-residual step
+    scalar(k_bl_scalar<3>);
+    hipLaunchKernelGGL(k_bl_mgs, gr, bl, 0, st, rows, nt, r0, r1, r2, part_rows, nt, states, d_sub_sys);
+    scalar(k_bl_scalar<4>);
+    prof.mark(KID_UPDATE, 0, st);
+    hipLaunchKernelGGL(k_bl_final, gr, bl, 0, st, rows, nt, b2d, r0, r1, r2, u0, u1, u2, rt, part_rows, nt, states,
+                       d_sub_sys);
+    prof.mark(KID_UPDATE, 1, st);
+    prof.mark(KID_TEST, 0, st);
+    scalar(k_bl_scalar<5>);
+    prof.mark(KID_TEST, 1, st);
+}
+
 // r0 = P(b - A y0), stopping test, s0 = M^{-1} r0, rho0, p0 = s0
 void Handle::initial(hipStream_t st) {
     const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
@@ -1302,6 +1372,15 @@ void Handle::initial(hipStream_t st) {
                            d_sto_rows, states, hist, hist_stride, prm.rtol, prm.maxiter);
         return;
     }
+    if (bicg2()) {
+        // r~ = r0, d = u0 = 0, rho0 = omega = 1, alpha = 0, (r0, r~) = ||r0||^2
+        hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, r, rt);
+        hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, (const double *)nullptr, b2d);
+        hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, (const double *)nullptr, b2u0);
+        hipLaunchKernelGGL(k_bl_scalar<6>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, nrow_tiles, d_sto_rows,
+                           states, hist, hist_stride, prm.rtol, prm.maxiter);
+        return;
+    }
     precond(st, r, s);
     hipLaunchKernelGGL(k_rho<1>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
                        d_sys_cjob_off0, states);
@@ -1312,6 +1391,13 @@ void Handle::initial(hipStream_t st) {
 void Handle::finish(hipStream_t st) {
     const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
     if (bicg()) hipLaunchKernelGGL(k_bicg_halffix, gr, bl, 0, st, rows, nrow_tiles, y, ph, states, d_sub_sys);
+    if (bicg2()) {
+        // y = y0 + M^{-1} d, the preconditioner run for every system
+        if (M) M->apply(st, b2d, b2tmp, part_rs, part_rs_job, states_running, d_sub_sys, nullptr);
+        else hipLaunchKernelGGL(k_identity, gr, bl, 0, st, rows, nrow_tiles, b2d, b2tmp, part_rs, states_running,
+                                d_sub_sys);
+        hipLaunchKernelGGL(k_axpy1, gr, bl, 0, st, rows, nrow_tiles, b2tmp, y);
+    }
     outer(1, st, y, b, w);
     project_solve(st, false, d_subto_A, part_A, A.ntiles, 0);
     with_ndv(ndv(), [&](auto c) {
@@ -1328,6 +1414,7 @@ void Handle::launch_iterations(int k) {
         for (int i = 0; i < k; ++i) {
             prof.slot = i;
             if (bicg()) iteration_bicg(stream);
+            else if (bicg2()) iteration_bicg2(stream);
             else iteration(stream);
         }
         return;
@@ -1338,6 +1425,7 @@ void Handle::launch_iterations(int k) {
         for (int i = 0; i < prm.graph_iters; ++i) {
             prof.slot = i;
             if (bicg()) iteration_bicg(cap_stream);
+            else if (bicg2()) iteration_bicg2(cap_stream);
             else iteration(cap_stream);
         }
         HIP_CHECK(hipStreamEndCapture(cap_stream, &graph));

@@ -654,7 +654,8 @@ HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes,
 namespace {
 
 void validate_params(const dfamg_params &p) {
-    if (p.solver != DFAMG_SOLVER_CG && p.solver != DFAMG_SOLVER_BICGSTAB) fail(DFAMG_EINVAL, "unknown solver");
+    if (p.solver != DFAMG_SOLVER_CG && p.solver != DFAMG_SOLVER_BICGSTAB && p.solver != DFAMG_SOLVER_BICGSTAB2)
+        fail(DFAMG_EINVAL, "unknown solver");
     if (p.maxiter < 0) fail(DFAMG_EINVAL, "maxiter must be >= 0");
     if (!(p.rtol >= 0.0) || !std::isfinite(p.rtol)) fail(DFAMG_EINVAL, "rtol must be finite and >= 0");
     if (p.precision != DFAMG_PREC_FP64 && p.precision != DFAMG_PREC_MIXED) fail(DFAMG_EINVAL, "unknown precision");

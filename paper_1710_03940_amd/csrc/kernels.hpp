@@ -44,6 +44,7 @@ struct SysState {
     double relres;                   // ||r|| / ||b|| of the last test
     double tt, ts;                   // BiCGStab (t,t), (t,s)
     double rho_old, pad0;
+    double bl[8];                    // BiCGStab(2): see the kBl* slots below
     int32_t iter;
     int32_t done;                    // 0 running, 1 converged, 2 maxiter, 3 nan, 4 breakdown
     int32_t half;                    // BiCGStab: stopped on the half step
@@ -51,6 +52,10 @@ struct SysState {
 };
 
 enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kNaN = 3, kBreakdown = 4 };
+
+// BiCGStab(2) scalars in SysState::bl (rho0 lives in rho, alpha, beta, omega
+// in their fields)
+enum { kBlRhoNext = 0, kBlTau = 1, kBlSigma1 = 2, kBlG1p = 3, kBlG2p = 4, kBlG1 = 5, kBlG2 = 6 };
 
 // ---------------------------------------------------------------------------
 // matrix views
@@ -856,6 +861,241 @@ static __global__ void __launch_bounds__(kBlock) k_bicg_halffix(const DevTile *_
     if (!S.half) return;
     const double a = S.alpha;
     for_tile_rows(T, [&](int row) { y[row] += a * ph[row]; });
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab(2) (Sleijpen & Fokkema) on K = P A M^{-1}: K d = r_0 from d = 0,
+// y = y_0 + M^{-1} d at the end.  One cycle: two BiCG steps (u^ and r^
+// sequences, four products with K), then the minimal-residual step over
+// r^_1, r^_2 (modified Gram-Schmidt).  The vector kernels below carry the
+// updates between the products, each with the dot products the next scalar
+// step needs as tile partials.
+// ---------------------------------------------------------------------------
+
+// u0 = r0 - beta u0 (first BiCG step)
+static __global__ void __launch_bounds__(kBlock) k_bl_u(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                        const double *__restrict__ r0, double *__restrict__ u0,
+                                                        const double *__restrict__ r1, double *__restrict__ u1,
+                                                        const SysState *__restrict__ st,
+                                                        const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const SysState &S = st[sub_sys[T.sub]];
+    if (S.done) return;
+    const double beta = S.beta;
+    // second BiCG step also updates u1 = r1 - beta u1 (r1 non-null)
+    for_tile_rows(T, [&](int row) {
+        u0[row] = r0[row] - beta * u0[row];
+        if (r1) u1[row] = r1[row] - beta * u1[row];
+    });
+}
+
+// r0 -= alpha u1, d += alpha u0; second BiCG step (r1 non-null) also
+// r1 -= alpha u2 with partials (r1, r1), (r0, r1)
+static __global__ void __launch_bounds__(kBlock) k_bl_r(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                        double *__restrict__ r0, const double *__restrict__ u1,
+                                                        double *__restrict__ r1, const double *__restrict__ u2,
+                                                        double *__restrict__ d, const double *__restrict__ u0,
+                                                        double *__restrict__ part, int32_t nslots,
+                                                        const SysState *__restrict__ st,
+                                                        const int32_t *__restrict__ sub_sys) {
+    __shared__ double lds[4];
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const SysState &S = st[sub_sys[T.sub]];
+    if (S.done) return;
+    const double a = S.alpha;
+    double d0 = 0.0, d1 = 0.0;
+    for_tile_rows(T, [&](int row) {
+        const double r0n = r0[row] - a * u1[row];
+        r0[row] = r0n;
+        d[row] += a * u0[row];
+        if (r1) {
+            const double r1n = r1[row] - a * u2[row];
+            r1[row] = r1n;
+            d0 += r1n * r1n;
+            d1 += r0n * r1n;
+        }
+    });
+    if (!r1) return;
+    const double s0 = block_sum(d0, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = s0;
+    const double s1 = block_sum(d1, lds, kBlock);
+    if (threadIdx.x == 0) part[(int64_t)nslots + T.slot] = s1;
+}
+
+// r2 -= tau r1 (Gram-Schmidt) with partials (r2, r2), (r0, r2)
+static __global__ void __launch_bounds__(kBlock) k_bl_mgs(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                          const double *__restrict__ r0, const double *__restrict__ r1,
+                                                          double *__restrict__ r2, double *__restrict__ part,
+                                                          int32_t nslots, const SysState *__restrict__ st,
+                                                          const int32_t *__restrict__ sub_sys) {
+    __shared__ double lds[4];
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const SysState &S = st[sub_sys[T.sub]];
+    if (S.done) return;
+    const double tau = S.bl[kBlTau];
+    double d0 = 0.0, d1 = 0.0;
+    for_tile_rows(T, [&](int row) {
+        const double v = r2[row] - tau * r1[row];
+        r2[row] = v;
+        d0 += v * v;
+        d1 += r0[row] * v;
+    });
+    const double s0 = block_sum(d0, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = s0;
+    const double s1 = block_sum(d1, lds, kBlock);
+    if (threadIdx.x == 0) part[(int64_t)nslots + T.slot] = s1;
+}
+
+// end of a cycle: d += g1 r0 + g2 r1; r0 -= g2' r2, then -= g1' r1;
+// u0 -= g2 u2, then -= g1 u1; partials (r0, r0), (r0, r~)
+static __global__ void __launch_bounds__(kBlock) k_bl_final(
+    const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ d, double *__restrict__ r0,
+    const double *__restrict__ r1, const double *__restrict__ r2, double *__restrict__ u0,
+    const double *__restrict__ u1, const double *__restrict__ u2, const double *__restrict__ rt,
+    double *__restrict__ part, int32_t nslots, const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    __shared__ double lds[4];
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const SysState &S = st[sub_sys[T.sub]];
+    if (S.done) return;
+    const double g1 = S.bl[kBlG1], g2 = S.bl[kBlG2], g1p = S.bl[kBlG1p], g2p = S.bl[kBlG2p];
+    double d0 = 0.0, d1 = 0.0;
+    for_tile_rows(T, [&](int row) {
+        const double a0 = r0[row], a1 = r1[row];
+        d[row] += g1 * a0;
+        d[row] += g2 * a1;       // gamma''_1 = gamma_2 for ell = 2
+        double rn = a0 - g2p * r2[row];
+        rn -= g1p * a1;
+        r0[row] = rn;
+        double un = u0[row] - g2 * u2[row];
+        un -= g1 * u1[row];
+        u0[row] = un;
+        d0 += rn * rn;
+        d1 += rt[row] * rn;
+    });
+    const double s0 = block_sum(d0, lds, kBlock);
+    if (threadIdx.x == 0) part[T.slot] = s0;
+    const double s1 = block_sum(d1, lds, kBlock);
+    if (threadIdx.x == 0) part[(int64_t)nslots + T.slot] = s1;
+}
+
+// dst += src
+static __global__ void __launch_bounds__(kBlock) k_axpy1(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                         const double *__restrict__ src, double *__restrict__ dst) {
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    for_tile_rows(T, [&](int row) { dst[row] += src[row]; });
+}
+
+// Per-system scalar steps of BiCGStab(2) (1024 threads, sums of partials):
+//   STEP 0 (cycle start): rho0 = -omega rho0, rho1 = (r0, r~) kept from the
+//                         last test, beta = alpha rho1 / rho0, rho0 = rho1
+//   STEP 1 (second step): rho1 = (r1, r~) from partials, beta and rho0 as above
+//   STEP 2 (alpha):       alpha = rho0 / (u_{j+1}, r~)
+//   STEP 3 (MR, first):   sigma1 = (r1, r1), tau = (r2, r1) / sigma1,
+//                         g1' = (r0, r1) / sigma1 (three partial regions)
+//   STEP 4 (MR, second):  sigma2 = (r2, r2), g2' = (r0, r2) / sigma2, g2 = g2',
+//                         omega = g2, g1 = g1' - tau g2
+//   STEP 5 (test):        ||r0|| / ||b||, iteration, history, stop test,
+//                         (r0, r~) kept for the next cycle
+//   STEP 6 (init):        rho0 = omega = 1, alpha = 0, (r0, r~) = ||r0||^2
+// A zero rho, (u, r~) or sigma is a breakdown; one in the BiCG part leaves the
+// cycle uncounted, one in the MR part counts it.
+template <int STEP>
+__global__ void __launch_bounds__(kWideBlock) k_bl_scalar(const double *__restrict__ part, int32_t nslots,
+                                                          const int32_t *__restrict__ sys_tile_off,
+                                                          SysState *__restrict__ st, double *__restrict__ hist,
+                                                          int32_t hist_stride, double rtol, int32_t maxiter) {
+    __shared__ double lds[16];
+    const int sys = blockIdx.x;
+    SysState &S = st[sys];
+    if (STEP != 6 && S.done) return;
+    constexpr bool two = STEP == 3 || STEP == 4 || STEP == 5;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (STEP == 1 || STEP == 2 || two) {
+        for (int tl = sys_tile_off[sys] + threadIdx.x; tl < sys_tile_off[sys + 1]; tl += kWideBlock) {
+            a0 += part[tl];
+            if (two) a1 += part[(int64_t)nslots + tl];
+            if (STEP == 3) a2 += part[2 * (int64_t)nslots + tl];
+        }
+    }
+    const double s0 = (STEP == 1 || STEP == 2 || two) ? block_sum(a0, lds, kWideBlock) : 0.0;
+    const double s1 = two ? block_sum(a1, lds, kWideBlock) : 0.0;
+    const double s2 = STEP == 3 ? block_sum(a2, lds, kWideBlock) : 0.0;
+    if (threadIdx.x != 0) return;
+    if (STEP == 6) {
+        S.rho = 1.0;
+        S.omega = 1.0;
+        S.alpha = 0.0;
+        S.bl[kBlRhoNext] = S.rr;
+        return;
+    }
+    if (STEP == 0 || STEP == 1) {
+        double rho0 = S.rho;
+        if (STEP == 0) rho0 = -S.omega * rho0;
+        const double rho1 = STEP == 0 ? S.bl[kBlRhoNext] : s0;
+        if (rho0 == 0.0 || rho1 == 0.0) {
+            S.done = kBreakdown;
+            return;
+        }
+        S.beta = S.alpha * rho1 / rho0;
+        S.rho = rho1;
+        return;
+    }
+    if (STEP == 2) {
+        if (s0 == 0.0) {
+            S.done = kBreakdown;
+            return;
+        }
+        S.alpha = S.rho / s0;
+        return;
+    }
+    if (STEP == 3) {
+        // s0 = (r1, r1), s1 = (r0, r1), s2 = (r2, r1)
+        const double sig = s0;
+        if (sig == 0.0) {
+            S.iter = S.iter + 1;
+            S.done = kBreakdown;
+            return;
+        }
+        S.bl[kBlSigma1] = sig;
+        S.bl[kBlG1p] = s1 / sig;
+        S.bl[kBlTau] = s2 / sig;
+        return;
+    }
+    if (STEP == 4) {
+        if (s0 == 0.0) {
+            S.iter = S.iter + 1;
+            S.done = kBreakdown;
+            return;
+        }
+        const double g2p = s1 / s0;
+        S.bl[kBlG2p] = g2p;
+        S.bl[kBlG2] = g2p;
+        S.omega = g2p;
+        S.bl[kBlG1] = S.bl[kBlG1p] - S.bl[kBlTau] * g2p;
+        return;
+    }
+    // STEP 5
+    const double h = sqrt(s0 / S.bb);
+    const int it = S.iter + 1;
+    S.iter = it;
+    S.rr = s0;
+    S.relres = h;
+    S.bl[kBlRhoNext] = s1;
+    if (it < hist_stride) hist[(int64_t)sys * hist_stride + it] = h;
+    if (!isfinite(h)) S.done = kNaN;
+    else if (h <= rtol) S.done = kConverged;
+    else if (it >= maxiter) S.done = kMaxIter;
+    else if (S.omega == 0.0) S.done = kBreakdown;
 }
 
 // dst = src (used for r~ = r0 and zero-filled vectors)

@@ -129,3 +129,88 @@ def test_bicgstab_maxiter():
     out = S.solve(_t(P.b), _t(np.zeros(P.n)))
     S.close()
     assert out["status"] == L._lib.ENOCONV and out["iters"] == 2
+
+
+# --------------------------------------------------------------------------
+# BiCGStab(2): the library's "bicgstab2" against the oracle's BiCGStab(ell=2)
+# --------------------------------------------------------------------------
+
+def _pair2(P, kw, gpu_extra=None, x0=None):
+    return _pair_named(P, dict(kw, solver="bicgstabl", ell=2), dict(kw, solver="bicgstab2", **(gpu_extra or {})),
+                       x0=x0)
+
+
+def _pair_named(P, okw, gkw, x0=None):
+    import paper_1710_03940_amd as L
+    print(f"case {P.name} n={P.n} nsub={P.nsub} ndv={P.ndv} {gkw}", flush=True)
+    ref = OracleSolver(P.A, P.part, P.nsub, P.Z, OracleParams(**okw)).solve(P.b, x0=x0)
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, **gkw)
+    x = _t(np.zeros(P.n) if x0 is None else x0)
+    out = S.solve(_t(P.b), x)
+    out["x"] = x.cpu().numpy()
+    S.close()
+    print(f"  gpu iters {out['iters']} status {out['status']} relres_true {out['relres_true']:.3e}"
+          f" | oracle iters {ref['iters']} {ref['status']}", flush=True)
+    return ref, out
+
+
+@pytest.mark.parametrize("N,pieces,deflation,peclet,ce", [
+    (12, (2, 2, 1), "linear", 2.0, 40),
+    (10, (2, 1, 1), "constant", 5.0, 20),
+    (15, (1, 3, 1), "linear", 0.0, 500),      # symmetric (pure diffusion)
+])
+def test_bicgstab2_fp64_parity(N, pieces, deflation, peclet, ce):
+    P = _convdiff(N, pieces, deflation, peclet, seed=N + 1)
+    ref, out = _pair2(P, dict(coarse_enough=ce))
+    _check(ref, out)
+    h, g = out["history"], ref["history"]
+    k = min(len(h), len(g), 5)
+    assert np.allclose(h[:k], g[:k], rtol=1e-7)
+
+
+def test_bicgstab2_oseen_fp64_and_mixed():
+    P = config_oseen(N=16, pieces=(2, 2, 1))
+    ref, out = _pair2(P, dict(block_size=4))
+    _check(ref, out)
+    ref, out = _pair2(P, dict(block_size=4), dict(precision="mixed"))
+    assert out["status"] == 0
+    assert out["relres_true"] <= 1e-8 * (1 + 1e-6)
+    assert out["iters"] <= int(np.floor(ref["iters"] * 1.15)) + 1
+    assert np.linalg.norm(out["x"] - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+
+
+@pytest.mark.parametrize("rtol", [1e-3, 1e-5, 1e-7])
+def test_bicgstab2_stops_like_oracle(rtol):
+    P = _convdiff(9, (3, 1, 1), "constant", 3.0, seed=4)
+    ref, out = _pair2(P, dict(coarse_enough=30, rtol=rtol))
+    _check(ref, out, iters_tol=0, sol_tol=1e-9, rtol=rtol)
+
+
+def test_bicgstab2_initial_guess_and_no_preconditioner():
+    P = _convdiff(11, (1, 2, 2), "linear", 2.0, seed=6)
+    x0 = np.random.default_rng(9).standard_normal(P.n)
+    ref, out = _pair2(P, dict(coarse_enough=30), x0=x0)
+    _check(ref, out)
+    ref, out = _pair_named(P, dict(solver="bicgstabl", ell=2, precond="identity"),
+                           dict(solver="bicgstab2", precond="none"))
+    _check(ref, out)
+
+
+def test_bicgstab2_batched_equals_standalone():
+    import paper_1710_03940_amd as L
+    from workloads import concat_problems
+    probs = [_convdiff(n, pc, "linear", 2.0, seed=n) for n, pc in [(9, (2, 1, 1)), (12, (2, 2, 1))]]
+    A, part, nsub, Z, b, x0, off = concat_problems(probs)
+    kw = dict(solver="bicgstab2", coarse_enough=30, autotune=0)
+    S = L.BatchedSolver(A, part, nsub, Z, off, **kw)
+    xb = _t(np.zeros(A.shape[0]))
+    outb = S.solve(_t(b), xb)
+    S.close()
+    xb = xb.cpu().numpy()
+    for s, p in enumerate(probs):
+        S1 = L.Solver(p.A, p.part, p.nsub, p.Z, **kw)
+        x1 = _t(np.zeros(p.n))
+        o1 = S1.solve(_t(p.b), x1)
+        S1.close()
+        assert int(outb["iters"][s]) == o1["iters"]
+        assert np.array_equal(xb[off[s]:off[s + 1]], x1.cpu().numpy())
