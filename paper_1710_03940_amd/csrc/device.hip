@@ -896,11 +896,10 @@ struct Handle {
     // BiCGStab: r~, v, p^, s^, s, t
     double *rt = nullptr, *v = nullptr, *ph = nullptr, *sh = nullptr, *sv = nullptr, *tv = nullptr;
     bool bicg() const { return prm.solver == DFAMG_SOLVER_BICGSTAB; }
-    // BiCGStab(2): r^_1, r^_2, u^_0 .. u^_2, the iterate d of K d = r_0, and
-    // the preconditioner's output (r^_0 is r, r~ is rt)
-    double *b2r1 = nullptr, *b2r2 = nullptr, *b2u0 = nullptr, *b2u1 = nullptr, *b2u2 = nullptr, *b2d = nullptr,
-           *b2tmp = nullptr;
-    SysState *states_running = nullptr;     // all running: for the final M^{-1} d
+    // BiCGStab(2): r^_1, r^_2, u^_0 .. u^_2 and the preconditioned vectors
+    // pr0, pr1, pu0, pu1 (r^_0 is r, r~ is rt)
+    double *b2r1 = nullptr, *b2r2 = nullptr, *b2u0 = nullptr, *b2u1 = nullptr, *b2u2 = nullptr, *b2pr0 = nullptr,
+           *b2pr1 = nullptr, *b2pu0 = nullptr, *b2pu1 = nullptr;
     bool bicg2() const { return prm.solver == DFAMG_SOLVER_BICGSTAB2; }
     // partials and state
     double *part_A = nullptr, *part_rows = nullptr, *part_rs = nullptr, *part_rs_job = nullptr;
@@ -1095,10 +1094,10 @@ void Handle::setup_device() {
         b2u0 = ar.alloc<double>(n);
         b2u1 = ar.alloc<double>(n);
         b2u2 = ar.alloc<double>(n);
-        b2d = ar.alloc<double>(n);
-        b2tmp = ar.alloc<double>(n);
-        states_running = ar.alloc<SysState>(nsys);
-        HIP_CHECK(hipMemsetAsync(states_running, 0, sizeof(SysState) * nsys, sm));
+        b2pr0 = ar.alloc<double>(n);
+        b2pr1 = ar.alloc<double>(n);
+        b2pu0 = ar.alloc<double>(n);
+        b2pu1 = ar.alloc<double>(n);
     }
     part_A = ar.alloc<double>((size_t)A.ntiles * (ndv + 1));
     part_rows = ar.alloc<double>((size_t)nrow_tiles * std::max(ndv + 1, 3));
@@ -1304,10 +1303,11 @@ void Handle::iteration_bicg2(hipStream_t st) {
     const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock), gs(nsys()), wb(kWideBlock);
     const int nt = nrow_tiles;
     double *r0 = r, *r1 = b2r1, *r2 = b2r2, *u0 = b2u0, *u1 = b2u1, *u2 = b2u2;
-    // out = K in, with the partial (other, out) in partial region `region`
-    auto K = [&](const double *in, double *out, const double *other, int region, bool profiled) {
-        precond(st, in, b2tmp, profiled);
-        outer(3, st, b2tmp, nullptr, q, profiled);
+    // out = P A pre with pre = M^{-1} in, and the partial (other, out) in
+    // partial region `region`
+    auto K = [&](const double *in, double *pre, double *out, const double *other, int region, bool profiled) {
+        precond(st, in, pre, profiled);
+        outer(3, st, pre, nullptr, q, profiled);
         if (profiled) prof.mark(KID_PROJECT, 0, st);
         project_solve(st, true, d_subto_A, part_A, A.ntiles, 0);
         if (profiled) prof.mark(KID_PROJECT, 1, st);
@@ -1321,29 +1321,31 @@ void Handle::iteration_bicg2(hipStream_t st) {
         hipLaunchKernelGGL(kern, gs, wb, 0, st, part_rows, nt, d_sto_rows, states, hist, hist_stride, prm.rtol,
                            prm.maxiter);
     };
+    const double *cnull = nullptr;
+    double *null = nullptr;
     // first BiCG step
     scalar(k_bl_scalar<0>);
-    hipLaunchKernelGGL(k_bl_u, gr, bl, 0, st, rows, nt, r0, u0, (const double *)nullptr, (double *)nullptr, states,
-                       d_sub_sys);
-    K(u0, u1, rt, 0, true);
+    hipLaunchKernelGGL(k_bl_u, gr, bl, 0, st, rows, nt, r0, u0, cnull, null, cnull, null, states, d_sub_sys);
+    K(u0, b2pu0, u1, rt, 0, true);
     scalar(k_bl_scalar<2>);
-    hipLaunchKernelGGL(k_bl_r, gr, bl, 0, st, rows, nt, r0, u1, (double *)nullptr, (const double *)nullptr, b2d, u0,
-                       part_rows, nt, states, d_sub_sys);
-    K(r0, r1, rt, 0, false);
+    hipLaunchKernelGGL(k_bl_r, gr, bl, 0, st, rows, nt, r0, u1, null, cnull, null, cnull, y, b2pu0, part_rows, nt,
+                       states, d_sub_sys);
+    K(r0, b2pr0, r1, rt, 0, false);
     // second BiCG step
     scalar(k_bl_scalar<1>);
-    hipLaunchKernelGGL(k_bl_u, gr, bl, 0, st, rows, nt, r0, u0, r1, u1, states, d_sub_sys);
-    K(u1, u2, rt, 0, false);
+    hipLaunchKernelGGL(k_bl_u, gr, bl, 0, st, rows, nt, r0, u0, r1, u1, b2pr0, b2pu0, states, d_sub_sys);
+    K(u1, b2pu1, u2, rt, 0, false);
     scalar(k_bl_scalar<2>);
-    hipLaunchKernelGGL(k_bl_r, gr, bl, 0, st, rows, nt, r0, u1, r1, u2, b2d, u0, part_rows, nt, states, d_sub_sys);
-    K(r1, r2, r1, 2, false);
+    hipLaunchKernelGGL(k_bl_r, gr, bl, 0, st, rows, nt, r0, u1, r1, u2, b2pr0, b2pu1, y, b2pu0, part_rows, nt,
+                       states, d_sub_sys);
+    K(r1, b2pr1, r2, r1, 2, false);
     // minimal-residual step
     scalar(k_bl_scalar<3>);
     hipLaunchKernelGGL(k_bl_mgs, gr, bl, 0, st, rows, nt, r0, r1, r2, part_rows, nt, states, d_sub_sys);
     scalar(k_bl_scalar<4>);
     prof.mark(KID_UPDATE, 0, st);
-    hipLaunchKernelGGL(k_bl_final, gr, bl, 0, st, rows, nt, b2d, r0, r1, r2, u0, u1, u2, rt, part_rows, nt, states,
-                       d_sub_sys);
+    hipLaunchKernelGGL(k_bl_final, gr, bl, 0, st, rows, nt, y, b2pr0, b2pr1, r0, r1, r2, u0, u1, u2, rt, part_rows,
+                       nt, states, d_sub_sys);
     prof.mark(KID_UPDATE, 1, st);
     prof.mark(KID_TEST, 0, st);
     scalar(k_bl_scalar<5>);
@@ -1373,9 +1375,8 @@ void Handle::initial(hipStream_t st) {
         return;
     }
     if (bicg2()) {
-        // r~ = r0, d = u0 = 0, rho0 = omega = 1, alpha = 0, (r0, r~) = ||r0||^2
+        // r~ = r0, u0 = 0, rho0 = omega = 1, alpha = 0, (r0, r~) = ||r0||^2
         hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, r, rt);
-        hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, (const double *)nullptr, b2d);
         hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, (const double *)nullptr, b2u0);
         hipLaunchKernelGGL(k_bl_scalar<6>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, nrow_tiles, d_sto_rows,
                            states, hist, hist_stride, prm.rtol, prm.maxiter);
@@ -1391,13 +1392,6 @@ void Handle::initial(hipStream_t st) {
 void Handle::finish(hipStream_t st) {
     const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
     if (bicg()) hipLaunchKernelGGL(k_bicg_halffix, gr, bl, 0, st, rows, nrow_tiles, y, ph, states, d_sub_sys);
-    if (bicg2()) {
-        // y = y0 + M^{-1} d, the preconditioner run for every system
-        if (M) M->apply(st, b2d, b2tmp, part_rs, part_rs_job, states_running, d_sub_sys, nullptr);
-        else hipLaunchKernelGGL(k_identity, gr, bl, 0, st, rows, nrow_tiles, b2d, b2tmp, part_rs, states_running,
-                                d_sub_sys);
-        hipLaunchKernelGGL(k_axpy1, gr, bl, 0, st, rows, nrow_tiles, b2tmp, y);
-    }
     outer(1, st, y, b, w);
     project_solve(st, false, d_subto_A, part_A, A.ntiles, 0);
     with_ndv(ndv(), [&](auto c) {

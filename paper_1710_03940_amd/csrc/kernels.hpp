@@ -864,18 +864,23 @@ static __global__ void __launch_bounds__(kBlock) k_bicg_halffix(const DevTile *_
 }
 
 // ---------------------------------------------------------------------------
-// BiCGStab(2) (Sleijpen & Fokkema) on K = P A M^{-1}: K d = r_0 from d = 0,
-// y = y_0 + M^{-1} d at the end.  One cycle: two BiCG steps (u^ and r^
-// sequences, four products with K), then the minimal-residual step over
-// r^_1, r^_2 (modified Gram-Schmidt).  The vector kernels below carry the
-// updates between the products, each with the dot products the next scalar
-// step needs as tile partials.
+// BiCGStab(2) (Sleijpen & Fokkema) on K = P A M^{-1}.  One cycle: two BiCG
+// steps (u^ and r^ sequences, four products with K), then the
+// minimal-residual step over r^_1, r^_2 (modified Gram-Schmidt).  The iterate
+// y is updated with the preconditioned vectors whose products the residual
+// recurrence used: pu0, pu1 (u^_1 = P A pu0, u^_2 = P A pu1) and pr0, pr1
+// (r^_1 = P A pr0, r^_2 = P A pr1), kept by the same recurrences as u^ and r^,
+// so the recurrence residual stays the true one with an inexact (FP32)
+// preconditioner too.  The vector kernels carry the updates between the
+// products, each with the dot products the next scalar step needs.
 // ---------------------------------------------------------------------------
 
-// u0 = r0 - beta u0 (first BiCG step)
+// u0 = r0 - beta u0; second step (r1 non-null) also u1 = r1 - beta u1 and
+// pu0 = pr0 - beta pu0
 static __global__ void __launch_bounds__(kBlock) k_bl_u(const DevTile *__restrict__ tiles, int32_t ntiles,
                                                         const double *__restrict__ r0, double *__restrict__ u0,
                                                         const double *__restrict__ r1, double *__restrict__ u1,
+                                                        const double *__restrict__ pr0, double *__restrict__ pu0,
                                                         const SysState *__restrict__ st,
                                                         const int32_t *__restrict__ sub_sys) {
     const int tile = tile_of_block(ntiles);
@@ -884,19 +889,22 @@ static __global__ void __launch_bounds__(kBlock) k_bl_u(const DevTile *__restric
     const SysState &S = st[sub_sys[T.sub]];
     if (S.done) return;
     const double beta = S.beta;
-    // second BiCG step also updates u1 = r1 - beta u1 (r1 non-null)
     for_tile_rows(T, [&](int row) {
         u0[row] = r0[row] - beta * u0[row];
-        if (r1) u1[row] = r1[row] - beta * u1[row];
+        if (r1) {
+            u1[row] = r1[row] - beta * u1[row];
+            pu0[row] = pr0[row] - beta * pu0[row];
+        }
     });
 }
 
-// r0 -= alpha u1, d += alpha u0; second BiCG step (r1 non-null) also
-// r1 -= alpha u2 with partials (r1, r1), (r0, r1)
+// r0 -= alpha u1, y += alpha pu0; second step (r1 non-null) also
+// r1 -= alpha u2, pr0 -= alpha pu1, with partials (r1, r1), (r0, r1)
 static __global__ void __launch_bounds__(kBlock) k_bl_r(const DevTile *__restrict__ tiles, int32_t ntiles,
                                                         double *__restrict__ r0, const double *__restrict__ u1,
                                                         double *__restrict__ r1, const double *__restrict__ u2,
-                                                        double *__restrict__ d, const double *__restrict__ u0,
+                                                        double *__restrict__ pr0, const double *__restrict__ pu1,
+                                                        double *__restrict__ y, const double *__restrict__ pu0,
                                                         double *__restrict__ part, int32_t nslots,
                                                         const SysState *__restrict__ st,
                                                         const int32_t *__restrict__ sub_sys) {
@@ -911,10 +919,11 @@ static __global__ void __launch_bounds__(kBlock) k_bl_r(const DevTile *__restric
     for_tile_rows(T, [&](int row) {
         const double r0n = r0[row] - a * u1[row];
         r0[row] = r0n;
-        d[row] += a * u0[row];
+        y[row] += a * pu0[row];
         if (r1) {
             const double r1n = r1[row] - a * u2[row];
             r1[row] = r1n;
+            pr0[row] -= a * pu1[row];
             d0 += r1n * r1n;
             d1 += r0n * r1n;
         }
@@ -952,13 +961,15 @@ static __global__ void __launch_bounds__(kBlock) k_bl_mgs(const DevTile *__restr
     if (threadIdx.x == 0) part[(int64_t)nslots + T.slot] = s1;
 }
 
-// end of a cycle: d += g1 r0 + g2 r1; r0 -= g2' r2, then -= g1' r1;
+// end of a cycle: y += g1 pr0 + g2 pr1 (the iterate steps g1 r0 + g2 r1 of
+// K d = r_0, gamma''_1 = gamma_2 for ell = 2); r0 -= g2' r2, then -= g1' r1;
 // u0 -= g2 u2, then -= g1 u1; partials (r0, r0), (r0, r~)
 static __global__ void __launch_bounds__(kBlock) k_bl_final(
-    const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ d, double *__restrict__ r0,
-    const double *__restrict__ r1, const double *__restrict__ r2, double *__restrict__ u0,
-    const double *__restrict__ u1, const double *__restrict__ u2, const double *__restrict__ rt,
-    double *__restrict__ part, int32_t nslots, const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
+    const DevTile *__restrict__ tiles, int32_t ntiles, double *__restrict__ y, const double *__restrict__ pr0,
+    const double *__restrict__ pr1, double *__restrict__ r0, const double *__restrict__ r1,
+    const double *__restrict__ r2, double *__restrict__ u0, const double *__restrict__ u1,
+    const double *__restrict__ u2, const double *__restrict__ rt, double *__restrict__ part, int32_t nslots,
+    const SysState *__restrict__ st, const int32_t *__restrict__ sub_sys) {
     __shared__ double lds[4];
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
@@ -968,11 +979,11 @@ static __global__ void __launch_bounds__(kBlock) k_bl_final(
     const double g1 = S.bl[kBlG1], g2 = S.bl[kBlG2], g1p = S.bl[kBlG1p], g2p = S.bl[kBlG2p];
     double d0 = 0.0, d1 = 0.0;
     for_tile_rows(T, [&](int row) {
-        const double a0 = r0[row], a1 = r1[row];
-        d[row] += g1 * a0;
-        d[row] += g2 * a1;       // gamma''_1 = gamma_2 for ell = 2
-        double rn = a0 - g2p * r2[row];
-        rn -= g1p * a1;
+        double yn = y[row] + g1 * pr0[row];
+        yn += g2 * pr1[row];
+        y[row] = yn;
+        double rn = r0[row] - g2p * r2[row];
+        rn -= g1p * r1[row];
         r0[row] = rn;
         double un = u0[row] - g2 * u2[row];
         un -= g1 * u1[row];
@@ -984,15 +995,6 @@ static __global__ void __launch_bounds__(kBlock) k_bl_final(
     if (threadIdx.x == 0) part[T.slot] = s0;
     const double s1 = block_sum(d1, lds, kBlock);
     if (threadIdx.x == 0) part[(int64_t)nslots + T.slot] = s1;
-}
-
-// dst += src
-static __global__ void __launch_bounds__(kBlock) k_axpy1(const DevTile *__restrict__ tiles, int32_t ntiles,
-                                                         const double *__restrict__ src, double *__restrict__ dst) {
-    const int tile = tile_of_block(ntiles);
-    if (tile >= ntiles) return;
-    const DevTile T = tiles[tile];
-    for_tile_rows(T, [&](int row) { dst[row] += src[row]; });
 }
 
 // Per-system scalar steps of BiCGStab(2) (1024 threads, sums of partials):
