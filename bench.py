@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-oseen", action="store_true")
+    ap.add_argument("--no-bicgstab2", action="store_true")
     ap.add_argument("--sample-iters", type=int, default=20)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -179,6 +180,22 @@ def main():
                  "bytes_per_iter": stm["bytes_per_iter"]}
         Sm.close()
 
+    bicgstab2 = None
+    if not args.no_bicgstab2:
+        # the solver of the paper's Poisson runs, on the same problem
+        bicgstab2 = {}
+        g2 = load_golden("poisson150_lognormal2_boxes64_linear_bicgstab2")
+        for prec in ("fp64", "mixed"):
+            S2 = dfamg.Solver(P.A, P.part, P.nsub, P.Z, solver="bicgstab2", precision=prec)
+            log(f"timing BiCGStab(2) {prec}")
+            t2s, o2, it2 = time_solver(S2, b, x, args.steps, args.warmup, log)
+            S2.close()
+            bicgstab2[prec] = {"s_per_solve": t2s, "median_s": o2["median_s"], "iters": it2[-1],
+                               "relres_true": o2["relres_true"],
+                               "rel_error_vs_oracle_sampled": error_vs_oracle(x, g2)}
+        bicgstab2["oracle_iters"] = g2["iters"]
+        bicgstab2["note"] = "iterations are BiCGStab(2) cycles, four operator products each"
+
     oseen = None
     if not args.no_oseen:
         try:
@@ -236,7 +253,7 @@ def main():
         "setup_s": {"host": st64["setup_host_s"], "device": st64["setup_device_s"]},
         "bytes_per_iter": st64["bytes_per_iter"],
         "effective_GBps": st64["bytes_per_iter"] * out64["iters"] / t64 / 1e9,
-        "mixed": mixed, "batched": batched, "oseen": oseen,
+        "mixed": mixed, "batched": batched, "oseen": oseen, "bicgstab2": bicgstab2,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_outer (outer SpMV + (p,q) + Z^T q epilogue)",

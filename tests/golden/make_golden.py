@@ -75,6 +75,9 @@ if __name__ == "__main__":
         record("poisson150_lognormal2_boxes64_linear", config_lognormal_poisson())
     if "batched" in which:
         record_batched()
+    if "lognormal_bicgstab2" in which:
+        record("poisson150_lognormal2_boxes64_linear_bicgstab2", config_lognormal_poisson(),
+               OracleParams(solver="bicgstabl", ell=2))
     if "oseen" in which:
         record("oseen64_boxes256_field", config_oseen(),
                OracleParams(solver="bicgstab", block_size=4))

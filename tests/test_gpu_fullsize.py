@@ -114,3 +114,29 @@ def test_oseen64_matches_oracle(precision):
     gs = np.array(g["sample_x"])
     assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
     assert abs(np.linalg.norm(xs) - g["x_norm"]) <= 1e-6 * g["x_norm"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lognormal150_bicgstab2_matches_oracle(lognormal150, precision):
+    """BiCGStab(2), the solver of the paper's Poisson runs, on the 150^3
+    problem against the oracle's BiCGStab(ell = 2)."""
+    import paper_1710_03940_amd as L
+    P = lognormal150
+    g = _golden("poisson150_lognormal2_boxes64_linear_bicgstab2")
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, solver="bicgstab2", precision=precision)
+    dev = torch.device("cuda:0")
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    out = S.solve(torch.tensor(P.b, device=dev), x)
+    S.close()
+    print(f"bicgstab2 {precision}: gpu iters {out['iters']} oracle {g['iters']} relres_true "
+          f"{out['relres_true']:.3e}", flush=True)
+    assert out["status"] == 0
+    assert out["relres_true"] <= 1e-8
+    if precision == "fp64":
+        assert abs(out["iters"] - g["iters"]) <= 2
+    else:
+        assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
+    xs = x.cpu().numpy()
+    idx = np.array(g["sample_index"])
+    gs = np.array(g["sample_x"])
+    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
