@@ -243,3 +243,41 @@ def test_general_deflation_vectors():
     assert min(len(np.unique(Zx[P.part == s, 1])) for s in range(P.nsub)) > 256
     ref, out = _solve_pair(P2, dict(coarse_enough=30), dict(coarse_enough=30))
     _assert_parity(ref, out)
+
+
+@pytest.mark.parametrize("solver", ["cg", "bicgstab", "bicgstab2"])
+def test_one_and_two_row_subdomains(solver):
+    """Subdomains of one and two rows (solved directly on level 0) beside a
+    large one with a hierarchy; constant deflation."""
+    P = tiny_problem(N=6, pieces=(1, 1, 1), deflation="constant", sigma=1.0, seed=8)
+    part = np.full(P.n, 2, dtype=np.int32)
+    part[0] = 0
+    part[1:3] = 1
+    Z = np.ones((P.n, 1))
+    P2 = P.__class__("ragged", P.A, part, 3, Z, P.b, P.x0)
+    okw = dict(coarse_enough=10, solver="bicgstabl" if solver == "bicgstab2" else solver)
+    if solver == "bicgstab2":
+        okw["ell"] = 2
+    L = _lib()
+    ref = OracleSolver(P2.A, P2.part, P2.nsub, P2.Z, OracleParams(**okw)).solve(P2.b)
+    S = L.Solver(P2.A, P2.part, P2.nsub, P2.Z, coarse_enough=10, solver=solver)
+    x = _t(np.zeros(P2.n))
+    out = S.solve(_t(P2.b), x)
+    out["x"] = x.cpu().numpy()
+    S.close()
+    _assert_parity(ref, out)
+
+
+def test_bicgstab2_zero_rhs_and_maxiter():
+    L = _lib()
+    P = tiny_problem(N=8, pieces=(2, 1, 1))
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, coarse_enough=20, solver="bicgstab2")
+    x = _t(np.ones(P.n))
+    out = S.solve(_t(np.zeros(P.n)), x)
+    assert out["status"] == 0 and out["iters"] == 0
+    assert np.all(x.cpu().numpy() == 0.0)
+    S.close()
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, coarse_enough=20, solver="bicgstab2", maxiter=1, rtol=1e-14)
+    out = S.solve(_t(P.b), _t(np.zeros(P.n)))
+    S.close()
+    assert out["status"] == L._lib.ENOCONV and out["iters"] == 1

@@ -234,6 +234,17 @@ def test_validation_errors():
     _expect(_lib.EINVAL, P, A=A)
 
 
+def test_degenerate_inputs_rejected():
+    P = tiny_problem(N=6, pieces=(2, 1, 1), deflation="constant")
+    _expect(_lib.EINVAL, P, solver=7)                                 # unknown solver
+    empty = sp.csr_matrix((0, 0))
+    empty.indptr = empty.indptr.astype(np.int64)
+    empty.indices = empty.indices.astype(np.int32)
+    with pytest.raises((L.DfamgError, ValueError)):
+        plan = L.dfamg_plan_create(L.make_params(), empty, np.zeros(0, np.int32), 1, np.zeros((0, 1)))
+        L.dfamg_plan_destroy(plan)
+
+
 def test_rank_deficient_deflation_block_names_subdomain():
     P = make_problem("slab", (6, 6, 4), (1, 1, 4), deflation="linear")
     msg = _expect(_lib.ESINGULAR, P)
