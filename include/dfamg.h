@@ -45,7 +45,8 @@ typedef enum {
     DFAMG_ESINGULAR = 3,   /* E or a coarsest-level block is not invertible,
                               or a local deflation block is rank deficient    */
     DFAMG_ENOCONV = 4,     /* maxiter reached; outputs hold the last iterate  */
-    DFAMG_EBREAKDOWN = 5,  /* BiCGStab rho or omega became exactly zero       */
+    DFAMG_EBREAKDOWN = 5,  /* BiCGStab(2): a scalar it divides by (rho,
+                              (r~, v), omega, sigma) became exactly zero      */
     DFAMG_ENAN = 6,        /* a non-finite value appeared in the iteration    */
     DFAMG_EHIP = 7,        /* a HIP runtime call failed                       */
     DFAMG_ENOGPU = 8       /* no usable gfx950 device                         */
@@ -87,7 +88,8 @@ typedef struct {
     int32_t graph_iters;    /* Krylov iterations per captured HIP graph;
                                0 launches kernels directly (default 16)       */
     int32_t host_threads;   /* setup worker threads, 0 = hardware concurrency  */
-    int32_t verbose;        /* 1 prints setup/solve phase times to stderr      */
+    int32_t verbose;        /* 1 prints setup/solve phase times to stderr,
+                               2 also every autotuning candidate's time       */
     int32_t profile;        /* 1 records HIP events around the outer SpMV of
                                every Krylov iteration, 2 around every kernel
                                span (inside the captured graph as well);
