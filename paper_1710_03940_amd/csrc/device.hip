@@ -121,20 +121,54 @@ void tile_offsets(const std::vector<Tile> &tiles, const std::vector<int32_t> &su
     for (int i = 0; i < nsub; ++i) sub_off[i + 1] += sub_off[i];
 }
 
-// Uploads matrix M in layout L; returns false (nothing kept) when the layout
-// cannot hold M: 16-bit offsets that do not fit, or a staged column window
-// larger than the LDS budget.
+// Host form of a layout: SELL (rows per lane, row order, column width) or
+// CSR (lanes per row, rows per tile).  A staged and an unstaged candidate of
+// the same structure share one host form.
+struct HostLayout {
+    int fmt = DFAMG_FORMAT_SELL;
+    bool ok = false;          // false: 16-bit columns requested but do not fit
+    HostSell S;
+    HostCsrv C;
+};
+
+struct HostKey {
+    int fmt, par, sorted, idx16, tile_rows;
+    bool operator<(const HostKey &o) const {
+        return std::tie(fmt, par, sorted, idx16, tile_rows) < std::tie(o.fmt, o.par, o.sorted, o.idx16, o.tile_rows);
+    }
+};
+
+inline int csr_tile_rows_of(const Layout &L) { return L.rpg > 0 ? L.rpg * (kBlock / L.par) : kBlock; }
+
+HostKey host_key(const Layout &L) {
+    if (L.fmt == DFAMG_FORMAT_SELL) return HostKey{L.fmt, L.par, L.sorted ? 1 : 0, (L.idx16 || L.stage) ? 1 : 0, 0};
+    return HostKey{L.fmt, L.par, 0, 0, csr_tile_rows_of(L)};
+}
+
+void build_host_layout(const Csr &M, const std::vector<RowRange> &ranges, const HostKey &k, HostLayout &H) {
+    H.fmt = k.fmt;
+    if (k.fmt == DFAMG_FORMAT_SELL) {
+        H.ok = make_sell(M, ranges, k.par, k.sorted != 0, k.idx16 != 0, H.S);
+    } else {
+        H.C = make_csrv(M, ranges, k.par, k.tile_rows);
+        H.ok = true;
+    }
+}
+
+// Uploads the host form H as layout L; returns false (nothing kept) when the
+// layout cannot hold the matrix: 16-bit offsets that do not fit, or a staged
+// column window larger than the LDS budget.
 template <class VT>
-bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, const Layout &L,
-                   hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys, int nsub, DevMat<VT> &D,
-                   size_t stage_limit = kMaxStageBytes) {
+bool upload_built(DevArena &ar, const HostLayout &H, const Layout &L, hipStream_t s,
+                  const std::vector<int32_t> &sub_sys, int nsys, int nsub, DevMat<VT> &D,
+                  size_t stage_limit = kMaxStageBytes) {
+    if (!H.ok) return false;
     D = DevMat<VT>{};
     D.fmt = L.fmt;
     D.par = L.par;
     std::vector<Tile> tiles;
     if (L.fmt == DFAMG_FORMAT_SELL) {
-        HostSell S;
-        if (!make_sell(M, ranges, L.par, L.sorted, L.idx16 || L.stage, S)) return false;
+        const HostSell &S = H.S;
         if (L.stage) {
             const int32_t mx = S.cspan.empty() ? 1 : *std::max_element(S.cspan.begin(), S.cspan.end());
             if ((size_t)mx * sizeof(VT) > stage_limit) return false;
@@ -160,7 +194,7 @@ bool upload_layout(DevArena &ar, const Csr &M, const std::vector<RowRange> &rang
         D.nnz = S.nnz;
         D.stored = (int64_t)S.val.size();
     } else {
-        HostCsrv C = make_csrv(M, ranges, L.par, L.rpg > 0 ? L.rpg * (kBlock / L.par) : kBlock);
+        const HostCsrv &C = H.C;
         if (L.stage) {
             const int32_t mx = C.cspan.empty() ? 1 : *std::max_element(C.cspan.begin(), C.cspan.end());
             if ((size_t)mx * sizeof(VT) > stage_limit) return false;
@@ -316,8 +350,15 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
                     // smaller tiles where 256-row tiles leave the chip idle, and
                     // for restrictions (long rows gathering from a wide window)
                     if (rpg > 0 && (outer || (rows / 256 >= 2048 && kind != TUNE_RESTRICT))) continue;
-                    for (bool stage : {false, true})
-                        cand.push_back(Layout{DFAMG_FORMAT_CSR, l, false, false, stage, rpg});
+                    for (bool stage : {false, true}) {
+                        const Layout c{DFAMG_FORMAT_CSR, l, false, false, stage, rpg};
+                        // rpg values that give the same tile are one candidate
+                        bool dup = false;
+                        for (const Layout &o : cand)
+                            dup |= o.fmt == c.fmt && o.par == c.par && o.stage == c.stage &&
+                                   csr_tile_rows_of(o) == csr_tile_rows_of(c);
+                        if (!dup) cand.push_back(c);
+                    }
                 }
     }
     // a matrix tuned before in this process (same kind, value type, family and
@@ -346,15 +387,42 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     std::unique_ptr<DevArena> bestA;
     // the outer kernel also keeps its reduction slots in static LDS
     const size_t stage_limit = outer ? kMaxStageBytes - 512 : kMaxStageBytes;
+    // host forms of all candidates, built in parallel (one per distinct
+    // structure); 32-bit SELL forms for the unstaged candidates whose 16-bit
+    // offsets may not fit (the whole outer operator)
+    std::map<HostKey, HostLayout> built;
+    for (const Layout &c : cand) {
+        built[host_key(c)];
+        if (outer && c.fmt == DFAMG_FORMAT_SELL && !c.stage && c.idx16) {
+            Layout c32 = c;
+            c32.idx16 = false;
+            built[host_key(c32)];
+        }
+    }
+    {
+        std::vector<std::pair<const HostKey, HostLayout> *> jobs;
+        for (auto &kv : built) jobs.push_back(&kv);
+        parallel_for((int64_t)jobs.size(), std::min<int>(8, (int)jobs.size()),
+                     [&](int64_t j) { build_host_layout(M, ranges, jobs[j]->first, jobs[j]->second); });
+    }
+    auto form_of = [&](const Layout &c) -> const HostLayout * {
+        auto it = built.find(host_key(c));
+        if (it == built.end()) {   // a fallback not built above
+            HostLayout &H = built[host_key(c)];
+            build_host_layout(M, ranges, host_key(c), H);
+            return &H;
+        }
+        return &it->second;
+    };
     for (Layout c : cand) {
         auto A = std::make_unique<DevArena>();
         DevMat<VT> D;
-        if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D, stage_limit)) {
+        if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit)) {
             // 16-bit offsets that do not fit: fall back to 32-bit columns once
             if (c.fmt != DFAMG_FORMAT_SELL || c.stage || !c.idx16) continue;
             c.idx16 = false;
             A = std::make_unique<DevArena>();
-            if (!upload_layout<VT>(*A, M, ranges, c, s, sub_sys, nsys, nsub, D, stage_limit)) continue;
+            if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit)) continue;
         }
         const double t = cached_us >= 0.0 ? cached_us
                          : cand.size() > 1 ? (timer ? timer(D) : time_layout(kind, D, x, y, s))
