@@ -18,13 +18,13 @@ Contents (each module cites the passages it follows):
   Jacobi smoothing (sections "Implementation" and "Benchmarks");
 * `vcycle` - one V(1,1) cycle and the block-diagonal (non-overlapping local)
   preconditioner;
-* `krylov` - deflated preconditioned CG and BiCGStab;
+* `krylov` - deflated preconditioned CG, BiCGStab and BiCGStab(ell);
 * `solver` - setup + solve with the library's calling conventions.
 
 Readings of points the paper leaves open are listed in each module and in the
-design notes of the repository.  Parity status of each function is stated in
-its docstring; everything here is pinned by the CPU tests unless it says
-"parity unpinned".
+design notes of the repository.  Every function here is pinned by the CPU
+tests (tests/test_oracle_pins.py) against facts that do not come from the
+oracle itself; none is marked "parity unpinned".
 """
 from .solver import OracleSolver, OracleParams, OracleError
 
