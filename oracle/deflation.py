@@ -100,3 +100,53 @@ class Deflation:
         """x = y + Z E^{-1} Z^T (b - A y)."""
         lam = self.solve_E(self.Z.T @ (b - self.A @ y))
         return y + self.Z @ lam
+
+
+class CoarseSolve:
+    """t -> E_hat t, an approximation of E^{-1} t.
+
+    Section "On precision of the coarse system solution": an inexact inverse
+    E_hat of E is allowed once the projector is used as part of a (variable)
+    preconditioner of the original system instead of defining the deflated
+    system.  Kinds:
+    * "exact": the FP64 factorisation of `Deflation` (E^{-1} t to rounding);
+    * "fp32": E^{-1}, formed in FP64, rounded to single precision and applied
+      to the single-precision rounding of t in single-precision arithmetic
+      (a solve whose relative error is of the order of the single-precision
+      unit roundoff times the condition of the product).
+    """
+
+    def __init__(self, defl, kind="exact"):
+        if kind not in ("exact", "fp32"):
+            raise ValueError(kind)
+        self.defl, self.kind = defl, kind
+        if kind == "fp32" and defl.m > 0:
+            self.Einv32 = np.linalg.inv(defl.E).astype(np.float32)
+
+    def __call__(self, t1):
+        if self.defl.m == 0:
+            return np.zeros(0)
+        if self.kind == "exact":
+            return self.defl.solve_E(t1)
+        return (self.Einv32 @ t1.astype(np.float32)).astype(np.float64)
+
+
+def adef1_preconditioner(defl, coarse, precond):
+    """Multiplicative combination of the deflation and a preconditioner M.
+
+    Section "On precision of the coarse system solution": the projector acts
+    as a preconditioner of the original system, combined multiplicatively with
+    the other preconditioners.  Reading (Tang, Nabben, Vuik and Erlangga 2009,
+    the variant they call A-DEF1): with Q_hat = Z E_hat Z^T,
+
+        B(v) = Q_hat v + M^{-1} (v - A Q_hat v),
+
+    the coarse correction first, then M applied to the residual it leaves,
+    computed as t1 = Z^T v, t2 = E_hat t1, u = Z t2, v - (AZ) t2 (the
+    projector's own steps, section "Implementation"), s = M^{-1}(v - (AZ) t2),
+    B(v) = u + s.  With the exact E^{-1}, B(A Z c) = Z c.
+    """
+    def apply(v):
+        t2 = coarse(defl.Z.T @ v)
+        return defl.Z @ t2 + precond(v - defl.AZ @ t2)
+    return apply

@@ -195,3 +195,113 @@ def deflated_bicgstabl(A, defl, precond, b, y0, rtol, maxiter, ell=2, observe=No
         if omega == 0.0:
             return finish(BREAKDOWN, k)
     return finish(NOCONV, maxiter)
+
+
+def fgmres(A, precond, b, x0, rtol, maxiter, restart, observe=None):
+    """Restarted flexible GMRES, right-preconditioned, on A x = b.
+
+    Section "On precision of the coarse system solution": when the coarse
+    operator is solved inexactly the projector becomes part of a variable
+    preconditioner, which needs a flexible Krylov method such as flexible
+    GMRES; the same passage and the Navier-Stokes section name FGMRES.  The
+    iteration is Saad's flexible GMRES (Iterative Methods for Sparse Linear
+    Systems, 2nd ed., section 9.4.1): Arnoldi with modified Gram-Schmidt on the
+    vectors A z_j, where z_j = precond(v_j) may change from call to call, the
+    preconditioned vectors z_j kept, and x = x0 + Z_k y_k with y_k the
+    least-squares solution of the Hessenberg system, obtained with Givens
+    rotations.  Readings:
+
+    * one Arnoldi step (one preconditioner application, one product with A)
+      is one iteration; history[k] = |g_{k}| / ||b||, the residual norm of the
+      least-squares problem after k iterations (equal to ||b - A x_k|| in
+      exact arithmetic); history[0] = ||b - A x0|| / ||b||;
+    * stop at the first iteration with history[k] <= rtol, or at maxiter, or
+      when h_{j+1,j} = 0 (the Krylov space is invariant: the residual of the
+      least-squares problem is then zero); x is formed from the vectors of
+      the current cycle whenever the loop leaves it;
+    * after `restart` steps without convergence x is formed, r = b - A x is
+      recomputed and a new cycle starts from v_0 = r / ||r||;
+    * a zero diagonal after the rotations (singular Hessenberg) is a
+      breakdown; b = 0 returns x = 0 after 0 iterations.
+
+    observe(k, x_k, z_list), when given, is called at the end of every cycle
+    with the iterate and the preconditioned vectors of that cycle.
+    Returns (x, iters, history, status).
+    """
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return np.zeros_like(b), 0, [0.0], OK
+    x = x0.copy()
+    r = b - A @ x
+    beta = np.linalg.norm(r)
+    hist = [beta / bnorm]
+    if hist[0] <= rtol:
+        return x, 0, hist, OK
+    if maxiter <= 0:
+        return x, 0, hist, NOCONV
+    it = 0
+    m = restart
+    while True:
+        V = [r / beta]
+        Zs = []
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        k = 0
+        status = None
+        for j in range(m):
+            z = precond(V[j])
+            Zs.append(z)
+            w = A @ z
+            for i in range(j + 1):              # modified Gram-Schmidt
+                H[i, j] = w @ V[i]
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            hnext = H[j + 1, j]
+            for i in range(j):                  # earlier rotations on column j
+                a, c = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a + sn[i] * c
+                H[i + 1, j] = -sn[i] * a + cs[i] * c
+            d = np.hypot(H[j, j], H[j + 1, j])
+            k = j + 1
+            it += 1
+            if d == 0.0:
+                status = BREAKDOWN
+                k = j                            # column j is not usable
+                hist.append(hist[-1])
+                break
+            cs[j] = H[j, j] / d
+            sn[j] = H[j + 1, j] / d
+            H[j, j] = d
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            res = abs(g[j + 1])
+            hist.append(res / bnorm)
+            if not np.isfinite(res):
+                status = "nan"
+                break
+            if hist[-1] <= rtol or hnext == 0.0:
+                status = OK
+                break
+            if it >= maxiter:
+                status = NOCONV
+                break
+            V.append(w / hnext)
+        if k > 0:
+            # back substitution with the rotated (upper triangular) H
+            yk = np.zeros(k)
+            for i in range(k - 1, -1, -1):
+                yk[i] = (g[i] - H[i, i + 1:k] @ yk[i + 1:k]) / H[i, i]
+            for i in range(k):
+                x = x + yk[i] * Zs[i]
+        if observe is not None:
+            observe(it, x.copy(), Zs[:k])
+        if status is not None:
+            return x, it, hist, status
+        r = b - A @ x
+        beta = np.linalg.norm(r)
+        if beta == 0.0:
+            return x, it, hist, OK

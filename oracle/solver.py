@@ -13,8 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.sparse as sp
 
-from .deflation import Deflation, DeflationError
-from .krylov import deflated_cg, deflated_bicgstab, deflated_bicgstabl, OK, NOCONV, BREAKDOWN
+from .deflation import Deflation, DeflationError, CoarseSolve, adef1_preconditioner
+from .krylov import deflated_cg, deflated_bicgstab, deflated_bicgstabl, fgmres, OK, NOCONV, BREAKDOWN
 from .vcycle import BlockAMG
 
 
@@ -24,8 +24,10 @@ class OracleError(Exception):
 
 @dataclass
 class OracleParams:
-    solver: str = "cg"              # "cg", "bicgstab" or "bicgstabl"
+    solver: str = "cg"              # "cg", "bicgstab", "bicgstabl" or "fgmres"
     ell: int = 2                    # BiCGStab(ell)
+    restart: int = 30               # FGMRES cycle length
+    coarse_solve: str = "exact"     # FGMRES: "exact" or "fp32" E_hat
     rtol: float = 1e-8
     maxiter: int = 1000
     smoother: str = "spai0"         # "spai0" or "jacobi"
@@ -96,6 +98,12 @@ class OracleSolver:
         elif prm.solver == "bicgstabl":
             y, iters, hist, status = deflated_bicgstabl(
                 self.A, self.defl, self.precond, b, y0, rtol, maxiter, ell=prm.ell)
+        elif prm.solver == "fgmres":
+            # the original system, preconditioned by the deflation combined
+            # with the block AMG; no recovery step
+            B = adef1_preconditioner(self.defl, CoarseSolve(self.defl, prm.coarse_solve),
+                                     self.precond)
+            y, iters, hist, status = fgmres(self.A, B, b, y0, rtol, maxiter, prm.restart)
         else:
             raise OracleError(prm.solver)
         bnorm = np.linalg.norm(b)
@@ -103,7 +111,7 @@ class OracleSolver:
             x = np.zeros_like(b)
             true = 0.0
         else:
-            x = self.defl.recover(b, y)
+            x = y if prm.solver == "fgmres" else self.defl.recover(b, y)
             true = np.linalg.norm(b - self.A @ x) / bnorm
         return {"x": x, "y": y, "iters": iters, "history": np.array(hist),
                 "relres": hist[-1], "relres_true": true, "status": status}
