@@ -52,7 +52,13 @@ typedef enum {
     DFAMG_ENOGPU = 8       /* no usable gfx950 device                         */
 } dfamg_status;
 
-enum { DFAMG_SOLVER_CG = 0, DFAMG_SOLVER_BICGSTAB = 1, DFAMG_SOLVER_BICGSTAB2 = 2 };
+enum { DFAMG_SOLVER_CG = 0, DFAMG_SOLVER_BICGSTAB = 1, DFAMG_SOLVER_BICGSTAB2 = 2, DFAMG_SOLVER_FGMRES = 3 };
+/* Coarse solve t2 = E_hat t1 of the FGMRES path (section "On precision of
+ * the coarse system solution"): EXACT applies E^{-1} in FP64; FP32 applies
+ * E^{-1} rounded to single precision, in single precision.  The projected
+ * solvers (CG, BiCGStab, BiCGStab(2)) always use EXACT: the deflated system
+ * is only equivalent to A x = b when E is solved exactly. */
+enum { DFAMG_COARSE_EXACT = 0, DFAMG_COARSE_FP32 = 1 };
 enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
 enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1 };
 enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2 };
@@ -62,7 +68,13 @@ typedef struct {
     int32_t solver;         /* DFAMG_SOLVER_*; CG needs a symmetric A; one
                                BiCGStab(2) iteration is one cycle of two BiCG
                                steps and the minimal-residual step (four
-                               operator products)                             */
+                               operator products).  FGMRES solves A x = b
+                               itself (no deflated system, no recovery) with
+                               restarted flexible GMRES, preconditioned by
+                               B(v) = Z E_hat Z^T v + M^{-1}(v - AZ E_hat Z^T v):
+                               the deflation combined multiplicatively with
+                               the block AMG M; one iteration is one Arnoldi
+                               step                                           */
     int32_t maxiter;        /* iteration limit (default 1000)                  */
     double  rtol;           /* stop when ||r_k|| <= rtol ||b|| (default 1e-8)  */
     int32_t precision;      /* DFAMG_PREC_FP64: whole path FP64; MIXED: AMG
@@ -94,6 +106,9 @@ typedef struct {
                                every Krylov iteration, 2 around every kernel
                                span (inside the captured graph as well);
                                averages in dfamg_stats                        */
+    int32_t restart;        /* FGMRES: Arnoldi steps per cycle, 1..64 (30);
+                               one captured graph runs one cycle              */
+    int32_t coarse_solve;   /* DFAMG_COARSE_*; FP32 needs solver = FGMRES     */
 } dfamg_params;
 
 /* Fill *p with the defaults listed above. */

@@ -16,7 +16,8 @@ OK, EINVAL, ENOMEM, ESINGULAR, ENOCONV, EBREAKDOWN, ENAN, EHIP, ENOGPU = range(9
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESINGULAR: "ESINGULAR",
                 ENOCONV: "ENOCONV", EBREAKDOWN: "EBREAKDOWN", ENAN: "ENAN",
                 EHIP: "EHIP", ENOGPU: "ENOGPU"}
-SOLVER_CG, SOLVER_BICGSTAB, SOLVER_BICGSTAB2 = 0, 1, 2
+SOLVER_CG, SOLVER_BICGSTAB, SOLVER_BICGSTAB2, SOLVER_FGMRES = 0, 1, 2, 3
+COARSE_EXACT, COARSE_FP32 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 SMOOTHER_SPAI0, SMOOTHER_JACOBI = 0, 1
 FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL = 0, 1, 2
@@ -50,6 +51,7 @@ class Params(ctypes.Structure):
         ("precond", ctypes.c_int32), ("spmv_format", ctypes.c_int32),
         ("autotune", ctypes.c_int32), ("graph_iters", ctypes.c_int32), ("host_threads", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
+        ("restart", ctypes.c_int32), ("coarse_solve", ctypes.c_int32),
     ]
 
 

@@ -22,6 +22,7 @@
 #include "devmat.hpp"
 #include "host_plan.hpp"
 #include "kernels.hpp"
+#include "kernels_fgmres.hpp"
 
 namespace dfamg {
 
@@ -969,6 +970,14 @@ struct Handle {
     double *b2r1 = nullptr, *b2r2 = nullptr, *b2u0 = nullptr, *b2u1 = nullptr, *b2u2 = nullptr, *b2pr0 = nullptr,
            *b2pr1 = nullptr, *b2pu0 = nullptr, *b2pu1 = nullptr;
     bool bicg2() const { return prm.solver == DFAMG_SOLVER_BICGSTAB2; }
+    // FGMRES: Arnoldi vectors V_0..V_m (unnormalised), V-cycle outputs
+    // s_0..s_{m-1} and coarse solutions t2_0..t2_{m-1} of one cycle, the
+    // per-system state and the dot partials of the Gram-Schmidt passes
+    double *fgV = nullptr, *fgS = nullptr, *fgT2 = nullptr, *part_fg = nullptr;
+    float *Einv32 = nullptr;                // E^{-1} in single precision (FP32 coarse solve)
+    FgState *fg = nullptr;
+    int64_t fg_ld = 0, fg_mtot = 0;
+    bool fgmres() const { return prm.solver == DFAMG_SOLVER_FGMRES; }
     // partials and state
     double *part_A = nullptr, *part_rows = nullptr, *part_rs = nullptr, *part_rs_job = nullptr;
     int32_t *d_sys_cjob_off0 = nullptr;
@@ -1009,6 +1018,7 @@ struct Handle {
     void iteration(hipStream_t st);
     void iteration_bicg(hipStream_t st);
     void iteration_bicg2(hipStream_t st);
+    void cycle_fgmres(hipStream_t st);
     void initial(hipStream_t st);
     void finish(hipStream_t st);
     void precond(hipStream_t st, const double *rin, double *sout, bool profiled = false);
@@ -1167,6 +1177,23 @@ void Handle::setup_device() {
         b2pu0 = ar.alloc<double>(n);
         b2pu1 = ar.alloc<double>(n);
     }
+    if (fgmres()) {
+        const int m = prm.restart;
+        fg_ld = (n + 63) / 64 * 64;   // every vector starts on a 512-byte boundary
+        fg_mtot = (int64_t)nsub * std::max(ndv, 1);
+        fgV = ar.alloc<double>((size_t)(m + 1) * fg_ld);
+        fgS = ar.alloc<double>((size_t)m * fg_ld);
+        fgT2 = ar.alloc<double>((size_t)m * fg_mtot);
+        fg = ar.alloc<FgState>(nsys);
+        HIP_CHECK(hipMemsetAsync(fg, 0, sizeof(FgState) * nsys, sm));
+        part_fg = ar.alloc<double>((size_t)(m + 1) * nrow_tiles);
+        if (prm.coarse_solve == DFAMG_COARSE_FP32 && ndv > 0) {
+            const int64_t ne = P.sys_E_off[nsys];
+            Einv32 = ar.alloc<float>(ne);
+            hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, sm, ne, EinvT, Einv32);
+            HIP_CHECK(hipGetLastError());
+        }
+    }
     part_A = ar.alloc<double>((size_t)A.ntiles * (ndv + 1));
     part_rows = ar.alloc<double>((size_t)nrow_tiles * std::max(ndv + 1, 3));
     HIP_CHECK(hipHostMalloc((void **)&h_states, sizeof(SysState) * nsys, hipHostMallocDefault));
@@ -1196,7 +1223,7 @@ void Handle::setup_device() {
         d_sys_cjob_off0 = ar.upload(std::vector<int32_t>(nsys + 1, 0), sm);
     }
     if (prm.profile) {
-        prof.init(std::max(prm.graph_iters, 8));
+        prof.init(std::max({prm.graph_iters, 8, fgmres() ? prm.restart : 0}));
         prof.level = prm.profile;
         if (prm.graph_iters > 0 && !probe_graph_events()) {
             // event nodes cannot be captured here: profile with direct launches
@@ -1225,6 +1252,18 @@ void Handle::setup_device() {
                 if (M->kbytes[k] > 0) prof.bytes[k] = M->kbytes[k];
         bytes_iter = prof.bytes[KID_SPMV] + prof.bytes[KID_UPDATE] + prof.bytes[KID_PROJECT] + prof.bytes[KID_DIR];
         bytes_iter += M ? M->bytes : 16.0 * nd;
+        if (fgmres()) {
+            // one Arnoldi step at the cycle's mean basis size J = (m + 1) / 2:
+            // f = sc (V_j - AZ t2) reads V_j, AZ and writes f; the Gram-Schmidt
+            // span forms w = q + AZ t2 (q, AZ read, w written), reads the J
+            // basis vectors in each of its four passes, w in each pass, writes
+            // w and V_{j+1}, and reads Z for the Z^T V_{j+1} partials
+            const double J = 0.5 * (prm.restart + 1);
+            const double azb = 8.0 * ndv * nd + (ndv ? 12.0 * (double)P.AZoff.nnz() + 4.0 * nd : 0.0);
+            prof.bytes[KID_UPDATE] = 56.0 * nd + azb + 32.0 * J * nd + 8.0 * ndv * nd;
+            bytes_iter = prof.bytes[KID_SPMV] + prof.bytes[KID_PROJECT] + (M ? M->bytes : 16.0 * nd) +
+                         (16.0 * nd + azb) + prof.bytes[KID_UPDATE];
+        }
     }
     HIP_CHECK(hipStreamSynchronize(sm));
     setup_device_s = now_s() - t0;
@@ -1420,9 +1459,85 @@ void Handle::iteration_bicg2(hipStream_t st) {
     prof.mark(KID_TEST, 1, st);
 }
 
+// One restart cycle of flexible GMRES on A x = b (all systems at once; see
+// the kernels' comments): `restart` Arnoldi steps, then the update of the
+// iterate (held in y) and the first vector of the next cycle.
+void Handle::cycle_fgmres(hipStream_t st) {
+    const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock), gs(nsys()), wb(kWideBlock);
+    const int nt = nrow_tiles, m = prm.restart, nd = ndv();
+    for (int j = 0; j < m; ++j) {
+        prof.slot = j;
+        const double *Vj = fgV + (int64_t)j * fg_ld;
+        double *Sj = fgS + (int64_t)j * fg_ld, *t2j = fgT2 + (int64_t)j * fg_mtot;
+        double *Vn = fgV + (int64_t)(j + 1) * fg_ld;
+        const int J = j + 1;
+        // t2_j = E_hat Z^T V_j (the partials of Z^T V_0 come from the outer
+        // operator's epilogue, the later ones from the Gram-Schmidt update)
+        if (nd > 0) {
+            prof.mark(KID_PROJECT, 0, st);
+            const bool first = j == 0;
+            hipLaunchKernelGGL(k_t1<true>, dim3(plan.nsub), bl, 0, st, first ? part_A : part_rows,
+                               first ? A.ntiles : nt, first ? d_subto_A : d_subto_rows, nd, t1, psub, states,
+                               d_sub_sys, 0);
+            if (Einv32)
+                hipLaunchKernelGGL(k_egemv32<true>, dim3(njobs), bl, 0, st, d_jobs, Einv32, t1, t2j, states);
+            else
+                hipLaunchKernelGGL(k_egemv<true>, dim3(njobs), bl, 0, st, d_jobs, EinvT, t1, t2j, tt_part, states);
+            prof.mark(KID_PROJECT, 1, st);
+        }
+        with_ndv(nd, [&](auto c) {
+            hipLaunchKernelGGL((k_fg_rhs<decltype(c)::value>), gr, bl, 0, st, rows, nt, Vj, AZown, nd, AZoffp, AZoffc,
+                               AZoffv, t2j, fg, j, r, states, d_sub_sys);
+        });
+        precond(st, r, Sj, true);
+        outer(3, st, Sj, nullptr, q, true);
+        prof.mark(KID_UPDATE, 0, st);
+        with_ndv(nd, [&](auto c) {
+            constexpr int N = decltype(c)::value;
+            hipLaunchKernelGGL((k_fg_dots<true, N>), gr, bl, 0, st, rows, nt, q, w, AZown, nd, AZoffp, AZoffc,
+                               AZoffv, t2j, fgV, fg_ld, J, fg, j, part_fg, nt, states, d_sub_sys);
+            hipLaunchKernelGGL(k_fg_sum<1>, dim3(J, nsys()), wb, 0, st, part_fg, nt, d_sto_rows, fg, j, states);
+            hipLaunchKernelGGL((k_fg_axpy<false, N>), gr, bl, 0, st, rows, nt, w, w, fgV, fg_ld, J, fg, Z, nd,
+                               part_rows, nt, states, d_sub_sys);
+            hipLaunchKernelGGL((k_fg_dots<false, N>), gr, bl, 0, st, rows, nt, q, w, AZown, nd, AZoffp, AZoffc,
+                               AZoffv, t2j, fgV, fg_ld, J, fg, j, part_fg, nt, states, d_sub_sys);
+            hipLaunchKernelGGL(k_fg_sum<2>, dim3(J, nsys()), wb, 0, st, part_fg, nt, d_sto_rows, fg, j, states);
+            hipLaunchKernelGGL((k_fg_axpy<true, N>), gr, bl, 0, st, rows, nt, w, Vn, fgV, fg_ld, J, fg, Z, nd,
+                               part_rows, nt, states, d_sub_sys);
+        });
+        prof.mark(KID_UPDATE, 1, st);
+        prof.mark(KID_TEST, 0, st);
+        hipLaunchKernelGGL(k_fg_givens, gs, wb, 0, st, part_rows, d_sto_rows, fg, states, hist, hist_stride, prm.rtol,
+                           prm.maxiter, j);
+        prof.mark(KID_TEST, 1, st);
+    }
+    // x += sum_i y_i z_i, then V_0 = b - A x, its Z^T partials and norm
+    hipLaunchKernelGGL(k_fg_solve, dim3((nsys() + 63) / 64), dim3(64), 0, st, fg, nsys());
+    with_ndv(nd, [&](auto c) {
+        hipLaunchKernelGGL((k_fg_update_x<decltype(c)::value>), gr, bl, 0, st, rows, nt, y, fgS, fg_ld, Z, nd, fgT2,
+                           fg_mtot, fg, d_sub_sys);
+    });
+    outer(1, st, y, b, fgV);
+    hipLaunchKernelGGL(k_fg_norm<true>, gr, bl, 0, st, rows, nt, fgV, part_rows, states, d_sub_sys);
+    hipLaunchKernelGGL(k_fg_restart, gs, wb, 0, st, part_rows, d_sto_rows, fg, states);
+}
+
 // r0 = P(b - A y0), stopping test, s0 = M^{-1} r0, rho0, p0 = s0
 void Handle::initial(hipStream_t st) {
     const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
+    if (fgmres()) {
+        // V_0 = b - A x0 with the Z^T V_0 partials, (b, b) per subdomain,
+        // ||V_0||, the initial test, then beta, g and sc_0 of the first cycle
+        outer(1, st, y, b, fgV);
+        hipLaunchKernelGGL(k_t1<false>, dim3(plan.nsub), bl, 0, st, part_A, A.ntiles, d_subto_A, ndv(), t1, psub,
+                           states, d_sub_sys, 1);
+        hipLaunchKernelGGL(k_fg_norm<false>, gr, bl, 0, st, rows, nrow_tiles, fgV, part_rows, states, d_sub_sys);
+        hipLaunchKernelGGL(k_residual_test<1>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, d_sto_rows, states,
+                           hist, hist_stride, prm.rtol, prm.maxiter, nullptr, psub, ranges());
+        hipLaunchKernelGGL(k_zero_null_rhs, gr, bl, 0, st, rows, nrow_tiles, y, states, d_sub_sys);
+        hipLaunchKernelGGL(k_fg_restart, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, d_sto_rows, fg, states);
+        return;
+    }
     outer(1, st, y, b, w);
     project_solve(st, false, d_subto_A, part_A, A.ntiles, 1);
     with_ndv(ndv(), [&](auto c) {
@@ -1459,6 +1574,14 @@ void Handle::initial(hipStream_t st) {
 // x = y + Z E^{-1} Z^T (b - A y), then ||b - A x|| / ||b||
 void Handle::finish(hipStream_t st) {
     const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
+    if (fgmres()) {
+        // the iterate solves A x = b itself: no recovery step
+        hipLaunchKernelGGL(k_copy, gr, bl, 0, st, rows, nrow_tiles, (const double *)y, x);
+        outer(2, st, x, b, w);
+        hipLaunchKernelGGL(k_residual_test<2>, dim3(nsys()), dim3(kWideBlock), 0, st, part_A, d_sto_A, states, hist,
+                           hist_stride, prm.rtol, prm.maxiter, relres_true, psub, ranges());
+        return;
+    }
     if (bicg()) hipLaunchKernelGGL(k_bicg_halffix, gr, bl, 0, st, rows, nrow_tiles, y, ph, states, d_sub_sys);
     outer(1, st, y, b, w);
     project_solve(st, false, d_subto_A, part_A, A.ntiles, 0);
@@ -1471,6 +1594,25 @@ void Handle::finish(hipStream_t st) {
 }
 
 void Handle::launch_iterations(int k) {
+    if (fgmres()) {
+        // one restart cycle per call (one captured graph per cycle)
+        if (prm.graph_iters <= 0) {
+            prof.clear_used();
+            cycle_fgmres(stream);
+            return;
+        }
+        if (!graph_exec) {
+            prof.capturing = prof.on;
+            HIP_CHECK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
+            cycle_fgmres(cap_stream);
+            HIP_CHECK(hipStreamEndCapture(cap_stream, &graph));
+            HIP_CHECK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+            graph_k = prm.restart;
+            prof.capturing = false;
+        }
+        HIP_CHECK(hipGraphLaunch(graph_exec, stream));
+        return;
+    }
     if (prm.graph_iters <= 0) {
         prof.clear_used();
         for (int i = 0; i < k; ++i) {
@@ -1508,7 +1650,7 @@ dfamg_status Handle::run_solve(const double *rhs, double *xio) {
     have_rhs = true;
     initial(stream);
     HIP_CHECK(hipGetLastError());
-    const int chunk = prm.graph_iters > 0 ? prm.graph_iters : 8;
+    const int chunk = fgmres() ? prm.restart : (prm.graph_iters > 0 ? prm.graph_iters : 8);
     int done_iters = 0;
     std::vector<int32_t> it_before(nsys, 0);
     bool first = true;
@@ -1700,6 +1842,8 @@ void dfamg_params_default(dfamg_params *p) {
     p->host_threads = 0;
     p->verbose = 0;
     p->profile = 0;
+    p->restart = 30;
+    p->coarse_solve = DFAMG_COARSE_EXACT;
 }
 
 dfamg_status dfamg_setup(const dfamg_params *prm, int64_t n, const int64_t *row_ptr, const int32_t *col,

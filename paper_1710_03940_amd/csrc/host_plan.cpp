@@ -654,8 +654,15 @@ HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes,
 namespace {
 
 void validate_params(const dfamg_params &p) {
-    if (p.solver != DFAMG_SOLVER_CG && p.solver != DFAMG_SOLVER_BICGSTAB && p.solver != DFAMG_SOLVER_BICGSTAB2)
+    if (p.solver != DFAMG_SOLVER_CG && p.solver != DFAMG_SOLVER_BICGSTAB && p.solver != DFAMG_SOLVER_BICGSTAB2 &&
+        p.solver != DFAMG_SOLVER_FGMRES)
         fail(DFAMG_EINVAL, "unknown solver");
+    if (p.solver == DFAMG_SOLVER_FGMRES && (p.restart < 1 || p.restart > 64))
+        fail(DFAMG_EINVAL, "restart must be in [1, 64]");
+    if (p.coarse_solve != DFAMG_COARSE_EXACT && p.coarse_solve != DFAMG_COARSE_FP32)
+        fail(DFAMG_EINVAL, "unknown coarse_solve");
+    if (p.coarse_solve == DFAMG_COARSE_FP32 && p.solver != DFAMG_SOLVER_FGMRES)
+        fail(DFAMG_EINVAL, "an inexact coarse solve needs solver = FGMRES (the projected solvers need the exact E)");
     if (p.maxiter < 0) fail(DFAMG_EINVAL, "maxiter must be >= 0");
     if (!(p.rtol >= 0.0) || !std::isfinite(p.rtol)) fail(DFAMG_EINVAL, "rtol must be finite and >= 0");
     if (p.precision != DFAMG_PREC_FP64 && p.precision != DFAMG_PREC_MIXED) fail(DFAMG_EINVAL, "unknown precision");

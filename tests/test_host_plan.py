@@ -223,6 +223,14 @@ def test_validation_errors():
     Z[0, 1] = np.inf
     _expect(_lib.EINVAL, P, Z=Z)
     _expect(_lib.EINVAL, P, maxiter=-1)
+    _expect(_lib.EINVAL, P, solver=L.make_params().solver + 7)        # unknown solver
+    _expect(_lib.EINVAL, P, solver=_lib.SOLVER_FGMRES, restart=0)
+    _expect(_lib.EINVAL, P, solver=_lib.SOLVER_FGMRES, restart=65)
+    _expect(_lib.EINVAL, P, coarse_solve=2)
+    # an inexact E only inside the flexible method: the projected solvers need
+    # the exact coarse solve
+    _expect(_lib.EINVAL, P, coarse_solve=_lib.COARSE_FP32)
+    _expect(_lib.EINVAL, P, solver=_lib.SOLVER_BICGSTAB, coarse_solve=_lib.COARSE_FP32)
     _expect(_lib.EINVAL, P, coarse_enough=0)
     _expect(_lib.EINVAL, P, max_levels=21)
     _expect(_lib.EINVAL, P, block_size=4)                             # 216 rows, 4 | 216 but
