@@ -78,6 +78,9 @@ if __name__ == "__main__":
     if "lognormal_bicgstab2" in which:
         record("poisson150_lognormal2_boxes64_linear_bicgstab2", config_lognormal_poisson(),
                OracleParams(solver="bicgstabl", ell=2))
+    if "lognormal_fgmres" in which:
+        record("poisson150_lognormal2_boxes64_linear_fgmres30_fp32coarse", config_lognormal_poisson(),
+               OracleParams(solver="fgmres", restart=30, coarse_solve="fp32"))
     if "oseen" in which:
         record("oseen64_boxes256_field", config_oseen(),
                OracleParams(solver="bicgstab", block_size=4))

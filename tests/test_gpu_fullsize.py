@@ -145,3 +145,31 @@ def test_lognormal150_bicgstab2_matches_oracle(lognormal150, precision):
     idx = np.array(g["sample_index"])
     gs = np.array(g["sample_x"])
     assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+
+
+@pytest.mark.parametrize("coarse,precision", [("exact", "fp64"), ("fp32", "fp64"), ("fp32", "mixed")])
+def test_lognormal150_fgmres_matches_oracle(lognormal150, coarse, precision):
+    """Restarted FGMRES(30) on A x = b with the deflation combined with the
+    block AMG, at full size, against the oracle's FGMRES with the FP32 coarse
+    solve (the exact coarse solve changes the preconditioner by rounding only)."""
+    import paper_1710_03940_amd as L
+    P = lognormal150
+    g = _golden("poisson150_lognormal2_boxes64_linear_fgmres30_fp32coarse")
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, solver="fgmres", restart=30, coarse_solve=coarse,
+                 precision=precision)
+    dev = torch.device("cuda:0")
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    out = S.solve(torch.tensor(P.b, device=dev), x)
+    S.close()
+    print(f"fgmres {coarse} {precision}: gpu iters {out['iters']} oracle {g['iters']} relres_true "
+          f"{out['relres_true']:.3e}", flush=True)
+    assert out["status"] == 0
+    assert out["relres_true"] <= TRUE_RES_TOL
+    if precision == "fp64":
+        assert abs(out["iters"] - g["iters"]) <= 2
+    else:
+        assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
+    xs = x.cpu().numpy()
+    idx = np.array(g["sample_index"])
+    gs = np.array(g["sample_x"])
+    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
