@@ -1256,11 +1256,13 @@ void Handle::setup_device() {
             // one Arnoldi step at the cycle's mean basis size J = (m + 1) / 2:
             // f = sc (V_j - AZ t2) reads V_j, AZ and writes f; the Gram-Schmidt
             // span forms w = q + AZ t2 (q, AZ read, w written), reads the J
-            // basis vectors in each of its four passes, w in each pass, writes
+            // basis vectors in each of its three kernels (the fused update +
+            // dots kernel reads them twice, counted once: the second read
+            // comes from the caches), reads w in the two later kernels, writes
             // w and V_{j+1}, and reads Z for the Z^T V_{j+1} partials
             const double J = 0.5 * (prm.restart + 1);
             const double azb = 8.0 * ndv * nd + (ndv ? 12.0 * (double)P.AZoff.nnz() + 4.0 * nd : 0.0);
-            prof.bytes[KID_UPDATE] = 56.0 * nd + azb + 32.0 * J * nd + 8.0 * ndv * nd;
+            prof.bytes[KID_UPDATE] = 48.0 * nd + azb + 24.0 * J * nd + 8.0 * ndv * nd;
             bytes_iter = prof.bytes[KID_SPMV] + prof.bytes[KID_PROJECT] + (M ? M->bytes : 16.0 * nd) +
                          (16.0 * nd + azb) + prof.bytes[KID_UPDATE];
         }
@@ -1494,15 +1496,13 @@ void Handle::cycle_fgmres(hipStream_t st) {
         prof.mark(KID_UPDATE, 0, st);
         with_ndv(nd, [&](auto c) {
             constexpr int N = decltype(c)::value;
-            hipLaunchKernelGGL((k_fg_dots<true, N>), gr, bl, 0, st, rows, nt, q, w, AZown, nd, AZoffp, AZoffc,
+            hipLaunchKernelGGL((k_fg_dots<N>), gr, bl, 0, st, rows, nt, q, w, AZown, nd, AZoffp, AZoffc,
                                AZoffv, t2j, fgV, fg_ld, J, fg, j, part_fg, nt, states, d_sub_sys);
             hipLaunchKernelGGL(k_fg_sum<1>, dim3(J, nsys()), wb, 0, st, part_fg, nt, d_sto_rows, fg, j, states);
-            hipLaunchKernelGGL((k_fg_axpy<false, N>), gr, bl, 0, st, rows, nt, w, w, fgV, fg_ld, J, fg, Z, nd,
-                               part_rows, nt, states, d_sub_sys);
-            hipLaunchKernelGGL((k_fg_dots<false, N>), gr, bl, 0, st, rows, nt, q, w, AZown, nd, AZoffp, AZoffc,
-                               AZoffv, t2j, fgV, fg_ld, J, fg, j, part_fg, nt, states, d_sub_sys);
+            hipLaunchKernelGGL(k_fg_axpy_dots, gr, bl, 0, st, rows, nt, w, fgV, fg_ld, J, fg, part_fg, nt, states,
+                               d_sub_sys);
             hipLaunchKernelGGL(k_fg_sum<2>, dim3(J, nsys()), wb, 0, st, part_fg, nt, d_sto_rows, fg, j, states);
-            hipLaunchKernelGGL((k_fg_axpy<true, N>), gr, bl, 0, st, rows, nt, w, Vn, fgV, fg_ld, J, fg, Z, nd,
+            hipLaunchKernelGGL((k_fg_axpy<N>), gr, bl, 0, st, rows, nt, w, Vn, fgV, fg_ld, J, fg, Z, nd,
                                part_rows, nt, states, d_sub_sys);
         });
         prof.mark(KID_UPDATE, 1, st);

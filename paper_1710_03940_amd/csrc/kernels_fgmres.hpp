@@ -11,8 +11,9 @@
 //   f = v_j - (AZ) t2_j                                  k_fg_rhs
 //   s_j = M^{-1} f                                       V-cycle kernels
 //   q = A s_j                                            k_outer
-//   w = q + (AZ) t2_j = A z_j,  z_j = s_j + Z t2_j       k_fg_dots<true>
-//   two classical Gram-Schmidt passes against v_0..v_j   k_fg_dots, k_fg_sum, k_fg_axpy
+//   w = q + (AZ) t2_j = A z_j,  z_j = s_j + Z t2_j       k_fg_dots
+//   two classical Gram-Schmidt passes against v_0..v_j   k_fg_dots, k_fg_sum, k_fg_axpy_dots,
+//                                                        k_fg_axpy
 //   h_{j+1,j} = ||w||, Givens rotation, residual test    k_fg_givens
 // and at the end of a cycle
 //   y = R^{-1} g (back substitution)                     k_fg_solve
@@ -81,11 +82,10 @@ __global__ void __launch_bounds__(kBlock) k_fg_rhs(const DevTile *__restrict__ t
     });
 }
 
-// Dots of w with V_0 .. V_{J-1}: one partial per tile and vector,
-// part[i * nslots + slot].  FIRST: w = q + sc_j (AZ) t2_j is formed and
-// stored first (the product A z_j).  One row per thread (row tiles hold at
-// most kBlock rows).
-template <bool FIRST, int NDV>
+// w = q + sc_j (AZ) t2_j (the product A z_j, stored) and its dots with
+// V_0 .. V_{J-1}: one partial per tile and vector, part[i * nslots + slot].
+// One row per thread (row tiles hold at most kBlock rows).
+template <int NDV>
 __global__ void __launch_bounds__(kBlock) k_fg_dots(
     const DevTile *__restrict__ tiles, int32_t ntiles, const double *__restrict__ q, double *__restrict__ w,
     const double *__restrict__ AZown, int ndv_rt, const int32_t *__restrict__ offp, const int32_t *__restrict__ offc,
@@ -103,19 +103,15 @@ __global__ void __launch_bounds__(kBlock) k_fg_dots(
     const int64_t row = (int64_t)T.row0 + lr;
     double wv = 0.0;
     if (has) {
-        if (FIRST) {
-            const int ndv = ndv_rt;
-            double corr = 0.0;
+        const int ndv = ndv_rt;
+        double corr = 0.0;
 #pragma unroll
-            for (int k = 0; k < NDV; ++k)
-                if (k < ndv) corr += AZown[row * ndv + k] * t2[(int64_t)T.sub * ndv + k];
-            if (ndv > 0)
-                for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
-            wv = q[row] + fg[sys].sc[j] * corr;
-            w[row] = wv;
-        } else {
-            wv = w[row];
-        }
+        for (int k = 0; k < NDV; ++k)
+            if (k < ndv) corr += AZown[row * ndv + k] * t2[(int64_t)T.sub * ndv + k];
+        if (ndv > 0)
+            for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
+        wv = q[row] + fg[sys].sc[j] * corr;
+        w[row] = wv;
     }
     const int wave = threadIdx.x >> 6;
     for (int i = 0; i < J; ++i) {
@@ -152,12 +148,12 @@ __global__ void __launch_bounds__(kWideBlock) k_fg_sum(const double *__restrict_
     F.coef[i] = h * F.sc[i];
 }
 
-// w -= sum_i coef_i V_i.  LAST: the result is V_{j+1}, stored in place of w's
-// copy, with the partials ||V_{j+1}||^2 (part row 0) and Z^T V_{j+1} (rows
-// 1..ndv) for the next step.
-template <bool LAST, int NDV>
+// Second Gram-Schmidt update: V_{j+1} = w - sum_i coef_i V_i, with the
+// partials ||V_{j+1}||^2 (part row 0) and Z^T V_{j+1} (rows 1..ndv) for the
+// next step.
+template <int NDV>
 __global__ void __launch_bounds__(kBlock) k_fg_axpy(const DevTile *__restrict__ tiles, int32_t ntiles,
-                                                    const double *w, double *out,   // may alias (in place)
+                                                    const double *__restrict__ w, double *__restrict__ out,
                                                     const double *__restrict__ V, int64_t ld, int J,
                                                     const FgState *__restrict__ fg, const double *__restrict__ Z,
                                                     int ndv_rt, double *__restrict__ part, int32_t nslots,
@@ -187,7 +183,6 @@ __global__ void __launch_bounds__(kBlock) k_fg_axpy(const DevTile *__restrict__ 
         v = a0 + a1;
         out[row] = v;
     }
-    if (!LAST) return;
     const int ndv = ndv_rt;
     const int wave = threadIdx.x >> 6;
     const double s0 = wave_sum(v * v);
@@ -203,6 +198,52 @@ __global__ void __launch_bounds__(kBlock) k_fg_axpy(const DevTile *__restrict__ 
     if (threadIdx.x <= ndv)
         part[(int64_t)threadIdx.x * nslots + T.slot] =
             ((red[4 * threadIdx.x] + red[4 * threadIdx.x + 1]) + red[4 * threadIdx.x + 2]) + red[4 * threadIdx.x + 3];
+}
+
+// First Gram-Schmidt update fused with the dots of the second pass:
+// w' = w - sum_i coef_i V_i (stored in place), then the partials (w', V_i).
+// The second read of a row of V_i follows the first closely, so it is
+// mostly served by the caches: the pass costs one read of the basis from HBM
+// instead of two.
+static __global__ void __launch_bounds__(kBlock) k_fg_axpy_dots(const DevTile *__restrict__ tiles, int32_t ntiles,
+                                                                double *__restrict__ w, const double *__restrict__ V,
+                                                                int64_t ld, int J, const FgState *__restrict__ fg,
+                                                                double *__restrict__ part, int32_t nslots,
+                                                                const SysState *__restrict__ st,
+                                                                const int32_t *__restrict__ sub_sys) {
+    __shared__ double cf[kFgMax + 1];
+    __shared__ double red[(kFgMax + 1) * 4];
+    const int tile = tile_of_block(ntiles);
+    if (tile >= ntiles) return;
+    const DevTile T = tiles[tile];
+    const int sys = sub_sys[T.sub];
+    if (st[sys].done) return;
+    for (int i = threadIdx.x; i < J; i += kBlock) cf[i] = fg[sys].coef[i];
+    __syncthreads();
+    const int lr = threadIdx.x;
+    const bool has = lr < T.nrows;
+    const int64_t row = (int64_t)T.row0 + lr;
+    double v = 0.0;
+    if (has) {
+        double a0 = w[row], a1 = 0.0;
+        int i = 0;
+        for (; i + 1 < J; i += 2) {
+            a0 -= cf[i] * V[(int64_t)i * ld + row];
+            a1 -= cf[i + 1] * V[(int64_t)(i + 1) * ld + row];
+        }
+        if (i < J) a0 -= cf[i] * V[(int64_t)i * ld + row];
+        v = a0 + a1;
+        w[row] = v;
+    }
+    const int wave = threadIdx.x >> 6;
+    for (int i = 0; i < J; ++i) {
+        const double d = has ? v * V[(int64_t)i * ld + row] : 0.0;
+        const double s = wave_sum(d);
+        if ((threadIdx.x & 63) == 0) red[i * 4 + wave] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < J; i += kBlock)
+        part[(int64_t)i * nslots + T.slot] = ((red[i * 4] + red[i * 4 + 1]) + red[i * 4 + 2]) + red[i * 4 + 3];
 }
 
 // Partial ||v||^2 per tile (part row 0): the norm of a cycle's first vector.
