@@ -12,7 +12,11 @@
  *   - the preconditioner is block AMG without overlap: one smoothed-
  *     aggregation V-cycle per subdomain, built on the square diagonal block
  *     of A (section "Implementation");
- *   - lambda = E^{-1} Z^T (b - A y) recovers x (eqs. (4)-(5)).
+ *   - lambda = E^{-1} Z^T (b - A y) recovers x (eqs. (4)-(5));
+ *   - alternatively (solver FGMRES), the deflation with an exact or inexact
+ *     E^{-1} preconditions A x = b itself, combined multiplicatively with the
+ *     block AMG, inside restarted flexible GMRES (section "On precision of
+ *     the coarse system solution").
  * Usage follows Listing 1: setup once from a CRS matrix and parameters, then
  * solve(rhs, x) with x as the initial guess, returning iterations and the
  * relative residual.
@@ -46,7 +50,10 @@ typedef enum {
                               or a local deflation block is rank deficient    */
     DFAMG_ENOCONV = 4,     /* maxiter reached; outputs hold the last iterate  */
     DFAMG_EBREAKDOWN = 5,  /* BiCGStab(2): a scalar it divides by (rho,
-                              (r~, v), omega, sigma) became exactly zero      */
+                              (r~, v), omega, sigma) became exactly zero;
+                              FGMRES: a zero diagonal of the rotated
+                              Hessenberg matrix (x holds the iterate formed
+                              from the steps before it)                      */
     DFAMG_ENAN = 6,        /* a non-finite value appeared in the iteration    */
     DFAMG_EHIP = 7,        /* a HIP runtime call failed                       */
     DFAMG_ENOGPU = 8       /* no usable gfx950 device                         */

@@ -143,3 +143,24 @@ def test_fgmres_batched_equals_standalone_and_graph_equals_direct():
             xs.append(x1.cpu().numpy())
         assert np.array_equal(xb[off[s]:off[s + 1]], xs[0])
         assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("profile,graph_iters", [(2, 16), (2, 0), (1, 16)])
+def test_fgmres_profiled_solve_unchanged(profile, graph_iters):
+    """Event spans recorded inside the cycle graph (or around direct launches)
+    leave the iterate bitwise unchanged and report the outer operator."""
+    import paper_1710_03940_amd as L
+    P = _convdiff(10, (2, 1, 1), "linear", 2.0, seed=5)
+    kw = dict(solver="fgmres", restart=7, coarse_enough=30, autotune=0, graph_iters=graph_iters)
+    xs = []
+    for prof in (0, profile):
+        S = L.Solver(P.A, P.part, P.nsub, P.Z, profile=prof, **kw)
+        x = _t(np.zeros(P.n))
+        out = S.solve(_t(P.b), x)
+        st = S.stats()
+        S.close()
+        assert out["status"] == 0
+        xs.append(x.cpu().numpy())
+        if prof:
+            assert st["kernels"]["spmv"]["calls"] > 0 and st["kernels"]["spmv"]["ms"] > 0
+    assert np.array_equal(xs[0], xs[1])
