@@ -113,13 +113,17 @@ class CoarseSolve:
     * "fp32": E^{-1}, formed in FP64, rounded to single precision and applied
       to the single-precision rounding of t in single-precision arithmetic
       (a solve whose relative error is of the order of the single-precision
-      unit roundoff times the condition of the product).
+      unit roundoff times the condition of the product);
+    * "cg": an iterative solve to a relaxed tolerance (symmetric positive
+      definite E), the Krylov option the section discusses.
     """
 
-    def __init__(self, defl, kind="exact"):
-        if kind not in ("exact", "fp32"):
+    def __init__(self, defl, kind="exact", rtol=1e-3, maxiter=100):
+        if kind not in ("exact", "fp32", "cg"):
             raise ValueError(kind)
         self.defl, self.kind = defl, kind
+        self.rtol, self.maxiter = rtol, maxiter
+        self.iters = []                      # CG steps of every call (kind "cg")
         if kind == "fp32" and defl.m > 0:
             self.Einv32 = np.linalg.inv(defl.E).astype(np.float32)
 
@@ -128,7 +132,40 @@ class CoarseSolve:
             return np.zeros(0)
         if self.kind == "exact":
             return self.defl.solve_E(t1)
+        if self.kind == "cg":
+            return self._cg(t1)
         return (self.Einv32 @ t1.astype(np.float32)).astype(np.float64)
+
+    def _cg(self, t):
+        """Jacobi-preconditioned CG on E t2 = t from t2 = 0 (Hestenes and
+        Stiefel's method with the diagonal of E as preconditioner), stopped at
+        the first step with ||t - E t2|| <= rtol ||t|| or after maxiter steps:
+        a solve whose accuracy, and hence the preconditioner it belongs to,
+        changes from call to call."""
+        E = self.defl.E
+        d = np.diag(E)
+        x = np.zeros_like(t)
+        r = t.copy()
+        tn = np.linalg.norm(t)
+        k = 0
+        if tn == 0.0:
+            self.iters.append(0)
+            return x
+        z = r / d
+        p = z.copy()
+        rho = r @ z
+        while k < self.maxiter and np.linalg.norm(r) > self.rtol * tn:
+            q = E @ p
+            alpha = rho / (p @ q)
+            x = x + alpha * p
+            r = r - alpha * q
+            k += 1
+            z = r / d
+            rho_new = r @ z
+            p = z + (rho_new / rho) * p
+            rho = rho_new
+        self.iters.append(k)
+        return x
 
 
 def adef1_preconditioner(defl, coarse, precond):

@@ -27,7 +27,9 @@ class OracleParams:
     solver: str = "cg"              # "cg", "bicgstab", "bicgstabl" or "fgmres"
     ell: int = 2                    # BiCGStab(ell)
     restart: int = 30               # FGMRES cycle length
-    coarse_solve: str = "exact"     # FGMRES: "exact" or "fp32" E_hat
+    coarse_solve: str = "exact"     # FGMRES: "exact", "fp32" or "cg" E_hat
+    coarse_rtol: float = 1e-2       # "cg": relative residual of the coarse solve
+    coarse_maxiter: int = 100       # "cg": step limit of the coarse solve
     rtol: float = 1e-8
     maxiter: int = 1000
     smoother: str = "spai0"         # "spai0" or "jacobi"
@@ -101,7 +103,8 @@ class OracleSolver:
         elif prm.solver == "fgmres":
             # the original system, preconditioned by the deflation combined
             # with the block AMG; no recovery step
-            B = adef1_preconditioner(self.defl, CoarseSolve(self.defl, prm.coarse_solve),
+            B = adef1_preconditioner(self.defl, CoarseSolve(self.defl, prm.coarse_solve,
+                                                            prm.coarse_rtol, prm.coarse_maxiter),
                                      self.precond)
             y, iters, hist, status = fgmres(self.A, B, b, y0, rtol, maxiter, prm.restart)
         else:

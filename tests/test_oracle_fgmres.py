@@ -196,3 +196,53 @@ def test_inexact_coarse_solve_breaks_the_projector_but_not_fgmres():
     F = OracleSolver(P.A, P.part, P.nsub, P.Z, OracleParams(solver="fgmres", coarse_solve="fp32"))
     good = F.solve(P.b)
     assert good["status"] == "ok" and good["relres_true"] <= 1.01e-8
+
+
+def _spd_coarse():
+    P = make_problem("p", (10, 10, 10), (2, 2, 2), deflation="linear", sigma=1.0, coef_seed=3)
+    S = OracleSolver(P.A, P.part, P.nsub, P.Z, OracleParams(solver="fgmres", coarse_enough=30))
+    return P, S
+
+
+def test_cg_coarse_solve_finite_termination_and_first_step():
+    P, S = _spd_coarse()
+    E = S.defl.E
+    m = E.shape[0]
+    t = np.random.default_rng(3).standard_normal(m)
+    exact = np.linalg.solve(E, t)
+    C = CoarseSolve(S.defl, "cg", rtol=1e-14, maxiter=4 * m)
+    assert np.linalg.norm(C(t) - exact) <= 1e-10 * np.linalg.norm(exact)
+    # one step: x1 = a D^{-1} t with a = (t, D^{-1} t) / (D^{-1} t, E D^{-1} t)
+    z = t / np.diag(E)
+    x1 = (t @ z) / (z @ E @ z) * z
+    C1 = CoarseSolve(S.defl, "cg", rtol=0.0, maxiter=1)
+    assert np.linalg.norm(C1(t) - x1) <= 1e-13 * np.linalg.norm(x1)
+
+
+@pytest.mark.parametrize("rtol", [1e-1, 1e-2, 1e-4])
+def test_cg_coarse_solve_stops_at_first_step_below_tolerance(rtol):
+    P, S = _spd_coarse()
+    E = S.defl.E
+    t = np.random.default_rng(4).standard_normal(E.shape[0])
+    C = CoarseSolve(S.defl, "cg", rtol=rtol, maxiter=500)
+    x = C(t)
+    k = C.iters[-1]
+    assert np.linalg.norm(t - E @ x) <= rtol * np.linalg.norm(t)
+    assert k >= 1
+    Cp = CoarseSolve(S.defl, "cg", rtol=0.0, maxiter=k - 1)
+    xp = Cp(t)
+    assert np.linalg.norm(t - E @ xp) > rtol * np.linalg.norm(t)
+    assert not CoarseSolve(S.defl, "cg")(np.zeros_like(t)).any()
+
+
+def test_fgmres_with_iterative_coarse_solve_matches_dense_solve():
+    """A coarse solve to 1e-1 changes the preconditioner from call to call;
+    the flexible method still converges to the solution."""
+    P, S = _spd_coarse()
+    F = OracleSolver(P.A, P.part, P.nsub, P.Z,
+                     OracleParams(solver="fgmres", coarse_solve="cg", coarse_rtol=1e-1,
+                                  rtol=1e-12, coarse_enough=30))
+    res = F.solve(P.b)
+    xd = np.linalg.solve(P.A.toarray(), P.b)
+    assert res["status"] == "ok"
+    assert np.linalg.norm(res["x"] - xd) <= 1e-9 * np.linalg.norm(xd)
