@@ -62,10 +62,13 @@ typedef enum {
 enum { DFAMG_SOLVER_CG = 0, DFAMG_SOLVER_BICGSTAB = 1, DFAMG_SOLVER_BICGSTAB2 = 2, DFAMG_SOLVER_FGMRES = 3 };
 /* Coarse solve t2 = E_hat t1 of the FGMRES path (section "On precision of
  * the coarse system solution"): EXACT applies E^{-1} in FP64; FP32 applies
- * E^{-1} rounded to single precision, in single precision.  The projected
- * solvers (CG, BiCGStab, BiCGStab(2)) always use EXACT: the deflated system
- * is only equivalent to A x = b when E is solved exactly. */
-enum { DFAMG_COARSE_EXACT = 0, DFAMG_COARSE_FP32 = 1 };
+ * E^{-1} rounded to single precision, in single precision; CG runs
+ * Jacobi-preconditioned CG on E from zero until ||t1 - E t2|| <= coarse_rtol
+ * ||t1|| or coarse_maxiter steps (E must be symmetric with a positive
+ * diagonal), so the preconditioner changes from one application to the next.
+ * The projected solvers (CG, BiCGStab, BiCGStab(2)) always use EXACT: the
+ * deflated system is only equivalent to A x = b when E is solved exactly. */
+enum { DFAMG_COARSE_EXACT = 0, DFAMG_COARSE_FP32 = 1, DFAMG_COARSE_CG = 2 };
 enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
 enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1 };
 enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2 };
@@ -115,7 +118,9 @@ typedef struct {
                                averages in dfamg_stats                        */
     int32_t restart;        /* FGMRES: Arnoldi steps per cycle, 1..64 (30);
                                one captured graph runs one cycle              */
-    int32_t coarse_solve;   /* DFAMG_COARSE_*; FP32 needs solver = FGMRES     */
+    int32_t coarse_solve;   /* DFAMG_COARSE_*; FP32 and CG need solver = FGMRES */
+    double  coarse_rtol;    /* COARSE_CG: relative residual target (1e-2)    */
+    int32_t coarse_maxiter; /* COARSE_CG: step limit per coarse solve (100)  */
 } dfamg_params;
 
 /* Fill *p with the defaults listed above. */
@@ -239,6 +244,9 @@ typedef struct {
                                          width, couplings, vectors, Z as
                                          stored); the algorithmic figure is
                                          kernel_bytes[DFAMG_KERNEL_SPMV]     */
+    int64_t coarse_iters;             /* COARSE_CG: CG steps of all coarse
+                                         solves of the last solve call (sum
+                                         over systems)                        */
 } dfamg_stats;
 
 /* Kernel ids of the profile: the outer SpMV with its fused (p,q) and Z^T q

@@ -21,7 +21,7 @@ __all__ = ["Solver", "BatchedSolver", "make_params", "DfamgError"] + [
 _ENUMS = {
     "solver": {"cg": _lib.SOLVER_CG, "bicgstab": _lib.SOLVER_BICGSTAB, "bicgstab2": _lib.SOLVER_BICGSTAB2,
                "fgmres": _lib.SOLVER_FGMRES},
-    "coarse_solve": {"exact": _lib.COARSE_EXACT, "fp32": _lib.COARSE_FP32},
+    "coarse_solve": {"exact": _lib.COARSE_EXACT, "fp32": _lib.COARSE_FP32, "cg": _lib.COARSE_CG},
     "precision": {"fp64": _lib.PREC_FP64, "mixed": _lib.PREC_MIXED},
     "smoother": {"spai0": _lib.SMOOTHER_SPAI0, "jacobi": _lib.SMOOTHER_JACOBI},
     "spmv_format": {"auto": _lib.FORMAT_AUTO, "csr": _lib.FORMAT_CSR, "sell": _lib.FORMAT_SELL},

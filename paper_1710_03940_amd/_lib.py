@@ -17,7 +17,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESINGULAR: "ESINGU
                 ENOCONV: "ENOCONV", EBREAKDOWN: "EBREAKDOWN", ENAN: "ENAN",
                 EHIP: "EHIP", ENOGPU: "ENOGPU"}
 SOLVER_CG, SOLVER_BICGSTAB, SOLVER_BICGSTAB2, SOLVER_FGMRES = 0, 1, 2, 3
-COARSE_EXACT, COARSE_FP32 = 0, 1
+COARSE_EXACT, COARSE_FP32, COARSE_CG = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 SMOOTHER_SPAI0, SMOOTHER_JACOBI = 0, 1
 FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL = 0, 1, 2
@@ -52,6 +52,7 @@ class Params(ctypes.Structure):
         ("autotune", ctypes.c_int32), ("graph_iters", ctypes.c_int32), ("host_threads", ctypes.c_int32),
         ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("restart", ctypes.c_int32), ("coarse_solve", ctypes.c_int32),
+        ("coarse_rtol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
     ]
 
 
@@ -71,6 +72,7 @@ class Stats(ctypes.Structure):
         ("kernel_calls", ctypes.c_int64 * 16), ("kernel_ms", ctypes.c_double * 16),
         ("kernel_bytes", ctypes.c_double * 16), ("profile_in_graph", ctypes.c_int32),
         ("layouts", ctypes.c_char * 1024), ("outer_layout_bytes", ctypes.c_double),
+        ("coarse_iters", ctypes.c_int64),
     ]
 
 
@@ -221,6 +223,7 @@ def dfamg_get_stats(h):
             "solve_s": s.solve_s, "device_bytes": s.device_bytes,
             "bytes_per_iter": s.bytes_per_iter, "profile_in_graph": bool(s.profile_in_graph),
             "layouts": s.layouts.decode(), "outer_layout_bytes": s.outer_layout_bytes,
+            "coarse_iters": int(s.coarse_iters),
             "kernels": {name: {"calls": int(s.kernel_calls[i]), "ms": float(s.kernel_ms[i]),
                                "bytes": float(s.kernel_bytes[i])}
                         for i, name in enumerate(KERNEL_NAMES)}}

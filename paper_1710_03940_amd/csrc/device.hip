@@ -975,6 +975,12 @@ struct Handle {
     // per-system state and the dot partials of the Gram-Schmidt passes
     double *fgV = nullptr, *fgS = nullptr, *fgT2 = nullptr, *part_fg = nullptr;
     float *Einv32 = nullptr;                // E^{-1} in single precision (FP32 coarse solve)
+    // CG coarse solve: E in CSR (global coarse numbering), inverse diagonal,
+    // work vectors, per-system coarse-system offsets and step counters
+    int64_t *ecg_ptr = nullptr, *ecg_iters = nullptr;
+    int32_t *ecg_col = nullptr, *d_sys_coarse_off = nullptr;
+    double *ecg_val = nullptr, *ecg_dinv = nullptr, *ecg_work = nullptr;
+    int64_t coarse_iters_last = 0;
     FgState *fg = nullptr;
     int64_t fg_ld = 0, fg_mtot = 0;
     bool fgmres() const { return prm.solver == DFAMG_SOLVER_FGMRES; }
@@ -1187,6 +1193,46 @@ void Handle::setup_device() {
         fg = ar.alloc<FgState>(nsys);
         HIP_CHECK(hipMemsetAsync(fg, 0, sizeof(FgState) * nsys, sm));
         part_fg = ar.alloc<double>((size_t)(m + 1) * nrow_tiles);
+        if (prm.coarse_solve == DFAMG_COARSE_CG && ndv > 0) {
+            // E of every system in CSR (exact zeros dropped); CG needs it
+            // symmetric with a positive diagonal
+            std::vector<int64_t> ep(1, 0);
+            std::vector<int32_t> ec, co(nsys + 1, 0);
+            std::vector<double> ev, dv;
+            for (int sy = 0; sy < nsys; ++sy) {
+                const int m = P.sys_m[sy];
+                const int64_t c0 = (int64_t)P.sys_sub_off[sy] * ndv;
+                const double *E = &P.E[P.sys_E_off[sy]];
+                double emax = 0.0;
+                for (int64_t i = 0; i < (int64_t)m * m; ++i) emax = std::max(emax, std::fabs(E[i]));
+                for (int i = 0; i < m; ++i) {
+                    if (!(E[(int64_t)i * m + i] > 0.0))
+                        throw Error{DFAMG_EINVAL, "the CG coarse solve needs E with a positive diagonal (system " +
+                                                      std::to_string(sy) + ")"};
+                    for (int j = 0; j < m; ++j) {
+                        const double e = E[(int64_t)i * m + j];
+                        if (std::fabs(e - E[(int64_t)j * m + i]) > 1e-10 * emax)
+                            throw Error{DFAMG_EINVAL, "the CG coarse solve needs a symmetric E (system " +
+                                                          std::to_string(sy) + ")"};
+                        if (e != 0.0) {
+                            ec.push_back((int32_t)(c0 + j));
+                            ev.push_back(e);
+                        }
+                    }
+                    ep.push_back((int64_t)ec.size());
+                    dv.push_back(1.0 / E[(int64_t)i * m + i]);
+                }
+                co[sy + 1] = (int32_t)(c0 + m);
+            }
+            ecg_ptr = ar.upload(ep, sm);
+            ecg_col = ar.upload(ec, sm);
+            ecg_val = ar.upload(ev, sm);
+            ecg_dinv = ar.upload(dv, sm);
+            d_sys_coarse_off = ar.upload(co, sm);
+            ecg_work = ar.alloc<double>((size_t)3 * fg_mtot);
+            ecg_iters = ar.alloc<int64_t>(nsys);
+            HIP_CHECK(hipMemsetAsync(ecg_iters, 0, sizeof(int64_t) * nsys, sm));
+        }
         if (prm.coarse_solve == DFAMG_COARSE_FP32 && ndv > 0) {
             const int64_t ne = P.sys_E_off[nsys];
             Einv32 = ar.alloc<float>(ne);
@@ -1481,7 +1527,10 @@ void Handle::cycle_fgmres(hipStream_t st) {
             hipLaunchKernelGGL(k_t1<true>, dim3(plan.nsub), bl, 0, st, first ? part_A : part_rows,
                                first ? A.ntiles : nt, first ? d_subto_A : d_subto_rows, nd, t1, psub, states,
                                d_sub_sys, 0);
-            if (Einv32)
+            if (ecg_ptr)
+                hipLaunchKernelGGL(k_ecg, gs, wb, 0, st, ecg_ptr, ecg_col, ecg_val, ecg_dinv, d_sys_coarse_off, t1,
+                                   t2j, ecg_work, fg_mtot, prm.coarse_rtol, prm.coarse_maxiter, states, ecg_iters);
+            else if (Einv32)
                 hipLaunchKernelGGL(k_egemv32<true>, dim3(njobs), bl, 0, st, d_jobs, Einv32, t1, t2j, states);
             else
                 hipLaunchKernelGGL(k_egemv<true>, dim3(njobs), bl, 0, st, d_jobs, EinvT, t1, t2j, tt_part, states);
@@ -1647,6 +1696,7 @@ dfamg_status Handle::run_solve(const double *rhs, double *xio) {
     const int nb = (int)((n + 255) / 256);
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, stream, n, d_perm, rhs, b);
     hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, stream, n, d_perm, xio, y);
+    if (ecg_iters) HIP_CHECK(hipMemsetAsync(ecg_iters, 0, sizeof(int64_t) * nsys, stream));
     have_rhs = true;
     initial(stream);
     HIP_CHECK(hipGetLastError());
@@ -1685,7 +1735,11 @@ dfamg_status Handle::run_solve(const double *rhs, double *xio) {
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, stream, n, d_perm, x, xio);
     HIP_CHECK(hipGetLastError());
     HIP_CHECK(hipMemcpyAsync(h_states, states, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, stream));
+    std::vector<int64_t> cit(ecg_iters ? nsys : 0);
+    if (ecg_iters) HIP_CHECK(hipMemcpyAsync(cit.data(), ecg_iters, sizeof(int64_t) * nsys, hipMemcpyDeviceToHost, stream));
     HIP_CHECK(hipStreamSynchronize(stream));
+    coarse_iters_last = 0;
+    for (int64_t c : cit) coarse_iters_last += c;
     solve_s = now_s() - t0;
     dfamg_status st = DFAMG_OK;
     for (int i = 0; i < nsys && st == DFAMG_OK; ++i) {
@@ -1844,6 +1898,8 @@ void dfamg_params_default(dfamg_params *p) {
     p->profile = 0;
     p->restart = 30;
     p->coarse_solve = DFAMG_COARSE_EXACT;
+    p->coarse_rtol = 1e-2;
+    p->coarse_maxiter = 100;
 }
 
 dfamg_status dfamg_setup(const dfamg_params *prm, int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -1961,6 +2017,7 @@ dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *o) {
     }
     o->format_outer = H.A.fmt;
     o->outer_layout_bytes = H.outer_layout_bytes;
+    o->coarse_iters = H.coarse_iters_last;
     {
         const std::string t = "outer " + describe(H.A) + (H.outer_split ? "+couplings" : "") +
                               (H.M ? ";" + H.M->layouts : std::string());

@@ -659,10 +659,15 @@ void validate_params(const dfamg_params &p) {
         fail(DFAMG_EINVAL, "unknown solver");
     if (p.solver == DFAMG_SOLVER_FGMRES && (p.restart < 1 || p.restart > 64))
         fail(DFAMG_EINVAL, "restart must be in [1, 64]");
-    if (p.coarse_solve != DFAMG_COARSE_EXACT && p.coarse_solve != DFAMG_COARSE_FP32)
+    if (p.coarse_solve != DFAMG_COARSE_EXACT && p.coarse_solve != DFAMG_COARSE_FP32 &&
+        p.coarse_solve != DFAMG_COARSE_CG)
         fail(DFAMG_EINVAL, "unknown coarse_solve");
-    if (p.coarse_solve == DFAMG_COARSE_FP32 && p.solver != DFAMG_SOLVER_FGMRES)
+    if (p.coarse_solve != DFAMG_COARSE_EXACT && p.solver != DFAMG_SOLVER_FGMRES)
         fail(DFAMG_EINVAL, "an inexact coarse solve needs solver = FGMRES (the projected solvers need the exact E)");
+    if (p.coarse_solve == DFAMG_COARSE_CG) {
+        if (!(p.coarse_rtol >= 0.0) || !std::isfinite(p.coarse_rtol)) fail(DFAMG_EINVAL, "coarse_rtol must be >= 0");
+        if (p.coarse_maxiter < 1) fail(DFAMG_EINVAL, "coarse_maxiter must be >= 1");
+    }
     if (p.maxiter < 0) fail(DFAMG_EINVAL, "maxiter must be >= 0");
     if (!(p.rtol >= 0.0) || !std::isfinite(p.rtol)) fail(DFAMG_EINVAL, "rtol must be finite and >= 0");
     if (p.precision != DFAMG_PREC_FP64 && p.precision != DFAMG_PREC_MIXED) fail(DFAMG_EINVAL, "unknown precision");

@@ -440,6 +440,66 @@ __global__ void __launch_bounds__(kBlock) k_egemv32(const GemvJob *__restrict__ 
     if (lane == 0) t2[J.coarse0 + i] = (double)v;
 }
 
+// t2 = E_hat t1 by an iterative solve (the inexact coarse solve that varies
+// from call to call): Jacobi-preconditioned CG on E t2 = t1 from t2 = 0,
+// stopped at the first step with ||t1 - E t2|| <= rtol ||t1|| or after
+// maxiter steps.  One 1024-thread block per system; E in CSR over the global
+// coarse numbering (block diagonal by system, exact zeros dropped), dinv its
+// inverse diagonal; r, p, q in work (3 x mtot).  Every sum is a fixed-order
+// block reduction whose result every thread holds, so the loop test is
+// uniform over the block.  iters[sys] accumulates the steps taken.
+static __global__ void __launch_bounds__(kWideBlock) k_ecg(
+    const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, const double *__restrict__ val,
+    const double *__restrict__ dinv, const int32_t *__restrict__ sys_coarse_off, const double *__restrict__ t1,
+    double *__restrict__ t2, double *__restrict__ work, int64_t mtot, double rtol, int32_t maxiter,
+    const SysState *__restrict__ st, int64_t *__restrict__ iters) {
+    __shared__ double lds[16];
+    const int sys = blockIdx.x;
+    if (st[sys].done) return;
+    const int c0 = sys_coarse_off[sys], c1 = sys_coarse_off[sys + 1];
+    double *r = work, *p = work + mtot, *q = work + 2 * mtot;
+    double a = 0.0, b = 0.0;
+    for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) {
+        const double tc = t1[c];
+        const double zc = dinv[c] * tc;
+        r[c] = tc;
+        p[c] = zc;
+        t2[c] = 0.0;
+        a += tc * zc;
+        b += tc * tc;
+    }
+    double rho = block_sum(a, lds, kWideBlock);   // block_sum synchronises: p is visible
+    double rr = block_sum(b, lds, kWideBlock);
+    const double lim = rtol * rtol * rr;
+    int k = 0;
+    while (k < maxiter && rr > lim) {
+        double pq = 0.0;
+        for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) {
+            double s = 0.0;
+            for (int64_t e = ptr[c]; e < ptr[c + 1]; ++e) s += val[e] * p[col[e]];
+            q[c] = s;
+            pq += p[c] * s;
+        }
+        const double alpha = rho / block_sum(pq, lds, kWideBlock);
+        double rz = 0.0, r2 = 0.0;
+        for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) {
+            t2[c] += alpha * p[c];
+            const double rn = r[c] - alpha * q[c];
+            r[c] = rn;
+            rz += rn * (dinv[c] * rn);
+            r2 += rn * rn;
+        }
+        const double rho_new = block_sum(rz, lds, kWideBlock);
+        rr = block_sum(r2, lds, kWideBlock);
+        const double beta = rho_new / rho;
+        rho = rho_new;
+        for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) p[c] = dinv[c] * r[c] + beta * p[c];
+        __syncthreads();   // p complete before the next product
+        ++k;
+    }
+    if (threadIdx.x == 0) iters[sys] += k;
+}
+
 // dst = (float) src: E^{-1} rounded to single precision for the FP32 coarse
 // solve
 static __global__ void k_to_f32(int64_t n, const double *__restrict__ src, float *__restrict__ dst) {

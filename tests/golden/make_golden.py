@@ -81,6 +81,10 @@ if __name__ == "__main__":
     if "lognormal_fgmres" in which:
         record("poisson150_lognormal2_boxes64_linear_fgmres30_fp32coarse", config_lognormal_poisson(),
                OracleParams(solver="fgmres", restart=30, coarse_solve="fp32"))
+    if "lognormal_fgmres_cg" in which:
+        record("poisson150_lognormal2_boxes64_linear_fgmres30_cgcoarse", config_lognormal_poisson(),
+               OracleParams(solver="fgmres", restart=30, coarse_solve="cg", coarse_rtol=1e-2,
+                            coarse_maxiter=100))
     if "oseen" in which:
         record("oseen64_boxes256_field", config_oseen(),
                OracleParams(solver="bicgstab", block_size=4))

@@ -164,3 +164,35 @@ def test_fgmres_profiled_solve_unchanged(profile, graph_iters):
         if prof:
             assert st["kernels"]["spmv"]["calls"] > 0 and st["kernels"]["spmv"]["ms"] > 0
     assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("crtol", [1e-1, 1e-2, 1e-4])
+def test_fgmres_iterative_coarse_solve_parity(crtol):
+    """The CG coarse solve to a relaxed tolerance (a preconditioner that
+    changes from call to call) against the oracle's."""
+    from workloads import make_problem
+    P = make_problem("p16", (16, 16, 16), (2, 2, 2), deflation="linear", sigma=1.0, coef_seed=3,
+                     rhs="uniform", rhs_seed=4)
+    kw = dict(solver="fgmres", restart=12, coarse_solve="cg", coarse_rtol=crtol, coarse_enough=60)
+    ref, out = _pair(P, kw)
+    _check(ref, out)
+    h, g = out["history"], ref["history"]
+    k = min(len(h), len(g), 6)
+    assert np.allclose(h[:k], g[:k], rtol=1e-6)
+
+
+def test_fgmres_iterative_coarse_solve_reports_steps_and_rejects_nonsymmetric_E():
+    import paper_1710_03940_amd as L
+    from workloads import make_problem
+    P = make_problem("p12", (12, 12, 12), (2, 2, 1), deflation="linear", sigma=1.0, coef_seed=5)
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, solver="fgmres", coarse_solve="cg", coarse_enough=60)
+    x = _t(np.zeros(P.n))
+    out = S.solve(_t(P.b), x)
+    st = S.stats()
+    S.close()
+    assert out["status"] == 0
+    assert st["coarse_iters"] >= out["iters"]          # at least one CG step per application
+    Q = _convdiff(9, (2, 1, 1), "linear", 4.0, seed=2)
+    with pytest.raises(L.DfamgError) as ei:
+        L.Solver(Q.A, Q.part, Q.nsub, Q.Z, solver="fgmres", coarse_solve="cg", coarse_enough=20)
+    assert ei.value.status == 1                          # DFAMG_EINVAL

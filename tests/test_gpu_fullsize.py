@@ -173,3 +173,26 @@ def test_lognormal150_fgmres_matches_oracle(lognormal150, coarse, precision):
     idx = np.array(g["sample_index"])
     gs = np.array(g["sample_x"])
     assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+
+
+def test_lognormal150_fgmres_cg_coarse_matches_oracle(lognormal150):
+    """FGMRES(30) with the iterative coarse solve (CG on E to 1e-2)."""
+    import paper_1710_03940_amd as L
+    P = lognormal150
+    g = _golden("poisson150_lognormal2_boxes64_linear_fgmres30_cgcoarse")
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, solver="fgmres", restart=30, coarse_solve="cg",
+                 coarse_rtol=1e-2, coarse_maxiter=100)
+    dev = torch.device("cuda:0")
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    out = S.solve(torch.tensor(P.b, device=dev), x)
+    st = S.stats()
+    S.close()
+    print(f"fgmres cg coarse: gpu iters {out['iters']} oracle {g['iters']} relres_true "
+          f"{out['relres_true']:.3e} coarse steps {st['coarse_iters']}", flush=True)
+    assert out["status"] == 0
+    assert out["relres_true"] <= TRUE_RES_TOL
+    assert abs(out["iters"] - g["iters"]) <= 2
+    xs = x.cpu().numpy()
+    idx = np.array(g["sample_index"])
+    gs = np.array(g["sample_x"])
+    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)

@@ -231,6 +231,9 @@ def test_validation_errors():
     # the exact coarse solve
     _expect(_lib.EINVAL, P, coarse_solve=_lib.COARSE_FP32)
     _expect(_lib.EINVAL, P, solver=_lib.SOLVER_BICGSTAB, coarse_solve=_lib.COARSE_FP32)
+    _expect(_lib.EINVAL, P, coarse_solve=_lib.COARSE_CG)
+    _expect(_lib.EINVAL, P, solver=_lib.SOLVER_FGMRES, coarse_solve=_lib.COARSE_CG, coarse_rtol=-1.0)
+    _expect(_lib.EINVAL, P, solver=_lib.SOLVER_FGMRES, coarse_solve=_lib.COARSE_CG, coarse_maxiter=0)
     _expect(_lib.EINVAL, P, coarse_enough=0)
     _expect(_lib.EINVAL, P, max_levels=21)
     _expect(_lib.EINVAL, P, block_size=4)                             # 216 rows, 4 | 216 but
