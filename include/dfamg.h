@@ -318,6 +318,28 @@ dfamg_status dfamg_plan_coarse_operator(dfamg_plan p, int32_t sys, int32_t *m,
 
 dfamg_status dfamg_plan_destroy(dfamg_plan p);
 
+/*
+ * E^{-1} of system `sys` as the handle holds it on the device (the inverse
+ * the projection applies), copied to the host buffer Einv (row-major m x m,
+ * same ordering as dfamg_plan_coarse_operator); pass NULL to query m only.
+ * EINVAL when cap < m * m or sys is out of range.
+ */
+dfamg_status dfamg_coarse_inverse(dfamg_handle h, int32_t sys, int32_t *m,
+                                  double *Einv, int64_t cap);
+
+/*
+ * Dense FP64 inverse of the host row-major n x n matrix a into out (host),
+ * computed on the current device by one of the two eliminations the setup
+ * uses for E (Gauss-Jordan, partial pivoting, first row of largest |a_ik|):
+ * method 0, column panels of 64 with GEMM updates (rocBLAS on the FP64 matrix
+ * cores), the form used for coarse operators of 1024 or more unknowns;
+ * method 1, one pivot per step over the whole matrix, used for smaller
+ * ones and the coarsest AMG blocks.  1 <= n <= 4096.  ESINGULAR when a pivot
+ * column is exactly zero.  Synchronous.
+ */
+dfamg_status dfamg_dense_inverse(const double *a, int32_t n, int32_t method,
+                                 double *out);
+
 #ifdef __cplusplus
 }
 #endif

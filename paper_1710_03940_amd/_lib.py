@@ -31,7 +31,8 @@ EXPORTED = [
     "dfamg_solve_batched", "dfamg_apply", "dfamg_get_stats", "dfamg_destroy",
     "dfamg_last_error", "dfamg_plan_create", "dfamg_plan_levels",
     "dfamg_plan_aggregates", "dfamg_plan_level_matrix",
-    "dfamg_plan_coarse_operator", "dfamg_plan_destroy",
+    "dfamg_plan_coarse_operator", "dfamg_plan_destroy", "dfamg_coarse_inverse",
+    "dfamg_dense_inverse",
 ]
 
 
@@ -109,6 +110,8 @@ def load():
     lib.dfamg_plan_level_matrix.argtypes = [H, I32, I32, I32, P, P, P, P, P, P]
     lib.dfamg_plan_coarse_operator.argtypes = [H, I32, P, P, I64]
     lib.dfamg_plan_destroy.argtypes = [H]
+    lib.dfamg_coarse_inverse.argtypes = [H, I32, P, P, I64]
+    lib.dfamg_dense_inverse.argtypes = [P, I32, I32, P]
     for name in EXPORTED:
         f = getattr(lib, name)
         if name not in ("dfamg_params_default", "dfamg_last_error"):
@@ -303,6 +306,26 @@ def dfamg_plan_coarse_operator(p, sys=0):
     _check(lib.dfamg_plan_coarse_operator(ctypes.c_void_p(p), sys, ctypes.byref(m), _ptr(E),
                                           E.size))
     return E
+
+
+def dfamg_coarse_inverse(h, sys=0):
+    """E^{-1} of system `sys` as held on the device (numpy array)."""
+    lib = load()
+    m = ctypes.c_int32()
+    _check(lib.dfamg_coarse_inverse(ctypes.c_void_p(h), sys, ctypes.byref(m), None, 0))
+    X = np.zeros((m.value, m.value))
+    _check(lib.dfamg_coarse_inverse(ctypes.c_void_p(h), sys, ctypes.byref(m), _ptr(X), X.size))
+    return X
+
+
+def dfamg_dense_inverse(a, method=0):
+    """Inverse of a dense float64 matrix computed on the GPU (method 0 blocked,
+    1 unblocked)."""
+    lib = load()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.zeros_like(a)
+    _check(lib.dfamg_dense_inverse(_ptr(a), a.shape[0], method, _ptr(out)))
+    return out
 
 
 def dfamg_plan_destroy(p):

@@ -18,8 +18,9 @@ UNITS = [
     ("launch_outer.hip", [], "launch_outer.o"),
     ("launch_vcycle.hip", ["-DDFAMG_VT_DOUBLE"], "launch_vcycle_f64.o"),
     ("launch_vcycle.hip", [], "launch_vcycle_f32.o"),
+    ("dense_inverse.hip", [], "dense_inverse.o"),
 ]
-HEADERS = ["host_plan.hpp", "kernels.hpp", "devmat.hpp"]
+HEADERS = ["host_plan.hpp", "kernels.hpp", "kernels_fgmres.hpp", "devmat.hpp", "dense_inverse.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -61,7 +62,7 @@ def build(force=True, verbose=True, jobs=None):
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(run, cmds))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas", "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
