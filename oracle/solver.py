@@ -39,7 +39,7 @@ class OracleParams:
     max_levels: int = 20
     block_size: int = 1
     flexible: bool = False
-    precond: str = "amg"            # "amg" or "identity" (deflated CG only)
+    precond: str = "amg"            # "amg", "identity" or "spai0" (diagonal)
 
 
 def validate(A, part, nsub, Z):
@@ -78,6 +78,11 @@ class OracleSolver:
                               jacobi_omega=self.prm.jacobi_omega,
                               bs=self.prm.block_size)
             self.precond = self.M.apply
+        elif self.prm.precond == "spai0":
+            # purely local SPAI-0: m_i = a_ii / sum_j a_ij^2
+            self.M = None
+            m = A.diagonal() / np.asarray(A.multiply(A).sum(axis=1)).ravel()
+            self.precond = lambda r: m * r
         else:
             self.M = None
             self.precond = lambda r: r.copy()
