@@ -72,7 +72,11 @@ enum { DFAMG_COARSE_EXACT = 0, DFAMG_COARSE_FP32 = 1, DFAMG_COARSE_CG = 2 };
 enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
 enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1 };
 enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2 };
-enum { DFAMG_PRECOND_AMG = 0, DFAMG_PRECOND_NONE = 1 };
+/* Preconditioner M: the block-local SA-AMG V-cycle, none (M = I), or the
+ * purely local SPAI-0 diagonal m_i = a_ii / sum_j a_ij^2 (the velocity-block
+ * preconditioner of the Schur pressure correction, section "Navier-Stokes
+ * problem"). */
+enum { DFAMG_PRECOND_AMG = 0, DFAMG_PRECOND_NONE = 1, DFAMG_PRECOND_SPAI0 = 2 };
 
 typedef struct {
     int32_t solver;         /* DFAMG_SOLVER_*; CG needs a symmetric A; one
@@ -97,7 +101,8 @@ typedef struct {
                                on every coarser level                          */
     int32_t max_levels;     /* hierarchy depth limit (20)                      */
     int32_t block_size;     /* 1 (scalar) or 2..8 (point blocks, interleaved)  */
-    int32_t precond;        /* DFAMG_PRECOND_AMG (default) or _NONE (M = I)    */
+    int32_t precond;        /* DFAMG_PRECOND_AMG (default), _NONE (M = I) or
+                               _SPAI0 (diagonal)                              */
     int32_t spmv_format;    /* DFAMG_FORMAT_*: AUTO lets the setup autotuner
                                time the candidates on the device              */
     int32_t autotune;       /* 1 (default): time the candidate layouts of every
@@ -172,6 +177,34 @@ dfamg_status dfamg_setup_batched(const dfamg_params *prm, int32_t nsys,
                                  const double *val, const int32_t *part,
                                  int32_t nsub, int32_t ndv, const double *Z,
                                  void *stream, dfamg_handle *out);
+
+/*
+ * Setup of the Schur pressure-correction solver for a velocity-pressure
+ * system [K G; D S] (section "Navier-Stokes problem"): restarted flexible
+ * GMRES on A x = b (prm->solver must be DFAMG_SOLVER_FGMRES; restart, rtol,
+ * maxiter from prm; the paper runs FGMRES(50)) preconditioned by
+ *   1. u^ ~ K^{-1} r_u,  2. p ~ S^^{-1} (r_p - D u^),  3. u ~ K^{-1} (r_u - G p)
+ * with S^ = S - D diag(K)^{-1} G formed on the host.  The K solves are
+ * FGMRES(5) with the local SPAI-0 preconditioner to 1e-3 (at most 5 steps);
+ * the pressure solves are FGMRES(20) to 1e-2 (at most 20 steps) on S^,
+ * preconditioned by the subdomain deflation (exact E^{-1}) combined with the
+ * block-local AMG of S^ (precision, smoother, coarse_enough and eps_strong
+ * from prm): the settings of the paper's JSON listing.  Every inner solve
+ * starts from zero; one reaching its step limit returns its last iterate.
+ *   pmask   host, n flags: nonzero marks a pressure unknown; the velocity
+ *           and pressure unknowns are numbered in ascending index order
+ *   part    host, one subdomain id in [0, nsub) per pressure unknown
+ *   Z       host, (number of pressure unknowns) x ndv row-major deflation
+ *           vectors of the pressure block (as in dfamg_setup)
+ * Other arguments as in dfamg_setup.  The handle is solved with dfamg_solve;
+ * dfamg_apply and the batched calls reject it.  Errors as dfamg_setup, and
+ * EINVAL when a block is empty or a diagonal entry of K is zero.
+ */
+dfamg_status dfamg_setup_schur(const dfamg_params *prm, int64_t n,
+                               const int64_t *row_ptr, const int32_t *col,
+                               const double *val, const int32_t *pmask,
+                               const int32_t *part, int32_t nsub, int32_t ndv,
+                               const double *Z, void *stream, dfamg_handle *out);
 
 /*
  * Solve A x = b (single-system handle).

@@ -14,9 +14,9 @@ from ._lib import (DfamgError, dfamg_params_default, dfamg_setup, dfamg_setup_ba
                    dfamg_destroy, dfamg_last_error, dfamg_plan_create, dfamg_plan_levels,
                    dfamg_plan_aggregates, dfamg_plan_level_matrix,
                    dfamg_plan_coarse_operator, dfamg_plan_destroy, dfamg_coarse_inverse,
-                   dfamg_dense_inverse)
+                   dfamg_dense_inverse, dfamg_setup_schur)
 
-__all__ = ["Solver", "BatchedSolver", "make_params", "DfamgError"] + [
+__all__ = ["Solver", "BatchedSolver", "SchurSolver", "make_params", "DfamgError"] + [
     n for n in dir(_lib) if n.startswith("dfamg_")]
 
 _ENUMS = {
@@ -26,7 +26,7 @@ _ENUMS = {
     "precision": {"fp64": _lib.PREC_FP64, "mixed": _lib.PREC_MIXED},
     "smoother": {"spai0": _lib.SMOOTHER_SPAI0, "jacobi": _lib.SMOOTHER_JACOBI},
     "spmv_format": {"auto": _lib.FORMAT_AUTO, "csr": _lib.FORMAT_CSR, "sell": _lib.FORMAT_SELL},
-    "precond": {"amg": _lib.PRECOND_AMG, "none": _lib.PRECOND_NONE},
+    "precond": {"amg": _lib.PRECOND_AMG, "none": _lib.PRECOND_NONE, "spai0": _lib.PRECOND_SPAI0},
 }
 
 
@@ -97,3 +97,15 @@ class BatchedSolver(Solver):
 
     def solve(self, b, x, history=False):
         return dfamg_solve_batched(self.h, _dev_ptr(b, self.n), _dev_ptr(x, self.n), self.nsys)
+
+
+class SchurSolver(Solver):
+    """Flexible GMRES on a velocity-pressure system with the Schur
+    pressure-correction preconditioner (inner solvers as in dfamg.h)."""
+
+    def __init__(self, A, pmask, part, nsub, Z, **params):
+        self.n = A.shape[0]
+        params.setdefault("solver", "fgmres")
+        params.setdefault("restart", 50)
+        self.params = make_params(**params)
+        self.h = dfamg_setup_schur(self.params, A, pmask, part, nsub, Z, stream=_stream())

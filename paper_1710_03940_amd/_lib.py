@@ -21,7 +21,7 @@ COARSE_EXACT, COARSE_FP32, COARSE_CG = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 SMOOTHER_SPAI0, SMOOTHER_JACOBI = 0, 1
 FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL = 0, 1, 2
-PRECOND_AMG, PRECOND_NONE = 0, 1
+PRECOND_AMG, PRECOND_NONE, PRECOND_SPAI0 = 0, 1, 2
 OP_SPMV, OP_PROJECT, OP_PRECOND, OP_RECOVER = 0, 1, 2, 3
 KERNEL_NAMES = ["spmv", "project", "update", "test", "presmooth0", "restrict0", "coarser",
                 "prolong0", "postsmooth0", "direction"]
@@ -32,7 +32,7 @@ EXPORTED = [
     "dfamg_last_error", "dfamg_plan_create", "dfamg_plan_levels",
     "dfamg_plan_aggregates", "dfamg_plan_level_matrix",
     "dfamg_plan_coarse_operator", "dfamg_plan_destroy", "dfamg_coarse_inverse",
-    "dfamg_dense_inverse",
+    "dfamg_dense_inverse", "dfamg_setup_schur",
 ]
 
 
@@ -112,6 +112,8 @@ def load():
     lib.dfamg_plan_destroy.argtypes = [H]
     lib.dfamg_coarse_inverse.argtypes = [H, I32, P, P, I64]
     lib.dfamg_dense_inverse.argtypes = [P, I32, I32, P]
+    lib.dfamg_setup_schur.argtypes = [ctypes.POINTER(Params), I64, P, P, P, P, P, I32, I32, P, P,
+                                      ctypes.POINTER(H)]
     for name in EXPORTED:
         f = getattr(lib, name)
         if name not in ("dfamg_params_default", "dfamg_last_error"):
@@ -306,6 +308,23 @@ def dfamg_plan_coarse_operator(p, sys=0):
     _check(lib.dfamg_plan_coarse_operator(ctypes.c_void_p(p), sys, ctypes.byref(m), _ptr(E),
                                           E.size))
     return E
+
+
+def dfamg_setup_schur(prm, A, pmask, part, nsub, Z, stream=None):
+    """Schur pressure-correction handle.  A: scipy CSR of the whole system;
+    pmask: nonzero for pressure unknowns; part / Z: subdomain ids and
+    deflation vectors of the pressure unknowns (ascending index order)."""
+    lib = load()
+    ptr, col, val = _csr_arrays(A)
+    pmask = np.ascontiguousarray(pmask, dtype=np.int32)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    h = ctypes.c_void_p()
+    st = lib.dfamg_setup_schur(ctypes.byref(prm), A.shape[0], _ptr(ptr), _ptr(col), _ptr(val), _ptr(pmask),
+                               _ptr(part), int(nsub), Z.shape[1], _ptr(Z),
+                               ctypes.c_void_p(stream or 0), ctypes.byref(h))
+    _check(st)
+    return h.value
 
 
 def dfamg_coarse_inverse(h, sys=0):

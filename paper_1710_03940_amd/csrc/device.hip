@@ -24,6 +24,7 @@
 #include "host_plan.hpp"
 #include "kernels.hpp"
 #include "kernels_fgmres.hpp"
+#include "kernels_schur.hpp"
 
 namespace dfamg {
 
@@ -1003,6 +1004,11 @@ struct Handle {
     int32_t hist_stride = 0;
     double *relres_true = nullptr;
     std::unique_ptr<PrecondBase> M;
+    double *d_spai = nullptr;              // SPAI-0 diagonal (precond SPAI0)
+    // a preconditioner supplied by a composite solver (the Schur pressure
+    // correction); it may synchronise the stream, so it runs with direct
+    // launches only
+    std::function<void(hipStream_t, const double *, double *)> ext_precond;
     // graph of `graph_iters` iterations
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -1291,6 +1297,20 @@ void Handle::setup_device() {
         HIP_CHECK(hipMemsetAsync(part_rs_job, 0, sizeof(double) * std::max(1, M->ncjobs0), sm));
         d_sys_cjob_off0 = ar.upload(M->sys_cjob_off0, sm);
     } else {
+        if (prm.precond == DFAMG_PRECOND_SPAI0) {
+            // m_i = a_ii / sum_j a_ij^2 over the rows of the permuted matrix
+            std::vector<double> m(n);
+            for (int64_t i = 0; i < n; ++i) {
+                double d = 0.0, ss = 0.0;
+                for (int64_t e = P.A.ptr[i]; e < P.A.ptr[i + 1]; ++e) {
+                    ss += P.A.val[e] * P.A.val[e];
+                    if (P.A.col[e] == i) d = P.A.val[e];
+                }
+                if (d == 0.0) throw Error{DFAMG_EINVAL, "SPAI-0 needs a nonzero diagonal"};
+                m[i] = d / ss;
+            }
+            d_spai = ar.upload(m, sm);
+        }
         part_rs = ar.alloc<double>(nrow_tiles);
         d_sto0 = d_sto_rows;
         part_rs_job = ar.alloc<double>(1);
@@ -1406,7 +1426,12 @@ void Handle::project_solve(hipStream_t st, bool in_loop, const int32_t *subto, d
 }
 
 void Handle::precond(hipStream_t st, const double *rin, double *sout, bool profiled) {
-    if (M) {
+    if (ext_precond) {
+        ext_precond(st, rin, sout);
+    } else if (d_spai) {
+        hipLaunchKernelGGL(k_diag_scale, dim3(grid_for_tiles(nrow_tiles)), dim3(kBlock), 0, st, rows, nrow_tiles,
+                           d_spai, rin, sout, part_rs, states, d_sub_sys);
+    } else if (M) {
         M->apply(st, rin, sout, part_rs, part_rs_job, states, d_sub_sys, (profiled && prof.on) ? &prof : nullptr);
     } else {
         hipLaunchKernelGGL(k_identity, dim3(grid_for_tiles(nrow_tiles)), dim3(kBlock), 0, st, rows, nrow_tiles, rin,
@@ -1587,6 +1612,15 @@ void Handle::cycle_fgmres(hipStream_t st) {
         hipLaunchKernelGGL(k_fg_givens, gs, wb, 0, st, part_rows, d_sto_rows, fg, states, hist, hist_stride, prm.rtol,
                            prm.maxiter, j);
         prof.mark(KID_TEST, 1, st);
+        if (ext_precond) {
+            // an external preconditioner does real work even for stopped
+            // systems: leave the cycle as soon as every system has stopped
+            HIP_CHECK(hipMemcpyAsync(h_states, states, sizeof(SysState) * nsys(), hipMemcpyDeviceToHost, st));
+            HIP_CHECK(hipStreamSynchronize(st));
+            bool all = true;
+            for (int i = 0; i < nsys(); ++i) all = all && h_states[i].done != kRunning;
+            if (all) break;
+        }
     }
     // x += sum_i y_i z_i, then V_0 = b - A x, its Z^T partials and norm
     hipLaunchKernelGGL(k_fg_solve, dim3((nsys() + 63) / 64), dim3(64), 0, st, fg, nsys());
@@ -1829,8 +1863,54 @@ void Handle::apply_op(int op, const double *in, double *out) {
 
 using namespace dfamg;
 
+namespace dfamg {
+
+// Schur pressure correction (section "Navier-Stokes problem"): the velocity
+// and pressure blocks, the two inner solvers and the preconditioner step
+// that the outer FGMRES handle calls.
+struct SchurParts {
+    std::unique_ptr<Handle> K, P;        // velocity solves, pressure solves
+    DevArena ar;
+    hipStream_t stream = nullptr;
+    int64_t nu = 0, np = 0;
+    int64_t *uidx = nullptr, *pidx = nullptr;
+    int64_t *Dp = nullptr, *Gp = nullptr;
+    int32_t *Dc = nullptr, *Gc = nullptr;
+    double *Dv = nullptr, *Gv = nullptr;
+    double *ru = nullptr, *rp = nullptr, *uh = nullptr, *t = nullptr, *p = nullptr, *t2 = nullptr, *u = nullptr;
+    int64_t inner_k_iters = 0, inner_p_iters = 0;
+
+    static dim3 grid(int64_t m) { return dim3((unsigned)((m + 255) / 256)); }
+
+    // x = approximate H^{-1} rhs from x = 0; a solve that reaches its step
+    // limit (or breaks down) returns its last iterate
+    int inner(Handle &H, const double *rhs, double *x, int64_t m) {
+        HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * m, stream));
+        const dfamg_status st = H.run_solve(rhs, x);
+        if (st == DFAMG_ENAN) throw Error{DFAMG_ENAN, "an inner solve of the Schur preconditioner produced NaN"};
+        return H.h_states[0].iter;
+    }
+
+    // (u, p) for the residual r, both in the whole system's numbering
+    void apply(hipStream_t st, const double *rin, double *sout) {
+        hipLaunchKernelGGL(k_gather_idx, grid(nu), dim3(256), 0, st, nu, uidx, rin, ru);
+        hipLaunchKernelGGL(k_gather_idx, grid(np), dim3(256), 0, st, np, pidx, rin, rp);
+        inner_k_iters += inner(*K, ru, uh, nu);
+        hipLaunchKernelGGL(k_csr_resid, grid(np), dim3(256), 0, st, np, Dp, Dc, Dv, uh, rp, t);
+        inner_p_iters += inner(*P, t, p, np);
+        hipLaunchKernelGGL(k_csr_resid, grid(nu), dim3(256), 0, st, nu, Gp, Gc, Gv, p, ru, t2);
+        inner_k_iters += inner(*K, t2, u, nu);
+        hipLaunchKernelGGL(k_scatter_idx, grid(nu), dim3(256), 0, st, nu, uidx, u, sout);
+        hipLaunchKernelGGL(k_scatter_idx, grid(np), dim3(256), 0, st, np, pidx, p, sout);
+        HIP_CHECK(hipGetLastError());
+    }
+};
+
+}  // namespace dfamg
+
 struct dfamg_handle_s {
     Handle h;
+    std::unique_ptr<SchurParts> schur;   // set for a Schur pressure-correction handle
 };
 
 struct dfamg_plan_s {
@@ -1869,6 +1949,43 @@ void check_device() {
     HIP_CHECK(hipGetDeviceProperties(&prop, dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         throw Error{DFAMG_ENOGPU, std::string("this build targets gfx950, device is ") + prop.gcnArchName};
+}
+
+// Builds a handle in place (validation, host plan, device setup).
+void init_handle(Handle &H, const dfamg_params &p, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                 const double *val, const int32_t *part, int32_t nsub, int32_t ndv, const double *Z, void *stream) {
+    build_plan(H.plan, p, 1, nullptr, n, row_ptr, col, val, part, nsub, ndv, Z);
+    check_device();
+    H.prm = p;
+    H.stream = static_cast<hipStream_t>(stream);
+    HIP_CHECK(hipGetDevice(&H.device));
+    HIP_CHECK(hipStreamCreateWithFlags(&H.cap_stream, hipStreamNonBlocking));
+    H.setup_device();
+}
+
+// CSR block of the given rows restricted to the columns that have a position
+// in pos (-1: column outside the block), columns renumbered by pos, sorted.
+struct HostCsr {
+    std::vector<int64_t> ptr{0};
+    std::vector<int32_t> col;
+    std::vector<double> val;
+};
+
+HostCsr extract_block(const int64_t *row_ptr, const int32_t *col, const double *val, const std::vector<int64_t> &rows,
+                      const std::vector<int64_t> &pos) {
+    HostCsr B;
+    for (int64_t i : rows) {
+        std::vector<std::pair<int32_t, double>> e;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (pos[col[k]] >= 0) e.emplace_back((int32_t)pos[col[k]], val[k]);
+        std::sort(e.begin(), e.end());
+        for (auto &x : e) {
+            B.col.push_back(x.first);
+            B.val.push_back(x.second);
+        }
+        B.ptr.push_back((int64_t)B.col.size());
+    }
+    return B;
 }
 
 dfamg_status do_setup(const dfamg_params *prm, int32_t nsys, const int64_t *sys_row_off, int64_t n,
@@ -2012,6 +2129,10 @@ dfamg_status dfamg_apply(dfamg_handle h, int32_t op, const double *in, double *o
         return DFAMG_EINVAL;
     }
     Handle &H = h->h;
+    if (h->schur) {
+        H.err = "dfamg_apply does not take a Schur pressure-correction handle";
+        return DFAMG_EINVAL;
+    }
     return guarded(&H.err, [&]() -> dfamg_status {
         HIP_CHECK(hipSetDevice(H.device));
         H.apply_op(op, in, out);
@@ -2171,6 +2292,153 @@ dfamg_status dfamg_plan_coarse_operator(dfamg_plan p, int32_t sys, int32_t *m, d
 dfamg_status dfamg_plan_destroy(dfamg_plan p) {
     delete p;
     return DFAMG_OK;
+}
+
+dfamg_status dfamg_setup_schur(const dfamg_params *prm, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                               const double *val, const int32_t *pmask, const int32_t *part, int32_t nsub,
+                               int32_t ndv, const double *Z, void *stream, dfamg_handle *out) {
+    if (!out) {
+        g_last_error = "out is NULL";
+        return DFAMG_EINVAL;
+    }
+    *out = nullptr;
+    return guarded(nullptr, [&]() -> dfamg_status {
+        dfamg_params p;
+        if (prm) p = *prm;
+        else dfamg_params_default(&p);
+        if (p.solver != DFAMG_SOLVER_FGMRES) throw Error{DFAMG_EINVAL, "the Schur solver runs FGMRES (solver = FGMRES)"};
+        if (n < 2 || !row_ptr || !col || !val || !pmask) throw Error{DFAMG_EINVAL, "bad system arrays"};
+        for (int64_t i = 0; i < n; ++i)
+            if (row_ptr[i + 1] < row_ptr[i]) throw Error{DFAMG_EINVAL, "row_ptr not monotone"};
+        for (int64_t k = 0; k < row_ptr[n]; ++k)
+            if (col[k] < 0 || col[k] >= n) throw Error{DFAMG_EINVAL, "column index out of range"};
+        std::vector<int64_t> urows, prows, pos(n, -1);
+        for (int64_t i = 0; i < n; ++i) {
+            if (pmask[i]) {
+                pos[i] = (int64_t)prows.size();
+                prows.push_back(i);
+            } else {
+                pos[i] = (int64_t)urows.size();
+                urows.push_back(i);
+            }
+        }
+        if (urows.empty() || prows.empty()) throw Error{DFAMG_EINVAL, "the velocity or the pressure block is empty"};
+        std::vector<int64_t> upos(n, -1), ppos(n, -1);
+        for (int64_t i = 0; i < n; ++i) (pmask[i] ? ppos : upos)[i] = pos[i];
+        HostCsr K = extract_block(row_ptr, col, val, urows, upos);
+        HostCsr G = extract_block(row_ptr, col, val, urows, ppos);
+        HostCsr D = extract_block(row_ptr, col, val, prows, upos);
+        HostCsr S = extract_block(row_ptr, col, val, prows, ppos);
+        const int64_t nu = (int64_t)urows.size(), np = (int64_t)prows.size();
+        // S^ = S - D diag(K)^{-1} G, rows accumulated densely over a marker
+        std::vector<double> kinv(nu);
+        for (int64_t i = 0; i < nu; ++i) {
+            double d = 0.0;
+            for (int64_t e = K.ptr[i]; e < K.ptr[i + 1]; ++e)
+                if (K.col[e] == i) d = K.val[e];
+            if (d == 0.0) throw Error{DFAMG_EINVAL, "zero diagonal entry in the velocity block"};
+            kinv[i] = 1.0 / d;
+        }
+        HostCsr Sh;
+        {
+            std::vector<double> acc(np, 0.0);
+            std::vector<int64_t> mark(np, -1);
+            std::vector<int32_t> cols;
+            for (int64_t r = 0; r < np; ++r) {
+                cols.clear();
+                auto add = [&](int32_t c, double v) {
+                    if (mark[c] != r) {
+                        mark[c] = r;
+                        acc[c] = 0.0;
+                        cols.push_back(c);
+                    }
+                    acc[c] += v;
+                };
+                for (int64_t e = S.ptr[r]; e < S.ptr[r + 1]; ++e) add(S.col[e], S.val[e]);
+                for (int64_t e = D.ptr[r]; e < D.ptr[r + 1]; ++e) {
+                    const int32_t k = D.col[e];
+                    const double f = D.val[e] * kinv[k];
+                    for (int64_t g = G.ptr[k]; g < G.ptr[k + 1]; ++g) add(G.col[g], -f * G.val[g]);
+                }
+                std::sort(cols.begin(), cols.end());
+                for (int32_t c : cols) {
+                    Sh.col.push_back(c);
+                    Sh.val.push_back(acc[c]);
+                }
+                Sh.ptr.push_back((int64_t)Sh.col.size());
+            }
+        }
+        auto H = std::make_unique<dfamg_handle_s>();
+        auto parts = std::make_unique<SchurParts>();
+        parts->stream = static_cast<hipStream_t>(stream);
+        parts->nu = nu;
+        parts->np = np;
+        // velocity solves: FGMRES(5) to 1e-3 with the local SPAI-0
+        {
+            dfamg_params q = p;
+            q.solver = DFAMG_SOLVER_FGMRES;
+            q.restart = 5;
+            q.maxiter = 5;
+            q.rtol = 1e-3;
+            q.precond = DFAMG_PRECOND_SPAI0;
+            q.coarse_solve = DFAMG_COARSE_EXACT;
+            q.block_size = 1;
+            q.profile = 0;
+            q.graph_iters = 16;
+            std::vector<int32_t> part0(nu, 0);
+            parts->K = std::make_unique<Handle>();
+            init_handle(*parts->K, q, nu, K.ptr.data(), K.col.data(), K.val.data(), part0.data(), 1, 0, nullptr,
+                        stream);
+        }
+        // pressure solves: FGMRES(20) to 1e-2, deflation + block-local AMG of S^
+        {
+            dfamg_params q = p;
+            q.solver = DFAMG_SOLVER_FGMRES;
+            q.restart = 20;
+            q.maxiter = 20;
+            q.rtol = 1e-2;
+            q.precond = DFAMG_PRECOND_AMG;
+            q.coarse_solve = DFAMG_COARSE_EXACT;
+            q.block_size = 1;
+            q.profile = 0;
+            q.graph_iters = 16;
+            parts->P = std::make_unique<Handle>();
+            init_handle(*parts->P, q, np, Sh.ptr.data(), Sh.col.data(), Sh.val.data(), part, nsub, ndv, Z, stream);
+        }
+        // the outer FGMRES on the whole system, direct launches (the
+        // preconditioner synchronises)
+        {
+            dfamg_params q = p;
+            q.precond = DFAMG_PRECOND_NONE;
+            q.coarse_solve = DFAMG_COARSE_EXACT;
+            q.graph_iters = 0;
+            q.profile = 0;
+            std::vector<int32_t> part0(n, 0);
+            init_handle(H->h, q, n, row_ptr, col, val, part0.data(), 1, 0, nullptr, stream);
+        }
+        hipStream_t sm = parts->stream;
+        DevArena &ar = parts->ar;
+        parts->uidx = ar.upload(urows, sm);
+        parts->pidx = ar.upload(prows, sm);
+        parts->Dp = ar.upload(D.ptr, sm);
+        parts->Dc = ar.upload(D.col, sm);
+        parts->Dv = ar.upload(D.val, sm);
+        parts->Gp = ar.upload(G.ptr, sm);
+        parts->Gc = ar.upload(G.col, sm);
+        parts->Gv = ar.upload(G.val, sm);
+        parts->ru = ar.alloc<double>(nu);
+        parts->uh = ar.alloc<double>(nu);
+        parts->t2 = ar.alloc<double>(nu);
+        parts->u = ar.alloc<double>(nu);
+        parts->rp = ar.alloc<double>(np);
+        parts->t = ar.alloc<double>(np);
+        parts->p = ar.alloc<double>(np);
+        SchurParts *sp = parts.get();
+        H->h.ext_precond = [sp](hipStream_t st, const double *rin, double *sout) { sp->apply(st, rin, sout); };
+        H->schur = std::move(parts);
+        *out = H.release();
+        return DFAMG_OK;
+    });
 }
 
 dfamg_status dfamg_coarse_inverse(dfamg_handle h, int32_t sys, int32_t *m, double *Einv, int64_t cap) {

@@ -678,7 +678,8 @@ void validate_params(const dfamg_params &p) {
     if (!(p.eps_strong >= 0.0) || !std::isfinite(p.eps_strong)) fail(DFAMG_EINVAL, "eps_strong must be >= 0");
     if (p.max_levels < 1 || p.max_levels > 20) fail(DFAMG_EINVAL, "max_levels must be in [1, 20]");
     if (p.block_size < 1 || p.block_size > 8) fail(DFAMG_EINVAL, "block_size must be in [1, 8]");
-    if (p.precond != DFAMG_PRECOND_AMG && p.precond != DFAMG_PRECOND_NONE) fail(DFAMG_EINVAL, "unknown precond");
+    if (p.precond != DFAMG_PRECOND_AMG && p.precond != DFAMG_PRECOND_NONE && p.precond != DFAMG_PRECOND_SPAI0)
+        fail(DFAMG_EINVAL, "unknown precond");
     if (p.spmv_format < DFAMG_FORMAT_AUTO || p.spmv_format > DFAMG_FORMAT_SELL) fail(DFAMG_EINVAL, "unknown spmv_format");
     if (p.graph_iters < 0) fail(DFAMG_EINVAL, "graph_iters must be >= 0");
 }
@@ -942,7 +943,7 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
     SaParams sp;
     sp.eps_strong = prm.eps_strong;
     sp.coarse_enough = prm.coarse_enough;
-    sp.max_levels = prm.precond == DFAMG_PRECOND_NONE ? 1 : prm.max_levels;
+    sp.max_levels = prm.precond == DFAMG_PRECOND_AMG ? prm.max_levels : 1;
     sp.smoother = prm.smoother;
     sp.jacobi_omega = prm.jacobi_omega;
     sp.bs = bs;

@@ -283,3 +283,20 @@ def test_setup_without_gpu_fails_loudly():
     with pytest.raises(L.DfamgError) as ei:
         L.dfamg_setup(L.make_params(), P.A, P.part, P.nsub, P.Z)
     assert ei.value.status in (_lib.ENOGPU, _lib.EHIP)
+
+
+def test_schur_setup_validation():
+    """Rejected on the host before any device work."""
+    from workloads import oseen_q1
+    A, _ = oseen_q1(4)
+    n = A.shape[0]
+    pmask = (np.arange(n) % 4 == 3).astype(np.int32)
+    part = np.zeros(64, dtype=np.int32)
+    Z = np.ones((64, 1))
+    for kw, mask in [(dict(solver=_lib.SOLVER_CG), pmask),           # needs FGMRES
+                     (dict(solver=_lib.SOLVER_FGMRES), np.zeros(n, dtype=np.int32)),   # no pressure
+                     (dict(solver=_lib.SOLVER_FGMRES), np.ones(n, dtype=np.int32))]:   # no velocity
+        with pytest.raises(L.DfamgError) as ei:
+            L.dfamg_setup_schur(L.make_params(**kw), A, mask, part, 1, Z)
+        assert ei.value.status == _lib.EINVAL
+
