@@ -114,6 +114,7 @@ def main():
     ap.add_argument("--no-oseen", action="store_true")
     ap.add_argument("--no-bicgstab2", action="store_true")
     ap.add_argument("--no-fgmres", action="store_true")
+    ap.add_argument("--no-schur", action="store_true")
     ap.add_argument("--sample-iters", type=int, default=20)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -229,6 +230,13 @@ def main():
         except Exception as exc:  # reported, never silently dropped
             oseen = {"error": str(exc)}
 
+    schur = None
+    if not args.no_schur:
+        try:
+            schur = bench_schur(args, log)
+        except Exception as exc:  # reported, never silently dropped
+            schur = {"error": str(exc)}
+
     batched = None
     if not args.no_batched:
         try:
@@ -280,6 +288,7 @@ def main():
         "bytes_per_iter": st64["bytes_per_iter"],
         "effective_GBps": st64["bytes_per_iter"] * out64["iters"] / t64 / 1e9,
         "mixed": mixed, "batched": batched, "oseen": oseen, "bicgstab2": bicgstab2, "fgmres": fgmres,
+        "schur": schur,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_outer (outer SpMV + (p,q) + Z^T q epilogue)",
@@ -450,6 +459,38 @@ def bench_oseen(args, log):
                      "bytes_per_iter": st["bytes_per_iter"]}
         log(f"  oseen {prec}: {t * 1e3:.1f} ms, {its[-1]} iterations, relres {o['relres_true']:.2e}")
     out["speedup_mixed_vs_fp64"] = out["fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
+    return out
+
+
+def bench_schur(args, log):
+    """The 64^3 Oseen system (one backward-Euler step, dt = 0.1) solved by
+    FGMRES(50) with the Schur pressure-correction preconditioner (FP64 and
+    FP32 pressure AMG)."""
+    import time
+    import torch
+    import paper_1710_03940_amd as dfamg
+    from workloads import config_oseen_schur
+    log("generating the 64^3 Oseen system for the Schur pressure correction")
+    P, pmask, part_p, nsub, Zp = config_oseen_schur()
+    golden = load_golden("oseen64_boxes256_schur")
+    dev = torch.device("cuda:0")
+    b = torch.tensor(P.b, device=dev)
+    out = {"workload": P.name + "_dt0.1_schur", "n": P.n, "pressure_subdomains": nsub,
+           "solver": "fgmres(50) + Schur pressure correction", "oracle_iters": golden["iters"]}
+    for prec in ("fp64", "mixed"):
+        t0 = time.time()
+        S = dfamg.SchurSolver(P.A, pmask, part_p, nsub, Zp, precision=prec, rtol=1e-8)
+        setup = time.time() - t0
+        x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+        ts, o, its = time_solver(S, b, x, max(1, min(args.steps, 3)), args.warmup, log)
+        st = S.stats()
+        S.close()
+        out[prec] = {"s_per_solve": ts, "median_s": o["median_s"], "iters": its[-1],
+                     "relres_true": o["relres_true"], "rel_error_vs_oracle_sampled": error_vs_oracle(x, golden),
+                     "inner_iters_velocity": st["schur_inner_iters"][0],
+                     "inner_iters_pressure": st["schur_inner_iters"][1], "setup_s": setup}
+        log(f"  schur {prec}: {ts * 1e3:.1f} ms, {its[-1]} iterations, relres {o['relres_true']:.2e}, "
+            f"inner {st['schur_inner_iters']}")
     return out
 
 

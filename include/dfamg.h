@@ -280,6 +280,9 @@ typedef struct {
     int64_t coarse_iters;             /* COARSE_CG: CG steps of all coarse
                                          solves of the last solve call (sum
                                          over systems)                        */
+    int64_t schur_inner_iters[2];     /* Schur handle: iterations of the
+                                         velocity and of the pressure inner
+                                         solves in the last solve call        */
 } dfamg_stats;
 
 /* Kernel ids of the profile: the outer SpMV with its fused (p,q) and Z^T q

@@ -73,7 +73,7 @@ class Stats(ctypes.Structure):
         ("kernel_calls", ctypes.c_int64 * 16), ("kernel_ms", ctypes.c_double * 16),
         ("kernel_bytes", ctypes.c_double * 16), ("profile_in_graph", ctypes.c_int32),
         ("layouts", ctypes.c_char * 1024), ("outer_layout_bytes", ctypes.c_double),
-        ("coarse_iters", ctypes.c_int64),
+        ("coarse_iters", ctypes.c_int64), ("schur_inner_iters", ctypes.c_int64 * 2),
     ]
 
 
@@ -229,6 +229,7 @@ def dfamg_get_stats(h):
             "bytes_per_iter": s.bytes_per_iter, "profile_in_graph": bool(s.profile_in_graph),
             "layouts": s.layouts.decode(), "outer_layout_bytes": s.outer_layout_bytes,
             "coarse_iters": int(s.coarse_iters),
+            "schur_inner_iters": [int(s.schur_inner_iters[0]), int(s.schur_inner_iters[1])],
             "kernels": {name: {"calls": int(s.kernel_calls[i]), "ms": float(s.kernel_ms[i]),
                                "bytes": float(s.kernel_bytes[i])}
                         for i, name in enumerate(KERNEL_NAMES)}}

@@ -2076,6 +2076,7 @@ dfamg_status dfamg_solve(dfamg_handle h, const double *rhs, double *x, int32_t *
     }
     return guarded(&H.err, [&]() -> dfamg_status {
         HIP_CHECK(hipSetDevice(H.device));
+        if (h->schur) h->schur->inner_k_iters = h->schur->inner_p_iters = 0;
         const dfamg_status st = H.run_solve(rhs, x);
         const SysState &S = H.h_states[0];
         if (iters) *iters = S.iter;
@@ -2167,6 +2168,10 @@ dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *o) {
     o->format_outer = H.A.fmt;
     o->outer_layout_bytes = H.outer_layout_bytes;
     o->coarse_iters = H.coarse_iters_last;
+    if (h->schur) {
+        o->schur_inner_iters[0] = h->schur->inner_k_iters;
+        o->schur_inner_iters[1] = h->schur->inner_p_iters;
+    }
     {
         const std::string t = "outer " + describe(H.A) + (H.outer_split ? "+couplings" : "") +
                               (H.M ? ";" + H.M->layouts : std::string());

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from workloads import (config_lognormal_poisson, config_small_poisson, config_batched,  # noqa: E402
-                       config_oseen)
+                       config_oseen, config_oseen_schur)
 from oracle import OracleSolver, OracleParams  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -48,6 +48,25 @@ def record(name, P, prm=None):
 
 
 BATCHED_SAMPLE_SYSTEMS = [2, 12, 19, 28, 31, 42, 44, 47]
+
+
+def record_schur():
+    """The 64^3 Oseen system (one backward-Euler step, dt = 0.1) with the
+    Schur pressure-correction preconditioner inside FGMRES(50), rtol 1e-8."""
+    from oracle.schur import schur_fgmres
+    P, pmask, part_p, nsub, Zp = config_oseen_schur()
+    t0 = time.time()
+    r = schur_fgmres(P.A, P.b, pmask, part_p, nsub, Zp, rtol=1e-8, restart=50)
+    t1 = time.time()
+    idx = np.sort(np.random.default_rng(12345).choice(P.n, size=NSAMPLE, replace=False))
+    out = {"workload": P.name + "_dt0.1_schur", "n": int(P.n), "nnz": int(P.A.nnz), "nsub": int(nsub), "ndv": 1,
+           "rtol": 1e-8, "iters": int(r["iters"]), "restart": 50, "relres": float(r["relres"]),
+           "relres_true": float(r["relres_true"]), "history": [float(h) for h in r["history"]],
+           "x_norm": float(np.linalg.norm(r["x"])), "sample_index": [int(i) for i in idx],
+           "sample_x": [float(v) for v in r["x"][idx]]}
+    with open(os.path.join(HERE, "oseen64_boxes256_schur.json"), "w") as fh:
+        json.dump(out, fh)
+    print("oseen64_boxes256_schur", r["iters"], r["relres_true"], f"solve {t1 - t0:.1f}s", flush=True)
 
 
 def record_batched():
@@ -85,6 +104,8 @@ if __name__ == "__main__":
         record("poisson150_lognormal2_boxes64_linear_fgmres30_cgcoarse", config_lognormal_poisson(),
                OracleParams(solver="fgmres", restart=30, coarse_solve="cg", coarse_rtol=1e-2,
                             coarse_maxiter=100))
+    if "oseen_schur" in which:
+        record_schur()
     if "oseen" in which:
         record("oseen64_boxes256_field", config_oseen(),
                OracleParams(solver="bicgstab", block_size=4))

@@ -196,3 +196,27 @@ def test_lognormal150_fgmres_cg_coarse_matches_oracle(lognormal150):
     idx = np.array(g["sample_index"])
     gs = np.array(g["sample_x"])
     assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+
+
+def test_oseen64_schur_matches_oracle():
+    """FGMRES(50) with the Schur pressure correction on the 64^3 Oseen
+    system against the oracle's run."""
+    import paper_1710_03940_amd as L
+    from workloads import config_oseen_schur
+    P, pmask, part_p, nsub, Zp = config_oseen_schur()
+    g = _golden("oseen64_boxes256_schur")
+    S = L.SchurSolver(P.A, pmask, part_p, nsub, Zp, rtol=1e-8)
+    dev = torch.device("cuda:0")
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    out = S.solve(torch.tensor(P.b, device=dev), x)
+    st = S.stats()
+    S.close()
+    print(f"schur: gpu iters {out['iters']} oracle {g['iters']} relres_true {out['relres_true']:.3e} "
+          f"inner {st['schur_inner_iters']}", flush=True)
+    assert out["status"] == 0
+    assert out["relres_true"] <= TRUE_RES_TOL
+    assert abs(out["iters"] - g["iters"]) <= 2
+    xs = x.cpu().numpy()
+    idx = np.array(g["sample_index"])
+    gs = np.array(g["sample_x"])
+    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)

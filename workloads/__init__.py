@@ -18,7 +18,7 @@ from .partition import box_partition, slab_partition
 from .deflation import constant_deflation, linear_deflation
 from .configs import (Problem, config_small_poisson, config_lognormal_poisson,
                       config_batched, batched_recipe, concat_problems,
-                      make_problem, tiny_problem, config_oseen)
+                      make_problem, tiny_problem, config_oseen, config_oseen_schur)
 from .oseen import oseen_q1, field_deflation
 from .convdiff import convection_diffusion7
 
@@ -27,5 +27,5 @@ __all__ = [
     "constant_deflation", "linear_deflation", "Problem",
     "config_small_poisson", "config_lognormal_poisson", "config_batched",
     "batched_recipe", "concat_problems", "make_problem", "tiny_problem",
-    "config_oseen", "oseen_q1", "field_deflation", "convection_diffusion7",
+    "config_oseen", "config_oseen_schur", "oseen_q1", "field_deflation", "convection_diffusion7",
 ]

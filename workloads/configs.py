@@ -163,3 +163,15 @@ def config_oseen(N=64, pieces=(8, 8, 4), nu=1e-2, dt=None):
     return Problem(f"oseen{N}_boxes{nsub}_field", A, part, nsub, Z, b,
                    np.zeros(n), (N, N, N), tuple(pieces),
                    {"nu": nu, "dt": dt, "block_size": 4, "deflation": "field"})
+
+
+def config_oseen_schur(N=64, pieces=(8, 8, 4), nu=1e-2, dt=0.1):
+    """The Oseen system of config_oseen, as one backward-Euler step of size dt
+    (the mass term of a transient solver), split for the Schur pressure
+    correction: pressure mask (every fourth unknown), box partition of the
+    pressure nodes and one constant deflation vector per subdomain."""
+    P = config_oseen(N=N, pieces=pieces, nu=nu, dt=dt)
+    pmask = (np.arange(P.n) % 4 == 3).astype(np.int32)
+    part_p, nsub = box_partition(N, N, N, *pieces)
+    return P, pmask, part_p, nsub, np.ones((N ** 3, 1))
+
