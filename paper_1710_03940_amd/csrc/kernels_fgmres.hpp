@@ -249,9 +249,9 @@ static __global__ void __launch_bounds__(kBlock) k_fg_axpy_dots(const DevTile *_
 // Partial ||v||^2 per tile (part row 0): the norm of a cycle's first vector.
 template <bool CHECK_DONE>
 __global__ void __launch_bounds__(kBlock) k_fg_norm(const DevTile *__restrict__ tiles, int32_t ntiles,
-                                                           const double *__restrict__ v, double *__restrict__ part,
-                                                           const SysState *__restrict__ st,
-                                                           const int32_t *__restrict__ sub_sys) {
+                                                    const double *__restrict__ v, double *__restrict__ part,
+                                                    const SysState *__restrict__ st,
+                                                    const int32_t *__restrict__ sub_sys) {
     __shared__ double lds[4];
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
