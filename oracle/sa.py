@@ -34,9 +34,10 @@ out their internals, so the oracle fixes the following readings:
   block diagonal of A_F (for b = 1: sum_j |a^F_ij| / |a^F_ii|), rows with a
   singular diagonal block excluded, computed per subdomain and level;
 * P = P_t - omega D^{-1} A_F P_t, R = P^T, A_{l+1} = R A_l P;
-* smoother diagonal on every non-coarsest level: SPAI-0
-  m_i = a_ii / sum_j a_ij^2 (Broeker & Grote 2002, scalar rows even for
-  block matrices) or damped Jacobi m_i = 0.8 / a_ii;
+* smoother on every non-coarsest level: SPAI-0 m_i = a_ii / sum_j a_ij^2
+  (Broeker & Grote 2002, scalar rows even for block matrices), damped
+  Jacobi m_i = 0.8 / a_ii, or block SPAI-0 (b x b diagonal blocks, see
+  block_spai0) for point-block matrices;
 * the coarsest level is solved exactly (dense LU with partial pivoting).
 """
 from dataclasses import dataclass, field
@@ -202,14 +203,36 @@ def smoothed_prolongation(AF, Ptent, omega, Dinv):
     return P
 
 
-def smoother_diagonal(A, kind="spai0", jacobi_omega=0.8):
+def smoother_diagonal(A, kind="spai0", jacobi_omega=0.8, bs=1):
+    """The smoother M of one level: a vector (diagonal SPAI-0 or damped
+    Jacobi) or, for "block_spai0", a block-diagonal sparse matrix."""
     d = A.diagonal()
     if kind == "spai0":
         sq = np.asarray(A.multiply(A).sum(axis=1)).ravel()
         return d / sq
     if kind == "jacobi":
         return jacobi_omega / d
+    if kind == "block_spai0":
+        return block_spai0(A, bs)
     raise ValueError(kind)
+
+
+def block_spai0(A, bs):
+    """Block SPAI-0: the block-diagonal M minimising ||I - M A||_F over
+    matrices with b x b diagonal blocks (the block form of the SPAI-0 of
+    Broeker and Grote).  Row block i of I - M A is E_i - M_i A_(i,:), whose
+    least-squares minimiser is M_i = A_ii^T (A_(i,:) A_(i,:)^T)^{-1}; for b = 1
+    this is a_ii / sum_j a_ij^2."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    nb = n // bs
+    blocks = []
+    for i in range(nb):
+        rows = A[i * bs:(i + 1) * bs]
+        G = (rows @ rows.T).toarray()
+        Aii = rows[:, i * bs:(i + 1) * bs].toarray()
+        blocks.append(np.linalg.solve(G.T, Aii).T)         # A_ii^T G^{-1}
+    return sp.block_diag(blocks, format="csr")
 
 
 def build_hierarchy(A, eps_strong=0.08, coarse_enough=500, max_levels=20,
@@ -240,7 +263,7 @@ def build_hierarchy(A, eps_strong=0.08, coarse_enough=500, max_levels=20,
         Ac.sum_duplicates()
         Ac.sort_indices()
         lvl.P, lvl.R, lvl.agg, lvl.n_agg, lvl.omega = P, R, agg, n_agg, omega
-        lvl.m = smoother_diagonal(A, smoother, jacobi_omega)
+        lvl.m = smoother_diagonal(A, smoother, jacobi_omega, bs)
         A = Ac
         eps = eps * 0.5
     H.coarse_lu = sla.lu_factor(H.levels[-1].A.toarray(), check_finite=True)

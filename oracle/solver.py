@@ -32,7 +32,7 @@ class OracleParams:
     coarse_maxiter: int = 100       # "cg": step limit of the coarse solve
     rtol: float = 1e-8
     maxiter: int = 1000
-    smoother: str = "spai0"         # "spai0" or "jacobi"
+    smoother: str = "spai0"         # "spai0", "jacobi" or "block_spai0"
     jacobi_omega: float = 0.8
     coarse_enough: int = 500
     eps_strong: float = 0.08

@@ -20,10 +20,11 @@ def vcycle(H, l, f):
     if l == H.nlevels - 1:
         return sla.lu_solve(H.coarse_lu, f)
     lvl = H.levels[l]
-    x = lvl.m * f                                   # pre-smooth from x = 0
+    M = (lambda v: lvl.m * v) if isinstance(lvl.m, np.ndarray) else (lambda v: lvl.m @ v)
+    x = M(f)                                        # pre-smooth from x = 0
     r = f - lvl.A @ x
     x = x + lvl.P @ vcycle(H, l + 1, lvl.R @ r)
-    x = x + lvl.m * (f - lvl.A @ x)                 # post-smooth
+    x = x + M(f - lvl.A @ x)                        # post-smooth
     return x
 
 

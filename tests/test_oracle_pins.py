@@ -595,3 +595,40 @@ def test_single_level_is_exact_solve():
     assert H.nlevels == 1
     f = np.random.default_rng(0).standard_normal(P.n)
     assert np.allclose(P.A @ vcycle(H, 0, f), f, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# block SPAI-0
+# --------------------------------------------------------------------------
+
+def test_block_spai0_scalar_case_is_spai0():
+    A = sp.csr_matrix(convection_diffusion7(5, peclet=2.0))
+    Mb = sa.block_spai0(A, 1)
+    assert np.allclose(Mb.diagonal(), sa.smoother_diagonal(A, "spai0"), rtol=1e-14, atol=0)
+    assert Mb.nnz == A.shape[0]
+
+
+def test_block_spai0_inverts_block_diagonal_matrices():
+    rng = np.random.default_rng(3)
+    blocks = [rng.standard_normal((4, 4)) + 4 * np.eye(4) for _ in range(5)]
+    A = sp.block_diag(blocks, format="csr")
+    M = sa.block_spai0(A, 4)
+    assert np.allclose((M @ A).toarray(), np.eye(20), atol=1e-12)
+
+
+def test_block_spai0_is_the_frobenius_minimiser():
+    """||I - M A||_F grows under any perturbation of the diagonal blocks
+    (least-squares optimality), and its gradient vanishes."""
+    from workloads import config_oseen
+    A = config_oseen(N=4, pieces=(1, 1, 1)).A
+    M = sa.block_spai0(A, 4).toarray()
+    Ad = A.toarray()
+    n = Ad.shape[0]
+    base = np.linalg.norm(np.eye(n) - M @ Ad)
+    rng = np.random.default_rng(5)
+    mask = sp.block_diag([np.ones((4, 4))] * (n // 4)).toarray()
+    for _ in range(5):
+        D = rng.standard_normal((n, n)) * mask * 1e-3
+        assert np.linalg.norm(np.eye(n) - (M + D) @ Ad) > base
+    grad = ((np.eye(n) - M @ Ad) @ Ad.T) * mask
+    assert np.abs(grad).max() <= 1e-10 * np.abs(Ad).max()
