@@ -70,7 +70,11 @@ enum { DFAMG_SOLVER_CG = 0, DFAMG_SOLVER_BICGSTAB = 1, DFAMG_SOLVER_BICGSTAB2 = 
  * deflated system is only equivalent to A x = b when E is solved exactly. */
 enum { DFAMG_COARSE_EXACT = 0, DFAMG_COARSE_FP32 = 1, DFAMG_COARSE_CG = 2 };
 enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
-enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1 };
+/* Smoother of the V-cycle: SPAI-0 (m_i = a_ii / sum_j a_ij^2), damped
+ * Jacobi, or block SPAI-0 for point-block matrices (block_size b: per node
+ * the b x b block M_i = A_ii^T (A_(i,:) A_(i,:)^T)^{-1} minimising
+ * ||I - M A||_F over block-diagonal M; with b = 1 it is SPAI-0). */
+enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1, DFAMG_SMOOTHER_BLOCK_SPAI0 = 2 };
 enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2 };
 /* Preconditioner M: the block-local SA-AMG V-cycle, none (M = I), or the
  * purely local SPAI-0 diagonal m_i = a_ii / sum_j a_ij^2 (the velocity-block
@@ -94,7 +98,8 @@ typedef struct {
     int32_t precision;      /* DFAMG_PREC_FP64: whole path FP64; MIXED: AMG
                                hierarchy, smoother and V-cycle vectors FP32,
                                Krylov vectors, dots and deflation FP64        */
-    int32_t smoother;       /* DFAMG_SMOOTHER_SPAI0 (default) or _JACOBI       */
+    int32_t smoother;       /* DFAMG_SMOOTHER_SPAI0 (default), _JACOBI or
+                               _BLOCK_SPAI0                                   */
     double  jacobi_omega;   /* damped Jacobi damping (default 0.8, Listing 1)  */
     int32_t coarse_enough;  /* stop coarsening at <= this many unknowns (500)  */
     double  eps_strong;     /* strength threshold on level 0 (0.08), halved
@@ -339,8 +344,10 @@ dfamg_status dfamg_plan_aggregates(dfamg_plan p, int32_t sub, int32_t level,
 
 /* CRS of matrix `which` (0 = A_l, 1 = P_l, 2 = B_l = R_l (I - A_l diag(m_l)),
  * the operator the solve applies for pre-smoothing from a zero guess,
- * residual and restriction together) of level `level` of subdomain `sub` in
- * local numbering; pass NULL arrays to query sizes only. */
+ * residual and restriction together (empty with the block smoother),
+ * 3 = the smoother M_l as a matrix: diagonal, or block diagonal for block
+ * SPAI-0) of level `level` of subdomain `sub` in local numbering; pass NULL
+ * arrays to query sizes only. */
 dfamg_status dfamg_plan_level_matrix(dfamg_plan p, int32_t sub, int32_t level,
                                      int32_t which, int64_t *nrows,
                                      int64_t *ncols, int64_t *nnz,

@@ -19,7 +19,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESINGULAR: "ESINGU
 SOLVER_CG, SOLVER_BICGSTAB, SOLVER_BICGSTAB2, SOLVER_FGMRES = 0, 1, 2, 3
 COARSE_EXACT, COARSE_FP32, COARSE_CG = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-SMOOTHER_SPAI0, SMOOTHER_JACOBI = 0, 1
+SMOOTHER_SPAI0, SMOOTHER_JACOBI, SMOOTHER_BLOCK_SPAI0 = 0, 1, 2
 FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL = 0, 1, 2
 PRECOND_AMG, PRECOND_NONE, PRECOND_SPAI0 = 0, 1, 2
 OP_SPMV, OP_PROJECT, OP_PRECOND, OP_RECOVER = 0, 1, 2, 3
@@ -287,8 +287,8 @@ def dfamg_plan_aggregates(p, sub, level):
 
 
 def dfamg_plan_level_matrix(p, sub, level, which):
-    """Returns (row_ptr, col, val, shape) of A_l (which=0), P_l (which=1) or
-    B_l = R_l (I - A_l diag(m_l)) (which=2)."""
+    """Returns (row_ptr, col, val, shape) of A_l (which=0), P_l (which=1),
+    B_l = R_l (I - A_l diag(m_l)) (which=2) or the smoother M_l (which=3)."""
     lib = load()
     nr, nc, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(lib.dfamg_plan_level_matrix(ctypes.c_void_p(p), sub, level, which, ctypes.byref(nr),

@@ -25,6 +25,7 @@
 #include "kernels.hpp"
 #include "kernels_fgmres.hpp"
 #include "kernels_schur.hpp"
+#include "kernels_bsmooth.hpp"
 
 namespace dfamg {
 
@@ -723,6 +724,7 @@ struct Hierarchy_dev : PrecondBase {
         DevMat<VT> A, P, R, B;   // B = R (I - A diag(m)), see k_restrict
         bool fused = false;      // restrict with B, else pre-smoothing residual then R
         VT *m = nullptr;
+        VT *mb = nullptr, *xpre = nullptr;   // block SPAI-0 rows and the pre-smoothed iterate
         VT *f = nullptr, *res = nullptr, *z = nullptr, *x = nullptr;
         CoarseEntry *coarse = nullptr;
         CoarseJob *cjobs = nullptr;
@@ -730,6 +732,8 @@ struct Hierarchy_dev : PrecondBase {
         VT *coarse_inv = nullptr;
     };
     std::vector<Lvl> lv;
+    int bs = 1;
+    bool block = false;                  // block SPAI-0 smoother
     std::vector<int32_t> sto0;
     int32_t slots0 = 0;
 
@@ -739,6 +743,8 @@ struct Hierarchy_dev : PrecondBase {
     void build(DevArena &ar, const Plan &plan, hipStream_t s, int format, bool autotune, int verbose) {
         const int L = plan.nlevels_max;
         lv.resize(L);
+        block = plan.prm.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0;
+        bs = plan.bs;
         const double sv = sizeof(VT), ib = 4.0;
         for (int l = 0; l < L; ++l) {
             const PackedLevel &PL = plan.levels[l];
@@ -768,7 +774,7 @@ struct Hierarchy_dev : PrecondBase {
                     DevArena arR, arB;
                     D.R = upload_tuned<VT>(arR, PL.R, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys, plan.nsys,
                                            plan.nsub, {}, verbose);
-                    if (autotune) {
+                    if (autotune && !block) {
                         D.B = upload_tuned<VT>(arB, PL.B, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
                                                plan.nsys, plan.nsub, {}, verbose);
                         D.fused = D.B.tuned_us < D.A.tuned_us + D.R.tuned_us;
@@ -791,6 +797,12 @@ struct Hierarchy_dev : PrecondBase {
                 std::vector<VT> m(PL.m.size());
                 for (size_t i = 0; i < m.size(); ++i) m[i] = (VT)PL.m[i];
                 D.m = ar.upload(m, s);
+                if (block) {
+                    std::vector<VT> mb(PL.mb.size());
+                    for (size_t i = 0; i < mb.size(); ++i) mb[i] = (VT)PL.mb[i];
+                    D.mb = ar.upload(mb, s);
+                    D.xpre = ar.alloc<VT>(PL.nrows);
+                }
                 HIP_CHECK(hipStreamSynchronize(s));
                 const double n0 = (double)PL.nrows, n1 = (double)PN.nrows;
                 // the level's right-hand side is FP64 on level 0
@@ -874,8 +886,65 @@ struct Hierarchy_dev : PrecondBase {
         if (sys_cjob_off0.empty()) sys_cjob_off0.assign(plan.nsys + 1, 0);
     }
 
+    // V(1,1) with the block SPAI-0 smoother: per level x = M f, y = A x,
+    // f_c = R (f - y); after the coarse solves z = x + P x_c, y = A z,
+    // out = z + M (f - y).  The same steps as the diagonal smoother's, as
+    // separate passes (the node's rows share one block of M).
+    void apply_block(hipStream_t st, const double *r, double *s, double *part, double *part_job,
+                     const SysState *states, const int32_t *sub_sys) {
+        const int L = (int)lv.size();
+        const dim3 b(kBlock);
+        for (int l = 0; l + 1 < L; ++l) {
+            Lvl &D = lv[l];
+            if (!D.active) continue;
+            const dim3 g(grid_for_tiles(D.A.ntiles));
+            if (l == 0) {
+                hipLaunchKernelGGL((k_bsm_pre<VT, double>), g, b, 0, st, D.A.tiles, D.A.ntiles, bs, D.mb, r, D.xpre,
+                                   states, sub_sys);
+                launch_spmv<VT>(D.A, D.xpre, D.res, states, sub_sys, st);
+                hipLaunchKernelGGL((k_bsm_res<VT, double>), g, b, 0, st, D.A.tiles, D.A.ntiles, r, D.res, states,
+                                   sub_sys);
+            } else {
+                hipLaunchKernelGGL((k_bsm_pre<VT, VT>), g, b, 0, st, D.A.tiles, D.A.ntiles, bs, D.mb, D.f, D.xpre,
+                                   states, sub_sys);
+                launch_spmv<VT>(D.A, D.xpre, D.res, states, sub_sys, st);
+                hipLaunchKernelGGL((k_bsm_res<VT, VT>), g, b, 0, st, D.A.tiles, D.A.ntiles, D.f, D.res, states,
+                                   sub_sys);
+            }
+            launch_spmv<VT>(D.R, D.res, lv[l + 1].f, states, sub_sys, st);
+        }
+        for (int l = 0; l < L; ++l) {
+            Lvl &D = lv[l];
+            if (!D.ncoarse) continue;
+            if (l == 0)
+                hipLaunchKernelGGL((k_coarse<VT, double, double, true>), dim3(D.ncjobs), b, 0, st, D.cjobs, D.coarse,
+                                   D.coarse_inv, r, s, part_job, states, sub_sys);
+            else
+                hipLaunchKernelGGL((k_coarse<VT, VT, VT, false>), dim3(D.ncjobs), b, 0, st, D.cjobs, D.coarse,
+                                   D.coarse_inv, D.f, D.x, part_job, states, sub_sys);
+        }
+        for (int l = L - 2; l >= 0; --l) {
+            Lvl &D = lv[l];
+            if (!D.active) continue;
+            const dim3 g(grid_for_tiles(D.A.ntiles));
+            launch_spmv<VT>(D.P, lv[l + 1].x, D.z, states, sub_sys, st);
+            hipLaunchKernelGGL((k_bsm_add<VT>), g, b, 0, st, D.A.tiles, D.A.ntiles, D.xpre, D.z, states, sub_sys);
+            launch_spmv<VT>(D.A, D.z, D.res, states, sub_sys, st);
+            if (l == 0)
+                hipLaunchKernelGGL((k_bsm_post<VT, double, double, true>), g, b, 0, st, D.A.tiles, D.A.ntiles, bs,
+                                   D.mb, r, D.z, D.res, s, part, states, sub_sys);
+            else
+                hipLaunchKernelGGL((k_bsm_post<VT, VT, VT, false>), g, b, 0, st, D.A.tiles, D.A.ntiles, bs, D.mb,
+                                   D.f, D.z, D.res, D.x, part, states, sub_sys);
+        }
+    }
+
     void apply(hipStream_t st, const double *r, double *s, double *part, double *part_job,
                const SysState *states, const int32_t *sub_sys, Prof *prof) override {
+        if (block) {
+            apply_block(st, r, s, part, part_job, states, sub_sys);
+            return;
+        }
         const int L = (int)lv.size();
         auto mark = [&](int kid, int which) {
             if (prof) prof->mark(kid, which, st);
@@ -2268,11 +2337,32 @@ dfamg_status dfamg_plan_level_matrix(dfamg_plan p, int32_t sub, int32_t level, i
                                      int64_t *ncols, int64_t *nnz, int64_t *row_ptr, int32_t *col, double *val) {
     const Hierarchy *H = plan_hier(p, sub);
     if (!H || level < 0 || level >= H->nlevels() || (which >= 1 && level + 1 >= H->nlevels()) || which < 0 ||
-        which > 2) {
+        which > 3) {
         g_last_error = "bad plan, subdomain, level or matrix";
         return DFAMG_EINVAL;
     }
-    const Csr &M = which == 0 ? H->lv[level].A : which == 1 ? H->lv[level].P : H->lv[level].B;
+    Csr Msm;   // which 3: the smoother as a matrix
+    if (which == 3) {
+        const Level &Lv = H->lv[level];
+        const int64_t n = Lv.A.nrows;
+        const int bs = Lv.mb.empty() ? 1 : (int)(Lv.mb.size() / std::max<int64_t>(n, 1));
+        Msm.nrows = Msm.ncols = n;
+        Msm.ptr.assign(1, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            if (Lv.mb.empty()) {
+                Msm.col.push_back((int32_t)i);
+                Msm.val.push_back(Lv.m[i]);
+            } else {
+                const int64_t nb = i / bs * bs;
+                for (int k = 0; k < bs; ++k) {
+                    Msm.col.push_back((int32_t)(nb + k));
+                    Msm.val.push_back(Lv.mb[(size_t)i * bs + k]);
+                }
+            }
+            Msm.ptr.push_back((int64_t)Msm.col.size());
+        }
+    }
+    const Csr &M = which == 0 ? H->lv[level].A : which == 1 ? H->lv[level].P : which == 2 ? H->lv[level].B : Msm;
     if (nrows) *nrows = M.nrows;
     if (ncols) *ncols = M.ncols;
     if (nnz) *nnz = M.nnz();

@@ -449,6 +449,69 @@ void smoothed_prolongation(const Csr &AF, const std::vector<int32_t> &agg, int32
 // B = R - (R A) diag(m), rows merged column by column; exact zeros dropped.
 // With one pre-smoothing sweep from a zero guess, x = m o f and the level's
 // restricted residual is R (f - A x) = B f.
+// Block SPAI-0 of a point-block matrix: per node i the bs x bs block
+// M_i = A_ii^T G_i^{-1}, G_i = A_(i,:) A_(i,:)^T (the Gram matrix of the node's
+// rows), the minimiser of ||I - M A||_F over block-diagonal M.  Row r of the
+// result holds row r % bs of its node's block.
+void block_spai0(const Csr &A, int bs, std::vector<double> &mb) {
+    const int64_t n = A.nrows, nb = n / bs;
+    mb.assign((size_t)n * bs, 0.0);
+    std::vector<double> G((size_t)bs * bs), Aii((size_t)bs * bs), dense;
+    std::vector<int64_t> where(A.ncols, -1);
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t r0 = b * bs;
+        // the node's rows as a dense block over the union of their columns
+        std::vector<int32_t> cols;
+        for (int r = 0; r < bs; ++r)
+            for (int64_t k = A.ptr[r0 + r]; k < A.ptr[r0 + r + 1]; ++k)
+                if (where[A.col[k]] < 0) {
+                    where[A.col[k]] = (int64_t)cols.size();
+                    cols.push_back(A.col[k]);
+                }
+        const size_t nc = cols.size();
+        dense.assign((size_t)bs * nc, 0.0);
+        for (int r = 0; r < bs; ++r)
+            for (int64_t k = A.ptr[r0 + r]; k < A.ptr[r0 + r + 1]; ++k) dense[r * nc + where[A.col[k]]] = A.val[k];
+        for (int r = 0; r < bs; ++r)
+            for (int c = 0; c < bs; ++c) {
+                double g = 0.0;
+                for (size_t j = 0; j < nc; ++j) g += dense[r * nc + j] * dense[c * nc + j];
+                G[r * bs + c] = g;
+                const int64_t w = where[r0 + c];
+                Aii[r * bs + c] = w >= 0 ? dense[r * nc + w] : 0.0;
+            }
+        for (int32_t c : cols) where[c] = -1;
+        // M_i = A_ii^T G^{-1}: solve G^T M_i^T = A_ii (G is symmetric), by
+        // Gauss-Jordan with partial pivoting on [G | A_ii]
+        std::vector<double> aug((size_t)bs * 2 * bs);
+        for (int r = 0; r < bs; ++r)
+            for (int c = 0; c < bs; ++c) {
+                aug[r * 2 * bs + c] = G[c * bs + r];
+                aug[r * 2 * bs + bs + c] = Aii[r * bs + c];
+            }
+        for (int k = 0; k < bs; ++k) {
+            int p = k;
+            for (int r = k + 1; r < bs; ++r)
+                if (std::fabs(aug[r * 2 * bs + k]) > std::fabs(aug[p * 2 * bs + k])) p = r;
+            if (aug[p * 2 * bs + k] == 0.0)
+                fail(DFAMG_ESINGULAR, "block SPAI-0: rows of node " + std::to_string(b) + " are linearly dependent");
+            if (p != k)
+                for (int c = 0; c < 2 * bs; ++c) std::swap(aug[k * 2 * bs + c], aug[p * 2 * bs + c]);
+            const double d = aug[k * 2 * bs + k];
+            for (int c = 0; c < 2 * bs; ++c) aug[k * 2 * bs + c] /= d;
+            for (int r = 0; r < bs; ++r) {
+                if (r == k) continue;
+                const double f = aug[r * 2 * bs + k];
+                if (f != 0.0)
+                    for (int c = 0; c < 2 * bs; ++c) aug[r * 2 * bs + c] -= f * aug[k * 2 * bs + c];
+            }
+        }
+        // aug's right half is X = G^{-T} A_ii = M_i^T: M_i[r][c] = X[c][r]
+        for (int r = 0; r < bs; ++r)
+            for (int c = 0; c < bs; ++c) mb[(size_t)(r0 + r) * bs + c] = aug[c * 2 * bs + bs + r];
+    }
+}
+
 Csr restricted_residual_map(const Csr &R, const Csr &RA, const std::vector<double> &m) {
     Csr B;
     B.nrows = R.nrows;
@@ -512,8 +575,10 @@ Hierarchy build_hierarchy(Csr A, const SaParams &prm) {
             }
             L.m[i] = prm.smoother == DFAMG_SMOOTHER_JACOBI ? prm.jacobi_omega / d : d / s;
         }
+        if (prm.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0) block_spai0(L.A, bs, L.mb);
         const Csr RA = multiply(L.R, L.A);
-        L.B = restricted_residual_map(L.R, RA, L.m);
+        // the fused restriction operator assumes a diagonal smoother
+        if (prm.smoother != DFAMG_SMOOTHER_BLOCK_SPAI0) L.B = restricted_residual_map(L.R, RA, L.m);
         A = multiply(RA, L.P);
         eps *= 0.5;
     }
@@ -671,7 +736,9 @@ void validate_params(const dfamg_params &p) {
     if (p.maxiter < 0) fail(DFAMG_EINVAL, "maxiter must be >= 0");
     if (!(p.rtol >= 0.0) || !std::isfinite(p.rtol)) fail(DFAMG_EINVAL, "rtol must be finite and >= 0");
     if (p.precision != DFAMG_PREC_FP64 && p.precision != DFAMG_PREC_MIXED) fail(DFAMG_EINVAL, "unknown precision");
-    if (p.smoother != DFAMG_SMOOTHER_SPAI0 && p.smoother != DFAMG_SMOOTHER_JACOBI) fail(DFAMG_EINVAL, "unknown smoother");
+    if (p.smoother != DFAMG_SMOOTHER_SPAI0 && p.smoother != DFAMG_SMOOTHER_JACOBI &&
+        p.smoother != DFAMG_SMOOTHER_BLOCK_SPAI0)
+        fail(DFAMG_EINVAL, "unknown smoother");
     if (!std::isfinite(p.jacobi_omega)) fail(DFAMG_EINVAL, "jacobi_omega must be finite");
     if (p.coarse_enough < 1) fail(DFAMG_EINVAL, "coarse_enough must be >= 1");
     if (p.coarse_enough > 4096) fail(DFAMG_EINVAL, "coarse_enough must be <= 4096 (dense coarsest blocks)");
@@ -996,6 +1063,7 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
         PL.P.ncols = ncoarse;
         PL.P.ptr.assign(PL.nrows + 1, 0);
         PL.m.assign(PL.nrows, 0.0);
+        if (prm.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0) PL.mb.assign((size_t)PL.nrows * bs, 0.0);
         for (int s = 0; s < nsub; ++s) {
             if (PL.sub_off[s] < 0) continue;
             const Hierarchy &H = plan.hier[s];
@@ -1015,6 +1083,8 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
                         PL.P.val.push_back(P.val[k]);
                     }
                     PL.m[o + i] = H.lv[l].m[i];
+                    if (!H.lv[l].mb.empty())
+                        for (int k = 0; k < bs; ++k) PL.mb[(size_t)(o + i) * bs + k] = H.lv[l].mb[(size_t)i * bs + k];
                 }
                 PL.A.ptr[o + i + 1] = (int64_t)PL.A.col.size();
                 PL.P.ptr[o + i + 1] = (int64_t)PL.P.col.size();

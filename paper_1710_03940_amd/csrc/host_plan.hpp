@@ -38,6 +38,7 @@ struct Level {
     Csr B;                   // R (I - A diag(m)): the restricted residual of the
                              // pre-smoothed iterate (zero initial guess) as one map
     std::vector<double> m;   // smoother diagonal
+    std::vector<double> mb;  // block SPAI-0: row i holds row i % bs of its node's block
     double eps = 0.0, omega = 0.0;
     std::vector<int32_t> agg;  // node -> aggregate (-1: none)
     int32_t nagg = 0;
@@ -117,6 +118,7 @@ struct PackedLevel {
     std::vector<int32_t> sub_len;
     Csr A, P, R, B;                      // packed (block-diagonal) matrices
     std::vector<double> m;               // smoother diagonal (0 when inactive)
+    std::vector<double> mb;              // block smoother rows (bs per row), block SPAI-0 only
     std::vector<int32_t> active_subs;    // subdomains smoothing on this level
     std::vector<int32_t> coarse_subs;    // subdomains whose coarsest level is this
 };

@@ -300,3 +300,28 @@ def test_schur_setup_validation():
             L.dfamg_setup_schur(L.make_params(**kw), A, mask, part, 1, Z)
         assert ei.value.status == _lib.EINVAL
 
+
+
+@pytest.mark.parametrize("smoother", ["spai0", "block_spai0"])
+def test_smoother_matrices_match_oracle(smoother):
+    """The smoother of every level (diagonal SPAI-0, or the 4 x 4 blocks of
+    block SPAI-0 on the Oseen point-block hierarchy) equals the oracle's."""
+    from workloads import config_oseen
+    from oracle import OracleSolver, OracleParams
+    P = config_oseen(N=8, pieces=(2, 1, 1))
+    kw = dict(block_size=4, coarse_enough=60)
+    ref = OracleSolver(P.A, P.part, P.nsub, P.Z, OracleParams(solver="bicgstab", smoother=smoother, **kw))
+    code = {"spai0": _lib.SMOOTHER_SPAI0, "block_spai0": _lib.SMOOTHER_BLOCK_SPAI0}[smoother]
+    plan = L.dfamg_plan_create(L.make_params(solver=1, smoother=code, **kw), P.A, P.part, P.nsub, P.Z)
+    try:
+        checked = 0
+        for s, H in enumerate(ref.M.hierarchies):
+            for l, lvl in enumerate(H.levels[:-1]):
+                ptr, col, val, shape = L.dfamg_plan_level_matrix(plan, s, l, 3)
+                M = sp.csr_matrix((val, col, ptr), shape=shape).toarray()
+                R = np.diag(lvl.m) if isinstance(lvl.m, np.ndarray) else lvl.m.toarray()
+                assert np.allclose(M, R, rtol=1e-11, atol=1e-14 * np.abs(R).max())
+                checked += 1
+        assert checked >= 2
+    finally:
+        L.dfamg_plan_destroy(plan)
