@@ -459,6 +459,17 @@ def bench_oseen(args, log):
                      "bytes_per_iter": st["bytes_per_iter"]}
         log(f"  oseen {prec}: {t * 1e3:.1f} ms, {its[-1]} iterations, relres {o['relres_true']:.2e}")
     out["speedup_mixed_vs_fp64"] = out["fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
+    # the block SPAI-0 smoother (4 x 4 node blocks) in place of scalar SPAI-0
+    gb = load_golden("oseen64_boxes256_field_blockspai0")
+    out["block_spai0"] = {"oracle_iters": gb["iters"]}
+    for prec in ("mixed", "fp64"):
+        S = dfamg.Solver(P.A, P.part, P.nsub, P.Z, solver="bicgstab", block_size=4, precision=prec,
+                         smoother="block_spai0")
+        t, o, its = time_solver(S, b, x, args.steps, args.warmup, log)
+        S.close()
+        out["block_spai0"][prec] = {"s_per_solve": t, "iters": its[-1], "relres_true": o["relres_true"],
+                                    "rel_error_vs_oracle_sampled": error_vs_oracle(x, gb)}
+        log(f"  oseen block SPAI-0 {prec}: {t * 1e3:.1f} ms, {its[-1]} iterations")
     return out
 
 

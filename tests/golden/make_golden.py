@@ -106,6 +106,9 @@ if __name__ == "__main__":
                             coarse_maxiter=100))
     if "oseen_schur" in which:
         record_schur()
+    if "oseen_block" in which:
+        record("oseen64_boxes256_field_blockspai0", config_oseen(),
+               OracleParams(solver="bicgstab", block_size=4, smoother="block_spai0"))
     if "oseen" in which:
         record("oseen64_boxes256_field", config_oseen(),
                OracleParams(solver="bicgstab", block_size=4))

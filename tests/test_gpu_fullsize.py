@@ -220,3 +220,30 @@ def test_oseen64_schur_matches_oracle():
     idx = np.array(g["sample_index"])
     gs = np.array(g["sample_x"])
     assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_oseen64_block_spai0_matches_oracle(precision):
+    """BiCGStab with the block SPAI-0 smoother on the 64^3 Oseen system."""
+    import paper_1710_03940_amd as L
+    from workloads import config_oseen
+    P = config_oseen()
+    g = _golden("oseen64_boxes256_field_blockspai0")
+    S = L.Solver(P.A, P.part, P.nsub, P.Z, solver="bicgstab", block_size=4, smoother="block_spai0",
+                 precision=precision)
+    dev = torch.device("cuda:0")
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    out = S.solve(torch.tensor(P.b, device=dev), x)
+    S.close()
+    print(f"oseen block spai0 {precision}: gpu iters {out['iters']} oracle {g['iters']} relres_true "
+          f"{out['relres_true']:.3e}", flush=True)
+    assert out["status"] == 0
+    assert out["relres_true"] <= TRUE_RES_TOL
+    if precision == "fp64":
+        assert abs(out["iters"] - g["iters"]) <= 2
+    else:
+        assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
+    xs = x.cpu().numpy()
+    idx = np.array(g["sample_index"])
+    gs = np.array(g["sample_x"])
+    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
