@@ -132,8 +132,8 @@ def main():
         cpu_baseline_worker(args.sample_iters)
         return 0
     if args.gpus != 1:
-        print("bench.py measures one GPU: the deflated solve is not sharded across GPUs in this "
-              "build (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the deflated solve is not sharded across GPUs "
+              "(run with --gpus 1)", file=sys.stderr)
         return 2
 
     def log(msg):

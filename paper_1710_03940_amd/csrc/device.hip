@@ -2017,7 +2017,7 @@ void check_device() {
     hipDeviceProp_t prop;
     HIP_CHECK(hipGetDeviceProperties(&prop, dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        throw Error{DFAMG_ENOGPU, std::string("this build targets gfx950, device is ") + prop.gcnArchName};
+        throw Error{DFAMG_ENOGPU, std::string("the library is compiled for gfx950, device is ") + prop.gcnArchName};
 }
 
 // Builds a handle in place (validation, host plan, device setup).
