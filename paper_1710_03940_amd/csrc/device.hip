@@ -1112,6 +1112,7 @@ struct Handle {
     void finish(hipStream_t st);
     void precond(hipStream_t st, const double *rin, double *sout, bool profiled = false);
     void launch_iterations(int k);
+    void solve_one_cycle(const double *rhs, double *xio, int64_t *iter_acc);
     dfamg_status run_solve(const double *rhs, double *xio);
     void apply_op(int op, const double *in, double *out);
 };
@@ -1820,6 +1821,26 @@ void Handle::launch_iterations(int k) {
     for (int i = 0; i < k; i += graph_k) HIP_CHECK(hipGraphLaunch(graph_exec, stream));
 }
 
+// A solve that fits in one FGMRES cycle (maxiter <= restart), issued on the
+// handle's stream without any host synchronisation: the inner solves of a
+// composite preconditioner.  The iterations taken are added to *iter_acc on
+// the device.
+void Handle::solve_one_cycle(const double *rhs, double *xio, int64_t *iter_acc) {
+    if (!fgmres() || prm.maxiter > prm.restart)
+        throw Error{DFAMG_EINVAL, "a single-cycle solve needs FGMRES with maxiter <= restart"};
+    const int64_t n = plan.n;
+    const int nb = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, stream, n, d_perm, rhs, b);
+    hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, stream, n, d_perm, xio, y);
+    have_rhs = true;
+    initial(stream);
+    launch_iterations(prm.restart);
+    finish(stream);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, stream, n, d_perm, x, xio);
+    hipLaunchKernelGGL(k_add_iters, dim3(1), dim3(64), 0, stream, states, nsys(), iter_acc);
+    HIP_CHECK(hipGetLastError());
+}
+
 dfamg_status Handle::run_solve(const double *rhs, double *xio) {
     const double t0 = now_s();
     const int64_t n = plan.n;
@@ -1947,28 +1968,31 @@ struct SchurParts {
     int32_t *Dc = nullptr, *Gc = nullptr;
     double *Dv = nullptr, *Gv = nullptr;
     double *ru = nullptr, *rp = nullptr, *uh = nullptr, *t = nullptr, *p = nullptr, *t2 = nullptr, *u = nullptr;
-    int64_t inner_k_iters = 0, inner_p_iters = 0;
+    int64_t *d_iters = nullptr;          // device: velocity, pressure inner iterations
 
     static dim3 grid(int64_t m) { return dim3((unsigned)((m + 255) / 256)); }
+    static dim3 rgrid(int64_t rows) {   // k_csr_resid: kBlock / kCsrLanes rows per block
+        const int64_t per = kBlock / kCsrLanes;
+        return dim3((unsigned)((rows + per - 1) / per));
+    }
 
-    // x = approximate H^{-1} rhs from x = 0; a solve that reaches its step
+    // x = approximate H^{-1} rhs from x = 0 in one FGMRES cycle (maxiter =
+    // restart), without host synchronisation; a solve that reaches its step
     // limit (or breaks down) returns its last iterate
-    int inner(Handle &H, const double *rhs, double *x, int64_t m) {
+    void inner(Handle &H, const double *rhs, double *x, int64_t m, int64_t *acc) {
         HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * m, stream));
-        const dfamg_status st = H.run_solve(rhs, x);
-        if (st == DFAMG_ENAN) throw Error{DFAMG_ENAN, "an inner solve of the Schur preconditioner produced NaN"};
-        return H.h_states[0].iter;
+        H.solve_one_cycle(rhs, x, acc);
     }
 
     // (u, p) for the residual r, both in the whole system's numbering
     void apply(hipStream_t st, const double *rin, double *sout) {
         hipLaunchKernelGGL(k_gather_idx, grid(nu), dim3(256), 0, st, nu, uidx, rin, ru);
         hipLaunchKernelGGL(k_gather_idx, grid(np), dim3(256), 0, st, np, pidx, rin, rp);
-        inner_k_iters += inner(*K, ru, uh, nu);
-        hipLaunchKernelGGL(k_csr_resid, grid(np), dim3(256), 0, st, np, Dp, Dc, Dv, uh, rp, t);
-        inner_p_iters += inner(*P, t, p, np);
-        hipLaunchKernelGGL(k_csr_resid, grid(nu), dim3(256), 0, st, nu, Gp, Gc, Gv, p, ru, t2);
-        inner_k_iters += inner(*K, t2, u, nu);
+        inner(*K, ru, uh, nu, d_iters);
+        hipLaunchKernelGGL(k_csr_resid, rgrid(np), dim3(kBlock), 0, st, np, Dp, Dc, Dv, uh, rp, t);
+        inner(*P, t, p, np, d_iters + 1);
+        hipLaunchKernelGGL(k_csr_resid, rgrid(nu), dim3(kBlock), 0, st, nu, Gp, Gc, Gv, p, ru, t2);
+        inner(*K, t2, u, nu, d_iters);
         hipLaunchKernelGGL(k_scatter_idx, grid(nu), dim3(256), 0, st, nu, uidx, u, sout);
         hipLaunchKernelGGL(k_scatter_idx, grid(np), dim3(256), 0, st, np, pidx, p, sout);
         HIP_CHECK(hipGetLastError());
@@ -2145,7 +2169,7 @@ dfamg_status dfamg_solve(dfamg_handle h, const double *rhs, double *x, int32_t *
     }
     return guarded(&H.err, [&]() -> dfamg_status {
         HIP_CHECK(hipSetDevice(H.device));
-        if (h->schur) h->schur->inner_k_iters = h->schur->inner_p_iters = 0;
+        if (h->schur) HIP_CHECK(hipMemsetAsync(h->schur->d_iters, 0, sizeof(int64_t) * 2, H.stream));
         const dfamg_status st = H.run_solve(rhs, x);
         const SysState &S = H.h_states[0];
         if (iters) *iters = S.iter;
@@ -2238,8 +2262,11 @@ dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *o) {
     o->outer_layout_bytes = H.outer_layout_bytes;
     o->coarse_iters = H.coarse_iters_last;
     if (h->schur) {
-        o->schur_inner_iters[0] = h->schur->inner_k_iters;
-        o->schur_inner_iters[1] = h->schur->inner_p_iters;
+        int64_t it[2] = {0, 0};
+        if (hipMemcpy(it, h->schur->d_iters, sizeof(it), hipMemcpyDeviceToHost) == hipSuccess) {
+            o->schur_inner_iters[0] = it[0];
+            o->schur_inner_iters[1] = it[1];
+        }
     }
     {
         const std::string t = "outer " + describe(H.A) + (H.outer_split ? "+couplings" : "") +
@@ -2528,6 +2555,8 @@ dfamg_status dfamg_setup_schur(const dfamg_params *prm, int64_t n, const int64_t
         parts->rp = ar.alloc<double>(np);
         parts->t = ar.alloc<double>(np);
         parts->p = ar.alloc<double>(np);
+        parts->d_iters = ar.alloc<int64_t>(2);
+        HIP_CHECK(hipMemsetAsync(parts->d_iters, 0, sizeof(int64_t) * 2, sm));
         SchurParts *sp = parts.get();
         H->h.ext_precond = [sp](hipStream_t st, const double *rin, double *sout) { sp->apply(st, rin, sout); };
         H->schur = std::move(parts);

@@ -32,15 +32,24 @@ static __global__ void __launch_bounds__(kBlock) k_diag_scale(const DevTile *__r
     if (threadIdx.x == 0) part[T.slot] = sum;
 }
 
-// y = b - M x for a CSR block (one wavefront per 64 rows, one row per lane)
-static __global__ void k_csr_resid(int64_t nrows, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                                   const double *__restrict__ val, const double *__restrict__ x,
-                                   const double *__restrict__ b, double *__restrict__ y) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows) return;
+// y = b - M x for a CSR block: kCsrLanes lanes per row stride over the
+// row's entries (consecutive lanes read consecutive entries), then a
+// shuffle reduction inside the lane group
+constexpr int kCsrLanes = 16;
+
+static __global__ void __launch_bounds__(kBlock) k_csr_resid(int64_t nrows, const int64_t *__restrict__ ptr,
+                                                             const int32_t *__restrict__ col,
+                                                             const double *__restrict__ val,
+                                                             const double *__restrict__ x,
+                                                             const double *__restrict__ b, double *__restrict__ y) {
+    const int64_t row = (int64_t)blockIdx.x * (kBlock / kCsrLanes) + threadIdx.x / kCsrLanes;
+    const int lane = threadIdx.x % kCsrLanes;
     double a = 0.0;
-    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) a += val[e] * x[col[e]];
-    y[i] = b[i] - a;
+    if (row < nrows)
+        for (int64_t e = ptr[row] + lane; e < ptr[row + 1]; e += kCsrLanes) a += stream_load(val + e) * x[col[e]];
+#pragma unroll
+    for (int o = kCsrLanes / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, kCsrLanes);
+    if (row < nrows && lane == 0) y[row] = b[row] - a;
 }
 
 // dst[i] = src[idx[i]]
@@ -55,6 +64,16 @@ static __global__ void k_scatter_idx(int64_t n, const int64_t *__restrict__ idx,
                                      double *__restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[idx[i]] = src[i];
+}
+
+// acc[0] += iterations of the system (the inner solves of the Schur step run
+// one system per handle)
+static __global__ void k_add_iters(const SysState *__restrict__ st, int nsys, int64_t *__restrict__ acc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int64_t a = 0;
+        for (int i = 0; i < nsys; ++i) a += st[i].iter;
+        acc[0] += a;
+    }
 }
 
 }  // namespace dfamg
