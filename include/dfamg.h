@@ -371,6 +371,17 @@ dfamg_status dfamg_coarse_inverse(dfamg_handle h, int32_t sys, int32_t *m,
                                   double *Einv, int64_t cap);
 
 /*
+ * E = Z^T A Z of system `sys` assembled on the device from the handle's own
+ * operator and deflation vectors (one operator product per column, the
+ * operator's Z^T epilogue giving the column; the setup forms E this way for
+ * coarse operators of 1024 or more unknowns), copied to the host buffer E
+ * (row-major m x m, ordering as dfamg_plan_coarse_operator); NULL E queries
+ * m.  Uses the handle's work vectors: not concurrent with a solve.
+ */
+dfamg_status dfamg_coarse_operator(dfamg_handle h, int32_t sys, int32_t *m, double *E,
+                                   int64_t cap);
+
+/*
  * Dense FP64 inverse of the host row-major n x n matrix a into out (host),
  * computed on the current device by one of the two eliminations the setup
  * uses for E (Gauss-Jordan, partial pivoting, first row of largest |a_ik|):

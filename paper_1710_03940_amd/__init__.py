@@ -14,7 +14,7 @@ from ._lib import (DfamgError, dfamg_params_default, dfamg_setup, dfamg_setup_ba
                    dfamg_destroy, dfamg_last_error, dfamg_plan_create, dfamg_plan_levels,
                    dfamg_plan_aggregates, dfamg_plan_level_matrix,
                    dfamg_plan_coarse_operator, dfamg_plan_destroy, dfamg_coarse_inverse,
-                   dfamg_dense_inverse, dfamg_setup_schur)
+                   dfamg_dense_inverse, dfamg_setup_schur, dfamg_coarse_operator)
 
 __all__ = ["Solver", "BatchedSolver", "SchurSolver", "make_params", "DfamgError"] + [
     n for n in dir(_lib) if n.startswith("dfamg_")]
@@ -70,6 +70,10 @@ class Solver:
 
     def stats(self):
         return dfamg_get_stats(self.h)
+
+    def coarse_operator(self, sys=0):
+        """E of one system assembled on the device (host numpy copy)."""
+        return dfamg_coarse_operator(self.h, sys)
 
     def coarse_inverse(self, sys=0):
         """E^{-1} of one system as the device holds it (host numpy copy)."""

@@ -32,7 +32,7 @@ EXPORTED = [
     "dfamg_last_error", "dfamg_plan_create", "dfamg_plan_levels",
     "dfamg_plan_aggregates", "dfamg_plan_level_matrix",
     "dfamg_plan_coarse_operator", "dfamg_plan_destroy", "dfamg_coarse_inverse",
-    "dfamg_dense_inverse", "dfamg_setup_schur",
+    "dfamg_dense_inverse", "dfamg_setup_schur", "dfamg_coarse_operator",
 ]
 
 
@@ -111,6 +111,7 @@ def load():
     lib.dfamg_plan_coarse_operator.argtypes = [H, I32, P, P, I64]
     lib.dfamg_plan_destroy.argtypes = [H]
     lib.dfamg_coarse_inverse.argtypes = [H, I32, P, P, I64]
+    lib.dfamg_coarse_operator.argtypes = [H, I32, P, P, I64]
     lib.dfamg_dense_inverse.argtypes = [P, I32, I32, P]
     lib.dfamg_setup_schur.argtypes = [ctypes.POINTER(Params), I64, P, P, P, P, P, I32, I32, P, P,
                                       ctypes.POINTER(H)]
@@ -336,6 +337,16 @@ def dfamg_coarse_inverse(h, sys=0):
     X = np.zeros((m.value, m.value))
     _check(lib.dfamg_coarse_inverse(ctypes.c_void_p(h), sys, ctypes.byref(m), _ptr(X), X.size))
     return X
+
+
+def dfamg_coarse_operator(h, sys=0):
+    """E of system `sys` assembled on the device from the handle's operator."""
+    lib = load()
+    m = ctypes.c_int32()
+    _check(lib.dfamg_coarse_operator(ctypes.c_void_p(h), sys, ctypes.byref(m), None, 0))
+    E = np.zeros((m.value, m.value))
+    _check(lib.dfamg_coarse_operator(ctypes.c_void_p(h), sys, ctypes.byref(m), _ptr(E), E.size))
+    return E
 
 
 def dfamg_dense_inverse(a, method=0):

@@ -26,6 +26,7 @@
 #include "kernels_fgmres.hpp"
 #include "kernels_schur.hpp"
 #include "kernels_bsmooth.hpp"
+#include "kernels_coarse_setup.hpp"
 
 namespace dfamg {
 
@@ -1113,6 +1114,7 @@ struct Handle {
     void precond(hipStream_t st, const double *rin, double *sout, bool profiled = false);
     void launch_iterations(int k);
     void solve_one_cycle(const double *rhs, double *xio, int64_t *iter_acc);
+    void assemble_E(double *Eout);
     dfamg_status run_solve(const double *rhs, double *xio);
     void apply_op(int op, const double *in, double *out);
 };
@@ -1224,41 +1226,7 @@ void Handle::setup_device() {
     d_sys_job_off = ar.upload(joff, sm);
     tt_part = ar.alloc<double>(std::max(1, njobs));
     HIP_CHECK(hipStreamSynchronize(sm));
-    // E^{-1} per system (FP64 Gauss-Jordan with partial pivoting on the
-    // device): large systems one at a time in column panels with GEMM
-    // updates, small ones together with the unblocked elimination
     EinvT = ar.alloc<double>(std::max<int64_t>(1, P.sys_E_off[nsys]));
-    if (ndv > 0) {
-        std::vector<const double *> mats;
-        std::vector<int32_t> ns, which;
-        std::vector<int64_t> off;
-        for (int sy = 0; sy < nsys; ++sy) {
-            const int m = P.sys_m[sy];
-            if (m >= kBlockedInverseMin) {
-                double *Ed = EinvT + P.sys_E_off[sy];
-                HIP_CHECK(hipMemcpyAsync(Ed, &P.E[P.sys_E_off[sy]], sizeof(double) * (size_t)m * m,
-                                         hipMemcpyHostToDevice, sm));
-                bool ok = false;
-                try {
-                    ok = invert_dense_inplace(sm, Ed, m);
-                } catch (const DenseInverseError &e) {
-                    throw Error{DFAMG_EHIP, e.msg};
-                }
-                if (!ok) throw Error{DFAMG_ESINGULAR, "E = Z^T A Z of system " + std::to_string(sy) + " is singular"};
-                continue;
-            }
-            mats.push_back(&P.E[P.sys_E_off[sy]]);
-            ns.push_back(m);
-            off.push_back(P.sys_E_off[sy]);
-            which.push_back(sy);
-        }
-        if (!mats.empty()) {
-            const int bad = invert_on_device<double>(sm, mats, ns, EinvT, off, ns);
-            if (bad >= 0)
-                throw Error{DFAMG_ESINGULAR,
-                            "E = Z^T A Z of system " + std::to_string(which[bad]) + " is singular"};
-        }
-    }
     b = ar.alloc<double>(n);
     y = ar.alloc<double>(n);
     r = ar.alloc<double>(n);
@@ -1337,15 +1305,55 @@ void Handle::setup_device() {
             ecg_iters = ar.alloc<int64_t>(nsys);
             HIP_CHECK(hipMemsetAsync(ecg_iters, 0, sizeof(int64_t) * nsys, sm));
         }
-        if (prm.coarse_solve == DFAMG_COARSE_FP32 && ndv > 0) {
-            const int64_t ne = P.sys_E_off[nsys];
-            Einv32 = ar.alloc<float>(ne);
-            hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, sm, ne, EinvT, Einv32);
-            HIP_CHECK(hipGetLastError());
-        }
+
     }
     part_A = ar.alloc<double>((size_t)A.ntiles * (ndv + 1));
     part_rows = ar.alloc<double>((size_t)nrow_tiles * std::max(ndv + 1, 3));
+    // E^{-1} per system (FP64 Gauss-Jordan with partial pivoting on the
+    // device): large systems one at a time in column panels with GEMM
+    // updates, small ones together with the unblocked elimination
+    if (ndv > 0) {
+        // large coarse operators are assembled on the device (one operator
+        // product per column) and inverted in place there
+        bool any_large = false;
+        for (int sy = 0; sy < nsys; ++sy) any_large = any_large || P.sys_m[sy] >= kBlockedInverseMin;
+        if (any_large) assemble_E(EinvT);
+        std::vector<const double *> mats;
+        std::vector<int32_t> ns, which;
+        std::vector<int64_t> off;
+        for (int sy = 0; sy < nsys; ++sy) {
+            const int m = P.sys_m[sy];
+            if (m >= kBlockedInverseMin) {
+                double *Ed = EinvT + P.sys_E_off[sy];   // E assembled on the device above
+                bool ok = false;
+                try {
+                    ok = invert_dense_inplace(sm, Ed, m);
+                } catch (const DenseInverseError &e) {
+                    throw Error{DFAMG_EHIP, e.msg};
+                }
+                if (!ok) throw Error{DFAMG_ESINGULAR, "E = Z^T A Z of system " + std::to_string(sy) + " is singular"};
+                continue;
+            }
+            mats.push_back(&P.E[P.sys_E_off[sy]]);
+            ns.push_back(m);
+            off.push_back(P.sys_E_off[sy]);
+            which.push_back(sy);
+        }
+        if (!mats.empty()) {
+            const int bad = invert_on_device<double>(sm, mats, ns, EinvT, off, ns);
+            if (bad >= 0)
+                throw Error{DFAMG_ESINGULAR,
+                            "E = Z^T A Z of system " + std::to_string(which[bad]) + " is singular"};
+        }
+    }
+    // the single-precision copy of E^{-1} for the inexact coarse solve
+    if (fgmres() && prm.coarse_solve == DFAMG_COARSE_FP32 && ndv > 0) {
+        const int64_t ne = P.sys_E_off[nsys];
+        Einv32 = ar.alloc<float>(ne);
+        hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, sm, ne, EinvT, Einv32);
+        HIP_CHECK(hipGetLastError());
+    }
+
     HIP_CHECK(hipHostMalloc((void **)&h_states, sizeof(SysState) * nsys, hipHostMallocDefault));
     hist_stride = prm.maxiter + 1;
     hist = ar.alloc<double>((size_t)nsys * hist_stride);
@@ -1819,6 +1827,36 @@ void Handle::launch_iterations(int k) {
         prof.capturing = false;
     }
     for (int i = 0; i < k; i += graph_k) HIP_CHECK(hipGraphLaunch(graph_exec, stream));
+}
+
+// E = Z^T A Z of every system assembled on the device into Eout (row-major
+// blocks at the systems' E offsets): for each coarse column c (subdomain s,
+// vector k) v = Z e_c goes through the outer operator (mode 3, whose
+// epilogue leaves the Z^T (A v) partials of every tile) and the per-subdomain
+// sums are column c of its system's block.  Uses the vectors x and q and
+// resets the Krylov state.
+void Handle::assemble_E(double *Eout) {
+    const int nd = ndv();
+    if (nd == 0) return;
+    const Plan &P = plan;
+    const dim3 gr(grid_for_tiles(nrow_tiles)), bl(kBlock);
+    HIP_CHECK(hipMemsetAsync(states, 0, sizeof(SysState) * P.nsys, stream));
+    for (int sy = 0; sy < P.nsys; ++sy) {
+        const int m = P.sys_m[sy];
+        const int64_t c0 = (int64_t)P.sys_sub_off[sy] * nd;
+        for (int sub = P.sys_sub_off[sy]; sub < P.sys_sub_off[sy + 1]; ++sub)
+            for (int k = 0; k < nd; ++k) {
+                const int col = (int)((int64_t)sub * nd + k - c0);
+                hipLaunchKernelGGL(k_zcol, gr, bl, 0, stream, rows, nrow_tiles, Z, nd, sub, k, x);
+                outer(3, stream, x, nullptr, q);
+                hipLaunchKernelGGL(k_t1<false>, dim3(P.nsub), bl, 0, stream, part_A, A.ntiles, d_subto_A, nd, t1, psub,
+                                   states, d_sub_sys, 0);
+                hipLaunchKernelGGL(k_ecol, dim3((m + 255) / 256), dim3(256), 0, stream, t1, c0, m, col,
+                                   Eout + P.sys_E_off[sy]);
+            }
+    }
+    HIP_CHECK(hipGetLastError());
+    HIP_CHECK(hipStreamSynchronize(stream));
 }
 
 // A solve that fits in one FGMRES cycle (maxiter <= restart), issued on the
@@ -2583,6 +2621,29 @@ dfamg_status dfamg_coarse_inverse(dfamg_handle h, int32_t sys, int32_t *m, doubl
         HIP_CHECK(hipMemcpyAsync(Einv, H.EinvT + P.sys_E_off[sys], sizeof(double) * (size_t)mm * mm,
                                  hipMemcpyDeviceToHost, H.stream));
         HIP_CHECK(hipStreamSynchronize(H.stream));
+        return DFAMG_OK;
+    });
+}
+
+dfamg_status dfamg_coarse_operator(dfamg_handle h, int32_t sys, int32_t *m, double *E, int64_t cap) {
+    if (!h) {
+        g_last_error = "null handle";
+        return DFAMG_EINVAL;
+    }
+    Handle &H = h->h;
+    return guarded(&H.err, [&]() -> dfamg_status {
+        const Plan &P = H.plan;
+        if (sys < 0 || sys >= P.nsys) throw Error{DFAMG_EINVAL, "system out of range"};
+        const int32_t mm = P.ndv > 0 ? P.sys_m[sys] : 0;
+        if (m) *m = mm;
+        if (!E) return DFAMG_OK;
+        if (cap < (int64_t)mm * mm) throw Error{DFAMG_EINVAL, "buffer too small for E"};
+        if (mm == 0) return DFAMG_OK;
+        HIP_CHECK(hipSetDevice(H.device));
+        DevArena tmp;
+        double *d = tmp.alloc<double>(std::max<int64_t>(1, P.sys_E_off[P.nsys]));
+        H.assemble_E(d);
+        HIP_CHECK(hipMemcpy(E, d + P.sys_E_off[sys], sizeof(double) * (size_t)mm * mm, hipMemcpyDeviceToHost));
         return DFAMG_OK;
     });
 }

@@ -81,3 +81,23 @@ def test_handle_coarse_inverse_blocked_and_unblocked():
         print(f"m={E.shape[0]}", flush=True)
         assert X.shape == E.shape
         _check(E, X, tol=1e-10)
+
+
+def test_coarse_operator_assembled_on_device_matches_setup():
+    """E = Z^T A Z from one operator product per column on the device against
+    the host setup's E (linear deflation, coded Z; per-field deflation of the
+    Oseen operator, m = 1024, the size the setup assembles on the device)."""
+    import paper_1710_03940_amd as L
+    from workloads import config_oseen, make_problem
+    for P, kw in [(make_problem("p", (16, 16, 16), (4, 2, 2), deflation="linear", sigma=1.0, coef_seed=2), dict()),
+                  (config_oseen(N=32, pieces=(8, 8, 4)), dict(solver="bicgstab", block_size=4))]:
+        plan = L.dfamg_plan_create(L.make_params(**kw), P.A, P.part, P.nsub, P.Z)
+        E = L.dfamg_plan_coarse_operator(plan)
+        L.dfamg_plan_destroy(plan)
+        S = L.Solver(P.A, P.part, P.nsub, P.Z, **kw)
+        Ed = S.coarse_operator()
+        X = S.coarse_inverse()
+        S.close()
+        print(f"m={E.shape[0]}", flush=True)
+        assert np.abs(Ed - E).max() <= 1e-12 * np.abs(E).max()
+        _check(E, X, tol=1e-10)
