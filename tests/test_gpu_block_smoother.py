@@ -69,3 +69,23 @@ def test_block_smoother_with_scalar_blocks_is_spai0():
         outs.append((o["iters"], x.cpu().numpy()))
     assert outs[0][0] == outs[1][0]
     assert np.linalg.norm(outs[0][1] - outs[1][1]) <= 1e-10 * np.linalg.norm(outs[0][1])
+
+
+def test_block_smoother_batched_equals_standalone():
+    import paper_1710_03940_amd as L
+    from workloads import concat_problems
+    probs = [config_oseen(N=n, pieces=pc) for n, pc in [(8, (2, 1, 1)), (10, (1, 2, 1))]]
+    A, part, nsub, Z, b, x0, off = concat_problems(probs)
+    kw = dict(solver="bicgstab", block_size=4, smoother="block_spai0", coarse_enough=60, autotune=0)
+    S = L.BatchedSolver(A, part, nsub, Z, off, **kw)
+    xb = _t(np.zeros(A.shape[0]))
+    outb = S.solve(_t(b), xb)
+    S.close()
+    xb = xb.cpu().numpy()
+    for s, p in enumerate(probs):
+        S1 = L.Solver(p.A, p.part, p.nsub, p.Z, **kw)
+        x1 = _t(np.zeros(p.n))
+        o1 = S1.solve(_t(p.b), x1)
+        S1.close()
+        assert int(outb["iters"][s]) == o1["iters"]
+        assert np.array_equal(xb[off[s]:off[s + 1]], x1.cpu().numpy())

@@ -91,3 +91,15 @@ def test_spai0_preconditioner_parity(solver):
     assert ref["status"] == "ok" and out["status"] == 0
     assert abs(out["iters"] - ref["iters"]) <= 2
     assert np.linalg.norm(x.cpu().numpy() - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+
+
+def test_schur_without_pressure_deflation():
+    """The pressure solves with the block AMG alone (no deflation vectors)."""
+    A, pmask, part_p, nsub, Zp, b = _oseen(12, (2, 1, 1))
+    Z0 = np.zeros((Zp.shape[0], 0))
+    ref = schur_fgmres(A, b, pmask, part_p, nsub, Z0, rtol=1e-8)
+    out = _gpu(A, pmask, part_p, nsub, Z0, b, rtol=1e-8)
+    print(f"no deflation: gpu {out['iters']} oracle {ref['iters']}", flush=True)
+    assert ref["status"] == "ok" and out["status"] == 0
+    assert abs(out["iters"] - ref["iters"]) <= 2
+    assert np.linalg.norm(out["x"] - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
