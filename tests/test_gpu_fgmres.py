@@ -196,3 +196,11 @@ def test_fgmres_iterative_coarse_solve_reports_steps_and_rejects_nonsymmetric_E(
     with pytest.raises(L.DfamgError) as ei:
         L.Solver(Q.A, Q.part, Q.nsub, Q.Z, solver="fgmres", coarse_solve="cg", coarse_enough=20)
     assert ei.value.status == 1                          # DFAMG_EINVAL
+
+
+def test_fgmres_restart_one():
+    """FGMRES(1): a preconditioned minimal-residual iteration, one step per
+    cycle (every kernel of the cycle runs with a single basis vector)."""
+    P = _convdiff(9, (2, 1, 1), "linear", 2.0, seed=11)
+    ref, out = _pair(P, dict(solver="fgmres", restart=1, coarse_enough=30, rtol=1e-6, maxiter=400))
+    _check(ref, out, rtol=1e-6)
