@@ -20,7 +20,8 @@ UNITS = [
     ("launch_vcycle.hip", [], "launch_vcycle_f32.o"),
     ("dense_inverse.hip", [], "dense_inverse.o"),
 ]
-HEADERS = ["host_plan.hpp", "kernels.hpp", "kernels_fgmres.hpp", "devmat.hpp", "dense_inverse.hpp"]
+HEADERS = ["host_plan.hpp", "kernels.hpp", "kernels_fgmres.hpp", "kernels_schur.hpp", "kernels_bsmooth.hpp",
+           "kernels_coarse_setup.hpp", "devmat.hpp", "dense_inverse.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
