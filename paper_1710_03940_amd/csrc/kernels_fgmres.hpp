@@ -51,6 +51,43 @@ struct FgState {
     int32_t pad[3];
 };
 
+// (AZ t2)_row: the own-subdomain AZ block (ndv contiguous values per row,
+// read as two 16-byte loads when ndv = 4) plus the row's couplings to other
+// subdomains, four independent gathers at a time
+template <int NDV>
+__device__ __forceinline__ double az_times_t2(int64_t row, const double *__restrict__ AZown, int ndv,
+                                              const double *t2s, const int32_t *__restrict__ offp,
+                                              const int32_t *__restrict__ offc, const double *__restrict__ offv,
+                                              const double *__restrict__ t2) {
+    double corr = 0.0;
+    if (NDV == 4 && ndv == 4) {
+        const f64x2 *az = reinterpret_cast<const f64x2 *>(AZown + row * 4);
+        const f64x2 a01 = stream_load(az), a23 = stream_load(az + 1);
+        corr = ((a01.x * t2s[0] + a01.y * t2s[1]) + a23.x * t2s[2]) + a23.y * t2s[3];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NDV; ++k)
+            if (k < ndv) corr += stream_load(AZown + row * ndv + k) * t2s[k];
+    }
+    if (ndv > 0) {
+        int e = offp[row];
+        const int e1 = offp[row + 1];
+        for (; e + 4 <= e1; e += 4) {
+            int c[4];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = offc[e + u];
+                v[u] = offv[e + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) corr += v[u] * t2[c[u]];
+        }
+        for (; e < e1; ++e) corr += offv[e] * t2[offc[e]];
+    }
+    return corr;
+}
+
 // f = sc_j (V_j - (AZ) t2_j): the residual the coarse correction leaves,
 // handed to the V-cycle
 template <int NDV>
@@ -72,13 +109,9 @@ __global__ void __launch_bounds__(kBlock) k_fg_rhs(const DevTile *__restrict__ t
 #pragma unroll
     for (int k = 0; k < NDV; ++k) t2s[k] = k < ndv ? t2[(int64_t)T.sub * ndv + k] : 0.0;
     for_tile_rows(T, [&](int row) {
-        double corr = 0.0;
-#pragma unroll
-        for (int k = 0; k < NDV; ++k)
-            if (k < ndv) corr += AZown[(int64_t)row * ndv + k] * t2s[k];
-        if (ndv > 0)
-            for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
-        f[row] = sc * (Vj[row] - corr);
+        const double vj = stream_load(Vj + row);
+        const double corr = az_times_t2<NDV>(row, AZown, ndv, t2s, offp, offc, offv, t2);
+        f[row] = sc * (vj - corr);
     });
 }
 
@@ -104,13 +137,12 @@ __global__ void __launch_bounds__(kBlock) k_fg_dots(
     double wv = 0.0;
     if (has) {
         const int ndv = ndv_rt;
-        double corr = 0.0;
+        double t2s[NDV > 0 ? NDV : 1];
 #pragma unroll
-        for (int k = 0; k < NDV; ++k)
-            if (k < ndv) corr += AZown[row * ndv + k] * t2[(int64_t)T.sub * ndv + k];
-        if (ndv > 0)
-            for (int e = offp[row]; e < offp[row + 1]; ++e) corr += offv[e] * t2[offc[e]];
-        wv = q[row] + fg[sys].sc[j] * corr;
+        for (int k = 0; k < NDV; ++k) t2s[k] = k < ndv ? t2[(int64_t)T.sub * ndv + k] : 0.0;
+        const double qv = stream_load(q + row);
+        const double corr = az_times_t2<NDV>(row, AZown, ndv, t2s, offp, offc, offv, t2);
+        wv = qv + fg[sys].sc[j] * corr;
         w[row] = wv;
     }
     const int wave = threadIdx.x >> 6;
