@@ -1060,6 +1060,7 @@ struct Handle {
     int32_t *ecg_col = nullptr, *d_sys_coarse_off = nullptr;
     double *ecg_val = nullptr, *ecg_dinv = nullptr, *ecg_work = nullptr;
     int64_t coarse_iters_last = 0;
+    int ecg_mmax = 0;                       // largest coarse system (LDS form of k_ecg)
     FgState *fg = nullptr;
     int64_t fg_ld = 0, fg_mtot = 0;
     bool fgmres() const { return prm.solver == DFAMG_SOLVER_FGMRES; }
@@ -1302,6 +1303,7 @@ void Handle::setup_device() {
             ecg_dinv = ar.upload(dv, sm);
             d_sys_coarse_off = ar.upload(co, sm);
             ecg_work = ar.alloc<double>((size_t)3 * fg_mtot);
+            for (int sy = 0; sy < nsys; ++sy) ecg_mmax = std::max(ecg_mmax, P.sys_m[sy]);
             ecg_iters = ar.alloc<int64_t>(nsys);
             HIP_CHECK(hipMemsetAsync(ecg_iters, 0, sizeof(int64_t) * nsys, sm));
         }
@@ -1658,9 +1660,14 @@ void Handle::cycle_fgmres(hipStream_t st) {
             hipLaunchKernelGGL(k_t1<true>, dim3(plan.nsub), bl, 0, st, first ? part_A : part_rows,
                                first ? A.ntiles : nt, first ? d_subto_A : d_subto_rows, nd, t1, psub, states,
                                d_sub_sys, 0);
-            if (ecg_ptr)
-                hipLaunchKernelGGL(k_ecg, gs, wb, 0, st, ecg_ptr, ecg_col, ecg_val, ecg_dinv, d_sys_coarse_off, t1,
-                                   t2j, ecg_work, fg_mtot, prm.coarse_rtol, prm.coarse_maxiter, states, ecg_iters);
+            if (ecg_ptr && ecg_mmax <= kEcgLdsRows)
+                hipLaunchKernelGGL(k_ecg<true>, gs, wb, sizeof(double) * 3 * ecg_mmax, st, ecg_ptr, ecg_col, ecg_val,
+                                   ecg_dinv, d_sys_coarse_off, t1, t2j, ecg_work, fg_mtot, prm.coarse_rtol,
+                                   prm.coarse_maxiter, states, ecg_iters);
+            else if (ecg_ptr)
+                hipLaunchKernelGGL(k_ecg<false>, gs, wb, 0, st, ecg_ptr, ecg_col, ecg_val, ecg_dinv,
+                                   d_sys_coarse_off, t1, t2j, ecg_work, fg_mtot, prm.coarse_rtol, prm.coarse_maxiter,
+                                   states, ecg_iters);
             else if (Einv32)
                 hipLaunchKernelGGL(k_egemv32<true>, dim3(njobs), bl, 0, st, d_jobs, Einv32, t1, t2j, states);
             else

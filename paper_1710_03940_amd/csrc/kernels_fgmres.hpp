@@ -477,55 +477,84 @@ __global__ void __launch_bounds__(kBlock) k_egemv32(const GemvJob *__restrict__ 
 // stopped at the first step with ||t1 - E t2|| <= rtol ||t1|| or after
 // maxiter steps.  One 1024-thread block per system; E in CSR over the global
 // coarse numbering (block diagonal by system, exact zeros dropped), dinv its
-// inverse diagonal; r, p, q in work (3 x mtot).  Every sum is a fixed-order
-// block reduction whose result every thread holds, so the loop test is
-// uniform over the block.  iters[sys] accumulates the steps taken.
-static __global__ void __launch_bounds__(kWideBlock) k_ecg(
+// inverse diagonal.  LDS: r, p, q of the system in dynamic shared memory
+// (systems of at most kEcgLdsRows unknowns); else in work (3 x mtot).  Every
+// sum is a fixed-order block reduction whose result every thread holds, so
+// the loop test is uniform over the block; (r, z) and (r, r) share one.
+// iters[sys] accumulates the steps taken.
+constexpr int kEcgLdsRows = 2048;
+
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *lds) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        lds[w] = a;
+        lds[16 + w] = b;
+    }
+    __syncthreads();
+    double ra = 0.0, rb = 0.0;
+    for (int i = 0; i < kWideBlock / 64; ++i) {
+        ra += lds[i];
+        rb += lds[16 + i];
+    }
+    __syncthreads();
+    a = ra;
+    b = rb;
+}
+
+template <bool LDS>
+__global__ void __launch_bounds__(kWideBlock) k_ecg(
     const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ dinv, const int32_t *__restrict__ sys_coarse_off, const double *__restrict__ t1,
     double *__restrict__ t2, double *__restrict__ work, int64_t mtot, double rtol, int32_t maxiter,
     const SysState *__restrict__ st, int64_t *__restrict__ iters) {
-    __shared__ double lds[16];
+    __shared__ double lds[32];
+    extern __shared__ double ecg_lds[];
     const int sys = blockIdx.x;
     if (st[sys].done) return;
     const int c0 = sys_coarse_off[sys], c1 = sys_coarse_off[sys + 1];
-    double *r = work, *p = work + mtot, *q = work + 2 * mtot;
+    // vectors indexed by c - base
+    const int base = LDS ? c0 : 0;
+    const int64_t len = LDS ? (c1 - c0) : mtot;
+    double *r = LDS ? ecg_lds : work;
+    double *p = r + len, *q = p + len;
     double a = 0.0, b = 0.0;
     for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) {
         const double tc = t1[c];
         const double zc = dinv[c] * tc;
-        r[c] = tc;
-        p[c] = zc;
+        r[c - base] = tc;
+        p[c - base] = zc;
         t2[c] = 0.0;
         a += tc * zc;
         b += tc * tc;
     }
-    double rho = block_sum(a, lds, kWideBlock);   // block_sum synchronises: p is visible
-    double rr = block_sum(b, lds, kWideBlock);
+    block_sum2(a, b, lds);   // synchronises: p is visible
+    double rho = a, rr = b;
     const double lim = rtol * rtol * rr;
     int k = 0;
     while (k < maxiter && rr > lim) {
         double pq = 0.0;
         for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) {
-            double s = 0.0;
-            for (int64_t e = ptr[c]; e < ptr[c + 1]; ++e) s += val[e] * p[col[e]];
-            q[c] = s;
-            pq += p[c] * s;
+            double sacc = 0.0;
+            for (int64_t e = ptr[c]; e < ptr[c + 1]; ++e) sacc += val[e] * p[col[e] - base];
+            q[c - base] = sacc;
+            pq += p[c - base] * sacc;
         }
         const double alpha = rho / block_sum(pq, lds, kWideBlock);
         double rz = 0.0, r2 = 0.0;
         for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) {
-            t2[c] += alpha * p[c];
-            const double rn = r[c] - alpha * q[c];
-            r[c] = rn;
+            t2[c] += alpha * p[c - base];
+            const double rn = r[c - base] - alpha * q[c - base];
+            r[c - base] = rn;
             rz += rn * (dinv[c] * rn);
             r2 += rn * rn;
         }
-        const double rho_new = block_sum(rz, lds, kWideBlock);
-        rr = block_sum(r2, lds, kWideBlock);
-        const double beta = rho_new / rho;
-        rho = rho_new;
-        for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) p[c] = dinv[c] * r[c] + beta * p[c];
+        block_sum2(rz, r2, lds);
+        const double beta = rz / rho;
+        rho = rz;
+        rr = r2;
+        for (int c = c0 + threadIdx.x; c < c1; c += kWideBlock) p[c - base] = dinv[c] * r[c - base] + beta * p[c - base];
         __syncthreads();   // p complete before the next product
         ++k;
     }
