@@ -75,7 +75,7 @@ enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
  * the b x b block M_i = A_ii^T (A_(i,:) A_(i,:)^T)^{-1} minimising
  * ||I - M A||_F over block-diagonal M; with b = 1 it is SPAI-0). */
 enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1, DFAMG_SMOOTHER_BLOCK_SPAI0 = 2 };
-enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2 };
+enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2, DFAMG_FORMAT_CSR_GATHER = 3 };
 /* Preconditioner M: the block-local SA-AMG V-cycle, none (M = I), or the
  * purely local SPAI-0 diagonal m_i = a_ii / sum_j a_ij^2 (the velocity-block
  * preconditioner of the Schur pressure correction, section "Navier-Stokes
@@ -109,12 +109,18 @@ typedef struct {
     int32_t precond;        /* DFAMG_PRECOND_AMG (default), _NONE (M = I) or
                                _SPAI0 (diagonal)                              */
     int32_t spmv_format;    /* DFAMG_FORMAT_*: AUTO lets the setup autotuner
-                               time the candidates on the device              */
+                               time the candidates on the device; CSR_GATHER
+                               restricts the multigrid operators to CSR that
+                               stages each tile's distinct input columns in
+                               LDS (a gather list; unstaged CSR where the list
+                               exceeds 64 KiB), the outer operator to CSR     */
     int32_t autotune;       /* 1 (default): time the candidate layouts of every
                                matrix at setup and keep the fastest; 0: one
                                fixed layout (SELL, one row per lane, natural
                                order, 32-bit columns; CSR with 8 lanes when
-                               spmv_format = CSR), so that two handles built
+                               spmv_format = CSR, and with gather lists for
+                               the multigrid operators when CSR_GATHER), so
+                               that two handles built
                                from the same subdomains sum every dot product
                                in the same order (bitwise-equal results)       */
     int32_t graph_iters;    /* Krylov iterations per captured HIP graph;

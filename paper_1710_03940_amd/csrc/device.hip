@@ -200,6 +200,49 @@ bool upload_built(DevArena &ar, const HostLayout &H, const Layout &L, hipStream_
         D.stored = (int64_t)S.val.size();
     } else {
         const HostCsrv &C = H.C;
+        if (L.stage && L.glist) {
+            // per tile: its distinct columns in ascending order, and every
+            // entry's position among them
+            const size_t nt = C.tiles.size();
+            std::vector<std::vector<int32_t>> lists(nt);
+            std::vector<int32_t> lcol(C.col.size());
+            parallel_for((int64_t)nt, 8, [&](int64_t ti) {
+                const Tile &t = C.tiles[ti];
+                const int32_t k0 = C.ptr[t.row0], k1 = C.ptr[t.row0 + t.nrows];
+                std::vector<int32_t> &u = lists[ti];
+                u.assign(C.col.begin() + k0, C.col.begin() + k1);
+                std::sort(u.begin(), u.end());
+                u.erase(std::unique(u.begin(), u.end()), u.end());
+                for (int32_t k = k0; k < k1; ++k)
+                    lcol[k] = (int32_t)(std::lower_bound(u.begin(), u.end(), C.col[k]) - u.begin());
+            });
+            std::vector<int32_t> uoff(nt + 1, 0), ucol;
+            size_t mx = 1;
+            for (size_t ti = 0; ti < nt; ++ti) {
+                uoff[ti + 1] = uoff[ti] + (int32_t)lists[ti].size();
+                mx = std::max(mx, lists[ti].size());
+            }
+            if (mx * sizeof(VT) > stage_limit) return false;
+            ucol.reserve((size_t)uoff[nt]);
+            for (auto &u : lists) ucol.insert(ucol.end(), u.begin(), u.end());
+            D.max_span = (int32_t)mx;
+            D.stage = true;
+            tiles = C.tiles;
+            D.ptr = ar.upload(C.ptr, s);
+            D.col = ar.upload(lcol, s);
+            D.uoff = ar.upload(uoff, s);
+            D.ucol = ar.upload(ucol, s);
+            std::vector<VT> v(C.val.size());
+            for (size_t i = 0; i < v.size(); ++i) v[i] = (VT)C.val[i];
+            D.val = ar.upload(v, s);
+            D.nnz = C.nnz;
+            D.stored = C.nnz;
+            D.host_tiles = to_dev_tiles(tiles);
+            D.tiles = ar.upload(D.host_tiles, s);
+            D.ntiles = (int32_t)tiles.size();
+            tile_offsets(tiles, sub_sys, nsys, nsub, D.sys_tile_off, D.sub_tile_off);
+            return true;
+        }
         if (L.stage) {
             const int32_t mx = C.cspan.empty() ? 1 : *std::max_element(C.cspan.begin(), C.cspan.end());
             if ((size_t)mx * sizeof(VT) > stage_limit) return false;
@@ -342,11 +385,21 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     const double avg_len = rows ? (double)M.nnz() / (double)rows : 0.0;
     std::vector<Layout> cand;
     const bool outer = kind == TUNE_OUTER;
+    // CSR_GATHER: the CSR family, with the multigrid operators staged from
+    // gather lists only (the outer operator as plain CSR)
+    const bool gather = format == DFAMG_FORMAT_CSR_GATHER;
+    const int family = gather ? DFAMG_FORMAT_CSR : format;
     if (!autotune) {
-        cand.push_back(format == DFAMG_FORMAT_CSR ? Layout{DFAMG_FORMAT_CSR, 8, false, false, false, 0}
-                                                  : Layout{DFAMG_FORMAT_SELL, 1, false, false, false, 0});
+        if (gather && !outer) {
+            Layout c{DFAMG_FORMAT_CSR, 8, false, false, true, 0};
+            c.glist = true;
+            cand.push_back(c);
+        } else {
+            cand.push_back(family == DFAMG_FORMAT_CSR ? Layout{DFAMG_FORMAT_CSR, 8, false, false, false, 0}
+                                                      : Layout{DFAMG_FORMAT_SELL, 1, false, false, false, 0});
+        }
     } else {
-        if (format == DFAMG_FORMAT_SELL || format == DFAMG_FORMAT_AUTO) {
+        if (family == DFAMG_FORMAT_SELL || family == DFAMG_FORMAT_AUTO) {
             for (int r : outer ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2}) {
                 if (r > 1 && rows / (256 * r) < 512) continue;
                 for (bool sorted : {false, true}) {
@@ -355,19 +408,25 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
                 }
             }
         }
-        if ((format == DFAMG_FORMAT_CSR || format == DFAMG_FORMAT_AUTO) &&
-            (avg_len >= 10.0 || format == DFAMG_FORMAT_CSR))
+        if ((family == DFAMG_FORMAT_CSR || family == DFAMG_FORMAT_AUTO) &&
+            (avg_len >= 10.0 || family == DFAMG_FORMAT_CSR))
             for (int l : outer ? std::vector<int>{8, 16} : std::vector<int>{4, 8, 16})
                 for (int rpg : {0, 1, 4}) {
                     // smaller tiles where 256-row tiles leave the chip idle, and
                     // for restrictions (long rows gathering from a wide window)
                     if (rpg > 0 && (outer || (rows / 256 >= 2048 && kind != TUNE_RESTRICT))) continue;
-                    for (bool stage : {false, true}) {
-                        const Layout c{DFAMG_FORMAT_CSR, l, false, false, stage, rpg};
+                    // unstaged, staged window, staged gather list (for the
+                    // restrictions, whose rows read the most scattered
+                    // columns; every multigrid operator with CSR_GATHER)
+                    const int nsv = outer ? 2 : (gather || kind == TUNE_RESTRICT) ? 3 : 2;
+                    for (int sv = 0; sv < nsv; ++sv) {
+                        if (gather && !outer && sv != 2) continue;
+                        Layout c{DFAMG_FORMAT_CSR, l, false, false, sv > 0, rpg};
+                        c.glist = sv == 2;
                         // rpg values that give the same tile are one candidate
                         bool dup = false;
                         for (const Layout &o : cand)
-                            dup |= o.fmt == c.fmt && o.par == c.par && o.stage == c.stage &&
+                            dup |= o.fmt == c.fmt && o.par == c.par && o.stage == c.stage && o.glist == c.glist &&
                                    csr_tile_rows_of(o) == csr_tile_rows_of(c);
                         if (!dup) cand.push_back(c);
                     }
@@ -430,9 +489,17 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
         auto A = std::make_unique<DevArena>();
         DevMat<VT> D;
         if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit)) {
-            // 16-bit offsets that do not fit: fall back to 32-bit columns once
-            if (c.fmt != DFAMG_FORMAT_SELL || c.stage || !c.idx16) continue;
-            c.idx16 = false;
+            // 16-bit offsets that do not fit: fall back to 32-bit columns
+            // once; a gather list above the LDS budget (CSR_GATHER): to the
+            // unstaged form
+            if (c.fmt == DFAMG_FORMAT_SELL && !c.stage && c.idx16) {
+                c.idx16 = false;
+            } else if (gather && c.glist) {
+                c.stage = false;
+                c.glist = false;
+            } else {
+                continue;
+            }
             A = std::make_unique<DevArena>();
             if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit)) continue;
         }
@@ -560,7 +627,7 @@ std::string describe(const DevMat<VT> &D) {
     } else if (!D.host_tiles.empty()) {
         t += "/t" + std::to_string(D.host_tiles[0].nrows);
     }
-    if (D.stage) t += "/stage";
+    if (D.stage) t += D.ucol ? "/glist" : "/stage";
     return t;
 }
 

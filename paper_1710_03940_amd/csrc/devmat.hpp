@@ -20,6 +20,7 @@ struct Layout {
     int fmt, par;
     bool sorted, idx16, stage;
     int rpg = 0;   // CSR: rows per lane group in a tile (tile = rpg * 256 / lanes rows); 0 = 256-row tiles
+    bool glist = false;   // staged CSR: stage the tile's distinct columns (gather list), not a window
 };
 
 template <class VT>
@@ -36,8 +37,9 @@ struct DevMat {
     uint16_t *col16 = nullptr;
     int32_t *cbase = nullptr, *cspan = nullptr;
     int16_t *ridx = nullptr;
+    int32_t *uoff = nullptr, *ucol = nullptr;   // gather list of the staged CSR form (null: window)
     VT *val = nullptr;
-    int32_t max_span = 0;         // LDS window of the staged layouts
+    int32_t max_span = 0;         // LDS entries of the staged layouts (window or gather list)
     int64_t nnz = 0, stored = 0;
     double tuned_us = 0.0;
     std::vector<int32_t> sys_tile_off;  // host: tiles of each system
@@ -54,7 +56,8 @@ template <class VT, class Fn>
 void with_mat(const DevMat<VT> &M, Fn &&fn) {
 #define DFAMG_SELL(R, I, S) \
     fn(SellM<VT, R, I, S>{M.tiles, M.soff, M.sw, M.col, M.col16, M.cbase, M.cspan, M.ridx, M.val, M.ntiles})
-#define DFAMG_CSR(L, S) fn(CsrM<VT, L, S>{M.tiles, M.ptr, M.col, M.cbase, M.cspan, M.val, M.ntiles})
+#define DFAMG_CSR(L, S) \
+    fn(CsrM<VT, L, S>{M.tiles, M.ptr, M.col, M.cbase, M.cspan, M.val, M.ntiles, M.uoff, M.ucol})
     if (M.fmt == DFAMG_FORMAT_SELL) {
         if (!M.stage) {
             if (M.idx16) {

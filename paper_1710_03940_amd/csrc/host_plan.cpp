@@ -747,7 +747,7 @@ void validate_params(const dfamg_params &p) {
     if (p.block_size < 1 || p.block_size > 8) fail(DFAMG_EINVAL, "block_size must be in [1, 8]");
     if (p.precond != DFAMG_PRECOND_AMG && p.precond != DFAMG_PRECOND_NONE && p.precond != DFAMG_PRECOND_SPAI0)
         fail(DFAMG_EINVAL, "unknown precond");
-    if (p.spmv_format < DFAMG_FORMAT_AUTO || p.spmv_format > DFAMG_FORMAT_SELL) fail(DFAMG_EINVAL, "unknown spmv_format");
+    if (p.spmv_format < DFAMG_FORMAT_AUTO || p.spmv_format > DFAMG_FORMAT_CSR_GATHER) fail(DFAMG_EINVAL, "unknown spmv_format");
     if (p.graph_iters < 0) fail(DFAMG_EINVAL, "graph_iters must be >= 0");
 }
 

@@ -81,7 +81,12 @@ struct SellM {
     int32_t ntiles;
 };
 
-// CSR with L lanes per row; STAGE as above (cbase/cspan per tile).
+// CSR with L lanes per row; STAGE as above (cbase/cspan per tile), or, when
+// ucol is set, from a gather list: the tile's distinct columns
+// ucol[uoff[tile] .. uoff[tile+1]) in ascending order are copied into LDS and
+// col holds each entry's position in that list, so a column that several
+// rows of the tile read is fetched once per tile however far apart the
+// columns lie.
 template <class VT, int L, bool STAGE>
 struct CsrM {
     const DevTile *tiles;
@@ -91,6 +96,8 @@ struct CsrM {
     const int32_t *cspan;
     const VT *val;
     int32_t ntiles;
+    const int32_t *uoff;
+    const int32_t *ucol;
 };
 
 __device__ __forceinline__ int tile_of_block(int ntiles) {
@@ -115,6 +122,16 @@ template <class VT, class SRC>
 __device__ __forceinline__ VT *stage_window(int cb, int span, SRC src) {
     VT *lds = reinterpret_cast<VT *>(dfamg_stage_lds);
     for (int k = threadIdx.x; k < span; k += kBlock) lds[k] = (VT)src(cb + k);
+    __syncthreads();
+    return lds;
+}
+
+// Copies src(ucol[u0 + k]), k < u1 - u0, into LDS; every thread of the block
+// calls it.
+template <class VT, class SRC>
+__device__ __forceinline__ VT *stage_list(int u0, int u1, const int32_t *__restrict__ ucol, SRC src) {
+    VT *lds = reinterpret_cast<VT *>(dfamg_stage_lds);
+    for (int k = threadIdx.x; k < u1 - u0; k += kBlock) lds[k] = (VT)src(ucol[u0 + k]);
     __syncthreads();
     return lds;
 }
@@ -179,8 +196,12 @@ __device__ __forceinline__ void for_rows(const CsrM<VT, L, STAGE> &M, int tile, 
     int cb = 0;
     const VT *lds = nullptr;
     if (STAGE) {
-        cb = M.cbase[tile];
-        lds = stage_window<VT>(cb, M.cspan[tile], src);
+        if (M.ucol) {
+            lds = stage_list<VT>(M.uoff[tile], M.uoff[tile + 1], M.ucol, src);
+        } else {
+            cb = M.cbase[tile];
+            lds = stage_window<VT>(cb, M.cspan[tile], src);
+        }
     }
     auto x = [&](int c) -> VT {
         if (STAGE) return lds[c - cb];

@@ -61,12 +61,21 @@ def test_small_poisson_fp64_parity():
     assert np.allclose(h[:k], ref["history"][:k], rtol=1e-6, atol=0)
 
 
-@pytest.mark.parametrize("fmt,tune", [("auto", 1), ("sell", 1), ("csr", 1), ("sell", 0), ("csr", 0)])
+@pytest.mark.parametrize("fmt,tune", [("auto", 1), ("sell", 1), ("csr", 1), ("sell", 0), ("csr", 0),
+                                      ("csr_gather", 1), ("csr_gather", 0)])
 def test_layouts_fp64_parity(fmt, tune):
     P = tiny_problem(N=20, pieces=(2, 2, 2), deflation="linear", sigma=2.0, seed=20)
     ref, out = _solve_pair(P, dict(coarse_enough=40),
                            dict(coarse_enough=40, spmv_format=fmt, autotune=tune))
     _assert_parity(ref, out)
+    lay = out["stats"]["layouts"]
+    print(lay, flush=True)
+    if fmt == "csr_gather":
+        # every multigrid operator is CSR staged from a gather list (or
+        # unstaged CSR), the outer operator CSR
+        outer, levels = lay.split(";", 1)
+        assert "csr" in outer and "/glist" not in outer, lay
+        assert "/glist" in levels and "/stage" not in levels and "sell" not in levels, lay
 
 
 def test_autotuned_batched_matches_standalone_closely():

@@ -227,6 +227,8 @@ def test_validation_errors():
     _expect(_lib.EINVAL, P, maxiter=-1)
     _expect(_lib.EINVAL, P, solver=L.make_params().solver + 7)        # unknown solver
     _expect(_lib.EINVAL, P, solver=_lib.SOLVER_FGMRES, restart=0)
+    _expect(_lib.EINVAL, P, spmv_format=_lib.FORMAT_CSR_GATHER + 1)   # unknown layout family
+    _expect(_lib.EINVAL, P, spmv_format=-1)
     _expect(_lib.EINVAL, P, solver=_lib.SOLVER_FGMRES, restart=65)
     _expect(_lib.EINVAL, P, coarse_solve=2)
     # an inexact E only inside the flexible method: the projected solvers need
