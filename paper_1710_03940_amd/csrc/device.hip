@@ -160,13 +160,49 @@ void build_host_layout(const Csr &M, const std::vector<RowRange> &ranges, const 
     }
 }
 
+// Gather lists of a CSR host form (see CsrM): per tile its distinct columns
+// in ascending order, and every entry's position among them.  They depend
+// only on the tiles, so CSR forms with the same tile height share them.
+struct GatherLists {
+    std::vector<int32_t> uoff, ucol, lcol;
+    size_t longest = 0;
+};
+
+GatherLists make_gather_lists(const HostCsrv &C) {
+    const size_t nt = C.tiles.size();
+    std::vector<std::vector<int32_t>> lists(nt);
+    GatherLists G;
+    G.lcol.resize(C.col.size());
+    parallel_for((int64_t)nt, 8, [&](int64_t ti) {
+        const Tile &t = C.tiles[ti];
+        const int32_t k0 = C.ptr[t.row0], k1 = C.ptr[t.row0 + t.nrows];
+        std::vector<int32_t> &u = lists[ti];
+        u.assign(C.col.begin() + k0, C.col.begin() + k1);
+        std::sort(u.begin(), u.end());
+        u.erase(std::unique(u.begin(), u.end()), u.end());
+        for (int32_t k = k0; k < k1; ++k)
+            G.lcol[k] = (int32_t)(std::lower_bound(u.begin(), u.end(), C.col[k]) - u.begin());
+    });
+    G.uoff.assign(nt + 1, 0);
+    G.longest = 1;
+    for (size_t ti = 0; ti < nt; ++ti) {
+        G.uoff[ti + 1] = G.uoff[ti] + (int32_t)lists[ti].size();
+        G.longest = std::max(G.longest, lists[ti].size());
+    }
+    G.ucol.reserve((size_t)G.uoff[nt]);
+    for (auto &u : lists) G.ucol.insert(G.ucol.end(), u.begin(), u.end());
+    return G;
+}
+
 // Uploads the host form H as layout L; returns false (nothing kept) when the
 // layout cannot hold the matrix: 16-bit offsets that do not fit, or a staged
-// column window larger than the LDS budget.
+// column window or gather list larger than the LDS budget.  gl_cache (may be
+// null) keeps the gather lists by tile height for the other candidates of
+// the same matrix.
 template <class VT>
 bool upload_built(DevArena &ar, const HostLayout &H, const Layout &L, hipStream_t s,
                   const std::vector<int32_t> &sub_sys, int nsys, int nsub, DevMat<VT> &D,
-                  size_t stage_limit = kMaxStageBytes) {
+                  size_t stage_limit = kMaxStageBytes, std::map<int, GatherLists> *gl_cache = nullptr) {
     if (!H.ok) return false;
     D = DevMat<VT>{};
     D.fmt = L.fmt;
@@ -201,37 +237,27 @@ bool upload_built(DevArena &ar, const HostLayout &H, const Layout &L, hipStream_
     } else {
         const HostCsrv &C = H.C;
         if (L.stage && L.glist) {
-            // per tile: its distinct columns in ascending order, and every
-            // entry's position among them
-            const size_t nt = C.tiles.size();
-            std::vector<std::vector<int32_t>> lists(nt);
-            std::vector<int32_t> lcol(C.col.size());
-            parallel_for((int64_t)nt, 8, [&](int64_t ti) {
-                const Tile &t = C.tiles[ti];
-                const int32_t k0 = C.ptr[t.row0], k1 = C.ptr[t.row0 + t.nrows];
-                std::vector<int32_t> &u = lists[ti];
-                u.assign(C.col.begin() + k0, C.col.begin() + k1);
-                std::sort(u.begin(), u.end());
-                u.erase(std::unique(u.begin(), u.end()), u.end());
-                for (int32_t k = k0; k < k1; ++k)
-                    lcol[k] = (int32_t)(std::lower_bound(u.begin(), u.end(), C.col[k]) - u.begin());
-            });
-            std::vector<int32_t> uoff(nt + 1, 0), ucol;
-            size_t mx = 1;
-            for (size_t ti = 0; ti < nt; ++ti) {
-                uoff[ti + 1] = uoff[ti] + (int32_t)lists[ti].size();
-                mx = std::max(mx, lists[ti].size());
+            GatherLists own;
+            const GatherLists *G = nullptr;
+            if (gl_cache) {
+                // keyed by the nominal tile height (equal heights give equal tiles)
+                const int th = csr_tile_rows_of(L);
+                auto it = gl_cache->find(th);
+                if (it == gl_cache->end()) it = gl_cache->emplace(th, make_gather_lists(C)).first;
+                G = &it->second;
             }
-            if (mx * sizeof(VT) > stage_limit) return false;
-            ucol.reserve((size_t)uoff[nt]);
-            for (auto &u : lists) ucol.insert(ucol.end(), u.begin(), u.end());
-            D.max_span = (int32_t)mx;
+            if (!G || G->uoff.size() != C.tiles.size() + 1 || G->lcol.size() != C.col.size()) {
+                own = make_gather_lists(C);
+                G = &own;
+            }
+            if (G->longest * sizeof(VT) > stage_limit) return false;
+            D.max_span = (int32_t)G->longest;
             D.stage = true;
             tiles = C.tiles;
             D.ptr = ar.upload(C.ptr, s);
-            D.col = ar.upload(lcol, s);
-            D.uoff = ar.upload(uoff, s);
-            D.ucol = ar.upload(ucol, s);
+            D.col = ar.upload(G->lcol, s);
+            D.uoff = ar.upload(G->uoff, s);
+            D.ucol = ar.upload(G->ucol, s);
             std::vector<VT> v(C.val.size());
             for (size_t i = 0; i < v.size(); ++i) v[i] = (VT)C.val[i];
             D.val = ar.upload(v, s);
@@ -485,10 +511,11 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
         }
         return &it->second;
     };
+    std::map<int, GatherLists> gl_cache;
     for (Layout c : cand) {
         auto A = std::make_unique<DevArena>();
         DevMat<VT> D;
-        if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit)) {
+        if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit, &gl_cache)) {
             // 16-bit offsets that do not fit: fall back to 32-bit columns
             // once; a gather list above the LDS budget (CSR_GATHER): to the
             // unstaged form
@@ -501,7 +528,7 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
                 continue;
             }
             A = std::make_unique<DevArena>();
-            if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit)) continue;
+            if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit, &gl_cache)) continue;
         }
         const double t = cached_us >= 0.0 ? cached_us
                          : cand.size() > 1 ? (timer ? timer(D) : time_layout(kind, D, x, y, s))
