@@ -153,10 +153,13 @@ def _mixed_bound(ref_iters):
     return int(np.floor(ref_iters * 1.15)) + 1
 
 
-def test_small_poisson_mixed_reaches_fp64_residual():
+@pytest.mark.parametrize("fmt,tune", [("auto", 1), ("csr_gather", 0)])
+def test_small_poisson_mixed_reaches_fp64_residual(fmt, tune):
     P = config_small_poisson()
-    ref, out = _solve_pair(P, gpu_kw=dict(precision="mixed"))
-    print(f"mixed iters {out['iters']} oracle fp64 {ref['iters']}", flush=True)
+    ref, out = _solve_pair(P, gpu_kw=dict(precision="mixed", spmv_format=fmt, autotune=tune))
+    print(f"mixed iters {out['iters']} oracle fp64 {ref['iters']} {out['stats']['layouts']}", flush=True)
+    if fmt == "csr_gather":
+        assert "/glist" in out["stats"]["layouts"].split(";", 1)[1]
     assert out["status"] == 0
     assert out["relres_true"] <= 1e-8
     assert out["iters"] <= _mixed_bound(ref["iters"])
@@ -164,15 +167,15 @@ def test_small_poisson_mixed_reaches_fp64_residual():
     assert rel <= 1e-6
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_batched_equals_standalone(precision):
+@pytest.mark.parametrize("precision,fmt", [("fp64", "auto"), ("mixed", "auto"), ("mixed", "csr_gather")])
+def test_batched_equals_standalone(precision, fmt):
     L = _lib()
     from workloads import concat_problems
     probs = [tiny_problem(N=n, pieces=pc, deflation="linear", sigma=1.0, seed=n)
              for n, pc in [(9, (2, 1, 1)), (12, (2, 2, 1)), (7, (1, 1, 2)), (15, (3, 1, 1))]]
     A, part, nsub, Z, b, x0, off = concat_problems(probs)
     # one layout family so that both handles sum every row in the same order
-    kw = dict(precision=precision, coarse_enough=30, autotune=0)
+    kw = dict(precision=precision, coarse_enough=30, autotune=0, spmv_format=fmt)
     SB = L.BatchedSolver(A, part, nsub, Z, off, **kw)
     xb = _t(np.zeros(A.shape[0]))
     outb = SB.solve(_t(b), xb)
