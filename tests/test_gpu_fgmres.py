@@ -62,6 +62,15 @@ def test_fgmres_convdiff_parity(N, pieces, deflation, peclet, ce, restart, coars
     assert np.allclose(h[:k], g[:k], rtol=1e-7 if coarse == "exact" else 1e-5)
 
 
+def test_fgmres_largest_restart():
+    # restart 64, the largest the device state holds: one full cycle of 64
+    # steps, then a second one (the oracle takes 111 steps)
+    P = _convdiff(20, (1, 1, 2), "constant", 1.0, seed=20)
+    ref, out = _pair(P, dict(solver="fgmres", restart=64, precond="none", coarse_enough=40))
+    assert ref["iters"] > 64
+    _check(ref, out)
+
+
 @pytest.mark.parametrize("coarse", ["exact", "fp32"])
 def test_fgmres_poisson_slabs_parity(coarse):
     P = config_small_poisson()
