@@ -115,6 +115,7 @@ def main():
     ap.add_argument("--no-bicgstab2", action="store_true")
     ap.add_argument("--no-fgmres", action="store_true")
     ap.add_argument("--no-schur", action="store_true")
+    ap.add_argument("--no-coarse-inverse", action="store_true")
     ap.add_argument("--sample-iters", type=int, default=20)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -237,6 +238,13 @@ def main():
         except Exception as exc:  # reported, never silently dropped
             schur = {"error": str(exc)}
 
+    coarse_inverse = None
+    if not args.no_coarse_inverse:
+        try:
+            coarse_inverse = bench_coarse_inverse(log)
+        except Exception as exc:  # reported, never silently dropped
+            coarse_inverse = {"error": str(exc)}
+
     batched = None
     if not args.no_batched:
         try:
@@ -288,7 +296,7 @@ def main():
         "bytes_per_iter": st64["bytes_per_iter"],
         "effective_GBps": st64["bytes_per_iter"] * out64["iters"] / t64 / 1e9,
         "mixed": mixed, "batched": batched, "oseen": oseen, "bicgstab2": bicgstab2, "fgmres": fgmres,
-        "schur": schur,
+        "schur": schur, "coarse_inverse": coarse_inverse,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_outer (outer SpMV + (p,q) + Z^T q epilogue)",
@@ -503,6 +511,42 @@ def bench_schur(args, log):
         log(f"  schur {prec}: {ts * 1e3:.1f} ms, {its[-1]} iterations, relres {o['relres_true']:.2e}, "
             f"inner {st['schur_inner_iters']}")
     return out
+
+
+def bench_coarse_inverse(log):
+    """Setup on the GPU: the FP64 inverse of dense systems of the sizes the
+    coarse operator E = Z^T A Z takes (m = subdomains x vectors), by the
+    blocked Gauss-Jordan elimination (panel GEMMs on the FP64 matrix cores)
+    and by the unblocked one, host copies included (the second of two calls
+    is timed).  Each inverse is checked
+    on 64 sampled rows of A X - I (a full host product would disturb the
+    single-threaded CPU baseline running beside the benchmark)."""
+    import time
+    import numpy as np
+    import paper_1710_03940_amd as dfamg
+    log("dense FP64 inverses (coarse-operator sizes)")
+    rows = []
+    for n in (256, 1024, 2048, 4096):
+        rng = np.random.default_rng(n)
+        A = rng.standard_normal((n, n)) + 2.0 * np.sqrt(n) * np.eye(n)
+        pick = np.sort(rng.choice(n, size=min(n, 64), replace=False))
+        row = {"m": n}
+        for name, method in (("blocked", 0), ("unblocked", 1)):
+            dt = 0.0
+            for _ in range(2):   # the second call is timed (the first loads GEMM kernels of new shapes)
+                t0 = time.perf_counter()
+                X = dfamg.dfamg_dense_inverse(A, method)
+                dt = time.perf_counter() - t0
+            res = A[pick] @ X
+            res[np.arange(len(pick)), pick] -= 1.0
+            row[name + "_ms"] = dt * 1e3
+            row[name + "_max_abs_AX_minus_I_sampled"] = float(np.abs(res).max())
+        row["blocked_TFLOPs"] = 2.0 * n ** 3 / (row["blocked_ms"] * 1e-3) / 1e12
+        rows.append(row)
+        log(f"  m={n}: blocked {row['blocked_ms']:.1f} ms, unblocked {row['unblocked_ms']:.1f} ms, "
+            f"max|AX-I| {max(row['blocked_max_abs_AX_minus_I_sampled'], row['unblocked_max_abs_AX_minus_I_sampled']):.1e}")
+    return {"note": "dfamg_dense_inverse, host copies included; 2 m^3 flops per inverse; the library "
+                    "takes the blocked form for systems with m >= 1024", "rows": rows}
 
 
 def bench_batched(args, log):

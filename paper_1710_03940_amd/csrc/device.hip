@@ -671,9 +671,10 @@ std::vector<RowRange> ranges_of(const PackedLevel &L, const std::vector<int32_t>
 // matrix or -1.
 // Coarse operators of at least this size are inverted one at a time by the
 // blocked elimination (dense_inverse.hip); smaller ones, and the coarsest
-// AMG blocks, together by the unblocked one below (measured on the MI355X:
-// 21 against 23 ms at 1024 unknowns, 64 against 638 ms at 4096; below 1024
-// the blocked form's fixed costs dominate).
+// AMG blocks, together by the unblocked one below (measured on the MI355X,
+// host copies included: 8 against 20 ms at 1024 unknowns, 62 against 622 ms
+// at 4096, equal at 256, where the unblocked form also serves many systems
+// in one pass).
 constexpr int kBlockedInverseMin = 1024;
 
 template <class VT>
