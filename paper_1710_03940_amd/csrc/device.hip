@@ -250,12 +250,15 @@ bool upload_built(DevArena &ar, const HostLayout &H, const Layout &L, hipStream_
                 own = make_gather_lists(C);
                 G = &own;
             }
-            if (G->longest * sizeof(VT) > stage_limit) return false;
+            // positions within a list are 16-bit: the LDS budget keeps every
+            // list far below 65536 entries
+            if (G->longest * sizeof(VT) > stage_limit || G->longest > 65536) return false;
             D.max_span = (int32_t)G->longest;
             D.stage = true;
             tiles = C.tiles;
             D.ptr = ar.upload(C.ptr, s);
-            D.col = ar.upload(G->lcol, s);
+            std::vector<uint16_t> l16(G->lcol.begin(), G->lcol.end());
+            D.col16 = ar.upload(l16, s);
             D.uoff = ar.upload(G->uoff, s);
             D.ucol = ar.upload(G->ucol, s);
             std::vector<VT> v(C.val.size());

@@ -57,7 +57,7 @@ void with_mat(const DevMat<VT> &M, Fn &&fn) {
 #define DFAMG_SELL(R, I, S) \
     fn(SellM<VT, R, I, S>{M.tiles, M.soff, M.sw, M.col, M.col16, M.cbase, M.cspan, M.ridx, M.val, M.ntiles})
 #define DFAMG_CSR(L, S) \
-    fn(CsrM<VT, L, S>{M.tiles, M.ptr, M.col, M.cbase, M.cspan, M.val, M.ntiles, M.uoff, M.ucol})
+    fn(CsrM<VT, L, S>{M.tiles, M.ptr, M.col, M.cbase, M.cspan, M.val, M.ntiles, M.uoff, M.ucol, M.col16})
     if (M.fmt == DFAMG_FORMAT_SELL) {
         if (!M.stage) {
             if (M.idx16) {

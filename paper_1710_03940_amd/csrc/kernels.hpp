@@ -84,9 +84,9 @@ struct SellM {
 // CSR with L lanes per row; STAGE as above (cbase/cspan per tile), or, when
 // ucol is set, from a gather list: the tile's distinct columns
 // ucol[uoff[tile] .. uoff[tile+1]) in ascending order are copied into LDS and
-// col holds each entry's position in that list, so a column that several
-// rows of the tile read is fetched once per tile however far apart the
-// columns lie.
+// col16 (16 bits: a list never exceeds the LDS budget) holds each entry's
+// position in that list, so a column that several rows of the tile read is
+// fetched once per tile however far apart the columns lie.
 template <class VT, int L, bool STAGE>
 struct CsrM {
     const DevTile *tiles;
@@ -98,6 +98,7 @@ struct CsrM {
     int32_t ntiles;
     const int32_t *uoff;
     const int32_t *ucol;
+    const uint16_t *col16;
 };
 
 __device__ __forceinline__ int tile_of_block(int ntiles) {
@@ -207,23 +208,27 @@ __device__ __forceinline__ void for_rows(const CsrM<VT, L, STAGE> &M, int tile, 
         if (STAGE) return lds[c - cb];
         return (VT)src(c);
     };
-    for (int lr = g; lr < T.nrows; lr += G) {
-        const int row = T.row0 + lr;
-        const int k0 = M.ptr[row], k1 = M.ptr[row + 1];
-        ACC a0 = 0, a1 = 0;
-        int k = k0 + lane;
-        for (; k + L < k1; k += 2 * L) {
-            const int c0 = stream_load(M.col + k), c1 = stream_load(M.col + k + L);
-            const ACC v0 = (ACC)stream_load(M.val + k), v1 = (ACC)stream_load(M.val + k + L);
-            a0 += v0 * x(c0);
-            a1 += v1 * x(c1);
-        }
-        if (k < k1) a0 += (ACC)stream_load(M.val + k) * x(stream_load(M.col + k));
-        ACC acc = a0 + a1;
+    auto rows = [&](const auto *__restrict__ colp) {
+        for (int lr = g; lr < T.nrows; lr += G) {
+            const int row = T.row0 + lr;
+            const int k0 = M.ptr[row], k1 = M.ptr[row + 1];
+            ACC a0 = 0, a1 = 0;
+            int k = k0 + lane;
+            for (; k + L < k1; k += 2 * L) {
+                const int c0 = (int)stream_load(colp + k), c1 = (int)stream_load(colp + k + L);
+                const ACC v0 = (ACC)stream_load(M.val + k), v1 = (ACC)stream_load(M.val + k + L);
+                a0 += v0 * x(c0);
+                a1 += v1 * x(c1);
+            }
+            if (k < k1) a0 += (ACC)stream_load(M.val + k) * x((int)stream_load(colp + k));
+            ACC acc = a0 + a1;
 #pragma unroll
-        for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
-        if (lane == 0) f(row, acc);
-    }
+            for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+            if (lane == 0) f(row, acc);
+        }
+    };
+    if (STAGE && M.ucol) rows(M.col16);
+    else rows(M.col);
 }
 
 // Rows of a tile for kernels without a matrix: thread t takes rows t, t+256, ..
