@@ -327,3 +327,23 @@ def test_smoother_matrices_match_oracle(smoother):
         assert checked >= 2
     finally:
         L.dfamg_plan_destroy(plan)
+
+
+def test_header_constants_match_binding():
+    # every enumerator of the C header has the same value in the binding (the
+    # per-kernel span ids as the order of KERNEL_NAMES)
+    import re
+    import os
+    from paper_1710_03940_amd import _lib
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "dfamg.h")).read()
+    pairs = re.findall(r"\bDFAMG_([A-Z0-9_]+)\s*=\s*(-?\d+)", hdr)
+    assert len(pairs) > 30
+    for name, value in pairs:
+        if name.startswith("KERNEL_"):
+            span = name[len("KERNEL_"):].lower()
+            if span == "count":
+                assert int(value) == len(_lib.KERNEL_NAMES)
+            else:
+                assert _lib.KERNEL_NAMES[int(value)] == span, name
+        else:
+            assert getattr(_lib, name) == int(value), name
