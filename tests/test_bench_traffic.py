@@ -1,6 +1,7 @@
-"""Host logic of the benchmark's HBM traffic figure: FETCH_SIZE / WRITE_SIZE
-counter values per dispatch (KiB) of the outer SpMV, scaled by what the same
-counters read for a copy kernel of known size.  Synthetic counter files."""
+"""Host logic of the benchmark: the HBM traffic figure, i.e. the FETCH_SIZE /
+WRITE_SIZE counter values per dispatch (KiB) of the outer SpMV scaled by what
+the same counters read for a copy kernel of known size (synthetic counter
+files), and the refusal of runs on more than one GPU."""
 import csv
 import json
 import os
@@ -49,3 +50,14 @@ def test_traffic_scaled_by_copy_calibration(tmp_path, monkeypatch):
     assert abs(t["write_bytes"] - 20000.0 * 1024.0) < 1e-3
     assert abs(t["bytes_per_launch"] - (t["fetch_bytes"] + t["write_bytes"])) < 1e-3
     assert t["kernel_source_hash"] == bench.kernel_source_hash()
+
+
+def test_more_than_one_gpu_is_refused():
+    # the solve is measured on one GPU; --gpus above 1 exits with a message
+    # before anything touches a device, and prints no result line
+    import subprocess
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout.strip() == ""
