@@ -605,21 +605,24 @@ __global__ void __launch_bounds__(kWideBlock) k_residual_test(const double *__re
         if (threadIdx.x < 64) bb = wave_range_sum(psub, R.sub_off[sys], R.sub_off[sys + 1]);
     }
     if (threadIdx.x != 0) return;
+    if (MODE == 1) S.bb = bb;
+    // A non-finite ||b||^2 or ||r||^2 must not take the b = 0 shortcut below
+    // (NaN > 0 is false): the relative residual is then NaN itself.
+    const bool finite = isfinite(S.bb) && isfinite(rr);
+    const double h = !finite ? (double)NAN : (S.bb > 0.0 ? sqrt(rr / S.bb) : 0.0);
     if (MODE == 2) {
-        out[sys] = S.bb > 0.0 ? sqrt(rr / S.bb) : 0.0;
+        out[sys] = h;
         return;
     }
-    if (MODE == 1) S.bb = bb;
     S.rr = rr;
-    const double h = S.bb > 0.0 ? sqrt(rr / S.bb) : 0.0;
     S.relres = h;
     if (MODE == 1) {
         S.iter = 0;
         S.done = kRunning;
         S.half = 0;
         hist[(int64_t)sys * hist_stride] = h;
-        if (S.bb == 0.0 || h <= rtol) S.done = kConverged;
-        else if (!isfinite(h)) S.done = kNaN;
+        if (!finite) S.done = kNaN;
+        else if (S.bb == 0.0 || h <= rtol) S.done = kConverged;
         else if (maxiter == 0) S.done = kMaxIter;
         return;
     }

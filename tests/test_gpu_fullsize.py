@@ -15,10 +15,30 @@ pytestmark = [pytest.mark.gpu,
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-# The iteration stops on the recurrence residual (<= 1e-8); the true residual
-# recomputed from the recovered x differs from it by rounding drift, which on
-# BiCGStab can reach a few parts in a thousand of it.
+# The iteration stops on the recurrence residual (<= 1e-8).  For CG the true
+# residual recomputed from the recovered x differs from it by rounding only,
+# far below the margin, so CG (FP64, mixed and batched) is held to 1e-8
+# exactly.  BiCGStab, BiCGStab(2) and FGMRES stop on a residual that their
+# recurrences (or, for FGMRES, the least-squares estimate) carry, and the true
+# residual of the same iterate drifts from it by rounding by up to a few parts
+# in a thousand on these problems: they get 1 % of slack, and the drift itself
+# is bounded below.
+TRUE_RES_TOL_CG = 1e-8
 TRUE_RES_TOL = 1e-8 * 1.01
+MAX_DRIFT = 1e-2
+
+
+def _check_drift(out):
+    """|true - recurrence| / recurrence stays within MAX_DRIFT."""
+    assert abs(out["relres_true"] - out["relres"]) <= MAX_DRIFT * out["relres"], out
+
+
+def _cpu_residual(A, b, x):
+    """||b - A x|| / ||b|| recomputed on the host from the GPU's whole x, and
+    the largest per-row residual relative to ||b||_inf: a wrong value in any
+    row, a tile or subdomain boundary included, shows up here."""
+    r = b - A @ x
+    return np.linalg.norm(r) / np.linalg.norm(b), np.abs(r).max() / np.abs(b).max()
 
 
 def _golden(name):
@@ -47,7 +67,11 @@ def test_lognormal150_matches_oracle(lognormal150, precision):
     print(f"{precision}: gpu iters {out['iters']} oracle {g['iters']} relres_true "
           f"{out['relres_true']:.3e}", flush=True)
     assert out["status"] == 0
-    assert out["relres_true"] <= TRUE_RES_TOL
+    assert out["relres_true"] <= TRUE_RES_TOL_CG
+    cpu_rel, cpu_row = _cpu_residual(P.A, P.b, x.cpu().numpy())
+    print(f"  host-recomputed residual {cpu_rel:.3e}, largest row {cpu_row:.3e}", flush=True)
+    assert cpu_rel <= TRUE_RES_TOL_CG * (1 + 1e-6)
+    assert abs(cpu_rel - out["relres_true"]) <= 1e-3 * out["relres_true"]
     if precision == "fp64":
         assert abs(out["iters"] - g["iters"]) <= 2
         k = min(len(out["history"]), len(g["history"]))
@@ -76,7 +100,10 @@ def test_batched48_matches_oracle_on_sampled_systems(precision):
     S.close()
     xs = x.cpu().numpy()
     assert out["status"] == 0
-    assert np.all(out["relres_true"] <= TRUE_RES_TOL)
+    assert np.all(out["relres_true"] <= TRUE_RES_TOL_CG)
+    cpu_rel, cpu_row = _cpu_residual(A, b, xs)
+    print(f"  host-recomputed residual of the whole batch {cpu_rel:.3e}, largest row {cpu_row:.3e}", flush=True)
+    assert cpu_rel <= TRUE_RES_TOL_CG * (1 + 1e-6)
     for key, gs in g.items():
         s = int(key)
         it = int(out["iters"][s])
@@ -110,6 +137,7 @@ def test_oseen64_matches_oracle(precision):
           f"{out['relres_true']:.3e}", flush=True)
     assert out["status"] == 0
     assert out["relres_true"] <= TRUE_RES_TOL
+    _check_drift(out)
     if precision == "fp64":
         assert abs(out["iters"] - g["iters"]) <= 2
     else:
@@ -137,6 +165,7 @@ def test_lognormal150_bicgstab2_matches_oracle(lognormal150, precision):
           f"{out['relres_true']:.3e}", flush=True)
     assert out["status"] == 0
     assert out["relres_true"] <= TRUE_RES_TOL
+    _check_drift(out)
     if precision == "fp64":
         assert abs(out["iters"] - g["iters"]) <= 2
     else:
@@ -165,6 +194,7 @@ def test_lognormal150_fgmres_matches_oracle(lognormal150, coarse, precision):
           f"{out['relres_true']:.3e}", flush=True)
     assert out["status"] == 0
     assert out["relres_true"] <= TRUE_RES_TOL
+    _check_drift(out)
     if precision == "fp64":
         assert abs(out["iters"] - g["iters"]) <= 2
     else:
@@ -191,6 +221,7 @@ def test_lognormal150_fgmres_cg_coarse_matches_oracle(lognormal150):
           f"{out['relres_true']:.3e} coarse steps {st['coarse_iters']}", flush=True)
     assert out["status"] == 0
     assert out["relres_true"] <= TRUE_RES_TOL
+    _check_drift(out)
     assert abs(out["iters"] - g["iters"]) <= 2
     xs = x.cpu().numpy()
     idx = np.array(g["sample_index"])
@@ -215,6 +246,7 @@ def test_oseen64_schur_matches_oracle():
           f"inner {st['schur_inner_iters']}", flush=True)
     assert out["status"] == 0
     assert out["relres_true"] <= TRUE_RES_TOL
+    _check_drift(out)
     assert abs(out["iters"] - g["iters"]) <= 2
     xs = x.cpu().numpy()
     idx = np.array(g["sample_index"])
@@ -239,6 +271,7 @@ def test_oseen64_block_spai0_matches_oracle(precision):
           f"{out['relres_true']:.3e}", flush=True)
     assert out["status"] == 0
     assert out["relres_true"] <= TRUE_RES_TOL
+    _check_drift(out)
     if precision == "fp64":
         assert abs(out["iters"] - g["iters"]) <= 2
     else:
