@@ -186,6 +186,22 @@ def test_singular_diagonal_block_is_left_out():
     assert np.allclose(H.levels[0].P.toarray(), want, rtol=0, atol=1e-15)
 
 
+def test_ill_conditioned_diagonal_block_is_inverted():
+    # D_0 = [[1, 1], [1, 1 + d]] with d = 2^-20 is invertible (det = d), with
+    # the exact inverse (1/d) [[1 + d, -1], [-1, 1]]: only an exactly singular
+    # block may be left out, whatever its condition number (here ~4e6), so a
+    # rank test with a loose tolerance must not drop it
+    d = 2.0 ** -20
+    blocks = {(0, 0): [[1, 1], [1, 1 + d]], (0, 1): C2, (1, 0): C2, (1, 1): D2}
+    A, _ = _blocks_to_csr(blocks, 2, 2)
+    Fm, strong = sa.strong_graph(A, EPS, bs=2)
+    AF = sa.filtered_matrix(A, Fm, strong, bs=2)
+    Dinv, ok = sa.block_diag_inverse(AF, bs=2)
+    assert list(ok) == [True, True]
+    want = np.array([[1 + d, -1.0], [-1.0, 1.0]]) / d
+    assert np.allclose(Dinv.toarray()[0:2, 0:2], want, rtol=1e-8, atol=0)
+
+
 # ---------------------------------------------------------------------------
 # Kronecker invariance
 # ---------------------------------------------------------------------------
