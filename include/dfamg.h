@@ -400,6 +400,28 @@ dfamg_status dfamg_coarse_operator(dfamg_handle h, int32_t sys, int32_t *m, doub
 dfamg_status dfamg_dense_inverse(const double *a, int32_t n, int32_t method,
                                  double *out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * unblocked inverse of dfamg_dense_inverse (method 1) on device memory,
+ * with no allocation by the library.  Its working storage (the augmented
+ * n x 2n matrix, the pivot column and the job record, 4 MiB at the limit)
+ * is one static array per GPU, which the process holds until it ends.
+ *   a       device, n x n row-major FP64 (not modified)
+ *   n       1 <= n <= DFAMG_NOALLOC_MAX_N; larger n is rejected (EINVAL)
+ *   out     device, n x n row-major FP64: the inverse, bitwise equal to
+ *           what dfamg_dense_inverse(a, n, 1, out) returns
+ *   stream  hipStream_t for the work (NULL = null stream); the call
+ *           synchronises it before returning
+ * ESINGULAR when a pivot column is exactly zero (out unspecified).  Every
+ * call starts from a freshly written workspace, but all calls on one GPU
+ * share it: calls that overlap on the same GPU (from several threads, or on
+ * several streams) race and give wrong results.
+ */
+#define DFAMG_NOALLOC_MAX_N 512
+dfamg_status dfamg_dense_inverse_noalloc(const double *a, int32_t n, double *out,
+                                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,8 @@ from ._lib import (DfamgError, dfamg_params_default, dfamg_setup, dfamg_setup_ba
                    dfamg_destroy, dfamg_last_error, dfamg_plan_create, dfamg_plan_levels,
                    dfamg_plan_aggregates, dfamg_plan_level_matrix,
                    dfamg_plan_coarse_operator, dfamg_plan_destroy, dfamg_coarse_inverse,
-                   dfamg_dense_inverse, dfamg_setup_schur, dfamg_coarse_operator)
+                   dfamg_dense_inverse, dfamg_setup_schur, dfamg_coarse_operator,
+                   dfamg_dense_inverse_noalloc)
 
 __all__ = ["Solver", "BatchedSolver", "SchurSolver", "make_params", "DfamgError"] + [
     n for n in dir(_lib) if n.startswith("dfamg_")]

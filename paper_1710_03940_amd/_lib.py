@@ -23,6 +23,7 @@ SMOOTHER_SPAI0, SMOOTHER_JACOBI, SMOOTHER_BLOCK_SPAI0 = 0, 1, 2
 FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL, FORMAT_CSR_GATHER = 0, 1, 2, 3
 PRECOND_AMG, PRECOND_NONE, PRECOND_SPAI0 = 0, 1, 2
 OP_SPMV, OP_PROJECT, OP_PRECOND, OP_RECOVER = 0, 1, 2, 3
+NOALLOC_MAX_N = 512
 KERNEL_NAMES = ["spmv", "project", "update", "test", "presmooth0", "restrict0", "coarser",
                 "prolong0", "postsmooth0", "direction"]
 
@@ -33,6 +34,7 @@ EXPORTED = [
     "dfamg_plan_aggregates", "dfamg_plan_level_matrix",
     "dfamg_plan_coarse_operator", "dfamg_plan_destroy", "dfamg_coarse_inverse",
     "dfamg_dense_inverse", "dfamg_setup_schur", "dfamg_coarse_operator",
+    "dfamg_dense_inverse_noalloc",
 ]
 
 
@@ -113,6 +115,7 @@ def load():
     lib.dfamg_coarse_inverse.argtypes = [H, I32, P, P, I64]
     lib.dfamg_coarse_operator.argtypes = [H, I32, P, P, I64]
     lib.dfamg_dense_inverse.argtypes = [P, I32, I32, P]
+    lib.dfamg_dense_inverse_noalloc.argtypes = [P, I32, P, P]
     lib.dfamg_setup_schur.argtypes = [ctypes.POINTER(Params), I64, P, P, P, P, P, I32, I32, P, P,
                                       ctypes.POINTER(H)]
     for name in EXPORTED:
@@ -356,6 +359,22 @@ def dfamg_dense_inverse(a, method=0):
     a = np.ascontiguousarray(a, dtype=np.float64)
     out = np.zeros_like(a)
     _check(lib.dfamg_dense_inverse(_ptr(a), a.shape[0], method, _ptr(out)))
+    return out
+
+
+def dfamg_dense_inverse_noalloc(a, out, stream=None):
+    """Inverse of the n x n float64 device tensor `a` into the device tensor
+    `out`, computed without any device allocation by the library (method 1 of
+    dfamg_dense_inverse); `stream` is a torch stream (default: current)."""
+    import torch
+    if not (a.is_cuda and out.is_cuda and a.dtype == torch.float64 and out.dtype == torch.float64
+            and a.is_contiguous() and out.is_contiguous() and a.dim() == 2 and a.shape[0] == a.shape[1]
+            and out.shape == a.shape):
+        raise ValueError("a and out must be contiguous square float64 CUDA tensors of the same shape")
+    st = stream if stream is not None else torch.cuda.current_stream(a.device)
+    _check(load().dfamg_dense_inverse_noalloc(ctypes.c_void_p(a.data_ptr()), a.shape[0],
+                                              ctypes.c_void_p(out.data_ptr()),
+                                              ctypes.c_void_p(st.cuda_stream)))
     return out
 
 

@@ -2260,6 +2260,64 @@ dfamg_status do_setup(const dfamg_params *prm, int32_t nsys, const int64_t *sys_
     });
 }
 
+
+// ---------------------------------------------------------------------------
+// Workspace of dfamg_dense_inverse_noalloc: one static array per device,
+// holding the job record, the offsets, the pivot column and the augmented
+// matrix [A | I] of the unblocked Gauss-Jordan elimination.  Host code never
+// passes `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returns on each device, looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr int kNoAllocMaxN = DFAMG_NOALLOC_MAX_N;
+constexpr int64_t kNoAllocHeader = 64;                      // doubles: job, col_off, out_off, out_ld
+constexpr int64_t kNoAllocColk = kNoAllocHeader;            // n doubles (pivot column)
+constexpr int64_t kNoAllocAug = kNoAllocColk + kNoAllocMaxN; // n x 2n doubles
+constexpr int64_t kNoAllocDoubles = kNoAllocAug + (int64_t)kNoAllocMaxN * 2 * kNoAllocMaxN;
+static_assert(kNoAllocAug * 8 % 256 == 0, "augmented matrix 256-byte aligned");
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+// Fills the job record and offsets of one n x n matrix and its augmented
+// copy [a | I] (row-major n x 2n) from the device matrix a.
+__global__ void k_noalloc_init(double *__restrict__ ws, const double *__restrict__ a, int n) {
+    const int64_t w2 = 2 * (int64_t)n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        InvJob *job = reinterpret_cast<InvJob *>(ws);
+        job->n = n;
+        job->singular = 0;
+        job->aug_off = 0;
+        int64_t *col_off = reinterpret_cast<int64_t *>(ws + 8);
+        col_off[0] = 0;
+        col_off[1] = n;
+        *reinterpret_cast<int64_t *>(ws + 12) = 0;   // out_off
+        *reinterpret_cast<int32_t *>(ws + 14) = n;   // out_ld
+    }
+    double *aug = ws + kNoAllocAug;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * w2;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / w2, j = e % w2;
+        aug[e] = j < n ? a[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    }
+}
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device.
+double *noalloc_workspace() {
+    static std::mutex mu;
+    static std::map<int, double *> ptrs;
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = ptrs.find(dev);
+    if (it != ptrs.end()) return it->second;
+    double *p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(scratch)));
+    if (!p) throw Error{DFAMG_EHIP, "hipGetSymbolAddress returned no address for the workspace"};
+    ptrs[dev] = p;
+    return p;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2786,6 +2844,40 @@ dfamg_status dfamg_dense_inverse(const double *a, int32_t n, int32_t method, dou
         const int bad = invert_on_device<double>(s, {a}, {n}, d, {0}, {n});
         if (bad >= 0) throw Error{DFAMG_ESINGULAR, "matrix is singular"};
         HIP_CHECK(hipMemcpy(out, d, sizeof(double) * nn, hipMemcpyDeviceToHost));
+        return DFAMG_OK;
+    });
+}
+
+
+dfamg_status dfamg_dense_inverse_noalloc(const double *a, int32_t n, double *out, void *stream) {
+    return guarded(nullptr, [&]() -> dfamg_status {
+        if (!a || !out || n < 1)
+            throw Error{DFAMG_EINVAL, "dfamg_dense_inverse_noalloc: need device pointers a, out and n >= 1"};
+        if (n > kNoAllocMaxN)
+            throw Error{DFAMG_EINVAL, "dfamg_dense_inverse_noalloc: n = " + std::to_string(n) +
+                                          " exceeds the workspace limit of " + std::to_string(kNoAllocMaxN)};
+        check_device();
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        double *ws = noalloc_workspace();
+        InvJob *d_job = reinterpret_cast<InvJob *>(ws);
+        const int64_t *d_coff = reinterpret_cast<const int64_t *>(ws + 8);
+        const int64_t *d_oof = reinterpret_cast<const int64_t *>(ws + 12);
+        const int32_t *d_old = reinterpret_cast<const int32_t *>(ws + 14);
+        double *d_colk = ws + kNoAllocColk;
+        double *d_aug = ws + kNoAllocAug;
+        const int64_t maxel = (int64_t)n * 2 * n;
+        const int gx = (int)std::min<int64_t>(1024, (maxel + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_noalloc_init, dim3(gx), dim3(kBlock), 0, s, ws, a, n);
+        for (int k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kBlock), 0, s, d_job, d_aug, d_colk, d_coff, k);
+            hipLaunchKernelGGL(k_gj_eliminate, dim3(gx, 1), dim3(kBlock), 0, s, d_job, d_aug, d_colk, d_coff, k);
+        }
+        hipLaunchKernelGGL(k_gj_extract<double>, dim3(gx, 1), dim3(kBlock), 0, s, d_job, d_aug, d_oof, d_old, out);
+        HIP_CHECK(hipGetLastError());
+        InvJob job{};
+        HIP_CHECK(hipMemcpyAsync(&job, d_job, sizeof(InvJob), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (job.singular) throw Error{DFAMG_ESINGULAR, "matrix is singular"};
         return DFAMG_OK;
     });
 }
