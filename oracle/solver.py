@@ -38,7 +38,9 @@ class OracleParams:
     eps_strong: float = 0.08
     max_levels: int = 20
     block_size: int = 1
-    flexible: bool = False
+    flexible: bool = False          # CG: Polak-Ribiere beta (flexible CG)
+    npre: int = 1                   # V-cycle pre-smoothing sweeps
+    npost: int = 1                  # V-cycle post-smoothing sweeps
     precond: str = "amg"            # "amg", "identity" or "spai0" (diagonal)
 
 
@@ -71,7 +73,8 @@ class OracleSolver:
         except DeflationError as exc:
             raise OracleError(str(exc))
         if self.prm.precond == "amg":
-            self.M = BlockAMG(A, part, nsub, eps_strong=self.prm.eps_strong,
+            self.M = BlockAMG(A, part, nsub, npre=self.prm.npre, npost=self.prm.npost,
+                              eps_strong=self.prm.eps_strong,
                               coarse_enough=self.prm.coarse_enough,
                               max_levels=self.prm.max_levels,
                               smoother=self.prm.smoother,
