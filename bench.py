@@ -10,9 +10,16 @@ permutation out) with inputs resident in HBM.
 
 The JSON line reports the FP64 path as `value` (seconds per solve), the
 mixed-precision path (FP32 hierarchy / FP64 Krylov and deflation) and, unless
---no-batched, the 48-system batched solve next to it, the roofline of the
-dominant kernel (the outer SpMV with its fused epilogue) measured with HIP
-events inside the timed solves, and the CPU oracle timed on a bounded sample.
+--no-batched, the 48-system batched solve (mixed and FP64) next to it, the
+32^3 eight-slab Poisson solve (cache-resident), the roofline of the dominant
+kernel (the slower of the outer SpMV with its fused epilogue and the level-0
+restriction) measured with HIP events inside the timed solves, the rate of
+every kernel span against the HBM peak, and the CPU oracle timed on a
+bounded sample.
+
+Layouts: the autotuner's choices are read from (and new ones appended to) the
+record named by DFAMG_TUNE_CACHE, by default the one shipped with the package,
+so that the timed solves and the profiler runs dispatch the same kernels.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
@@ -20,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -31,8 +39,25 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "time-to-solution at rtol 1e-8 (FP64 vs mixed vs batched); SpMV HBM GB/s % peak"
 # device code of the outer-operator kernel (its launcher, views and body)
 KERNEL_SOURCES = ["paper_1710_03940_amd/csrc/kernels.hpp", "paper_1710_03940_amd/csrc/launch_outer.hip",
-                  "paper_1710_03940_amd/csrc/devmat.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_lognormal150_traffic.json")
+                  "paper_1710_03940_amd/csrc/launch_vcycle.hip", "paper_1710_03940_amd/csrc/devmat.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lognormal150_traffic.json")
+TUNE_RECORD = os.path.join(ROOT, "paper_1710_03940_amd", "tuned_layouts_gfx950.txt")
+# what each per-span figure covers (DFAMG_KERNEL_* spans of the FP64 CG iteration)
+SPAN_DOC = {
+    "spmv": "k_outer: outer SpMV q = A p with the fused (p,q) and Z^T q epilogue",
+    "project": "t1 sums per system, t2 = E^-1 t1 (one wavefront per row), alpha",
+    "update": "y += alpha p, r -= alpha (q - AZ t2), ||r||^2 partials",
+    "test": "stopping test (per-system reductions)",
+    "presmooth0": "level 0: B0 = R0 (I - A0 diag(m0)) applied to r (pre-smoothing, residual, restriction)",
+    "restrict0": "level 0: restriction when it is not fused into presmooth0",
+    "coarser": "levels >= 1 and every coarsest direct solve (= restrict1 + deep + up1)",
+    "prolong0": "level 0: z = m r + P0 x1",
+    "postsmooth0": "level 0: s = z + m (r - A0 z) with (r,s) partials",
+    "direction": "beta from (r,s); p = s + beta p",
+    "restrict1": "level 1: B1 applied (pre-smoothing, residual, restriction)",
+    "deep": "levels >= 2 and all coarsest dense solves",
+    "up1": "level 1: prolongation and post-smoothing",
+}
 
 
 def kernel_source_hash():
@@ -116,13 +141,20 @@ def main():
     ap.add_argument("--no-fgmres", action="store_true")
     ap.add_argument("--no-schur", action="store_true")
     ap.add_argument("--no-coarse-inverse", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--only", choices=["oseen", "batched", "small"],
+                    help="run one leg alone and print its result (for kernel traces of that workload)")
+    ap.add_argument("--record-layouts", metavar="FILE",
+                    help="write the layouts the FP64 and mixed handles chose (for --traffic-from)")
     ap.add_argument("--sample-iters", type=int, default=20)
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a 2 GiB device copy (streaming ceiling; reference for HBM counters)")
-    ap.add_argument("--traffic-from", nargs=4, metavar=("SPMV_FETCH", "SPMV_WRITE", "COPY_FETCH", "COPY_WRITE"),
-                    help="rocprofv3 --pmc CSVs of FETCH_SIZE / WRITE_SIZE for bench and for --copy-calibration; "
-                         "writes the traffic file read by the roofline")
+    ap.add_argument("--traffic-from", nargs=5,
+                    metavar=("BENCH_FETCH", "BENCH_WRITE", "COPY_FETCH", "COPY_WRITE", "LAYOUTS"),
+                    help="rocprofv3 --pmc CSVs of FETCH_SIZE / WRITE_SIZE for bench and for --copy-calibration, "
+                         "and the --record-layouts file of the profiled bench run; writes the traffic file "
+                         "read by the roofline")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
@@ -140,8 +172,15 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    if args.only:
+        os.environ.setdefault("DFAMG_TUNE_CACHE", TUNE_RECORD)
+        leg = {"oseen": bench_oseen, "batched": bench_batched, "small": bench_small}[args.only]
+        print(json.dumps({"leg": args.only, "result": leg(args, log)}), flush=True)
+        return 0
+
     cpu_proc = None if args.no_cpu_baseline else start_cpu_baseline(args.sample_iters)
 
+    os.environ.setdefault("DFAMG_TUNE_CACHE", TUNE_RECORD)
     import numpy as np
     import torch
     import paper_1710_03940_amd as dfamg
@@ -159,6 +198,9 @@ def main():
     log(f"  host setup {st64['setup_host_s']:.2f} s, device setup {st64['setup_device_s']:.2f} s, "
         f"levels {st64['level_rows']}")
     log(f"  layouts: {st64['layouts']}")
+    if args.record_layouts:
+        with open(args.record_layouts, "w") as fh:
+            json.dump({"fp64": parse_layouts(st64["layouts"]), "text": st64["layouts"]}, fh, indent=1)
     log("timing FP64")
     t64, out64, it64 = time_solver(S64, b, x, args.steps, args.warmup, log)
     st64 = S64.stats()
@@ -253,18 +295,33 @@ def main():
             batched = {"error": str(exc)}
 
     # roofline of the dominant kernel, from events recorded in the timed solves
-    k = st64["kernels"]["spmv"]
-    avg_s = k["ms"] / max(k["calls"], 1) * 1e-3
-    achieved = k["bytes"] / avg_s / 1e9 if avg_s > 0 else 0.0
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tf = json.load(fh)
-        if tf.get("kernel_source_hash") == kernel_source_hash():
-            traffic = tf.get("bytes_per_launch")
-    kernels = kernel_breakdown(P, b, x, log) if not args.no_breakdown else None
     copy_gbps = copy_ceiling_gbps()
     log(f"  streaming copy ceiling {copy_gbps:.0f} GB/s")
+    layouts64 = parse_layouts(st64["layouts"])
+    live = {}
+    for name in ("spmv", "presmooth0"):
+        k = st64["kernels"][name]
+        if k["calls"]:
+            avg_s = k["ms"] / k["calls"] * 1e-3
+            live[name] = {"avg_us": avg_s * 1e6, "bytes_per_launch": k["bytes"],
+                          "achieved": k["bytes"] / avg_s / 1e9, "launches_timed": k["calls"]}
+    dom = max(live, key=lambda kname: live[kname]["avg_us"])
+    traffic = load_traffic(dom, layouts64)
+    roofline = {"bound": "hbm", "achieved": live[dom]["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": live[dom]["achieved"] / HBM_PEAK_GBS,
+                "traffic": traffic["bytes_per_launch"] if traffic else None,
+                "kernel": SPAN_DOC[dom], "span": dom, "layout": layouts64.get(dom),
+                "avg_us": live[dom]["avg_us"], "bytes_per_launch": live[dom]["bytes_per_launch"],
+                "copy_ceiling": copy_gbps, "frac_of_copy": live[dom]["achieved"] / copy_gbps,
+                "events_in_graph": st64["profile_in_graph"],
+                "other": {kname: dict(v, frac=v["achieved"] / HBM_PEAK_GBS, layout=layouts64.get(kname),
+                                      traffic=(load_traffic(kname, layouts64) or {}).get("bytes_per_launch"))
+                          for kname, v in live.items() if kname != dom}}
+    if dom == "spmv":
+        roofline["layout_bytes_per_launch"] = st64["outer_layout_bytes"]
+    kernels = kernel_breakdown(P, b, x, log, "fp64") if not args.no_breakdown else None
+    kernels_mixed = kernel_breakdown(P, b, x, log, "mixed") if not (args.no_breakdown or args.no_mixed) else None
+    small = None if args.no_small else bench_small(args, log)
 
     cpu = None
     if cpu_proc is not None:
@@ -295,17 +352,11 @@ def main():
         "setup_s": {"host": st64["setup_host_s"], "device": st64["setup_device_s"]},
         "bytes_per_iter": st64["bytes_per_iter"],
         "effective_GBps": st64["bytes_per_iter"] * out64["iters"] / t64 / 1e9,
-        "mixed": mixed, "batched": batched, "oseen": oseen, "bicgstab2": bicgstab2, "fgmres": fgmres,
-        "schur": schur, "coarse_inverse": coarse_inverse,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_outer (outer SpMV + (p,q) + Z^T q epilogue)",
-                     "avg_us": avg_s * 1e6, "bytes_per_launch": k["bytes"],
-                     "copy_ceiling": copy_gbps, "frac_of_copy": achieved / copy_gbps,
-                     "layout_bytes_per_launch": st64["outer_layout_bytes"],
-                     "layout_GBps": st64["outer_layout_bytes"] / avg_s / 1e9 if avg_s > 0 else 0.0,
-                     "events_in_graph": st64["profile_in_graph"]},
-        "kernels": kernels,
+        "layouts": st64["layouts"],
+        "mixed": mixed, "batched": batched, "small": small, "oseen": oseen, "bicgstab2": bicgstab2,
+        "fgmres": fgmres, "schur": schur, "coarse_inverse": coarse_inverse,
+        "roofline": roofline,
+        "kernels": kernels, "kernels_mixed": kernels_mixed,
         "cpu_baseline": cpu,
     }
     S64.close()
@@ -372,44 +423,115 @@ def copy_calibration():
     return 0
 
 
-def _pmc_kib(csv_path, name_part, counter, most_frequent=False):
-    """Per-dispatch counter values (KiB) of kernels whose name contains
-    name_part; with most_frequent, only those of the most often dispatched
-    such kernel (the in-loop instance, not the layouts timed at setup)."""
+def parse_layouts(text):
+    """Layout strings per profiled span from the stats' layout text, e.g.
+    'outer sell1/i32; L0{A sell2/i16/stage, B csr16/t64/glist, P ...} ...':
+    spmv -> the outer operator's, presmooth0 -> level 0's B (or A when the
+    level-0 restriction is not fused), prolong0 -> P of level 0,
+    postsmooth0 -> A of level 0."""
+    out = {}
+    m = re.search(r"outer ([^;]+);", text)
+    if m:
+        out["spmv"] = m.group(1).strip()
+    m = re.search(r"L0\{([^}]*)\}", text)
+    if m:
+        parts = dict(p.strip().split(" ", 1) for p in m.group(1).split(",") if " " in p.strip())
+        if "B" in parts:
+            out["presmooth0"] = "B " + parts["B"]
+        elif "A" in parts:
+            out["presmooth0"] = "A " + parts["A"]
+        if "P" in parts:
+            out["prolong0"] = "P " + parts["P"]
+        if "A" in parts:
+            out["postsmooth0"] = "A " + parts["A"]
+    return out
+
+
+def load_traffic(span, layouts):
+    """Counter-derived HBM bytes per launch of `span`, only when they were
+    taken on the same kernel source and the same layout as the timed run."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        tf = json.load(fh)
+    e = tf.get("kernels", {}).get(span)
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if e.get("layout") != layouts.get(span):
+        return None
+    return e
+
+
+# kernels whose launches the counters isolate: span -> (name prefix, rule);
+# the in-loop instance is the most often dispatched (name, grid) group, and of
+# the restriction groups (one per level) the one with the largest grid
+TRAFFIC_KERNELS = {"spmv": ("k_outer<0,", "most"), "presmooth0": ("k_restrict<double, double,", "largest")}
+
+
+def _pmc_groups(csv_path, prefix, counter):
+    """Per-dispatch counter values (KiB) of the kernels whose name contains
+    `prefix`, grouped by (kernel name, grid size)."""
     import collections
     import csv
     by = collections.defaultdict(list)
     with open(csv_path) as fh:
         for row in csv.DictReader(fh):
-            if name_part in row.get("Kernel_Name", "") and row.get("Counter_Name", counter) == counter:
-                by[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+            if prefix in row.get("Kernel_Name", "") and row.get("Counter_Name", counter) == counter:
+                by[(row["Kernel_Name"], int(float(row.get("Grid_Size", 0) or 0)))].append(float(row["Counter_Value"]))
+    return by
+
+
+def _pick_group(by, rule):
     if not by:
-        return []
-    if most_frequent:
-        return max(by.values(), key=len)
-    return [v for vals in by.values() for v in vals]
+        return None
+    if rule == "most":
+        return max(by, key=lambda k: len(by[k]))
+    top = max(len(v) for v in by.values())
+    busy = [k for k in by if len(by[k]) >= top // 2]
+    return max(busy, key=lambda k: k[1])
 
 
-def write_traffic(spmv_fetch, spmv_write, copy_fetch, copy_write):
-    """HBM bytes per launch of the outer SpMV from FETCH_SIZE / WRITE_SIZE,
-    scaled by what the same counters read for the plain copy of COPY_BYTES."""
+def _pmc_kib(csv_path, name_part, counter):
+    """Per-dispatch counter values (KiB) of kernels whose name contains name_part."""
+    import csv
+    vals = []
+    with open(csv_path) as fh:
+        for row in csv.DictReader(fh):
+            if name_part in row.get("Kernel_Name", "") and row.get("Counter_Name", counter) == counter:
+                vals.append(float(row["Counter_Value"]))
+    return vals
+
+
+def write_traffic(bench_fetch, bench_write, copy_fetch, copy_write, layouts_file):
+    """HBM bytes per launch of the outer SpMV and of the level-0 restriction
+    from FETCH_SIZE / WRITE_SIZE, scaled by what the same counters read for the
+    plain copy of COPY_BYTES; tagged with the layouts the profiled run used."""
     import statistics
     cf = statistics.median(_pmc_kib(copy_fetch, "elementwise", "FETCH_SIZE"))
     cw = statistics.median(_pmc_kib(copy_write, "elementwise", "WRITE_SIZE"))
     fscale = (COPY_BYTES / 1024.0) / cf      # true KiB per counted KiB
     wscale = (COPY_BYTES / 1024.0) / cw
-    # launches of the in-loop SpMV; skipped launches after convergence read ~nothing
-    f = _pmc_kib(spmv_fetch, "k_outer<0", "FETCH_SIZE", most_frequent=True)
-    w = _pmc_kib(spmv_write, "k_outer<0", "WRITE_SIZE", most_frequent=True)
-    fbig = [v for v in f if v > 0.5 * max(f)]
-    wbig = [v for v in w if v > 0.5 * max(w)]
-    fetch = statistics.median(fbig) * fscale * 1024.0
-    write = statistics.median(wbig) * wscale * 1024.0
-    out = {"kernel": "k_outer<0,...> (outer SpMV, 150^3 log-normal workload)",
-           "bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
-           "copy_scale_fetch": fscale, "copy_scale_write": wscale,
-           "launches_counted": [len(fbig), len(wbig)],
-           "kernel_source_hash": kernel_source_hash()}
+    with open(layouts_file) as fh:
+        lay = json.load(fh)["fp64"]
+    out = {"note": "HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch), "
+                   "scaled by the counters' reading of a plain copy of known size; only launches that did "
+                   "work (above half the group's largest reading) count", "kernels": {}}
+    for span, (prefix, rule) in TRAFFIC_KERNELS.items():
+        fg = _pmc_groups(bench_fetch, prefix, "FETCH_SIZE")
+        wg = _pmc_groups(bench_write, prefix, "WRITE_SIZE")
+        key = _pick_group(fg, rule)
+        if key is None or key not in wg:
+            continue
+        f, w = fg[key], wg[key]
+        fbig = [v for v in f if v > 0.5 * max(f)]
+        wbig = [v for v in w if v > 0.5 * max(w)]
+        fetch = statistics.median(fbig) * fscale * 1024.0
+        write = statistics.median(wbig) * wscale * 1024.0
+        out["kernels"][span] = {"kernel": key[0], "grid": key[1], "layout": lay.get(span),
+                                "bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+                                "copy_scale_fetch": fscale, "copy_scale_write": wscale,
+                                "launches_counted": [len(fbig), len(wbig)],
+                                "kernel_source_hash": kernel_source_hash()}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
@@ -417,24 +539,57 @@ def write_traffic(spmv_fetch, spmv_write, copy_fetch, copy_write):
     return 0
 
 
-def kernel_breakdown(P, b, x, log):
-    """Per-kernel spans of the FP64 path from a separate, untimed handle that
+def span_rates(st):
+    """Per-span average time, algorithmic bytes, rate and fraction of the HBM
+    peak from a handle's profile."""
+    out = {}
+    for name, kv in st["kernels"].items():
+        if kv["calls"]:
+            a = kv["ms"] / kv["calls"] * 1e-3
+            gbps = kv["bytes"] / a / 1e9 if kv["bytes"] and a > 0 else None
+            out[name] = {"avg_us": a * 1e6, "bytes_per_launch": kv["bytes"] or None, "GBps": gbps,
+                         "frac": gbps / HBM_PEAK_GBS if gbps else None}
+    return out
+
+
+def kernel_breakdown(P, b, x, log, precision):
+    """Per-kernel spans of one path from a separate, untimed handle that
     records an event pair around every kernel span of each iteration."""
     import paper_1710_03940_amd as dfamg
-    S = dfamg.Solver(P.A, P.part, P.nsub, P.Z, precision="fp64", profile=2)
+    S = dfamg.Solver(P.A, P.part, P.nsub, P.Z, precision=precision, profile=2)
     for _ in range(2):
         x.zero_()
         S.solve(b, x, history=False)
     st = S.stats()
     S.close()
-    out = {}
-    for name, kv in st["kernels"].items():
-        if kv["calls"]:
-            a = kv["ms"] / kv["calls"]
-            out[name] = {"avg_us": a * 1e3,
-                         "GBps": (kv["bytes"] / (a * 1e-3) / 1e9) if kv["bytes"] else None}
-    log("  per-kernel spans (us): " + ", ".join(f"{k} {v['avg_us']:.1f}" for k, v in out.items()))
+    out = span_rates(st)
+    log(f"  per-kernel spans {precision} (us): " + ", ".join(f"{k} {v['avg_us']:.1f}" for k, v in out.items()))
     return out
+
+
+def bench_small(args, log):
+    """32^3 Poisson, 8 slabs, constant deflation, CG, FP64: the whole working
+    set (about 20 MB) stays in the caches, so its rate is an effective one, not
+    an HBM figure; the solve is bound by launch and synchronisation latency."""
+    import torch
+    import paper_1710_03940_amd as dfamg
+    from workloads import config_small_poisson
+    P = config_small_poisson()
+    dev = torch.device("cuda:0")
+    b = torch.tensor(P.b, device=dev)
+    x = torch.zeros(P.n, dtype=torch.float64, device=dev)
+    golden = load_golden("poisson32_slabs8_constant")
+    S = dfamg.Solver(P.A, P.part, P.nsub, P.Z, precision="fp64")
+    log("timing the 32^3 slab problem")
+    t, o, its = time_solver(S, b, x, max(args.steps, 10), args.warmup, log)
+    st = S.stats()
+    S.close()
+    return {"workload": "poisson32_unit_slabs8_constant_cg", "n": P.n, "nnz": int(P.A.nnz), "subdomains": P.nsub,
+            "s_per_solve": t, "median_s": o["median_s"], "iters": its[-1], "oracle_iters": golden["iters"],
+            "relres_true": o["relres_true"], "rel_error_vs_oracle_sampled": error_vs_oracle(x, golden),
+            "bytes_per_iter": st["bytes_per_iter"], "us_per_iter": t / max(its[-1], 1) * 1e6,
+            "effective_GBps_cache_resident": st["bytes_per_iter"] * its[-1] / t / 1e9,
+            "note": "cache-resident working set: effective rate, latency-bound, not an HBM figure"}
 
 
 def bench_oseen(args, log):
@@ -549,8 +704,24 @@ def bench_coarse_inverse(log):
                     "takes the blocked form for systems with m >= 1024", "rows": rows}
 
 
+def _time_batched(Sb, b, x, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        x.zero_()
+        Sb.solve(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        out = Sb.solve(b, x)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
 def bench_batched(args, log):
-    """48 independent systems in one handle vs the same systems one by one."""
+    """48 independent systems in one handle (mixed and FP64) vs the same
+    systems one by one (FP64): the batching gain is the FP64 batched time
+    against the sequential one, the precision gain mixed against FP64 batched."""
     import numpy as np
     import torch
     import paper_1710_03940_amd as dfamg
@@ -559,30 +730,35 @@ def bench_batched(args, log):
     A, part, nsub, Z, bvec, x0, off = concat_problems(probs)
     dev = torch.device("cuda:0")
     log(f"batched: {len(probs)} systems, {A.shape[0]} unknowns")
-    Sb = dfamg.BatchedSolver(A, part, nsub, Z, off, precision="mixed")
     b = torch.tensor(bvec, device=dev)
     x = torch.zeros(A.shape[0], dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
-        x.zero_()
-        Sb.solve(b, x)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        x.zero_()
-        outb = Sb.solve(b, x)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / args.steps
-    Sb.close()
-    log(f"  batched mixed: {tb * 1e3:.2f} ms, iterations max {int(outb['iters'].max())}")
-    # error against the oracle on the systems whose oracle solutions are stored
+    ns = np.diff(np.asarray(off))
     gsys = load_golden("batched48_sample")["systems"]
-    xs_all = x.cpu().numpy()
-    errs = {}
-    for key, gs in gsys.items():
-        sidx = int(key)
-        xs = xs_all[off[sidx] + np.array(gs["sample_index"])]
-        ref = np.array(gs["sample_x"])
-        errs[key] = float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))
+    res = {}
+    for prec in ("mixed", "fp64"):
+        Sb = dfamg.BatchedSolver(A, part, nsub, Z, off, precision=prec)
+        tb, outb = _time_batched(Sb, b, x, args.steps, args.warmup)
+        st = Sb.stats()
+        Sb.close()
+        its = np.asarray(outb["iters"])
+        # bytes scale with the unknowns of each system: a system stops moving
+        # data once it has converged (its tiles exit early)
+        moved = st["bytes_per_iter"] * float((ns * its).sum()) / float(ns.sum())
+        xs_all = x.cpu().numpy()
+        errs = {}
+        for key, gs in gsys.items():
+            sidx = int(key)
+            xs = xs_all[off[sidx] + np.array(gs["sample_index"])]
+            ref = np.array(gs["sample_x"])
+            errs[key] = float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))
+        res[prec] = {"s_per_batch": tb, "iters_max": int(its.max()), "iters_min": int(its.min()),
+                     "relres_true_max": float(np.asarray(outb["relres_true"]).max()),
+                     "rel_error_vs_oracle_sampled_max": max(errs.values()), "status": int(outb["status"]),
+                     "bytes_per_iter_all_systems": st["bytes_per_iter"],
+                     "effective_GBps": moved / tb / 1e9, "setup_device_s": st["setup_device_s"],
+                     "setup_host_s": st["setup_host_s"]}
+        log(f"  batched {prec}: {tb * 1e3:.2f} ms, iterations max {int(its.max())}, "
+            f"effective {moved / tb / 1e9:.0f} GB/s")
     # plain FP64 path, one system after another
     solvers = []
     vecs = []
@@ -594,23 +770,22 @@ def bench_batched(args, log):
         S.solve(bb, xx, history=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    its = []
     for _ in range(max(1, args.steps // 2)):
         for S, (bb, xx) in zip(solvers, vecs):
             xx.zero_()
-            its.append(S.solve(bb, xx, history=False)["iters"])
+            S.solve(bb, xx, history=False)
     torch.cuda.synchronize()
     ts = (time.perf_counter() - t0) / max(1, args.steps // 2)
     for S in solvers:
         S.close()
     log(f"  sequential fp64: {ts * 1e3:.2f} ms")
-    return {"s_per_batch": tb, "sequential_fp64_s": ts, "speedup_vs_sequential_fp64": ts / tb,
+    return {"s_per_batch": res["mixed"]["s_per_batch"], "mixed": res["mixed"], "fp64": res["fp64"],
+            "sequential_fp64_s": ts,
+            "speedup_batching_fp64": ts / res["fp64"]["s_per_batch"],
+            "speedup_precision_batched": res["fp64"]["s_per_batch"] / res["mixed"]["s_per_batch"],
+            "speedup_vs_sequential_fp64": ts / res["mixed"]["s_per_batch"],
             "systems": len(probs), "unknowns": int(A.shape[0]),
-            "iters_max": int(outb["iters"].max()), "iters_min": int(outb["iters"].min()),
-            "relres_true_max": float(outb["relres_true"].max()),
-            "rel_error_vs_oracle_sampled_max": max(errs.values()),
-            "oracle_sampled_systems": sorted(int(k) for k in errs),
-            "status": int(outb["status"])}
+            "oracle_sampled_systems": sorted(int(k) for k in gsys)}
 
 
 if __name__ == "__main__":

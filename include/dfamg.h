@@ -128,15 +128,30 @@ typedef struct {
     int32_t host_threads;   /* setup worker threads, 0 = hardware concurrency  */
     int32_t verbose;        /* 1 prints setup/solve phase times to stderr,
                                2 also every autotuning candidate's time       */
-    int32_t profile;        /* 1 records HIP events around the outer SpMV of
-                               every Krylov iteration, 2 around every kernel
-                               span (inside the captured graph as well);
-                               averages in dfamg_stats                        */
+    int32_t profile;        /* 1 records HIP events around the outer SpMV and
+                               the level-0 restriction (DFAMG_KERNEL_SPMV and
+                               _PRESMOOTH0) of every Krylov iteration, 2
+                               around every kernel span (inside the captured
+                               graph as well); averages in dfamg_stats        */
     int32_t restart;        /* FGMRES: Arnoldi steps per cycle, 1..64 (30);
                                one captured graph runs one cycle              */
     int32_t coarse_solve;   /* DFAMG_COARSE_*; FP32 and CG need solver = FGMRES */
     double  coarse_rtol;    /* COARSE_CG: relative residual target (1e-2)    */
     int32_t coarse_maxiter; /* COARSE_CG: step limit per coarse solve (100)  */
+    int32_t flexible_cg;    /* CG only: 0 (default) beta = rho'/rho; 1 the
+                               flexible (Polak-Ribiere) beta
+                               (r', s' - s) / rho, equal in exact arithmetic
+                               for a fixed preconditioner and robust when the
+                               preconditioner varies (costs one more vector
+                               read per iteration)                           */
+    int32_t npre;           /* V-cycle pre-smoothing sweeps, 0..4 (1); with a
+                               value other than 1 the level operators keep
+                               the pre-smoothing, residual and restriction
+                               as separate steps                              */
+    int32_t npost;          /* V-cycle post-smoothing sweeps, 1..4 (1).  The
+                               paper's runs use V(1,1); CG needs npre = npost
+                               for a symmetric preconditioner.  The block
+                               SPAI-0 smoother supports V(1,1) only           */
 } dfamg_params;
 
 /* Fill *p with the defaults listed above. */
@@ -271,7 +286,9 @@ typedef struct {
     double  solve_s;                  /* wall time of the last solve call    */
     int64_t device_bytes;             /* device memory owned by the handle   */
     double  bytes_per_iter;           /* algorithmic HBM bytes per Krylov
-                                         iteration (whole batch)             */
+                                         iteration (whole batch) of CG,
+                                         BiCGStab and FGMRES; 0 for
+                                         BiCGStab(2)                          */
     /* Per-kernel profile (params.profile = 1), indexed by DFAMG_KERNEL_*:
        launches timed, total milliseconds and algorithmic bytes per launch. */
     int64_t kernel_calls[16];
@@ -300,7 +317,11 @@ typedef struct {
  * epilogue, the per-system projection reduction (t1 sums, t2 = E^{-1} t1,
  * alpha), the fused deflation-correction / Krylov update, the stopping test,
  * the level-0 V-cycle kernels, everything on coarser levels (including the
- * coarsest direct solves) as one span, and the (r,s) / direction update.
+ * coarsest direct solves) as one span, and the (r,s) / direction update;
+ * the coarser span is also split into the level-1 downward step (pre-
+ * smoothing residual and restriction), the level-1 upward step
+ * (prolongation and post-smoothing) and everything deeper (levels >= 2 and
+ * all coarsest direct solves).
  * When level 0 applies the pre-smoothing sweep, the residual and the
  * restriction as one operator (chosen at setup when it is faster), that
  * kernel is PRESMOOTH0 and RESTRICT0 records no launches. */
@@ -308,7 +329,8 @@ enum {
     DFAMG_KERNEL_SPMV = 0, DFAMG_KERNEL_PROJECT = 1, DFAMG_KERNEL_UPDATE = 2,
     DFAMG_KERNEL_TEST = 3, DFAMG_KERNEL_PRESMOOTH0 = 4, DFAMG_KERNEL_RESTRICT0 = 5,
     DFAMG_KERNEL_COARSER = 6, DFAMG_KERNEL_PROLONG0 = 7, DFAMG_KERNEL_POSTSMOOTH0 = 8,
-    DFAMG_KERNEL_DIRECTION = 9, DFAMG_KERNEL_COUNT = 10
+    DFAMG_KERNEL_DIRECTION = 9, DFAMG_KERNEL_RESTRICT1 = 10, DFAMG_KERNEL_DEEP = 11,
+    DFAMG_KERNEL_UP1 = 12, DFAMG_KERNEL_COUNT = 13
 };
 
 dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *out);

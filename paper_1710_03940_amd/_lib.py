@@ -25,7 +25,7 @@ PRECOND_AMG, PRECOND_NONE, PRECOND_SPAI0 = 0, 1, 2
 OP_SPMV, OP_PROJECT, OP_PRECOND, OP_RECOVER = 0, 1, 2, 3
 NOALLOC_MAX_N = 512
 KERNEL_NAMES = ["spmv", "project", "update", "test", "presmooth0", "restrict0", "coarser",
-                "prolong0", "postsmooth0", "direction"]
+                "prolong0", "postsmooth0", "direction", "restrict1", "deep", "up1"]
 
 EXPORTED = [
     "dfamg_params_default", "dfamg_setup", "dfamg_setup_batched", "dfamg_solve",
@@ -56,6 +56,7 @@ class Params(ctypes.Structure):
         ("verbose", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("restart", ctypes.c_int32), ("coarse_solve", ctypes.c_int32),
         ("coarse_rtol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
+        ("flexible_cg", ctypes.c_int32), ("npre", ctypes.c_int32), ("npost", ctypes.c_int32),
     ]
 
 

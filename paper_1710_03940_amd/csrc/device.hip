@@ -365,7 +365,13 @@ double time_layout(TuneKind kind, const DevMat<VT> &M, const VT *x, VT *y, hipSt
 // stage of the gathered vector; CSR: 4, 8 or 16 lanes per row, staged or
 // not, for rows of 10+ entries.  The block-diagonal part of the global
 // operator also tries 4 rows per lane and only 256-row CSR tiles.
-// Process-wide record of tuned layouts.
+// Process-wide record of tuned layouts.  When the environment variable
+// DFAMG_TUNE_CACHE names a file, the record also persists across processes:
+// it is read from that file on first use and every newly tuned matrix is
+// appended to it, one line per matrix:
+//   kind value-bytes format structure-hash  fmt par sorted idx16 stage rpg glist  microseconds
+// A matrix found there takes the stored layout without timing, so that the
+// choice (and hence every dispatch) is the same from one process to the next.
 struct TuneKey {
     int kind, vt, format;
     uint64_t hash;
@@ -373,13 +379,61 @@ struct TuneKey {
         return std::tie(kind, vt, format, hash) < std::tie(o.kind, o.vt, o.format, o.hash);
     }
 };
+constexpr const char *kTuneFileTag = "# dfamg tuned layouts v1";
+
+const char *tune_file() {
+    const char *f = std::getenv("DFAMG_TUNE_CACHE");
+    return (f && *f) ? f : nullptr;
+}
+
+// Callers hold tune_cache_mutex().
 std::map<TuneKey, std::pair<Layout, double>> &tune_cache() {
     static std::map<TuneKey, std::pair<Layout, double>> c;
+    static bool loaded = false;
+    if (!loaded) {
+        loaded = true;
+        if (const char *path = tune_file())
+            if (FILE *fp = std::fopen(path, "r")) {
+                char line[512];
+                while (std::fgets(line, sizeof line, fp)) {
+                    if (line[0] == '#') continue;
+                    TuneKey k{};
+                    Layout L{};
+                    unsigned long long h = 0;
+                    int so = 0, i16 = 0, st = 0, gl = 0;
+                    double us = 0.0;
+                    if (std::sscanf(line, "%d %d %d %llx %d %d %d %d %d %d %d %lf", &k.kind, &k.vt, &k.format, &h,
+                                    &L.fmt, &L.par, &so, &i16, &st, &L.rpg, &gl, &us) != 12)
+                        continue;
+                    k.hash = h;
+                    L.sorted = so != 0;
+                    L.idx16 = i16 != 0;
+                    L.stage = st != 0;
+                    L.glist = gl != 0;
+                    c[k] = {L, us};
+                }
+                std::fclose(fp);
+            }
+    }
     return c;
 }
 std::mutex &tune_cache_mutex() {
     static std::mutex m;
     return m;
+}
+
+// Callers hold tune_cache_mutex().
+void tune_cache_store(const TuneKey &k, const Layout &L, double us) {
+    tune_cache()[k] = {L, us};
+    const char *path = tune_file();
+    if (!path) return;
+    FILE *fp = std::fopen(path, "a+");
+    if (!fp) return;   // an unwritable record only costs the timing next time
+    std::fseek(fp, 0, SEEK_END);
+    if (std::ftell(fp) == 0) std::fprintf(fp, "%s\n", kTuneFileTag);
+    std::fprintf(fp, "%d %d %d %llx %d %d %d %d %d %d %d %.3f\n", k.kind, k.vt, k.format, (unsigned long long)k.hash,
+                 L.fmt, L.par, (int)L.sorted, (int)L.idx16, (int)L.stage, L.rpg, (int)L.glist, us);
+    std::fclose(fp);
 }
 
 // Hash of the row ranges, row lengths and columns of the rows covered
@@ -548,7 +602,7 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     }
     if (bestA && cand.size() > 1) {
         std::lock_guard<std::mutex> g(tune_cache_mutex());
-        tune_cache()[key] = {bestL, best};
+        tune_cache_store(key, bestL, best);
     }
     if (!bestA) throw Error{DFAMG_EINVAL, "no sparse layout can hold a matrix"};
     bestM.tuned_us = best;
@@ -734,7 +788,8 @@ enum KernelId {
     KID_SPMV = DFAMG_KERNEL_SPMV, KID_PROJECT = DFAMG_KERNEL_PROJECT, KID_UPDATE = DFAMG_KERNEL_UPDATE,
     KID_TEST = DFAMG_KERNEL_TEST, KID_PRE0 = DFAMG_KERNEL_PRESMOOTH0, KID_RESTRICT0 = DFAMG_KERNEL_RESTRICT0,
     KID_COARSER = DFAMG_KERNEL_COARSER, KID_PROLONG0 = DFAMG_KERNEL_PROLONG0, KID_POST0 = DFAMG_KERNEL_POSTSMOOTH0,
-    KID_DIR = DFAMG_KERNEL_DIRECTION, KID_N = DFAMG_KERNEL_COUNT
+    KID_DIR = DFAMG_KERNEL_DIRECTION, KID_RESTRICT1 = DFAMG_KERNEL_RESTRICT1, KID_DEEP = DFAMG_KERNEL_DEEP,
+    KID_UP1 = DFAMG_KERNEL_UP1, KID_N = DFAMG_KERNEL_COUNT
 };
 
 struct Prof {
@@ -752,9 +807,9 @@ struct Prof {
         used.assign((size_t)n * KID_N, 0);
         for (auto &e : ev) HIP_CHECK(hipEventCreate(&e));
     }
-    int level = 1;                        // 1: outer SpMV only, 2: every span
+    int level = 1;                        // 1: outer SpMV and level-0 restriction, 2: every span
     void mark(int kid, int which, hipStream_t st) {
-        if (!on || (level < 2 && kid != KID_SPMV)) return;
+        if (!on || (level < 2 && kid != KID_SPMV && kid != KID_PRE0)) return;
         hipEvent_t e = ev[((size_t)slot * KID_N + kid) * 2 + which];
         if (capturing) HIP_CHECK(record_in_capture(e, st));
         else HIP_CHECK(hipEventRecord(e, st));
@@ -832,6 +887,8 @@ struct Hierarchy_dev : PrecondBase {
         VT *m = nullptr;
         VT *mb = nullptr, *xpre = nullptr;   // block SPAI-0 rows and the pre-smoothed iterate
         VT *f = nullptr, *res = nullptr, *z = nullptr, *x = nullptr;
+        VT *w = nullptr;          // second iterate buffer of repeated smoothing sweeps
+        VT *xcur = nullptr;       // the pre-smoothed iterate (xpre or w) when npre >= 2
         CoarseEntry *coarse = nullptr;
         CoarseJob *cjobs = nullptr;
         int32_t ncoarse = 0, ncjobs = 0;
@@ -839,6 +896,7 @@ struct Hierarchy_dev : PrecondBase {
     };
     std::vector<Lvl> lv;
     int bs = 1;
+    int npre = 1, npost = 1;             // smoothing sweeps of the V-cycle
     bool block = false;                  // block SPAI-0 smoother
     std::vector<int32_t> sto0;
     int32_t slots0 = 0;
@@ -851,6 +909,8 @@ struct Hierarchy_dev : PrecondBase {
         lv.resize(L);
         block = plan.prm.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0;
         bs = plan.bs;
+        npre = plan.prm.npre;
+        npost = plan.prm.npost;
         const double sv = sizeof(VT), ib = 4.0;
         for (int l = 0; l < L; ++l) {
             const PackedLevel &PL = plan.levels[l];
@@ -880,7 +940,8 @@ struct Hierarchy_dev : PrecondBase {
                     DevArena arR, arB;
                     D.R = upload_tuned<VT>(arR, PL.R, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys, plan.nsys,
                                            plan.nsub, {}, verbose);
-                    if (autotune && !block) {
+                    // B holds exactly one pre-smoothing sweep from the zero guess
+                    if (autotune && !block && npre == 1) {
                         D.B = upload_tuned<VT>(arB, PL.B, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
                                                plan.nsys, plan.nsub, {}, verbose);
                         D.fused = D.B.tuned_us < D.A.tuned_us + D.R.tuned_us;
@@ -903,6 +964,10 @@ struct Hierarchy_dev : PrecondBase {
                 std::vector<VT> m(PL.m.size());
                 for (size_t i = 0; i < m.size(); ++i) m[i] = (VT)PL.m[i];
                 D.m = ar.upload(m, s);
+                if (npre >= 2 || npost >= 2) {
+                    D.xpre = ar.alloc<VT>(PL.nrows);
+                    D.w = ar.alloc<VT>(PL.nrows);
+                }
                 if (block) {
                     std::vector<VT> mb(PL.mb.size());
                     for (size_t i = 0; i < mb.size(); ++i) mb[i] = (VT)PL.mb[i];
@@ -914,11 +979,23 @@ struct Hierarchy_dev : PrecondBase {
                 // the level's right-hand side is FP64 on level 0
                 const double fb = l == 0 ? 8.0 : sv;
                 // pre-smoothing residual and restriction, or both as one operator B
-                const double kb_pre = D.fused ? D.B.nnz * (sv + ib) + n0 * fb + n1 * sv
-                                              : D.A.nnz * (sv + ib) + n0 * (fb + 2.0 * sv);
-                const double kb_res = D.fused ? 0.0 : D.R.nnz * (sv + ib) + n0 * sv + n1 * sv;
-                const double kb_pro = D.P.nnz * (sv + ib) + n0 * (2.0 * sv + fb) + n1 * sv;
-                const double kb_post = D.A.nnz * (sv + ib) + n0 * (2.0 * sv + fb + (l == 0 ? 8.0 : sv));
+                // (one sweep); a sweep x + m (f - A x) reads A, m, f, x and
+                // writes x; the first sweep from zero is x = m o f
+                const double sweep = D.A.nnz * (sv + ib) + n0 * (fb + 3.0 * sv);
+                double kb_pre = D.fused ? D.B.nnz * (sv + ib) + n0 * fb + n1 * sv
+                                        : D.A.nnz * (sv + ib) + n0 * (fb + 2.0 * sv);
+                double kb_res = D.fused ? 0.0 : D.R.nnz * (sv + ib) + n0 * sv + n1 * sv;
+                double kb_pro = D.P.nnz * (sv + ib) + n0 * (2.0 * sv + fb) + n1 * sv;
+                if (npre == 0) {
+                    kb_pre = D.R.nnz * (sv + ib) + n0 * fb + n1 * sv;
+                    kb_res = 0.0;
+                    kb_pro = D.P.nnz * (sv + ib) + n0 * sv + n1 * sv;
+                } else if (npre >= 2) {
+                    kb_pre = n0 * (fb + 2.0 * sv) + (npre - 1) * sweep + D.A.nnz * (sv + ib) + n0 * (fb + 2.0 * sv);
+                    kb_pro = D.P.nnz * (sv + ib) + n0 * 2.0 * sv + n1 * sv;
+                }
+                const double kb_post = (npost - 1) * sweep +
+                                       D.A.nnz * (sv + ib) + n0 * (2.0 * sv + fb + (l == 0 ? 8.0 : sv));
                 if (l == 0) {
                     sto0 = D.A.sys_tile_off;
                     slots0 = D.A.ntiles;
@@ -928,6 +1005,12 @@ struct Hierarchy_dev : PrecondBase {
                     kbytes[KID_POST0] = kb_post;
                 } else {
                     kbytes[KID_COARSER] += kb_pre + kb_res + kb_pro + kb_post;
+                    if (l == 1) {
+                        kbytes[KID_RESTRICT1] = kb_pre + kb_res;
+                        kbytes[KID_UP1] = kb_pro + kb_post;
+                    } else {
+                        kbytes[KID_DEEP] += kb_pre + kb_res + kb_pro + kb_post;
+                    }
                 }
                 bytes += kb_pre + kb_res + kb_pro + kb_post;
             }
@@ -982,7 +1065,10 @@ struct Hierarchy_dev : PrecondBase {
                 for (int nn : ns) nsq += (double)nn * nn;
                 const double cb = nsq * sv + 2.0 * PL.nrows * sv;
                 bytes += cb;
-                if (l > 0) kbytes[KID_COARSER] += cb;
+                if (l > 0) {
+                    kbytes[KID_COARSER] += cb;
+                    kbytes[KID_DEEP] += cb;
+                }
             }
         }
         if (L > 0 && !lv[0].active) {
@@ -1045,6 +1131,43 @@ struct Hierarchy_dev : PrecondBase {
         }
     }
 
+    // Downward step of a level with npre != 1 sweeps: fc = R (f - A x) with x
+    // the pre-smoothed iterate (x = 0 when npre = 0, else x = m o f followed
+    // by npre - 1 sweeps x + m o (f - A x)), kept in D.xcur for the upward step.
+    template <class FT>
+    void down_sweeps(Lvl &D, const FT *f, VT *fc, const SysState *states, const int32_t *sub_sys, hipStream_t st) {
+        if (npre == 0) {
+            launch_restrict<VT, FT>(D.R, f, fc, states, sub_sys, st);
+            D.xcur = nullptr;
+            return;
+        }
+        VT *x = D.xpre, *o = D.w;
+        const int g = (int)std::min<int64_t>(4096, (D.nrows + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_vscale<VT, FT>), dim3(std::max(g, 1)), dim3(kBlock), 0, st, D.nrows, D.m, f, x);
+        for (int k = 1; k < npre; ++k) {
+            launch_post<VT, FT, VT, false>(D.A, D.m, f, x, o, nullptr, states, sub_sys, st);
+            std::swap(x, o);
+        }
+        D.xcur = x;
+        launch_resid<VT, FT>(D.A, f, x, D.res, states, sub_sys, st);
+        launch_spmv<VT>(D.R, D.res, fc, states, sub_sys, st);
+    }
+
+    // Upward step: z = x_pre + P xc, then npost sweeps; the last one writes
+    // `out` (with the (f, out) partials when DOT).
+    template <class FT, class OT, bool DOT>
+    void up_sweeps(Lvl &D, const FT *f, const VT *xc, OT *out, double *part, const SysState *states,
+                   const int32_t *sub_sys, hipStream_t st) {
+        if (npre == 1) launch_prolong<VT, FT>(D.P, D.m, f, xc, D.z, states, sub_sys, st);
+        else launch_prolong_add<VT>(D.P, D.xcur, xc, D.z, states, sub_sys, st);
+        VT *z = D.z, *o = D.w;
+        for (int k = 1; k < npost; ++k) {
+            launch_post<VT, FT, VT, false>(D.A, D.m, f, z, o, nullptr, states, sub_sys, st);
+            std::swap(z, o);
+        }
+        launch_post<VT, FT, OT, DOT>(D.A, D.m, f, z, out, part, states, sub_sys, st);
+    }
+
     void apply(hipStream_t st, const double *r, double *s, double *part, double *part_job,
                const SysState *states, const int32_t *sub_sys, Prof *prof) override {
         if (block) {
@@ -1056,13 +1179,29 @@ struct Hierarchy_dev : PrecondBase {
             if (prof) prof->mark(kid, which, st);
         };
         const dim3 b(kBlock);
+        // spans of the profile: level 0 step by step, level 1 down and up,
+        // and everything deeper (levels >= 2 and the coarsest solves) as one
+        bool deep_open = false;
+        auto open_deep = [&] {
+            if (!deep_open) mark(KID_DEEP, 0);
+            deep_open = true;
+        };
+        auto close_deep = [&] {
+            if (deep_open) mark(KID_DEEP, 1);
+            deep_open = false;
+        };
         // downward: pre-smoothing residuals and restriction
         for (int l = 0; l + 1 < L; ++l) {
             Lvl &D = lv[l];
             if (!D.active) continue;
+            if (l >= 2) open_deep();
+            if (l == 1) mark(KID_RESTRICT1, 0);
             if (l == 0) {
                 mark(KID_PRE0, 0);
-                if (D.fused) {
+                if (npre != 1) {
+                    down_sweeps<double>(D, r, lv[1].f, states, sub_sys, st);
+                    mark(KID_PRE0, 1);
+                } else if (D.fused) {
                     launch_restrict<VT, double>(D.B, r, lv[1].f, states, sub_sys, st);
                     mark(KID_PRE0, 1);
                 } else {
@@ -1073,13 +1212,17 @@ struct Hierarchy_dev : PrecondBase {
                     mark(KID_RESTRICT0, 1);
                 }
                 mark(KID_COARSER, 0);
+            } else if (npre != 1) {
+                down_sweeps<VT>(D, D.f, lv[l + 1].f, states, sub_sys, st);
             } else if (D.fused) {
                 launch_restrict<VT, VT>(D.B, D.f, lv[l + 1].f, states, sub_sys, st);
             } else {
                 launch_pre_res<VT, VT>(D.A, D.m, D.f, D.res, states, sub_sys, st);
                 launch_spmv<VT>(D.R, D.res, lv[l + 1].f, states, sub_sys, st);
             }
+            if (l == 1) mark(KID_RESTRICT1, 1);
         }
+        open_deep();
         // direct solves on every subdomain's coarsest level
         for (int l = 0; l < L; ++l) {
             Lvl &D = lv[l];
@@ -1095,19 +1238,33 @@ struct Hierarchy_dev : PrecondBase {
         for (int l = L - 2; l >= 0; --l) {
             Lvl &D = lv[l];
             if (!D.active) continue;
+            if (l <= 1) close_deep();
             if (l == 0) {
                 mark(KID_COARSER, 1);
-                mark(KID_PROLONG0, 0);
-                launch_prolong<VT, double>(D.P, D.m, r, lv[1].x, D.z, states, sub_sys, st);
-                mark(KID_PROLONG0, 1);
-                mark(KID_POST0, 0);
-                launch_post<VT, double, double, true>(D.A, D.m, r, D.z, s, part, states, sub_sys, st);
-                mark(KID_POST0, 1);
+                if (npre == 1 && npost == 1) {
+                    mark(KID_PROLONG0, 0);
+                    launch_prolong<VT, double>(D.P, D.m, r, lv[1].x, D.z, states, sub_sys, st);
+                    mark(KID_PROLONG0, 1);
+                    mark(KID_POST0, 0);
+                    launch_post<VT, double, double, true>(D.A, D.m, r, D.z, s, part, states, sub_sys, st);
+                    mark(KID_POST0, 1);
+                } else {
+                    mark(KID_POST0, 0);
+                    up_sweeps<double, double, true>(D, r, lv[1].x, s, part, states, sub_sys, st);
+                    mark(KID_POST0, 1);
+                }
             } else {
-                launch_prolong<VT, VT>(D.P, D.m, D.f, lv[l + 1].x, D.z, states, sub_sys, st);
-                launch_post<VT, VT, VT, false>(D.A, D.m, D.f, D.z, D.x, part, states, sub_sys, st);
+                if (l == 1) mark(KID_UP1, 0);
+                if (npre == 1 && npost == 1) {
+                    launch_prolong<VT, VT>(D.P, D.m, D.f, lv[l + 1].x, D.z, states, sub_sys, st);
+                    launch_post<VT, VT, VT, false>(D.A, D.m, D.f, D.z, D.x, part, states, sub_sys, st);
+                } else {
+                    up_sweeps<VT, VT, false>(D, D.f, lv[l + 1].x, D.x, part, states, sub_sys, st);
+                }
+                if (l == 1) mark(KID_UP1, 1);
             }
         }
+        close_deep();
     }
 };
 
@@ -1128,6 +1285,7 @@ struct Handle {
     DevMat<double> A;
     OffM offA{};
     ZView zview{};                          // Z as the operator epilogue reads it
+    double zview_bytes = 0.0;               // bytes of Z in that form (0: read at FP64)
     bool outer_split = false;
     int64_t outer_off_nnz = 0;              // couplings stored apart (split form)
     double outer_layout_bytes = 0.0;
@@ -1246,6 +1404,7 @@ void Handle::setup_device() {
             zview.code = ar.upload(zc.code, sm);
             zview.tab = ar.upload(zc.tab, sm);
             zview.tab_off = ar.upload(zc.tab_off, sm);
+            zview_bytes = (double)zc.code.size() + 8.0 * (double)zc.tab.size() + 4.0 * (double)zc.tab_off.size();
         }
     }
     states = ar.alloc<SysState>(nsys);
@@ -1513,14 +1672,18 @@ void Handle::setup_device() {
     // algorithmic bytes per launch of the profiled kernels and per iteration
     {
         const double nd = (double)n, nnzA = (double)P.nnz;
-        prof.bytes[KID_SPMV] = nnzA * 12.0 + 16.0 * nd + 8.0 * ndv * nd;
+        // CSR of A (values, columns, row pointers), v read, q written, and Z
+        // at the size it is stored in (one-byte codes and per-subdomain
+        // tables when the deflation vectors take few distinct values)
+        const double zbytes = zview.code ? zview_bytes : 8.0 * ndv * nd;
+        prof.bytes[KID_SPMV] = nnzA * 12.0 + 4.0 * (nd + 1.0) + 16.0 * nd + zbytes;
         {
             const double ib = A.fmt == DFAMG_FORMAT_SELL ? (A.idx16 ? 2.0 : 4.0) : 4.0;
             double b = (double)A.stored * (8.0 + ib) + 16.0 * nd;
             if (A.fmt == DFAMG_FORMAT_CSR) b += 4.0 * nd;
             if (A.sorted) b += 2.0 * nd;
             if (outer_split) b += 12.0 * (double)outer_off_nnz + 4.0 * nd;
-            b += (zview.code ? 1.0 : 8.0) * ndv * nd;
+            b += zbytes;
             outer_layout_bytes = b;
         }
         prof.bytes[KID_UPDATE] = 48.0 * nd + 8.0 * ndv * nd + (ndv ? 12.0 * (double)P.AZoff.nnz() + 4.0 * nd : 0.0);
@@ -1531,6 +1694,22 @@ void Handle::setup_device() {
                 if (M->kbytes[k] > 0) prof.bytes[k] = M->kbytes[k];
         bytes_iter = prof.bytes[KID_SPMV] + prof.bytes[KID_UPDATE] + prof.bytes[KID_PROJECT] + prof.bytes[KID_DIR];
         bytes_iter += M ? M->bytes : 16.0 * nd;
+        if (prm.solver == DFAMG_SOLVER_BICGSTAB) {
+            // two operator products, each followed by the projection and the
+            // AZ correction (q, other vector and AZ read, result written), two
+            // preconditioner applications, and the vector kernels: p = r +
+            // beta (p - omega v) (r, v, p read, p written), s = r - alpha v
+            // (r, v read, s written), y += alpha p^ + omega s^ and
+            // r = s - omega t with its dots (y, p^, s^, s, t, r~ read; y, r
+            // written)
+            const double azb = 8.0 * ndv * nd + (ndv ? 12.0 * (double)P.AZoff.nnz() + 4.0 * nd : 0.0);
+            prof.bytes[KID_UPDATE] = 64.0 * nd;
+            bytes_iter = 2.0 * (prof.bytes[KID_SPMV] + prof.bytes[KID_PROJECT] + (M ? M->bytes : 16.0 * nd) +
+                                24.0 * nd + azb) +
+                         32.0 * nd + 24.0 * nd + prof.bytes[KID_UPDATE];
+        } else if (prm.solver == DFAMG_SOLVER_BICGSTAB2) {
+            bytes_iter = 0.0;   // not modelled
+        }
         if (fgmres()) {
             // one Arnoldi step at the cycle's mean basis size J = (m + 1) / 2:
             // f = sc (V_j - AZ t2) reads V_j, AZ and writes f; the Gram-Schmidt
@@ -1633,8 +1812,14 @@ void Handle::iteration(hipStream_t st) {
     prof.mark(KID_PROJECT, 1, st);
     prof.mark(KID_UPDATE, 0, st);
     with_ndv(ndv(), [&](auto c) {
-        hipLaunchKernelGGL((k_update<0, decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, p, q, y, r, AZown, ndv(),
-                           AZoffp, AZoffc, AZoffv, t2, part_rows, states, d_sub_sys, psub, tt_part, ranges());
+        if (prm.flexible_cg)
+            hipLaunchKernelGGL((k_update<3, decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, p, q, y, r, AZown,
+                               ndv(), AZoffp, AZoffc, AZoffv, t2, part_rows, states, d_sub_sys, psub, tt_part,
+                               ranges(), s);
+        else
+            hipLaunchKernelGGL((k_update<0, decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, p, q, y, r, AZown,
+                               ndv(), AZoffp, AZoffc, AZoffv, t2, part_rows, states, d_sub_sys, psub, tt_part,
+                               ranges(), nullptr);
     });
     prof.mark(KID_UPDATE, 1, st);
     prof.mark(KID_TEST, 0, st);
@@ -1643,8 +1828,12 @@ void Handle::iteration(hipStream_t st) {
     prof.mark(KID_TEST, 1, st);
     precond(st, r, s, true);
     prof.mark(KID_DIR, 0, st);
-    hipLaunchKernelGGL(k_rho<0>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
-                       d_sys_cjob_off0, states);
+    if (prm.flexible_cg)
+        hipLaunchKernelGGL(k_rho_flexible, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
+                           d_sys_cjob_off0, part_rows + nrow_tiles, d_sto_rows, states);
+    else
+        hipLaunchKernelGGL(k_rho<0>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
+                           d_sys_cjob_off0, states);
     hipLaunchKernelGGL(k_cg_direction<false>, gr, bl, 0, st, rows, nrow_tiles, s, p, states, d_sub_sys);
     prof.mark(KID_DIR, 1, st);
 }
@@ -1844,7 +2033,7 @@ void Handle::initial(hipStream_t st) {
     with_ndv(ndv(), [&](auto c) {
         hipLaunchKernelGGL((k_update<1, decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, nullptr, w, nullptr, r,
                            AZown, ndv(), AZoffp, AZoffc, AZoffv, t2, part_rows, states, d_sub_sys, psub, tt_part,
-                           ranges());
+                           ranges(), nullptr);
     });
     hipLaunchKernelGGL(k_residual_test<1>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rows, d_sto_rows, states, hist,
                        hist_stride, prm.rtol, prm.maxiter, nullptr, psub, ranges());
@@ -2073,7 +2262,7 @@ void Handle::apply_op(int op, const double *in, double *out) {
             with_ndv(ndv(), [&](auto c) {
                 hipLaunchKernelGGL((k_update<2, decltype(c)::value>), gr, bl, 0, st, rows, nrow_tiles, nullptr, w,
                                    nullptr, x, AZown, ndv(), AZoffp, AZoffc, AZoffv, t2, part_rows, states, d_sub_sys,
-                                   psub, tt_part, ranges());
+                                   psub, tt_part, ranges(), nullptr);
             });
             break;
         case DFAMG_OP_PRECOND:
@@ -2346,6 +2535,9 @@ void dfamg_params_default(dfamg_params *p) {
     p->coarse_solve = DFAMG_COARSE_EXACT;
     p->coarse_rtol = 1e-2;
     p->coarse_maxiter = 100;
+    p->flexible_cg = 0;
+    p->npre = 1;
+    p->npost = 1;
 }
 
 dfamg_status dfamg_setup(const dfamg_params *prm, int64_t n, const int64_t *row_ptr, const int32_t *col,

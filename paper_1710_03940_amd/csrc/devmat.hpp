@@ -117,6 +117,14 @@ void launch_prolong(const DevMat<VT> &P, const VT *m, const FT *f, const VT *xc,
 template <class VT, class FT, class OT, bool DOT>
 void launch_post(const DevMat<VT> &A, const VT *m, const FT *f, const VT *z, OT *x, double *part,
                  const SysState *st, const int32_t *sub_sys, hipStream_t s);
+// res = f - A x and z = x + P xc (x may be null) for V-cycles with other
+// than one pre-smoothing sweep
+template <class VT, class FT>
+void launch_resid(const DevMat<VT> &A, const FT *f, const VT *x, VT *res, const SysState *st,
+                  const int32_t *sub_sys, hipStream_t s);
+template <class VT>
+void launch_prolong_add(const DevMat<VT> &P, const VT *x, const VT *xc, VT *z, const SysState *st,
+                        const int32_t *sub_sys, hipStream_t s);
 
 // ---- outer operator (launch_outer.hip) -----------------------------------
 // A: block-diagonal part, off: couplings between subdomains (see OffM).

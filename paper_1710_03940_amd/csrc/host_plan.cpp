@@ -718,6 +718,57 @@ HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes,
 
 namespace {
 
+// Storage order of the levels of one subdomain's hierarchy on the device:
+// ord[l][new row] = row of level l in the hierarchy's numbering, pos[l] its
+// inverse.  Level 0 and the coarsest level keep their numbering; on every
+// level in between the nodes are grouped by their aggregate on the next
+// level, the aggregates taken in that level's storage order (recursively),
+// the nodes of one aggregate in ascending index and nodes in no aggregate
+// last; the rows of a point-block node stay together.  Renumbering every
+// coarse level consistently leaves the V-cycle the same linear map (only the
+// order of summation inside a row changes); what it changes is which
+// unknowns sit next to each other: a tile of consecutive rows of the
+// restriction then covers a compact cluster of the finer level, so the
+// finer vector entries that the tile reads overlap far more.
+void level_orders(const Hierarchy &H, int bs, std::vector<std::vector<int64_t>> &ord,
+                  std::vector<std::vector<int64_t>> &pos) {
+    const int L = H.nlevels();
+    std::vector<std::vector<int64_t>> node(L);   // node order per level
+    for (int l = L - 1; l >= 0; --l) {
+        const int64_t nn = H.lv[l].A.nrows / bs;
+        std::vector<int64_t> &o = node[l];
+        if (l == 0 || l == L - 1) {
+            o.resize(nn);
+            std::iota(o.begin(), o.end(), 0);
+            continue;
+        }
+        const std::vector<int32_t> &agg = H.lv[l].agg;
+        const int64_t nc = (int64_t)node[l + 1].size();
+        std::vector<int64_t> start(nc + 1, 0);
+        for (int64_t i = 0; i < nn; ++i)
+            if (agg[i] >= 0) start[agg[i] + 1]++;
+        for (int64_t c = 0; c < nc; ++c) start[c + 1] += start[c];
+        std::vector<int64_t> kids(start[nc]), fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < nn; ++i)
+            if (agg[i] >= 0) kids[fill[agg[i]]++] = i;   // ascending within an aggregate
+        o.reserve(nn);
+        for (int64_t c : node[l + 1])
+            for (int64_t k = start[c]; k < start[c + 1]; ++k) o.push_back(kids[k]);
+        for (int64_t i = 0; i < nn; ++i)
+            if (agg[i] < 0) o.push_back(i);
+    }
+    ord.assign(L, {});
+    pos.assign(L, {});
+    for (int l = 0; l < L; ++l) {
+        const int64_t nr = H.lv[l].A.nrows;
+        ord[l].resize(nr);
+        pos[l].resize(nr);
+        for (int64_t k = 0; k < (int64_t)node[l].size(); ++k)
+            for (int b = 0; b < bs; ++b) ord[l][k * bs + b] = node[l][k] * bs + b;
+        for (int64_t r = 0; r < nr; ++r) pos[l][ord[l][r]] = r;
+    }
+}
+
 void validate_params(const dfamg_params &p) {
     if (p.solver != DFAMG_SOLVER_CG && p.solver != DFAMG_SOLVER_BICGSTAB && p.solver != DFAMG_SOLVER_BICGSTAB2 &&
         p.solver != DFAMG_SOLVER_FGMRES)
@@ -749,6 +800,12 @@ void validate_params(const dfamg_params &p) {
         fail(DFAMG_EINVAL, "unknown precond");
     if (p.spmv_format < DFAMG_FORMAT_AUTO || p.spmv_format > DFAMG_FORMAT_CSR_GATHER) fail(DFAMG_EINVAL, "unknown spmv_format");
     if (p.graph_iters < 0) fail(DFAMG_EINVAL, "graph_iters must be >= 0");
+    if (p.flexible_cg != 0 && p.flexible_cg != 1) fail(DFAMG_EINVAL, "flexible_cg must be 0 or 1");
+    if (p.flexible_cg && p.solver != DFAMG_SOLVER_CG) fail(DFAMG_EINVAL, "flexible_cg needs solver = CG");
+    if (p.npre < 0 || p.npre > 4) fail(DFAMG_EINVAL, "npre must be in [0, 4]");
+    if (p.npost < 1 || p.npost > 4) fail(DFAMG_EINVAL, "npost must be in [1, 4]");
+    if ((p.npre != 1 || p.npost != 1) && p.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0)
+        fail(DFAMG_EINVAL, "the block SPAI-0 smoother supports npre = npost = 1 only");
 }
 
 // Rank of the local block of one subdomain (rows x ndv, row-major) by
@@ -1032,6 +1089,11 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
         });
     }
 
+    // storage order of every subdomain's levels (identity on level 0 and on
+    // the coarsest level)
+    std::vector<std::vector<std::vector<int64_t>>> ord(nsub), pos(nsub);
+    parallel_for(nsub, threads, [&](int64_t s) { level_orders(plan.hier[s], bs, ord[s], pos[s]); });
+
     // packed levels
     plan.nlevels_max = 0;
     for (auto &H : plan.hier) plan.nlevels_max = std::max(plan.nlevels_max, H.nlevels());
@@ -1064,27 +1126,35 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
         PL.P.ptr.assign(PL.nrows + 1, 0);
         PL.m.assign(PL.nrows, 0.0);
         if (prm.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0) PL.mb.assign((size_t)PL.nrows * bs, 0.0);
+        std::vector<std::pair<int32_t, double>> row;
+        // one renumbered row: columns through `cpos`, shifted by `coff`, ascending
+        auto put_row = [&](const Csr &M, int64_t i, const std::vector<int64_t> &cpos, int64_t coff, Csr &out) {
+            row.clear();
+            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k)
+                row.emplace_back((int32_t)(cpos[M.col[k]] + coff), M.val[k]);
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                          return a.first < b.first;
+                      });
+            for (auto &e : row) {
+                out.col.push_back(e.first);
+                out.val.push_back(e.second);
+            }
+        };
         for (int s = 0; s < nsub; ++s) {
             if (PL.sub_off[s] < 0) continue;
             const Hierarchy &H = plan.hier[s];
             const bool active = H.nlevels() - 1 > l;
             const int64_t o = PL.sub_off[s];
+            const std::vector<int64_t> &od = ord[s][l];
             for (int64_t i = 0; i < PL.sub_len[s]; ++i) {
                 if (active) {
-                    const Csr &M = H.lv[l].A;
-                    for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
-                        PL.A.col.push_back((int32_t)(M.col[k] + o));
-                        PL.A.val.push_back(M.val[k]);
-                    }
-                    const Csr &P = H.lv[l].P;
-                    const int64_t oc = plan.levels[l + 1].sub_off[s];
-                    for (int64_t k = P.ptr[i]; k < P.ptr[i + 1]; ++k) {
-                        PL.P.col.push_back((int32_t)(P.col[k] + oc));
-                        PL.P.val.push_back(P.val[k]);
-                    }
-                    PL.m[o + i] = H.lv[l].m[i];
+                    const int64_t io = od[i];   // the row in the hierarchy's own numbering
+                    put_row(H.lv[l].A, io, pos[s][l], o, PL.A);
+                    put_row(H.lv[l].P, io, pos[s][l + 1], plan.levels[l + 1].sub_off[s], PL.P);
+                    PL.m[o + i] = H.lv[l].m[io];
                     if (!H.lv[l].mb.empty())
-                        for (int k = 0; k < bs; ++k) PL.mb[(size_t)(o + i) * bs + k] = H.lv[l].mb[(size_t)i * bs + k];
+                        for (int k = 0; k < bs; ++k) PL.mb[(size_t)(o + i) * bs + k] = H.lv[l].mb[(size_t)io * bs + k];
                 }
                 PL.A.ptr[o + i + 1] = (int64_t)PL.A.col.size();
                 PL.P.ptr[o + i + 1] = (int64_t)PL.P.col.size();
@@ -1096,25 +1166,27 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
         PL.B.ncols = PL.nrows;
         PL.B.ptr.assign(ncoarse + 1, 0);
         if (has_next) {
+            // rows of the next level in its storage order
             for (int s = 0; s < nsub; ++s) {
                 if (PL.sub_off[s] < 0 || plan.hier[s].nlevels() - 1 <= l) continue;
                 const Csr &Bs = plan.hier[s].lv[l].B;
                 const int64_t oc = plan.levels[l + 1].sub_off[s];
-                for (int64_t k = 0; k < Bs.nrows; ++k) PL.B.ptr[oc + k + 1] = Bs.ptr[k + 1] - Bs.ptr[k];
+                const std::vector<int64_t> &odc = ord[s][l + 1];
+                for (int64_t k = 0; k < Bs.nrows; ++k) PL.B.ptr[oc + k + 1] = Bs.ptr[odc[k] + 1] - Bs.ptr[odc[k]];
             }
             for (int64_t k = 0; k < ncoarse; ++k) PL.B.ptr[k + 1] += PL.B.ptr[k];
-            PL.B.col.resize(PL.B.ptr[ncoarse]);
-            PL.B.val.resize(PL.B.ptr[ncoarse]);
+            PL.B.col.clear();
+            PL.B.val.clear();
+            PL.B.col.reserve(PL.B.ptr[ncoarse]);
+            PL.B.val.reserve(PL.B.ptr[ncoarse]);
             for (int s = 0; s < nsub; ++s) {
                 if (PL.sub_off[s] < 0 || plan.hier[s].nlevels() - 1 <= l) continue;
                 const Csr &Bs = plan.hier[s].lv[l].B;
                 const int64_t o = PL.sub_off[s], oc = plan.levels[l + 1].sub_off[s];
+                const std::vector<int64_t> &odc = ord[s][l + 1];
                 for (int64_t k = 0; k < Bs.nrows; ++k) {
-                    int64_t d = PL.B.ptr[oc + k];
-                    for (int64_t e = Bs.ptr[k]; e < Bs.ptr[k + 1]; ++e, ++d) {
-                        PL.B.col[d] = (int32_t)(Bs.col[e] + o);
-                        PL.B.val[d] = Bs.val[e];
-                    }
+                    if ((int64_t)PL.B.col.size() != PL.B.ptr[oc + k]) fail(DFAMG_EINVAL, "internal: B packing order");
+                    put_row(Bs, odc[k], pos[s][l], o, PL.B);
                 }
             }
         }

@@ -477,6 +477,8 @@ __device__ __forceinline__ double cg_curvature(const double *__restrict__ psub, 
 // MODE 0 (CG): alpha = rho / (p,PAp); w = q - AZ t2; y += alpha p; r -= alpha w; partial (r,r)
 // MODE 1 (init): r = w - AZ t2; partial (r,r)
 // MODE 2 (projection only): out = v - AZ t2
+// MODE 3 (flexible CG): MODE 0 and the partial (r, s) of the new residual with
+//         the previous preconditioned residual s, in part[ntiles + slot]
 template <int MODE, int NDV>
 __global__ void __launch_bounds__(kBlock) k_update(
     const DevTile *__restrict__ tiles, int32_t ntiles, const double *__restrict__ p, const double *__restrict__ q,
@@ -484,7 +486,8 @@ __global__ void __launch_bounds__(kBlock) k_update(
     const int32_t *__restrict__ offp, const int32_t *__restrict__ offc, const double *__restrict__ offv,
     const double *__restrict__ t2, double *__restrict__ part, SysState *__restrict__ st,
     const int32_t *__restrict__ sub_sys, const double *__restrict__ psub, const double *__restrict__ tt_part,
-    SysRanges R) {
+    SysRanges R, const double *__restrict__ s_prev) {
+    constexpr bool CG = MODE == 0 || MODE == 3;
     __shared__ double lds[4];
     __shared__ double alpha_s;
     const int tile = tile_of_block(ntiles);
@@ -492,16 +495,16 @@ __global__ void __launch_bounds__(kBlock) k_update(
     const DevTile T = tiles[tile];
     const int sys = sub_sys[T.sub];
     SysState &S = st[sys];
-    if (MODE == 0 && S.done) return;
-    if (MODE == 0) {
+    if (CG && S.done) return;
+    if (CG) {
         if (threadIdx.x < 64) {
             const double pq = cg_curvature(psub, tt_part, R, sys);
             if (threadIdx.x == 0) alpha_s = S.rho / pq;
         }
         __syncthreads();
     }
-    const double a = MODE == 0 ? alpha_s : 0.0;
-    double rr = 0.0;
+    const double a = CG ? alpha_s : 0.0;
+    double rr = 0.0, rs = 0.0;
     const int ndv = ndv_rt;   // <= NDV, the unroll bound
     double t2s[NDV > 0 ? NDV : 1];
 #pragma unroll
@@ -509,12 +512,13 @@ __global__ void __launch_bounds__(kBlock) k_update(
     for_tile_rows(T, [&](int row) {
         // every load that does not depend on another is issued first
         const double qv = stream_load(q + row);
-        double pv = 0.0, yv = 0.0, rv = 0.0;
-        if (MODE == 0) {
+        double pv = 0.0, yv = 0.0, rv = 0.0, sv = 0.0;
+        if (CG) {
             pv = stream_load(p + row);
             yv = y[row];
             rv = r[row];
         }
+        if (MODE == 3) sv = stream_load(s_prev + row);
         int e = 0, e1 = 0;
         if (ndv > 0) {
             e = offp[row];
@@ -545,11 +549,12 @@ __global__ void __launch_bounds__(kBlock) k_update(
         }
         for (; e < e1; ++e) corr += offv[e] * t2[offc[e]];
         const double wv = qv - corr;
-        if (MODE == 0) {
+        if (CG) {
             y[row] = yv + a * pv;
             const double rn = rv - a * wv;
             r[row] = rn;
             rr += rn * rn;
+            if (MODE == 3) rs += rn * sv;
         } else if (MODE == 1) {
             r[row] = wv;
             rr += wv * wv;
@@ -560,6 +565,11 @@ __global__ void __launch_bounds__(kBlock) k_update(
     if (MODE == 2) return;
     const double s = block_sum(rr, lds, kBlock);
     if (threadIdx.x == 0) part[T.slot] = s;
+    if (MODE == 3) {
+        __syncthreads();
+        const double s2 = block_sum(rs, lds, kBlock);
+        if (threadIdx.x == 0) part[ntiles + T.slot] = s2;
+    }
 }
 
 // x = y + Z t2 (solution recovery, x = y + Z lambda)
@@ -652,6 +662,30 @@ __global__ void __launch_bounds__(kWideBlock) k_rho(const double *__restrict__ p
     const double rs = block_sum(a, lds, kWideBlock);
     if (threadIdx.x == 0) {
         S.beta = MODE == 0 ? rs / S.rho : 0.0;
+        S.rho = rs;
+    }
+}
+
+// Flexible CG: rho' = (r, s) as in k_rho, and with (r, s_prev) from the
+// update's second partials beta = (rho' - (r, s_prev)) / rho (Polak-Ribiere)
+static __global__ void __launch_bounds__(kWideBlock) k_rho_flexible(
+    const double *__restrict__ part, const int32_t *__restrict__ sys_tile_off, const double *__restrict__ part_job,
+    const int32_t *__restrict__ sys_job_off, const double *__restrict__ part_prev,
+    const int32_t *__restrict__ sys_row_tile_off, SysState *__restrict__ st) {
+    __shared__ double lds[16];
+    const int sys = blockIdx.x;
+    SysState &S = st[sys];
+    if (S.done) return;
+    double a = 0.0, b = 0.0;
+    for (int tl = sys_tile_off[sys] + threadIdx.x; tl < sys_tile_off[sys + 1]; tl += kWideBlock) a += part[tl];
+    for (int j = sys_job_off[sys] + threadIdx.x; j < sys_job_off[sys + 1]; j += kWideBlock) a += part_job[j];
+    for (int tl = sys_row_tile_off[sys] + threadIdx.x; tl < sys_row_tile_off[sys + 1]; tl += kWideBlock)
+        b += part_prev[tl];
+    const double rs = block_sum(a, lds, kWideBlock);
+    __syncthreads();
+    const double rsp = block_sum(b, lds, kWideBlock);
+    if (threadIdx.x == 0) {
+        S.beta = (rs - rsp) / S.rho;
         S.rho = rs;
     }
 }
@@ -1201,6 +1235,40 @@ __global__ void __launch_bounds__(kBlock) k_prolong(MAT P, const VT *__restrict_
     if (st && st[sub_sys[T.sub]].done) return;
     for_rows<VT>(P, tile, T, [&](int c) { return xc[c]; },
                  [&](int row, VT px) { z[row] = m[row] * (VT)f[row] + px; });
+}
+
+// Kernels of V-cycles with other than one pre-smoothing sweep: the first
+// sweep from the zero guess x = m o f, the residual of an explicit iterate
+// res = f - A x, and the coarse correction of an explicit iterate z = x + P xc
+// (x == nullptr: z = P xc, no pre-smoothing).
+template <class VT, class FT>
+__global__ void __launch_bounds__(kBlock) k_vscale(int64_t n, const VT *__restrict__ m, const FT *__restrict__ f,
+                                                   VT *__restrict__ x) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        x[i] = m[i] * (VT)f[i];
+}
+
+template <class VT, class FT, class MAT>
+__global__ void __launch_bounds__(kBlock) k_resid(MAT A, const FT *__restrict__ f, const VT *__restrict__ x,
+                                                  VT *__restrict__ res, const SysState *__restrict__ st,
+                                                  const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(A.ntiles);
+    if (tile >= A.ntiles) return;
+    const DevTile T = A.tiles[tile];
+    if (st && st[sub_sys[T.sub]].done) return;
+    for_rows<VT>(A, tile, T, [&](int c) { return x[c]; }, [&](int row, VT ax) { res[row] = (VT)f[row] - ax; });
+}
+
+template <class VT, class MAT>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(MAT P, const VT *__restrict__ x, const VT *__restrict__ xc,
+                                                        VT *__restrict__ z, const SysState *__restrict__ st,
+                                                        const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(P.ntiles);
+    if (tile >= P.ntiles) return;
+    const DevTile T = P.tiles[tile];
+    if (st && st[sub_sys[T.sub]].done) return;
+    for_rows<VT>(P, tile, T, [&](int c) { return xc[c]; },
+                 [&](int row, VT px) { z[row] = (x ? x[row] : (VT)0) + px; });
 }
 
 // x = z + m o (f - A z)   (post-smoothing); DOT: partial (f, x) per tile

@@ -50,7 +50,29 @@ void launch_post(const DevMat<VT> &A, const VT *m, const FT *f, const VT *z, OT 
     });
 }
 
+template <class VT, class FT>
+void launch_resid(const DevMat<VT> &A, const FT *f, const VT *x, VT *res, const SysState *st,
+                  const int32_t *sub_sys, hipStream_t s) {
+    with_mat(A, [&](auto v) {
+        hipLaunchKernelGGL((k_resid<VT, FT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
+                           A.stage_bytes(), s, v, f, x, res, st, sub_sys);
+    });
+}
+
+template <class VT>
+void launch_prolong_add(const DevMat<VT> &P, const VT *x, const VT *xc, VT *z, const SysState *st,
+                        const int32_t *sub_sys, hipStream_t s) {
+    with_mat(P, [&](auto v) {
+        hipLaunchKernelGGL((k_prolong_add<VT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
+                           P.stage_bytes(), s, v, x, xc, z, st, sub_sys);
+    });
+}
+
 #ifdef DFAMG_VT_DOUBLE
+template void launch_resid<double, double>(const DevMat<double> &, const double *, const double *, double *,
+                                           const SysState *, const int32_t *, hipStream_t);
+template void launch_prolong_add<double>(const DevMat<double> &, const double *, const double *, double *,
+                                         const SysState *, const int32_t *, hipStream_t);
 template void launch_pre_res<double, double>(const DevMat<double> &, const double *, const double *, double *,
                                              const SysState *, const int32_t *, hipStream_t);
 template void launch_restrict<double, double>(const DevMat<double> &, const double *, double *, const SysState *,
@@ -66,6 +88,15 @@ template void launch_post<double, double, double, false>(const DevMat<double> &,
                                                          const double *, double *, double *, const SysState *,
                                                          const int32_t *, hipStream_t);
 #else
+template void launch_resid<float, float>(const DevMat<float> &, const float *, const float *, float *,
+                                         const SysState *, const int32_t *, hipStream_t);
+template void launch_resid<float, double>(const DevMat<float> &, const double *, const float *, float *,
+                                          const SysState *, const int32_t *, hipStream_t);
+template void launch_prolong_add<float>(const DevMat<float> &, const float *, const float *, float *,
+                                        const SysState *, const int32_t *, hipStream_t);
+template void launch_post<float, double, float, false>(const DevMat<float> &, const float *, const double *,
+                                                       const float *, float *, double *, const SysState *,
+                                                       const int32_t *, hipStream_t);
 template void launch_pre_res<float, float>(const DevMat<float> &, const float *, const float *, float *,
                                            const SysState *, const int32_t *, hipStream_t);
 template void launch_pre_res<float, double>(const DevMat<float> &, const float *, const double *, float *,

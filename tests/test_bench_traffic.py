@@ -1,7 +1,8 @@
-"""Host logic of the benchmark: the HBM traffic figure, i.e. the FETCH_SIZE /
-WRITE_SIZE counter values per dispatch (KiB) of the outer SpMV scaled by what
-the same counters read for a copy kernel of known size (synthetic counter
-files), and the refusal of runs on more than one GPU."""
+"""Host logic of the benchmark: the HBM traffic figures, i.e. the FETCH_SIZE /
+WRITE_SIZE counter values per dispatch (KiB) of the outer SpMV and of the
+level-0 restriction scaled by what the same counters read for a copy kernel of
+known size (synthetic counter files), kept only for the layout they were
+taken on, and the refusal of runs on more than one GPU."""
 import csv
 import json
 import os
@@ -14,42 +15,84 @@ import bench  # noqa: E402
 
 def _csv(path, rows):
     with open(path, "w", newline="") as fh:
-        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
         w.writeheader()
         for r in rows:
             w.writerow(r)
     return str(path)
 
 
-def test_traffic_scaled_by_copy_calibration(tmp_path, monkeypatch):
+def _rows(name, grid, counter, value, count):
+    return [{"Kernel_Name": name, "Grid_Size": grid, "Counter_Name": counter, "Counter_Value": value}] * count
+
+
+LAYOUT_TEXT = ("outer sell1/i32; L0{A sell2/i16/stage, B csr16/t64/glist, P sell2/i16/sorted/stage} "
+               "L1{A sell1/i16/sorted/stage, B csr16/t64/glist, P sell2/i16/sorted/stage}")
+
+
+def test_parse_layouts():
+    lay = bench.parse_layouts(LAYOUT_TEXT)
+    assert lay == {"spmv": "sell1/i32", "presmooth0": "B csr16/t64/glist",
+                   "prolong0": "P sell2/i16/sorted/stage", "postsmooth0": "A sell2/i16/stage"}
+    unfused = bench.parse_layouts("outer csr8; L0{A sell1/i32, R csr16/t64/glist, P sell1/i32}")
+    assert unfused["presmooth0"] == "A sell1/i32"
+
+
+def _traffic(tmp_path, monkeypatch):
     kib = bench.COPY_BYTES / 1024.0
-    copy_f = _csv(tmp_path / "cf.csv", [{"Kernel_Name": "at::native::elementwise_kernel", "Counter_Name":
-                                        "FETCH_SIZE", "Counter_Value": kib / 2.0}] * 3)
-    copy_w = _csv(tmp_path / "cw.csv", [{"Kernel_Name": "at::native::elementwise_kernel", "Counter_Name":
-                                        "WRITE_SIZE", "Counter_Value": kib}] * 3)
-    loop = "void dfamg::k_outer<0, 4, dfamg::SellM<double, 1, false, false> >(...)"
-    tuned = "void dfamg::k_outer<0, 4, dfamg::SellM<double, 2, false, false> >(...)"
-    # in-loop launches: 150,000 KiB fetched, 20,000 written; skipped launches
-    # after convergence read almost nothing; the tuner's candidate launches
-    # of another layout are fewer and must not count
-    fetch = ([{"Kernel_Name": loop, "Counter_Name": "FETCH_SIZE", "Counter_Value": 150000.0}] * 9 +
-             [{"Kernel_Name": loop, "Counter_Name": "FETCH_SIZE", "Counter_Value": 3.0}] * 4 +
-             [{"Kernel_Name": tuned, "Counter_Name": "FETCH_SIZE", "Counter_Value": 999999.0}] * 2)
-    write = ([{"Kernel_Name": loop, "Counter_Name": "WRITE_SIZE", "Counter_Value": 20000.0}] * 9 +
-             [{"Kernel_Name": loop, "Counter_Name": "WRITE_SIZE", "Counter_Value": 1.0}] * 4 +
-             [{"Kernel_Name": tuned, "Counter_Name": "WRITE_SIZE", "Counter_Value": 888888.0}] * 2)
+    copy_f = _csv(tmp_path / "cf.csv", _rows("at::native::elementwise_kernel", 1, "FETCH_SIZE", kib / 2.0, 3))
+    copy_w = _csv(tmp_path / "cw.csv", _rows("at::native::elementwise_kernel", 1, "WRITE_SIZE", kib, 3))
+    loop = "k_outer<0, 4, dfamg::SellM<double, 1, false, false> >(...)"
+    tuned = "k_outer<0, 4, dfamg::SellM<double, 2, false, false> >(...)"
+    restr = "k_restrict<double, double, dfamg::CsrM<double, 16, true> >(...)"
+    # outer: in-loop launches 150,000 KiB fetched / 20,000 written; skipped
+    # launches after convergence read almost nothing; the tuner's candidate
+    # launches of another layout are fewer and must not count.
+    # restriction: one instance per level (level 0 has the largest grid);
+    # level 1's launches are as many as level 0's but must not count
+    fetch = (_rows(loop, 540000, "FETCH_SIZE", 150000.0, 9) + _rows(loop, 540000, "FETCH_SIZE", 3.0, 4) +
+             _rows(tuned, 270000, "FETCH_SIZE", 999999.0, 2) +
+             _rows(restr, 2160000, "FETCH_SIZE", 200000.0, 9) + _rows(restr, 290000, "FETCH_SIZE", 50000.0, 9) +
+             _rows(restr, 9000000, "FETCH_SIZE", 777777.0, 2))
+    write = (_rows(loop, 540000, "WRITE_SIZE", 20000.0, 9) + _rows(loop, 540000, "WRITE_SIZE", 1.0, 4) +
+             _rows(tuned, 270000, "WRITE_SIZE", 888888.0, 2) +
+             _rows(restr, 2160000, "WRITE_SIZE", 4000.0, 9) + _rows(restr, 290000, "WRITE_SIZE", 600.0, 9) +
+             _rows(restr, 9000000, "WRITE_SIZE", 666666.0, 2))
     sf = _csv(tmp_path / "sf.csv", fetch)
     sw = _csv(tmp_path / "sw.csv", write)
+    lay = tmp_path / "layouts.json"
+    lay.write_text(json.dumps({"fp64": bench.parse_layouts(LAYOUT_TEXT)}))
     out = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
-    assert bench.write_traffic(sf, sw, copy_f, copy_w) == 0
-    t = json.load(open(out))
-    assert abs(t["copy_scale_fetch"] - 2.0) < 1e-12 and abs(t["copy_scale_write"] - 1.0) < 1e-12
-    assert t["launches_counted"] == [9, 9]
-    assert abs(t["fetch_bytes"] - 150000.0 * 2.0 * 1024.0) < 1e-3
-    assert abs(t["write_bytes"] - 20000.0 * 1024.0) < 1e-3
-    assert abs(t["bytes_per_launch"] - (t["fetch_bytes"] + t["write_bytes"])) < 1e-3
-    assert t["kernel_source_hash"] == bench.kernel_source_hash()
+    assert bench.write_traffic(sf, sw, copy_f, copy_w, str(lay)) == 0
+    return json.load(open(out))
+
+
+def test_traffic_scaled_by_copy_calibration(tmp_path, monkeypatch):
+    t = _traffic(tmp_path, monkeypatch)["kernels"]
+    o = t["spmv"]
+    assert abs(o["copy_scale_fetch"] - 2.0) < 1e-12 and abs(o["copy_scale_write"] - 1.0) < 1e-12
+    assert o["launches_counted"] == [9, 9] and o["grid"] == 540000
+    assert abs(o["fetch_bytes"] - 150000.0 * 2.0 * 1024.0) < 1e-3
+    assert abs(o["write_bytes"] - 20000.0 * 1024.0) < 1e-3
+    assert abs(o["bytes_per_launch"] - (o["fetch_bytes"] + o["write_bytes"])) < 1e-3
+    assert o["kernel_source_hash"] == bench.kernel_source_hash()
+    assert o["layout"] == "sell1/i32"
+    r = t["presmooth0"]
+    assert r["grid"] == 2160000 and r["launches_counted"] == [9, 9]
+    assert abs(r["fetch_bytes"] - 200000.0 * 2.0 * 1024.0) < 1e-3
+    assert abs(r["write_bytes"] - 4000.0 * 1024.0) < 1e-3
+    assert r["layout"] == "B csr16/t64/glist"
+
+
+def test_traffic_dropped_when_layout_differs(tmp_path, monkeypatch):
+    _traffic(tmp_path, monkeypatch)
+    same = bench.parse_layouts(LAYOUT_TEXT)
+    assert bench.load_traffic("spmv", same) is not None
+    assert bench.load_traffic("presmooth0", same) is not None
+    other = dict(same, spmv="sell2/i16/stage")
+    assert bench.load_traffic("spmv", other) is None
+    assert bench.load_traffic("presmooth0", other) is not None
 
 
 def test_more_than_one_gpu_is_refused():

@@ -347,3 +347,16 @@ def test_header_constants_match_binding():
                 assert _lib.KERNEL_NAMES[int(value)] == span, name
         else:
             assert getattr(_lib, name) == int(value), name
+
+
+def test_cycle_options_validated_on_the_host():
+    # flexible CG and the smoothing sweep counts: unsupported combinations
+    # fail in the host validation, before any device is touched
+    P = tiny_problem(N=6)
+    for kw in (dict(flexible_cg=1, solver=_lib.SOLVER_BICGSTAB), dict(npre=5), dict(npost=0), dict(npre=-1),
+               dict(flexible_cg=2), dict(npre=2, npost=2, smoother=_lib.SMOOTHER_BLOCK_SPAI0)):
+        with pytest.raises(L.DfamgError) as ei:
+            L.dfamg_setup(L.make_params(**kw), P.A, P.part, P.nsub, P.Z)
+        assert ei.value.status == _lib.EINVAL, kw
+    p = L.make_params()
+    assert p.flexible_cg == 0 and p.npre == 1 and p.npost == 1
