@@ -948,6 +948,7 @@ struct Hierarchy_dev : PrecondBase {
                     }
                     if (D.fused) {
                         ar.adopt(arB);
+                        D.B.rowmap = ar.upload(PL.B_rowmap, s);
                         D.R = DevMat<VT>{};
                     } else {
                         ar.adopt(arR);

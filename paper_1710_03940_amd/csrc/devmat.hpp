@@ -39,6 +39,7 @@ struct DevMat {
     int16_t *ridx = nullptr;
     int32_t *uoff = nullptr, *ucol = nullptr;   // gather list of the staged CSR form (null: window)
     VT *val = nullptr;
+    int32_t *rowmap = nullptr;    // restriction B: output position of each stored row (null: the row itself)
     int32_t max_span = 0;         // LDS entries of the staged layouts (window or gather list)
     int64_t nnz = 0, stored = 0;
     double tuned_us = 0.0;

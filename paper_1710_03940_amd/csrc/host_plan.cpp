@@ -718,18 +718,18 @@ HostCsrv make_csrv(const Csr &M, const std::vector<RowRange> &ranges, int lanes,
 
 namespace {
 
-// Storage order of the levels of one subdomain's hierarchy on the device:
-// ord[l][new row] = row of level l in the hierarchy's numbering, pos[l] its
-// inverse.  Level 0 and the coarsest level keep their numbering; on every
-// level in between the nodes are grouped by their aggregate on the next
-// level, the aggregates taken in that level's storage order (recursively),
-// the nodes of one aggregate in ascending index and nodes in no aggregate
-// last; the rows of a point-block node stay together.  Renumbering every
-// coarse level consistently leaves the V-cycle the same linear map (only the
-// order of summation inside a row changes); what it changes is which
-// unknowns sit next to each other: a tile of consecutive rows of the
-// restriction then covers a compact cluster of the finer level, so the
-// finer vector entries that the tile reads overlap far more.
+// Clustered order of the levels of one subdomain's hierarchy:
+// ord[l][k] = the k-th row of level l in that order, pos[l] its inverse.
+// Level 0 and the coarsest level keep their numbering; on every level in
+// between the nodes are grouped by their aggregate on the next level, the
+// aggregates taken in that level's clustered order (recursively), the nodes
+// of one aggregate in ascending index and nodes in no aggregate last; the
+// rows of a point-block node stay together.  The restriction operators B_l
+// store their rows (the nodes of level l+1) in this order: a tile of
+// consecutive rows then covers a compact cluster of level l, so the entries
+// of the finer vector that the tile gathers overlap far more than along the
+// natural (aggregate formation) order, while every vector keeps its natural
+// numbering (the kernel writes each row's result through a row map).
 void level_orders(const Hierarchy &H, int bs, std::vector<std::vector<int64_t>> &ord,
                   std::vector<std::vector<int64_t>> &pos) {
     const int L = H.nlevels();
@@ -1126,35 +1126,27 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
         PL.P.ptr.assign(PL.nrows + 1, 0);
         PL.m.assign(PL.nrows, 0.0);
         if (prm.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0) PL.mb.assign((size_t)PL.nrows * bs, 0.0);
-        std::vector<std::pair<int32_t, double>> row;
-        // one renumbered row: columns through `cpos`, shifted by `coff`, ascending
-        auto put_row = [&](const Csr &M, int64_t i, const std::vector<int64_t> &cpos, int64_t coff, Csr &out) {
-            row.clear();
-            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k)
-                row.emplace_back((int32_t)(cpos[M.col[k]] + coff), M.val[k]);
-            std::sort(row.begin(), row.end(),
-                      [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
-                          return a.first < b.first;
-                      });
-            for (auto &e : row) {
-                out.col.push_back(e.first);
-                out.val.push_back(e.second);
-            }
-        };
         for (int s = 0; s < nsub; ++s) {
             if (PL.sub_off[s] < 0) continue;
             const Hierarchy &H = plan.hier[s];
             const bool active = H.nlevels() - 1 > l;
             const int64_t o = PL.sub_off[s];
-            const std::vector<int64_t> &od = ord[s][l];
             for (int64_t i = 0; i < PL.sub_len[s]; ++i) {
                 if (active) {
-                    const int64_t io = od[i];   // the row in the hierarchy's own numbering
-                    put_row(H.lv[l].A, io, pos[s][l], o, PL.A);
-                    put_row(H.lv[l].P, io, pos[s][l + 1], plan.levels[l + 1].sub_off[s], PL.P);
-                    PL.m[o + i] = H.lv[l].m[io];
+                    const Csr &M = H.lv[l].A;
+                    for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+                        PL.A.col.push_back((int32_t)(M.col[k] + o));
+                        PL.A.val.push_back(M.val[k]);
+                    }
+                    const Csr &P = H.lv[l].P;
+                    const int64_t oc = plan.levels[l + 1].sub_off[s];
+                    for (int64_t k = P.ptr[i]; k < P.ptr[i + 1]; ++k) {
+                        PL.P.col.push_back((int32_t)(P.col[k] + oc));
+                        PL.P.val.push_back(P.val[k]);
+                    }
+                    PL.m[o + i] = H.lv[l].m[i];
                     if (!H.lv[l].mb.empty())
-                        for (int k = 0; k < bs; ++k) PL.mb[(size_t)(o + i) * bs + k] = H.lv[l].mb[(size_t)io * bs + k];
+                        for (int k = 0; k < bs; ++k) PL.mb[(size_t)(o + i) * bs + k] = H.lv[l].mb[(size_t)i * bs + k];
                 }
                 PL.A.ptr[o + i + 1] = (int64_t)PL.A.col.size();
                 PL.P.ptr[o + i + 1] = (int64_t)PL.P.col.size();
@@ -1166,7 +1158,10 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
         PL.B.ncols = PL.nrows;
         PL.B.ptr.assign(ncoarse + 1, 0);
         if (has_next) {
-            // rows of the next level in its storage order
+            // rows of the next level in its clustered order, row map to the
+            // natural packed row
+            PL.B_rowmap.assign(ncoarse, 0);
+            for (int64_t k = 0; k < ncoarse; ++k) PL.B_rowmap[k] = (int32_t)k;
             for (int s = 0; s < nsub; ++s) {
                 if (PL.sub_off[s] < 0 || plan.hier[s].nlevels() - 1 <= l) continue;
                 const Csr &Bs = plan.hier[s].lv[l].B;
@@ -1186,7 +1181,11 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
                 const std::vector<int64_t> &odc = ord[s][l + 1];
                 for (int64_t k = 0; k < Bs.nrows; ++k) {
                     if ((int64_t)PL.B.col.size() != PL.B.ptr[oc + k]) fail(DFAMG_EINVAL, "internal: B packing order");
-                    put_row(Bs, odc[k], pos[s][l], o, PL.B);
+                    for (int64_t e = Bs.ptr[odc[k]]; e < Bs.ptr[odc[k] + 1]; ++e) {
+                        PL.B.col.push_back((int32_t)(Bs.col[e] + o));
+                        PL.B.val.push_back(Bs.val[e]);
+                    }
+                    PL.B_rowmap[oc + k] = (int32_t)(oc + odc[k]);
                 }
             }
         }

@@ -1212,16 +1212,19 @@ __global__ void __launch_bounds__(kBlock) k_spmv(MAT M, const VT *__restrict__ x
 }
 
 // f_c = B f with B = R (I - A diag(m)): pre-smoothing from a zero guess,
-// residual and restriction of one level in a single operator
+// residual and restriction of one level in a single operator; stored row k
+// of B is coarse row rowmap[k] (rows kept in a clustered order), or k
 template <class VT, class FT, class MAT>
 __global__ void __launch_bounds__(kBlock) k_restrict(MAT B, const FT *__restrict__ f, VT *__restrict__ fc,
+                                                     const int32_t *__restrict__ rowmap,
                                                      const SysState *__restrict__ st,
                                                      const int32_t *__restrict__ sub_sys) {
     const int tile = tile_of_block(B.ntiles);
     if (tile >= B.ntiles) return;
     const DevTile T = B.tiles[tile];
     if (st && st[sub_sys[T.sub]].done) return;
-    for_rows<VT>(B, tile, T, [&](int c) { return (VT)f[c]; }, [&](int row, VT v) { fc[row] = v; });
+    for_rows<VT>(B, tile, T, [&](int c) { return (VT)f[c]; },
+                 [&](int row, VT v) { fc[rowmap ? rowmap[row] : row] = v; });
 }
 
 // z = m o f + P xc   (pre-smoothed iterate plus the coarse correction)

@@ -28,7 +28,7 @@ void launch_restrict(const DevMat<VT> &B, const FT *f, VT *fc, const SysState *s
                      hipStream_t s) {
     with_mat(B, [&](auto v) {
         hipLaunchKernelGGL((k_restrict<VT, FT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
-                           B.stage_bytes(), s, v, f, fc, st, sub_sys);
+                           B.stage_bytes(), s, v, f, fc, B.rowmap, st, sub_sys);
     });
 }
 
