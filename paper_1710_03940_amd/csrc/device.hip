@@ -941,14 +941,26 @@ struct Hierarchy_dev : PrecondBase {
                     D.R = upload_tuned<VT>(arR, PL.R, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys, plan.nsys,
                                            plan.nsub, {}, verbose);
                     // B holds exactly one pre-smoothing sweep from the zero guess
+                    bool clustered = false;
+                    DevArena arBc;
                     if (autotune && !block && npre == 1) {
                         D.B = upload_tuned<VT>(arB, PL.B, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
                                                plan.nsys, plan.nsub, {}, verbose);
+                        // the rows in the clustered order: fewer distinct
+                        // columns per tile, but wider column windows
+                        if (PL.Bc.nnz() > 0) {
+                            DevMat<VT> Bc = upload_tuned<VT>(arBc, PL.Bc, rn, format, autotune, TUNE_RESTRICT, s,
+                                                             plan.sub_sys, plan.nsys, plan.nsub, {}, verbose);
+                            if (Bc.tuned_us < D.B.tuned_us) {
+                                D.B = Bc;
+                                clustered = true;
+                            }
+                        }
                         D.fused = D.B.tuned_us < D.A.tuned_us + D.R.tuned_us;
                     }
                     if (D.fused) {
-                        ar.adopt(arB);
-                        D.B.rowmap = ar.upload(PL.B_rowmap, s);
+                        ar.adopt(clustered ? arBc : arB);
+                        if (clustered) D.B.rowmap = ar.upload(PL.B_rowmap, s);
                         D.R = DevMat<VT>{};
                     } else {
                         ar.adopt(arR);
@@ -961,7 +973,8 @@ struct Hierarchy_dev : PrecondBase {
                     par[l] = D.A.par;
                 }
                 layouts += " L" + std::to_string(l) + "{A " + describe(D.A) +
-                           (D.fused ? ", B " + describe(D.B) : ", R " + describe(D.R)) + ", P " + describe(D.P) + "}";
+                           (D.fused ? ", B " + describe(D.B) + (D.B.rowmap ? "/clustered" : "") : ", R " + describe(D.R)) +
+                           ", P " + describe(D.P) + "}";
                 std::vector<VT> m(PL.m.size());
                 for (size_t i = 0; i < m.size(); ++i) m[i] = (VT)PL.m[i];
                 D.m = ar.upload(m, s);

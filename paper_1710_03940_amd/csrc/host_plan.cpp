@@ -1154,41 +1154,46 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
         }
         PL.R = transpose(PL.P);
         // B packed like R: rows of the next level's packed order, this level's columns
-        PL.B.nrows = ncoarse;
-        PL.B.ncols = PL.nrows;
-        PL.B.ptr.assign(ncoarse + 1, 0);
-        if (has_next) {
-            // rows of the next level in its clustered order, row map to the
-            // natural packed row
-            PL.B_rowmap.assign(ncoarse, 0);
-            for (int64_t k = 0; k < ncoarse; ++k) PL.B_rowmap[k] = (int32_t)k;
+        // B in the natural row order, and again with the rows of every
+        // subdomain in the next level's clustered order (Bc, with the map
+        // from its rows to the natural packed rows); the device keeps the
+        // faster of the two
+        auto pack_b = [&](Csr &B, bool clustered, std::vector<int32_t> *rowmap) {
+            B.nrows = ncoarse;
+            B.ncols = PL.nrows;
+            B.ptr.assign(ncoarse + 1, 0);
+            if (!has_next) return;
+            if (rowmap) {
+                rowmap->resize(ncoarse);
+                for (int64_t k = 0; k < ncoarse; ++k) (*rowmap)[k] = (int32_t)k;
+            }
+            auto src = [&](int s, int64_t k) { return clustered ? ord[s][l + 1][k] : k; };
             for (int s = 0; s < nsub; ++s) {
                 if (PL.sub_off[s] < 0 || plan.hier[s].nlevels() - 1 <= l) continue;
                 const Csr &Bs = plan.hier[s].lv[l].B;
                 const int64_t oc = plan.levels[l + 1].sub_off[s];
-                const std::vector<int64_t> &odc = ord[s][l + 1];
-                for (int64_t k = 0; k < Bs.nrows; ++k) PL.B.ptr[oc + k + 1] = Bs.ptr[odc[k] + 1] - Bs.ptr[odc[k]];
+                for (int64_t k = 0; k < Bs.nrows; ++k) B.ptr[oc + k + 1] = Bs.ptr[src(s, k) + 1] - Bs.ptr[src(s, k)];
             }
-            for (int64_t k = 0; k < ncoarse; ++k) PL.B.ptr[k + 1] += PL.B.ptr[k];
-            PL.B.col.clear();
-            PL.B.val.clear();
-            PL.B.col.reserve(PL.B.ptr[ncoarse]);
-            PL.B.val.reserve(PL.B.ptr[ncoarse]);
+            for (int64_t k = 0; k < ncoarse; ++k) B.ptr[k + 1] += B.ptr[k];
+            B.col.resize(B.ptr[ncoarse]);
+            B.val.resize(B.ptr[ncoarse]);
             for (int s = 0; s < nsub; ++s) {
                 if (PL.sub_off[s] < 0 || plan.hier[s].nlevels() - 1 <= l) continue;
                 const Csr &Bs = plan.hier[s].lv[l].B;
                 const int64_t o = PL.sub_off[s], oc = plan.levels[l + 1].sub_off[s];
-                const std::vector<int64_t> &odc = ord[s][l + 1];
                 for (int64_t k = 0; k < Bs.nrows; ++k) {
-                    if ((int64_t)PL.B.col.size() != PL.B.ptr[oc + k]) fail(DFAMG_EINVAL, "internal: B packing order");
-                    for (int64_t e = Bs.ptr[odc[k]]; e < Bs.ptr[odc[k] + 1]; ++e) {
-                        PL.B.col.push_back((int32_t)(Bs.col[e] + o));
-                        PL.B.val.push_back(Bs.val[e]);
+                    const int64_t r = src(s, k);
+                    int64_t d = B.ptr[oc + k];
+                    for (int64_t e = Bs.ptr[r]; e < Bs.ptr[r + 1]; ++e, ++d) {
+                        B.col[d] = (int32_t)(Bs.col[e] + o);
+                        B.val[d] = Bs.val[e];
                     }
-                    PL.B_rowmap[oc + k] = (int32_t)(oc + odc[k]);
+                    if (rowmap) (*rowmap)[oc + k] = (int32_t)(oc + r);
                 }
             }
-        }
+        };
+        pack_b(PL.B, false, nullptr);
+        pack_b(PL.Bc, true, &PL.B_rowmap);
     }
     plan.host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }

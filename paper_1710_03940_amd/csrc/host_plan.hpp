@@ -116,9 +116,10 @@ struct PackedLevel {
     int64_t nrows = 0;                   // unknowns of all subdomains present
     std::vector<int64_t> sub_off;        // nsub+1 style: offset or -1 when absent
     std::vector<int32_t> sub_len;
-    Csr A, P, R, B;                      // packed (block-diagonal) matrices; the rows
-                                         // of B in each subdomain's clustered order
-    std::vector<int32_t> B_rowmap;       // packed row of B -> natural packed row
+    Csr A, P, R, B;                      // packed (block-diagonal) matrices
+    Csr Bc;                              // B with each subdomain's rows in the next
+                                         // level's clustered order
+    std::vector<int32_t> B_rowmap;       // packed row of Bc -> natural packed row
     std::vector<double> m;               // smoother diagonal (0 when inactive)
     std::vector<double> mb;              // block smoother rows (bs per row), block SPAI-0 only
     std::vector<int32_t> active_subs;    // subdomains smoothing on this level
