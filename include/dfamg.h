@@ -152,6 +152,12 @@ typedef struct {
                                paper's runs use V(1,1); CG needs npre = npost
                                for a symmetric preconditioner.  The block
                                SPAI-0 smoother supports V(1,1) only           */
+    int32_t setup_device;   /* 0 (default): the smoothed-aggregation
+                               hierarchies are built on the host; 1: on the
+                               current GPU (strength, aggregation, smoothed
+                               prolongator, Galerkin products), equal to the
+                               host's bit for bit; block_size 1 and a
+                               diagonal smoother (SPAI-0, damped Jacobi) only */
 } dfamg_params;
 
 /* Fill *p with the defaults listed above. */
@@ -311,6 +317,9 @@ typedef struct {
     int64_t schur_inner_iters[2];     /* Schur handle: iterations of the
                                          velocity and of the pressure inner
                                          solves in the last solve call        */
+    double  setup_hierarchy_s;        /* hierarchy construction time (part of
+                                         setup_host_s)                        */
+    int32_t setup_hierarchy_device;   /* 1: hierarchies built on the GPU      */
 } dfamg_stats;
 
 /* Kernel ids of the profile: the outer SpMV with its fused (p,q) and Z^T q
@@ -343,10 +352,10 @@ dfamg_status dfamg_destroy(dfamg_handle h);
 const char *dfamg_last_error(dfamg_handle h);
 
 /*
- * Host-only inspection of the setup (no device is touched): the same
- * validation, permutation, hierarchy, AZ and E construction that dfamg_setup
- * performs, kept on the host so that it can be compared with other
- * implementations.
+ * Inspection of the setup: the same validation, permutation, hierarchy, AZ
+ * and E construction that dfamg_setup performs, kept on the host so that it
+ * can be compared with other implementations.  No device is touched, except
+ * that with setup_device = 1 the hierarchies are built on the current GPU.
  */
 typedef struct dfamg_plan_s *dfamg_plan;
 

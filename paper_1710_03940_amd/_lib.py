@@ -57,6 +57,7 @@ class Params(ctypes.Structure):
         ("restart", ctypes.c_int32), ("coarse_solve", ctypes.c_int32),
         ("coarse_rtol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
         ("flexible_cg", ctypes.c_int32), ("npre", ctypes.c_int32), ("npost", ctypes.c_int32),
+        ("setup_device", ctypes.c_int32),
     ]
 
 
@@ -77,6 +78,7 @@ class Stats(ctypes.Structure):
         ("kernel_bytes", ctypes.c_double * 16), ("profile_in_graph", ctypes.c_int32),
         ("layouts", ctypes.c_char * 1024), ("outer_layout_bytes", ctypes.c_double),
         ("coarse_iters", ctypes.c_int64), ("schur_inner_iters", ctypes.c_int64 * 2),
+        ("setup_hierarchy_s", ctypes.c_double), ("setup_hierarchy_device", ctypes.c_int32),
     ]
 
 
@@ -235,6 +237,8 @@ def dfamg_get_stats(h):
             "layouts": s.layouts.decode(), "outer_layout_bytes": s.outer_layout_bytes,
             "coarse_iters": int(s.coarse_iters),
             "schur_inner_iters": [int(s.schur_inner_iters[0]), int(s.schur_inner_iters[1])],
+            "setup_hierarchy_s": float(s.setup_hierarchy_s),
+            "setup_hierarchy_device": int(s.setup_hierarchy_device),
             "kernels": {name: {"calls": int(s.kernel_calls[i]), "ms": float(s.kernel_ms[i]),
                                "bytes": float(s.kernel_bytes[i])}
                         for i, name in enumerate(KERNEL_NAMES)}}

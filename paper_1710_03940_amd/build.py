@@ -19,6 +19,8 @@ UNITS = [
     ("launch_vcycle.hip", ["-DDFAMG_VT_DOUBLE"], "launch_vcycle_f64.o"),
     ("launch_vcycle.hip", [], "launch_vcycle_f32.o"),
     ("dense_inverse.hip", [], "dense_inverse.o"),
+    # the setup kernels reproduce the host's rounding: no fused multiply-adds
+    ("setup_device.hip", ["-ffp-contract=off"], "setup_device.o"),
 ]
 HEADERS = ["host_plan.hpp", "kernels.hpp", "kernels_fgmres.hpp", "kernels_schur.hpp", "kernels_bsmooth.hpp",
            "kernels_coarse_setup.hpp", "devmat.hpp", "dense_inverse.hpp"]

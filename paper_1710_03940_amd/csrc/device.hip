@@ -2400,7 +2400,11 @@ void check_device() {
 // Builds a handle in place (validation, host plan, device setup).
 void init_handle(Handle &H, const dfamg_params &p, int64_t n, const int64_t *row_ptr, const int32_t *col,
                  const double *val, const int32_t *part, int32_t nsub, int32_t ndv, const double *Z, void *stream) {
-    build_plan(H.plan, p, 1, nullptr, n, row_ptr, col, val, part, nsub, ndv, Z);
+    if (p.setup_device) {
+        validate_params(p);
+        check_device();
+    }
+    build_plan(H.plan, p, 1, nullptr, n, row_ptr, col, val, part, nsub, ndv, Z, stream);
     check_device();
     H.prm = p;
     H.stream = static_cast<hipStream_t>(stream);
@@ -2447,7 +2451,11 @@ dfamg_status do_setup(const dfamg_params *prm, int32_t nsys, const int64_t *sys_
         if (prm) p = *prm;
         else dfamg_params_default(&p);
         auto H = std::make_unique<dfamg_handle_s>();
-        build_plan(H->h.plan, p, nsys, sys_row_off, n, row_ptr, col, val, part, nsub, ndv, Z);
+        if (p.setup_device) {
+        validate_params(p);
+        check_device();
+    }
+        build_plan(H->h.plan, p, nsys, sys_row_off, n, row_ptr, col, val, part, nsub, ndv, Z, stream);
         check_device();
         H->h.prm = p;
         H->h.stream = static_cast<hipStream_t>(stream);
@@ -2552,6 +2560,7 @@ void dfamg_params_default(dfamg_params *p) {
     p->flexible_cg = 0;
     p->npre = 1;
     p->npost = 1;
+    p->setup_device = 0;
 }
 
 dfamg_status dfamg_setup(const dfamg_params *prm, int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -2692,6 +2701,8 @@ dfamg_status dfamg_get_stats(dfamg_handle h, dfamg_stats *o) {
     o->solve_s = H.solve_s;
     o->device_bytes = H.ar.bytes;
     o->bytes_per_iter = H.bytes_iter;
+    o->setup_hierarchy_s = P.hier_seconds;
+    o->setup_hierarchy_device = P.hier_on_device;
     for (int k = 0; k < KID_N; ++k) {
         o->kernel_calls[k] = H.prof.calls[k];
         o->kernel_ms[k] = H.prof.ms[k];
@@ -2731,6 +2742,10 @@ dfamg_status dfamg_plan_create(const dfamg_params *prm, int32_t nsys, const int6
         if (prm) p = *prm;
         else dfamg_params_default(&p);
         auto P = std::make_unique<dfamg_plan_s>();
+        if (p.setup_device) {
+        validate_params(p);
+        check_device();
+    }
         build_plan(P->plan, p, nsys, sys_row_off, n, row_ptr, col, val, part, nsub, ndv, Z);
         *out = P.release();
         return DFAMG_OK;

@@ -769,44 +769,6 @@ void level_orders(const Hierarchy &H, int bs, std::vector<std::vector<int64_t>> 
     }
 }
 
-void validate_params(const dfamg_params &p) {
-    if (p.solver != DFAMG_SOLVER_CG && p.solver != DFAMG_SOLVER_BICGSTAB && p.solver != DFAMG_SOLVER_BICGSTAB2 &&
-        p.solver != DFAMG_SOLVER_FGMRES)
-        fail(DFAMG_EINVAL, "unknown solver");
-    if (p.solver == DFAMG_SOLVER_FGMRES && (p.restart < 1 || p.restart > 64))
-        fail(DFAMG_EINVAL, "restart must be in [1, 64]");
-    if (p.coarse_solve != DFAMG_COARSE_EXACT && p.coarse_solve != DFAMG_COARSE_FP32 &&
-        p.coarse_solve != DFAMG_COARSE_CG)
-        fail(DFAMG_EINVAL, "unknown coarse_solve");
-    if (p.coarse_solve != DFAMG_COARSE_EXACT && p.solver != DFAMG_SOLVER_FGMRES)
-        fail(DFAMG_EINVAL, "an inexact coarse solve needs solver = FGMRES (the projected solvers need the exact E)");
-    if (p.coarse_solve == DFAMG_COARSE_CG) {
-        if (!(p.coarse_rtol >= 0.0) || !std::isfinite(p.coarse_rtol)) fail(DFAMG_EINVAL, "coarse_rtol must be >= 0");
-        if (p.coarse_maxiter < 1) fail(DFAMG_EINVAL, "coarse_maxiter must be >= 1");
-    }
-    if (p.maxiter < 0) fail(DFAMG_EINVAL, "maxiter must be >= 0");
-    if (!(p.rtol >= 0.0) || !std::isfinite(p.rtol)) fail(DFAMG_EINVAL, "rtol must be finite and >= 0");
-    if (p.precision != DFAMG_PREC_FP64 && p.precision != DFAMG_PREC_MIXED) fail(DFAMG_EINVAL, "unknown precision");
-    if (p.smoother != DFAMG_SMOOTHER_SPAI0 && p.smoother != DFAMG_SMOOTHER_JACOBI &&
-        p.smoother != DFAMG_SMOOTHER_BLOCK_SPAI0)
-        fail(DFAMG_EINVAL, "unknown smoother");
-    if (!std::isfinite(p.jacobi_omega)) fail(DFAMG_EINVAL, "jacobi_omega must be finite");
-    if (p.coarse_enough < 1) fail(DFAMG_EINVAL, "coarse_enough must be >= 1");
-    if (p.coarse_enough > 4096) fail(DFAMG_EINVAL, "coarse_enough must be <= 4096 (dense coarsest blocks)");
-    if (!(p.eps_strong >= 0.0) || !std::isfinite(p.eps_strong)) fail(DFAMG_EINVAL, "eps_strong must be >= 0");
-    if (p.max_levels < 1 || p.max_levels > 20) fail(DFAMG_EINVAL, "max_levels must be in [1, 20]");
-    if (p.block_size < 1 || p.block_size > 8) fail(DFAMG_EINVAL, "block_size must be in [1, 8]");
-    if (p.precond != DFAMG_PRECOND_AMG && p.precond != DFAMG_PRECOND_NONE && p.precond != DFAMG_PRECOND_SPAI0)
-        fail(DFAMG_EINVAL, "unknown precond");
-    if (p.spmv_format < DFAMG_FORMAT_AUTO || p.spmv_format > DFAMG_FORMAT_CSR_GATHER) fail(DFAMG_EINVAL, "unknown spmv_format");
-    if (p.graph_iters < 0) fail(DFAMG_EINVAL, "graph_iters must be >= 0");
-    if (p.flexible_cg != 0 && p.flexible_cg != 1) fail(DFAMG_EINVAL, "flexible_cg must be 0 or 1");
-    if (p.flexible_cg && p.solver != DFAMG_SOLVER_CG) fail(DFAMG_EINVAL, "flexible_cg needs solver = CG");
-    if (p.npre < 0 || p.npre > 4) fail(DFAMG_EINVAL, "npre must be in [0, 4]");
-    if (p.npost < 1 || p.npost > 4) fail(DFAMG_EINVAL, "npost must be in [1, 4]");
-    if ((p.npre != 1 || p.npost != 1) && p.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0)
-        fail(DFAMG_EINVAL, "the block SPAI-0 smoother supports npre = npost = 1 only");
-}
 
 // Rank of the local block of one subdomain (rows x ndv, row-major) by
 // Gram-Schmidt with reorthogonalisation; columns whose remaining norm is
@@ -845,9 +807,53 @@ int local_rank(const double *Z, int64_t rows, int ndv) {
 
 }  // namespace
 
+void validate_params(const dfamg_params &p) {
+    if (p.solver != DFAMG_SOLVER_CG && p.solver != DFAMG_SOLVER_BICGSTAB && p.solver != DFAMG_SOLVER_BICGSTAB2 &&
+        p.solver != DFAMG_SOLVER_FGMRES)
+        fail(DFAMG_EINVAL, "unknown solver");
+    if (p.solver == DFAMG_SOLVER_FGMRES && (p.restart < 1 || p.restart > 64))
+        fail(DFAMG_EINVAL, "restart must be in [1, 64]");
+    if (p.coarse_solve != DFAMG_COARSE_EXACT && p.coarse_solve != DFAMG_COARSE_FP32 &&
+        p.coarse_solve != DFAMG_COARSE_CG)
+        fail(DFAMG_EINVAL, "unknown coarse_solve");
+    if (p.coarse_solve != DFAMG_COARSE_EXACT && p.solver != DFAMG_SOLVER_FGMRES)
+        fail(DFAMG_EINVAL, "an inexact coarse solve needs solver = FGMRES (the projected solvers need the exact E)");
+    if (p.coarse_solve == DFAMG_COARSE_CG) {
+        if (!(p.coarse_rtol >= 0.0) || !std::isfinite(p.coarse_rtol)) fail(DFAMG_EINVAL, "coarse_rtol must be >= 0");
+        if (p.coarse_maxiter < 1) fail(DFAMG_EINVAL, "coarse_maxiter must be >= 1");
+    }
+    if (p.maxiter < 0) fail(DFAMG_EINVAL, "maxiter must be >= 0");
+    if (!(p.rtol >= 0.0) || !std::isfinite(p.rtol)) fail(DFAMG_EINVAL, "rtol must be finite and >= 0");
+    if (p.precision != DFAMG_PREC_FP64 && p.precision != DFAMG_PREC_MIXED) fail(DFAMG_EINVAL, "unknown precision");
+    if (p.smoother != DFAMG_SMOOTHER_SPAI0 && p.smoother != DFAMG_SMOOTHER_JACOBI &&
+        p.smoother != DFAMG_SMOOTHER_BLOCK_SPAI0)
+        fail(DFAMG_EINVAL, "unknown smoother");
+    if (!std::isfinite(p.jacobi_omega)) fail(DFAMG_EINVAL, "jacobi_omega must be finite");
+    if (p.coarse_enough < 1) fail(DFAMG_EINVAL, "coarse_enough must be >= 1");
+    if (p.coarse_enough > 4096) fail(DFAMG_EINVAL, "coarse_enough must be <= 4096 (dense coarsest blocks)");
+    if (!(p.eps_strong >= 0.0) || !std::isfinite(p.eps_strong)) fail(DFAMG_EINVAL, "eps_strong must be >= 0");
+    if (p.max_levels < 1 || p.max_levels > 20) fail(DFAMG_EINVAL, "max_levels must be in [1, 20]");
+    if (p.block_size < 1 || p.block_size > 8) fail(DFAMG_EINVAL, "block_size must be in [1, 8]");
+    if (p.precond != DFAMG_PRECOND_AMG && p.precond != DFAMG_PRECOND_NONE && p.precond != DFAMG_PRECOND_SPAI0)
+        fail(DFAMG_EINVAL, "unknown precond");
+    if (p.spmv_format < DFAMG_FORMAT_AUTO || p.spmv_format > DFAMG_FORMAT_CSR_GATHER) fail(DFAMG_EINVAL, "unknown spmv_format");
+    if (p.graph_iters < 0) fail(DFAMG_EINVAL, "graph_iters must be >= 0");
+    if (p.flexible_cg != 0 && p.flexible_cg != 1) fail(DFAMG_EINVAL, "flexible_cg must be 0 or 1");
+    if (p.flexible_cg && p.solver != DFAMG_SOLVER_CG) fail(DFAMG_EINVAL, "flexible_cg needs solver = CG");
+    if (p.setup_device != 0 && p.setup_device != 1) fail(DFAMG_EINVAL, "setup_device must be 0 or 1");
+    if (p.setup_device && p.precond == DFAMG_PRECOND_AMG &&
+        (p.block_size != 1 || p.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0))
+        fail(DFAMG_EINVAL, "setup_device = 1 builds scalar hierarchies with a diagonal smoother only "
+                           "(block_size 1, SPAI-0 or damped Jacobi)");
+    if (p.npre < 0 || p.npre > 4) fail(DFAMG_EINVAL, "npre must be in [0, 4]");
+    if (p.npost < 1 || p.npost > 4) fail(DFAMG_EINVAL, "npost must be in [1, 4]");
+    if ((p.npre != 1 || p.npost != 1) && p.smoother == DFAMG_SMOOTHER_BLOCK_SPAI0)
+        fail(DFAMG_EINVAL, "the block SPAI-0 smoother supports npre = npost = 1 only");
+}
+
 void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t *sys_row_off,
                 int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
-                const int32_t *part, int32_t nsub, int32_t ndv, const double *Z) {
+                const int32_t *part, int32_t nsub, int32_t ndv, const double *Z, void *stream) {
     const auto t0 = std::chrono::steady_clock::now();
     validate_params(prm);
     plan.prm = prm;
@@ -1071,10 +1077,13 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
     sp.smoother = prm.smoother;
     sp.jacobi_omega = prm.jacobi_omega;
     sp.bs = bs;
+    const auto th = std::chrono::steady_clock::now();
     if (prm.precond == DFAMG_PRECOND_AMG) {
+        // the square diagonal block of every subdomain
+        std::vector<Csr> local(nsub);
         parallel_for(nsub, threads, [&](int64_t s) {
             const int64_t r0 = plan.sub_row_off[s], r1 = plan.sub_row_off[s + 1];
-            Csr L;
+            Csr &L = local[s];
             L.nrows = L.ncols = r1 - r0;
             L.ptr.assign(r1 - r0 + 1, 0);
             for (int64_t i = r0; i < r1; ++i) {
@@ -1085,9 +1094,15 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
                     }
                 L.ptr[i - r0 + 1] = (int64_t)L.col.size();
             }
-            plan.hier[s] = build_hierarchy(std::move(L), sp);
         });
+        if (prm.setup_device) {
+            build_hierarchies_device(local, sp, plan.hier, stream);
+            plan.hier_on_device = 1;
+        } else {
+            parallel_for(nsub, threads, [&](int64_t s) { plan.hier[s] = build_hierarchy(std::move(local[s]), sp); });
+        }
     }
+    plan.hier_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - th).count();
 
     // storage order of every subdomain's levels (identity on level 0 and on
     // the coarsest level)

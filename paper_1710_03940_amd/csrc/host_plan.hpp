@@ -1,7 +1,8 @@
 // Host-side setup of the deflated block-AMG solver: validation, subdomain
 // permutation, per-subdomain smoothed-aggregation hierarchies, AZ and E, and
-// the packed per-level layout that the device code consumes.  Nothing in this
-// header touches the GPU.
+// the packed per-level layout that the device code consumes.  Nothing here
+// touches the GPU except the hierarchy construction with setup_device = 1
+// (build_hierarchies_device).
 #pragma once
 
 #include <cstdint>
@@ -59,6 +60,15 @@ struct SaParams {
 };
 
 Hierarchy build_hierarchy(Csr A, const SaParams &prm);
+
+// Throws Error{EINVAL} for parameters the library does not accept.
+void validate_params(const dfamg_params &p);
+
+// The hierarchies of all subdomains (local diagonal blocks `local`) built on
+// the current HIP device (setup_device.hip), equal to build_hierarchy's;
+// scalar matrices and diagonal smoothers only.  `stream` is a hipStream_t.
+void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp, std::vector<Hierarchy> &out,
+                              void *stream);
 
 // A row-tile of a packed level: up to `rows per tile` consecutive rows of one
 // subdomain.
@@ -149,13 +159,15 @@ struct Plan {
     std::vector<PackedLevel> levels;
     int nlevels_max = 0;
     double host_seconds = 0.0;
+    double hier_seconds = 0.0;          // hierarchy construction (part of host_seconds)
+    int hier_on_device = 0;             // 1: built on the GPU
 };
 
 // Validates, permutes and builds everything; throws Error.
 void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys,
                 const int64_t *sys_row_off, int64_t n, const int64_t *row_ptr,
                 const int32_t *col, const double *val, const int32_t *part,
-                int32_t nsub, int32_t ndv, const double *Z);
+                int32_t nsub, int32_t ndv, const double *Z, void *stream = nullptr);
 
 // Device-ready layouts.  `ranges` lists, per subdomain covered by the
 // matrix, its first packed row and row count; tiles never straddle two
