@@ -192,11 +192,15 @@ def main():
     b = torch.tensor(P.b, device=dev)
     x = torch.zeros(P.n, dtype=torch.float64, device=dev)
 
-    log("setup FP64")
-    S64 = dfamg.Solver(P.A, P.part, P.nsub, P.Z, precision="fp64", profile=1)
+    log("setup FP64 (hierarchies built on the GPU)")
+    t0 = time.perf_counter()
+    S64 = dfamg.Solver(P.A, P.part, P.nsub, P.Z, precision="fp64", profile=1, setup_device=1)
+    t_setup64 = time.perf_counter() - t0
     st64 = S64.stats()
-    log(f"  host setup {st64['setup_host_s']:.2f} s, device setup {st64['setup_device_s']:.2f} s, "
+    log(f"  setup {t_setup64:.2f} s: host part {st64['setup_host_s']:.2f} s (hierarchies on the GPU "
+        f"{st64['setup_hierarchy_s']:.2f} s), device part {st64['setup_device_s']:.2f} s, "
         f"levels {st64['level_rows']}")
+    setup = setup_phases(dfamg, P, st64, t_setup64, log)
     log(f"  layouts: {st64['layouts']}")
     if args.record_layouts:
         with open(args.record_layouts, "w") as fh:
@@ -349,7 +353,7 @@ def main():
                    "rtol": 1e-8, "smoother": "spai0", "solver": "cg"},
         "iters": out64["iters"], "relres_true": out64["relres_true"], "median_s": out64["median_s"],
         "oracle_iters": golden["iters"], "rel_error_vs_oracle_sampled": err64,
-        "setup_s": {"host": st64["setup_host_s"], "device": st64["setup_device_s"]},
+        "setup_s": setup,
         "bytes_per_iter": st64["bytes_per_iter"],
         "effective_GBps": st64["bytes_per_iter"] * out64["iters"] / t64 / 1e9,
         "layouts": st64["layouts"],
@@ -537,6 +541,24 @@ def write_traffic(bench_fetch, bench_write, copy_fetch, copy_write, layouts_file
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
     return 0
+
+
+def setup_phases(dfamg, P, st, total, log):
+    """Setup of the timed FP64 handle in phases, and the same plan (validation,
+    permutation, hierarchies, AZ, E, packing) built with the hierarchies and AZ
+    on the host and on the GPU."""
+    out = {"total_s": total, "plan_s": st["setup_host_s"], "hierarchies_s": st["setup_hierarchy_s"],
+           "hierarchies_on": "gpu" if st["setup_hierarchy_device"] else "host",
+           "device_s": st["setup_device_s"],
+           "note": "plan_s: validation, permutation, hierarchies, AZ, E and packing; device_s: uploads, layouts "
+                   "(from the layout record), E inversion; the hierarchies are bit-for-bit those of the host"}
+    for dev in (0, 1):
+        t0 = time.perf_counter()
+        p = dfamg.dfamg_plan_create(dfamg.make_params(setup_device=dev), P.A, P.part, P.nsub, P.Z)
+        out[("plan_gpu_s" if dev else "plan_host_s")] = time.perf_counter() - t0
+        dfamg.dfamg_plan_destroy(p)
+    log(f"  plan with host hierarchies {out['plan_host_s']:.2f} s, with GPU hierarchies {out['plan_gpu_s']:.2f} s")
+    return out
 
 
 def span_rates(st):

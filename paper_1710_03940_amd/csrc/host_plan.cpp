@@ -1003,7 +1003,10 @@ void build_plan(Plan &plan, const dfamg_params &prm, int32_t nsys, const int64_t
     plan.AZoff.nrows = n;
     plan.AZoff.ncols = (int64_t)nsub * ndv;
     plan.AZoff.ptr.assign(n + 1, 0);
-    if (ndv > 0) {
+    if (ndv > 0 && prm.setup_device) {
+        build_az_device(A, row_sub, plan.Z, ndv, plan.AZown, plan.AZoff, stream);
+        plan.AZoff.ncols = (int64_t)nsub * ndv;
+    } else if (ndv > 0) {
         std::vector<std::vector<std::pair<int32_t, double>>> off_rows(nsub);
         std::vector<std::vector<int64_t>> off_cnt(nsub);
         parallel_for(nsub, threads, [&](int64_t s) {

@@ -64,11 +64,16 @@ Hierarchy build_hierarchy(Csr A, const SaParams &prm);
 // Throws Error{EINVAL} for parameters the library does not accept.
 void validate_params(const dfamg_params &p);
 
-// The hierarchies of all subdomains (local diagonal blocks `local`) built on
-// the current HIP device (setup_device.hip), equal to build_hierarchy's;
-// scalar matrices and diagonal smoothers only.  `stream` is a hipStream_t.
-void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp, std::vector<Hierarchy> &out,
+// The hierarchies of all subdomains (local diagonal blocks `local`, moved
+// from) built on the current HIP device (setup_device.hip), equal to
+// build_hierarchy's; scalar matrices and diagonal smoothers only.  `stream`
+// is a hipStream_t.
+void build_hierarchies_device(std::vector<Csr> &local, const SaParams &sp, std::vector<Hierarchy> &out,
                               void *stream);
+// AZ of the permuted operator on the current device (own-subdomain block
+// n x ndv and the couplings to other subdomains), equal to the host's.
+void build_az_device(const Csr &A, const std::vector<int32_t> &row_sub, const std::vector<double> &Z, int ndv,
+                     std::vector<double> &AZown, Csr &AZoff, void *stream);
 
 // A row-tile of a packed level: up to `rows per tile` consecutive rows of one
 // subdomain.

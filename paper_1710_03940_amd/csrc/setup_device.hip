@@ -39,7 +39,12 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <functional>
+#include <thread>
+#include <memory>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -63,6 +68,7 @@ constexpr int kAggBlock = 1024;
 constexpr int kRowCap = 160;      // aggregates one row of A_F P_tent may touch (per thread)
 constexpr int kMergeCap = 2048;   // entries of one product row held in LDS
 constexpr int kYCap = 512;        // entries of one row of the right operand of a product
+constexpr int kStatusLds = 150 * 1024;   // subdomains up to this many nodes keep pass 1 in LDS
 
 // error codes of the setup kernels (first one wins)
 enum { kSuOk = 0, kSuPass3 = 1, kSuRowCap = 2, kSuMergeCap = 3, kSuRounds = 4 };
@@ -97,6 +103,19 @@ std::vector<T> download(const T *d, size_t n, hipStream_t s) {
     if (n) SU_CHECK(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
     SU_CHECK(hipStreamSynchronize(s));
     return h;
+}
+
+// fn(i) for i in [0, count) on up to 16 host threads
+void host_parallel(int64_t count, const std::function<void(int64_t)> &fn) {
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(count, std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::atomic<int64_t> next{0};
+    auto work = [&] {
+        for (int64_t i; (i = next.fetch_add(1)) < count;) fn(i);
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
 }
 
 inline unsigned grid_of(int64_t n, int b = kSuBlock) {
@@ -166,43 +185,39 @@ __global__ void k_su_tfill(int64_t n, const int32_t *__restrict__ ptr, const int
             }
 }
 
-__device__ inline int32_t ld_status(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ inline void st_status(int32_t *p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
+// Status of a node during pass 1: in LDS (one byte per node of the
+// workgroup's subdomain) when it fits, else in global memory, read and
+// written with workgroup-scope atomics (every reader and writer of a
+// subdomain's entries is in its workgroup).
+struct StatusLds {
+    uint8_t *st;
+    __device__ int32_t ld(int64_t local) const { return st[local]; }
+    __device__ void put(int64_t local, int32_t v) const { st[local] = (uint8_t)v; }
+};
+struct StatusGlobal {
+    int32_t *st;
+    __device__ int32_t ld(int64_t local) const {
+        return __hip_atomic_load(st + local, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __device__ void put(int64_t local, int32_t v) const {
+        __hip_atomic_store(st + local, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+};
 
-// Pass 1 of one subdomain per workgroup, in rounds.  The seeds of the
-// ascending sweep are the nodes i with a strong neighbour such that no node
-// j < i that became a seed could claim i or one of i's strong neighbours
-// ({i} u N(i) meets {j} u N(j)); a node is decided once every such j is.
-// The smallest undecided node is decided in every round, so the rounds end;
-// the bound below is never reached.
-__global__ void __launch_bounds__(kAggBlock) k_su_pass1(const int32_t *__restrict__ subs,
-                                                        const int64_t *__restrict__ sub_row0,
-                                                        const int32_t *__restrict__ sub_n,
-                                                        const int32_t *__restrict__ ptr,
-                                                        const int32_t *__restrict__ col,
-                                                        const uint8_t *__restrict__ strong,
-                                                        const int32_t *__restrict__ tptr,
-                                                        const int32_t *__restrict__ tcol,
-                                                        const int32_t *__restrict__ has, int32_t *status,
-                                                        int32_t *__restrict__ err) {
-    const int s = subs[blockIdx.x];
-    const int64_t r0 = sub_row0[s];
-    const int32_t n = sub_n[s];
-    for (int32_t t = threadIdx.x; t < n; t += kAggBlock) st_status(&status[r0 + t], has[r0 + t] ? kUnd : kNot);
-    __syncthreads();
-    for (int32_t round = 0; round <= n; ++round) {
-        int open = 0;
-        for (int32_t t = threadIdx.x; t < n; t += kAggBlock) {
-            const int64_t i = r0 + t;
-            if (ld_status(&status[i]) != kUnd) continue;
-            bool root_conf = false, und_conf = false;
-            // k runs over {i} u N(i); the candidates are k itself (k < i) and
-            // the in-neighbours j < i of k
-            for (int32_t e = ptr[i] - 1; e < ptr[i + 1] && !root_conf; ++e) {
+// The nodes j < i whose seeding would block node i in pass 1: j = k and the
+// in-neighbours j of k, for k in {i} u N(i) (duplicates kept).  FILL = 0
+// counts them.
+template <bool FILL>
+__global__ void k_su_conflicts(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                               const uint8_t *__restrict__ strong, const int32_t *__restrict__ tptr,
+                               const int32_t *__restrict__ tcol, const int32_t *__restrict__ has,
+                               int32_t *__restrict__ cnt, const int64_t *__restrict__ cptr,
+                               int32_t *__restrict__ clist) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0;
+        const int64_t base = FILL ? cptr[i] : 0;
+        if (has[i])
+            for (int32_t e = ptr[i] - 1; e < ptr[i + 1]; ++e) {
                 int64_t k;
                 if (e < ptr[i]) {
                     k = i;
@@ -210,26 +225,65 @@ __global__ void __launch_bounds__(kAggBlock) k_su_pass1(const int32_t *__restric
                     if (!strong[e]) continue;
                     k = col[e];
                     if (k < i) {
-                        const int32_t sk = ld_status(&status[k]);
-                        root_conf |= sk == kRoot;
-                        und_conf |= sk == kUnd;
+                        if (FILL) clist[base + c] = (int32_t)k;
+                        ++c;
                     }
                 }
-                for (int32_t q = tptr[k]; q < tptr[k + 1] && !root_conf; ++q) {
-                    const int64_t j = tcol[q];
+                for (int32_t q = tptr[k]; q < tptr[k + 1]; ++q) {
+                    const int32_t j = tcol[q];
                     if (j >= i) continue;
-                    const int32_t sj = ld_status(&status[j]);
-                    root_conf |= sj == kRoot;
-                    und_conf |= sj == kUnd;
+                    if (FILL) clist[base + c] = j;
+                    ++c;
                 }
             }
-            if (root_conf) st_status(&status[i], kNot);
-            else if (!und_conf) st_status(&status[i], kRoot);
+        if (!FILL) cnt[i] = (int32_t)c;
+    }
+}
+
+// Pass 1 of one subdomain per workgroup, in rounds.  The seeds of the
+// ascending sweep are the nodes i with a strong neighbour such that none of
+// its conflicts (k_su_conflicts) became a seed; a node is decided once
+// every conflict is.  The smallest undecided node is decided in every
+// round, so the rounds end; the bound below is never reached.  The final
+// status goes to `status`.
+template <bool LDS>
+__global__ void __launch_bounds__(kAggBlock) k_su_pass1(const int32_t *__restrict__ subs,
+                                                        const int64_t *__restrict__ sub_row0,
+                                                        const int32_t *__restrict__ sub_n,
+                                                        const int64_t *__restrict__ cptr,
+                                                        const int32_t *__restrict__ clist,
+                                                        const int32_t *__restrict__ has, int32_t *status,
+                                                        int32_t *__restrict__ err) {
+    extern __shared__ uint8_t lds_status[];
+    const int s = subs[blockIdx.x];
+    const int64_t r0 = sub_row0[s];
+    const int32_t n = sub_n[s];
+    typename std::conditional<LDS, StatusLds, StatusGlobal>::type S;
+    if constexpr (LDS) S.st = lds_status;
+    else S.st = status + r0;
+    for (int32_t t = threadIdx.x; t < n; t += kAggBlock) S.put(t, has[r0 + t] ? kUnd : kNot);
+    __syncthreads();
+    bool done = false;
+    for (int32_t round = 0; round <= n && !done; ++round) {
+        int open = 0;
+        for (int32_t t = threadIdx.x; t < n; t += kAggBlock) {
+            if (S.ld(t) != kUnd) continue;
+            const int64_t i = r0 + t;
+            bool root_conf = false, und_conf = false;
+            for (int64_t q = cptr[i]; q < cptr[i + 1]; ++q) {
+                const int32_t sj = S.ld(clist[q] - r0);
+                root_conf |= sj == kRoot;
+                und_conf |= sj == kUnd;
+            }
+            if (root_conf) S.put(t, kNot);
+            else if (!und_conf) S.put(t, kRoot);
             else open = 1;
         }
-        if (!__syncthreads_or(open)) return;
+        done = !__syncthreads_or(open);
     }
-    if (threadIdx.x == 0) set_err(err, kSuRounds);
+    if (!done && threadIdx.x == 0) set_err(err, kSuRounds);
+    if constexpr (LDS)
+        for (int32_t t = threadIdx.x; t < n; t += kAggBlock) status[r0 + t] = S.ld(t);
 }
 
 // Seed numbers in ascending order per subdomain (one workgroup each):
@@ -332,16 +386,24 @@ __global__ void k_su_filtdiag(int64_t n, const int32_t *__restrict__ ptr, const 
 }
 
 // Row sums of |D^-1 A_F| in column order (the diagonal term at its column)
-// and their maximum per subdomain (as the bit pattern of a non-negative
-// double, which orders like the value).
-__global__ void k_su_rho(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                         const double *__restrict__ val, const uint8_t *__restrict__ strong,
-                         const int32_t *__restrict__ row_sub, const int32_t *__restrict__ cont,
-                         const double *__restrict__ D, const int32_t *__restrict__ hasd,
-                         unsigned long long *__restrict__ rho_bits, int32_t *__restrict__ any) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int s = row_sub[i];
-        if (!cont[s] || D[i] == 0.0) continue;
+// and their maximum over the rows of one subdomain per workgroup (rows with
+// a zero filtered diagonal are left out; any[s] = 0 when no row is left).
+__global__ void __launch_bounds__(kSuBlock) k_su_rho(const int32_t *__restrict__ subs,
+                                                     const int64_t *__restrict__ sub_row0,
+                                                     const int32_t *__restrict__ sub_n,
+                                                     const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     const uint8_t *__restrict__ strong,
+                                                     const double *__restrict__ D, const int32_t *__restrict__ hasd,
+                                                     double *__restrict__ rho, int32_t *__restrict__ any) {
+    __shared__ double red[kSuBlock];
+    __shared__ int32_t got[kSuBlock];
+    const int s = subs[blockIdx.x];
+    const int64_t r0 = sub_row0[s];
+    double best = 0.0;
+    int32_t g = 0;
+    for (int64_t i = r0 + threadIdx.x; i < r0 + sub_n[s]; i += kSuBlock) {
+        if (D[i] == 0.0) continue;
         const double dinv = 1.0 / D[i];
         double r = 0.0;
         bool placed = !hasd[i];
@@ -354,8 +416,23 @@ __global__ void k_su_rho(int64_t n, const int32_t *__restrict__ ptr, const int32
             if (j != i && strong[k]) r = r + std::fabs(dinv * val[k]);
         }
         if (!placed) r = r + std::fabs(dinv * D[i]);
-        atomicMax(&rho_bits[s], (unsigned long long)__double_as_longlong(r));
-        any[s] = 1;
+        best = (g == 0 || r > best) ? r : best;
+        g = 1;
+    }
+    red[threadIdx.x] = best;
+    got[threadIdx.x] = g;
+    __syncthreads();
+    for (int w = kSuBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double o = red[threadIdx.x + w];
+            if (got[threadIdx.x + w] && (!got[threadIdx.x] || o > red[threadIdx.x])) red[threadIdx.x] = o;
+            got[threadIdx.x] |= got[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        rho[s] = red[0];
+        any[s] = got[0];
     }
 }
 
@@ -503,6 +580,24 @@ __global__ void k_su_sort_rows(int64_t n, const int32_t *__restrict__ ptr, int32
         }
 }
 
+// Per row of L: the longest row of M it reaches and the sum of their
+// lengths (a bound on the product row's length), as maxima over all rows.
+__global__ void k_su_bound(int64_t nrows, const int32_t *__restrict__ Lp, const int32_t *__restrict__ Lj,
+                           const int32_t *__restrict__ Mp, int32_t *__restrict__ maxes) {
+    int32_t my = 0, mb = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t b = 0;
+        for (int32_t k = Lp[r]; k < Lp[r + 1]; ++k) {
+            const int32_t ny = Mp[Lj[k] + 1] - Mp[Lj[k]];
+            my = max(my, ny);
+            b += ny;
+        }
+        mb = max(mb, (int32_t)min<int64_t>(b, INT32_MAX));
+    }
+    atomicMax(&maxes[0], my);
+    atomicMax(&maxes[1], mb);
+}
+
 // C = L * M, one wavefront per row of C.  The row is kept in LDS as a
 // sorted list; for every entry (j, a) of L's row, in order, row j of M
 // scaled by a is merged in: a column already present gets the product added
@@ -515,12 +610,16 @@ __global__ void __launch_bounds__(64) k_su_spgemm(int64_t nrows, const int32_t *
                                                   const int32_t *__restrict__ Mp, const int32_t *__restrict__ Mj,
                                                   const double *__restrict__ Mx, int32_t *__restrict__ Ccount,
                                                   const int32_t *__restrict__ Cp, int32_t *__restrict__ Cj,
-                                                  double *__restrict__ Cx, int32_t *__restrict__ err) {
-    __shared__ int32_t cbuf[2][kMergeCap];
-    __shared__ double vbuf[2][kMergeCap];
-    __shared__ int32_t tpos[kYCap];     // per entry of M's row: insert position, -1 when the column exists
-    __shared__ int32_t newpos[kYCap];   // per new column, in ascending order: insert position
-    __shared__ int32_t newsrc[kYCap];   // per new column: its entry in M's row
+                                                  double *__restrict__ Cx, int32_t cap, int32_t ycap,
+                                                  int32_t *__restrict__ err) {
+    // LDS: two lists of cap (column, value) entries and three arrays of ycap
+    extern __shared__ double lds_merge[];
+    double *vbuf[2] = {lds_merge, lds_merge + cap};
+    int32_t *cbuf[2] = {reinterpret_cast<int32_t *>(lds_merge + 2 * cap),
+                        reinterpret_cast<int32_t *>(lds_merge + 2 * cap) + cap};
+    int32_t *tpos = cbuf[1] + cap;      // per entry of M's row: insert position, -1 when the column exists
+    int32_t *newpos = tpos + ycap;      // per new column, in ascending order: insert position
+    int32_t *newsrc = newpos + ycap;    // per new column: its entry in M's row
     const int lane = threadIdx.x;
     for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
         int cur = 0;
@@ -530,7 +629,7 @@ __global__ void __launch_bounds__(64) k_su_spgemm(int64_t nrows, const int32_t *
             const int32_t j = Lj[ka];
             const double a = Lx[ka];
             const int32_t y0 = Mp[j], ny = Mp[j + 1] - y0;
-            if (ny > kYCap || len + ny > kMergeCap) {
+            if (ny > ycap || len + ny > cap) {
                 over = true;
                 break;
             }
@@ -655,6 +754,72 @@ __global__ void k_su_bmap(int64_t nrows, int fill, const int32_t *__restrict__ R
     }
 }
 
+// AZ of one row i of the permuted operator: the own-subdomain columns
+// (row_sub[j] == own) summed into AZown[i][q] in the row's order, the others
+// as (t * ndv + q, a_ij z_jq) pairs ordered by column (stable) with equal
+// columns summed in that order.  FILL = 0 counts the row's coupling entries.
+constexpr int kAzCap = 256;
+template <bool FILL>
+__global__ void k_su_az(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                        const double *__restrict__ val, const int32_t *__restrict__ row_sub,
+                        const double *__restrict__ Z, int ndv, double *__restrict__ AZown,
+                        int32_t *__restrict__ cnt, const int64_t *__restrict__ optr, int32_t *__restrict__ ocol,
+                        double *__restrict__ oval, int32_t *__restrict__ err) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t own = row_sub[i];
+        int32_t key[kAzCap];
+        double v[kAzCap];
+        int32_t ne = 0;
+        double acc[8];
+        for (int q = 0; q < ndv; ++q) acc[q] = 0.0;
+        bool over = false;
+        for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            const int32_t t = row_sub[j];
+            for (int q = 0; q < ndv; ++q) {
+                const double p = val[k] * Z[(int64_t)j * ndv + q];
+                if (t == own) {
+                    acc[q] += p;
+                } else if (ne < kAzCap) {
+                    // stable insertion by column
+                    const int32_t c = t * ndv + q;
+                    int32_t b = ne - 1;
+                    while (b >= 0 && key[b] > c) {
+                        key[b + 1] = key[b];
+                        v[b + 1] = v[b];
+                        --b;
+                    }
+                    key[b + 1] = c;
+                    v[b + 1] = p;
+                    ++ne;
+                } else {
+                    over = true;
+                }
+            }
+        }
+        if (over) {
+            set_err(err, kSuRowCap);
+            if (!FILL) cnt[i] = 0;
+            continue;
+        }
+        if (FILL)
+            for (int q = 0; q < ndv; ++q) AZown[i * ndv + q] = acc[q];
+        int32_t out = 0;
+        for (int32_t a = 0; a < ne;) {
+            int32_t e = a + 1;
+            double sum = v[a];
+            while (e < ne && key[e] == key[a]) sum += v[e++];
+            if (FILL) {
+                ocol[optr[i] + out] = key[a];
+                oval[optr[i] + out] = sum;
+            }
+            ++out;
+            a = e;
+        }
+        if (!FILL) cnt[i] = out;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------
@@ -703,16 +868,24 @@ DCsr spgemm(Arena &ar, const DCsr &L, const DCsr &M, int32_t *err, hipStream_t s
     C.nrows = L.nrows;
     C.ncols = M.ncols;
     int32_t *cnt = ar.alloc<int32_t>(C.nrows + 1);
+    // LDS sized for the longest rows this product meets
+    int32_t *maxes = ar.alloc<int32_t>(2);
+    SU_CHECK(hipMemsetAsync(maxes, 0, 2 * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_su_bound, dim3(grid_of(C.nrows)), dim3(kSuBlock), 0, s, C.nrows, L.ptr, L.col, M.ptr, maxes);
+    const std::vector<int32_t> mx = download(maxes, 2, s);
+    const int32_t ycap = std::min<int32_t>(std::max(mx[0], 1), kYCap);
+    const int32_t cap = std::min<int32_t>(std::max<int32_t>(std::min<int64_t>(mx[1], M.ncols), 1), kMergeCap);
+    const size_t lds = (size_t)cap * 2 * (sizeof(double) + sizeof(int32_t)) + (size_t)ycap * 3 * sizeof(int32_t);
     const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(C.nrows, 65536));
-    hipLaunchKernelGGL(k_su_spgemm<false>, dim3(g), dim3(64), 0, s, C.nrows, L.ptr, L.col, L.val, M.ptr, M.col,
-                       M.val, cnt, nullptr, nullptr, nullptr, err);
+    hipLaunchKernelGGL(k_su_spgemm<false>, dim3(g), dim3(64), lds, s, C.nrows, L.ptr, L.col, L.val, M.ptr, M.col,
+                       M.val, cnt, nullptr, nullptr, nullptr, cap, ycap, err);
     SU_CHECK(hipGetLastError());
     C.ptr = ar.alloc<int32_t>(C.nrows + 1);
     C.nnz = scan_counts(ar, cnt, C.ptr, C.nrows, s);
     C.col = ar.alloc<int32_t>(C.nnz);
     C.val = ar.alloc<double>(C.nnz);
-    hipLaunchKernelGGL(k_su_spgemm<true>, dim3(g), dim3(64), 0, s, C.nrows, L.ptr, L.col, L.val, M.ptr, M.col,
-                       M.val, nullptr, C.ptr, C.col, C.val, err);
+    hipLaunchKernelGGL(k_su_spgemm<true>, dim3(g), dim3(64), lds, s, C.nrows, L.ptr, L.col, L.val, M.ptr, M.col,
+                       M.val, nullptr, C.ptr, C.col, C.val, cap, ycap, err);
     SU_CHECK(hipGetLastError());
     return C;
 }
@@ -739,7 +912,8 @@ void check_err(const int32_t *err, hipStream_t s) {
     SU_CHECK(hipStreamSynchronize(s));
     if (e == kSuOk) return;
     const char *why = e == kSuPass3   ? "a node left by the first two aggregation passes (internal error)"
-                      : e == kSuRowCap ? "a row of the smoothed prolongator touches more than 160 aggregates"
+                      : e == kSuRowCap ? "a row of the smoothed prolongator touches more than 160 aggregates "
+                                         "(or a row of AZ more than 256 coupling entries)"
                       : e == kSuMergeCap ? "a row of a Galerkin product exceeds 2048 entries (or a row of "
                                            "its right operand 512)"
                                          : "the aggregation rounds did not end (internal error)";
@@ -748,7 +922,7 @@ void check_err(const int32_t *err, hipStream_t s) {
 
 }  // namespace
 
-void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp, std::vector<Hierarchy> &out,
+void build_hierarchies_device(std::vector<Csr> &local, const SaParams &sp, std::vector<Hierarchy> &out,
                               void *stream) {
     const hipStream_t s = static_cast<hipStream_t>(stream);
     if (sp.bs != 1) throw Error{DFAMG_EINVAL, "device setup supports scalar matrices (block_size 1) only"};
@@ -760,53 +934,74 @@ void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp,
     int32_t *err = ar.alloc<int32_t>(1);
     SU_CHECK(hipMemsetAsync(err, 0, sizeof(int32_t), s));
 
-    // level 0: the subdomains' diagonal blocks, packed
+    // level 0: the subdomains' diagonal blocks, packed (block diagonal); the
+    // packed operator of every later level is the previous level's Galerkin
+    // product, which the kernels leave in exactly that layout
     std::vector<int32_t> alive(nsub, 1);
-    std::vector<Csr> curA(local);   // host copy of every alive subdomain's current level
+    std::unique_ptr<Arena> a_mem(new Arena);   // device memory of the current level's operator
+    DCsr A;
+    {
+        int64_t n = 0, nnz = 0;
+        for (const Csr &M : local) {
+            n += M.nrows;
+            nnz += M.nnz();
+        }
+        if (nnz > INT32_MAX) throw Error{DFAMG_EINVAL, "device setup: a level exceeds 2^31 entries"};
+        std::vector<int32_t> p(n + 1, 0), c(nnz);
+        std::vector<double> v(nnz);
+        std::vector<int64_t> r0(nsub + 1, 0), k0(nsub + 1, 0);
+        for (int sb = 0; sb < nsub; ++sb) {
+            r0[sb + 1] = r0[sb] + local[sb].nrows;
+            k0[sb + 1] = k0[sb] + local[sb].nnz();
+        }
+        host_parallel(nsub, [&](int64_t sb) {
+            const Csr &M = local[sb];
+            for (int64_t i = 0; i < M.nrows; ++i) {
+                for (int64_t e = M.ptr[i]; e < M.ptr[i + 1]; ++e) {
+                    c[k0[sb] + e] = (int32_t)(M.col[e] + r0[sb]);
+                    v[k0[sb] + e] = M.val[e];
+                }
+                p[r0[sb] + i + 1] = (int32_t)(k0[sb] + M.ptr[i + 1]);
+            }
+        });
+        A.nrows = A.ncols = n;
+        A.nnz = nnz;
+        A.ptr = a_mem->upload(p, s);
+        A.col = a_mem->upload(c, s);
+        A.val = a_mem->upload(v, s);
+    }
+    std::vector<Csr> &curA = local;   // host copy of every alive subdomain's current level
     double eps = sp.eps_strong;
     for (int lvl = 0;; ++lvl) {
-        // packed layout of the alive subdomains
+        // layout of the alive subdomains (in subdomain order)
         std::vector<int64_t> row0(nsub, 0);
         std::vector<int32_t> nrow(nsub, 0), coarsen(nsub, 0);
-        int64_t n = 0, nnz = 0;
+        int64_t n = 0;
+        int32_t nmax = 0;
         for (int sb = 0; sb < nsub; ++sb) {
             if (!alive[sb]) continue;
             row0[sb] = n;
             nrow[sb] = (int32_t)curA[sb].nrows;
             n += curA[sb].nrows;
-            nnz += curA[sb].nnz();
             Level L;
-            L.A = curA[sb];
+            L.A = std::move(curA[sb]);
             L.eps = eps;
             out[sb].lv.push_back(std::move(L));
-            coarsen[sb] = curA[sb].nrows > sp.coarse_enough && (int)out[sb].lv.size() < sp.max_levels;
+            coarsen[sb] = nrow[sb] > sp.coarse_enough && (int)out[sb].lv.size() < sp.max_levels;
         }
         std::vector<int32_t> subs;
         for (int sb = 0; sb < nsub; ++sb)
-            if (alive[sb] && coarsen[sb]) subs.push_back(sb);
-        if (subs.empty()) break;
-        if (nnz > INT32_MAX) throw Error{DFAMG_EINVAL, "device setup: a level exceeds 2^31 entries"};
-        // packed CSR of the level (block diagonal)
-        Csr P0;
-        P0.nrows = P0.ncols = n;
-        P0.ptr.assign(n + 1, 0);
-        P0.col.reserve(nnz);
-        P0.val.reserve(nnz);
-        std::vector<int32_t> row_sub(n);
-        for (int sb = 0; sb < nsub; ++sb) {
-            if (!alive[sb]) continue;
-            const Csr &M = curA[sb];
-            for (int64_t i = 0; i < M.nrows; ++i) {
-                for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
-                    P0.col.push_back((int32_t)(M.col[k] + row0[sb]));
-                    P0.val.push_back(M.val[k]);
-                }
-                P0.ptr[row0[sb] + i + 1] = (int64_t)P0.col.size();
-                row_sub[row0[sb] + i] = sb;
+            if (alive[sb] && coarsen[sb]) {
+                subs.push_back(sb);
+                nmax = std::max(nmax, nrow[sb]);
             }
-        }
-        Arena lv;   // device memory of this level
-        const DCsr A = upload_csr(lv, P0, s);
+        if (subs.empty()) break;
+        if (n != A.nrows) throw Error{DFAMG_EINVAL, "device setup: internal error (level layout)"};
+        std::vector<int32_t> row_sub(n);
+        for (int sb = 0; sb < nsub; ++sb)
+            if (alive[sb])
+                for (int64_t i = 0; i < nrow[sb]; ++i) row_sub[row0[sb] + i] = sb;
+        Arena lv;   // device memory of this level's steps
         int32_t *d_row_sub = lv.upload(row_sub, s);
         int32_t *d_coarsen = lv.upload(coarsen, s);
         int32_t *d_nrow = lv.upload(nrow, s);
@@ -832,8 +1027,25 @@ void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp,
         int32_t *agg = lv.alloc<int32_t>(n), *d_nagg = lv.alloc<int32_t>(nsub);
         SU_CHECK(hipMemsetAsync(d_nagg, 0, sizeof(int32_t) * nsub, s));
         hipLaunchKernelGGL(k_su_fill_i32, dim3(g), dim3(kSuBlock), 0, s, n, status, (int32_t)kNot);
-        hipLaunchKernelGGL(k_su_pass1, dim3((unsigned)subs.size()), dim3(kAggBlock), 0, s, d_subs, d_row0, d_nrow,
-                           A.ptr, A.col, strong, tptr, tcol, has, status, err);
+        {
+            // conflict lists, then the rounds
+            int32_t *ccnt = lv.alloc<int32_t>(n);
+            hipLaunchKernelGGL(k_su_conflicts<false>, dim3(g), dim3(kSuBlock), 0, s, n, A.ptr, A.col, strong, tptr,
+                               tcol, has, ccnt, nullptr, nullptr);
+            const std::vector<int32_t> cc = download(ccnt, n, s);
+            std::vector<int64_t> cp(n + 1, 0);
+            for (int64_t i = 0; i < n; ++i) cp[i + 1] = cp[i] + cc[i];
+            int64_t *d_cptr = lv.upload(cp, s);
+            int32_t *clist = lv.alloc<int32_t>(cp[n]);
+            hipLaunchKernelGGL(k_su_conflicts<true>, dim3(g), dim3(kSuBlock), 0, s, n, A.ptr, A.col, strong, tptr,
+                               tcol, has, nullptr, d_cptr, clist);
+            if (nmax <= kStatusLds)
+                hipLaunchKernelGGL(k_su_pass1<true>, dim3((unsigned)subs.size()), dim3(kAggBlock), (size_t)nmax, s,
+                                   d_subs, d_row0, d_nrow, d_cptr, clist, has, status, err);
+            else
+                hipLaunchKernelGGL(k_su_pass1<false>, dim3((unsigned)subs.size()), dim3(kAggBlock), 0, s, d_subs,
+                                   d_row0, d_nrow, d_cptr, clist, has, status, err);
+        }
         hipLaunchKernelGGL(k_su_fill_i32, dim3(g), dim3(kSuBlock), 0, s, n, seed, (int32_t)-1);
         hipLaunchKernelGGL(k_su_seed_ids, dim3((unsigned)subs.size()), dim3(kAggBlock), 0, s, d_subs, d_row0,
                            d_nrow, status, seed, d_nagg);
@@ -845,38 +1057,33 @@ void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp,
         check_err(err, s);
         const std::vector<int32_t> nagg = download(d_nagg, nsub, s);
         // subdomains whose level stays the coarsest: no aggregate, or no reduction
-        std::vector<int32_t> cont(nsub, 0), coarse_off(nsub, 0);
+        std::vector<int32_t> cont(nsub, 0), coarse_off(nsub, 0), csubs;
         int64_t nc = 0;
         for (int sb : subs)
             if (nagg[sb] > 0 && nagg[sb] < nrow[sb]) {
                 cont[sb] = 1;
                 coarse_off[sb] = (int32_t)nc;
                 nc += nagg[sb];
+                csubs.push_back(sb);
             }
-        bool any_cont = false;
-        for (int sb : subs) any_cont |= cont[sb] != 0;
-        if (!any_cont) break;
+        if (csubs.empty()) break;
         int32_t *d_cont = lv.upload(cont, s);
         int32_t *d_coff = lv.upload(coarse_off, s);
+        int32_t *d_csubs = lv.upload(csubs, s);
         // 3. filtered diagonal, omega, smoothed prolongator
         double *D = lv.alloc<double>(n);
         int32_t *hasd = lv.alloc<int32_t>(n);
         hipLaunchKernelGGL(k_su_filtdiag, dim3(g), dim3(kSuBlock), 0, s, n, A.ptr, A.col, A.val, strong, d_row_sub,
                            d_cont, D, hasd);
-        unsigned long long *rho_bits = lv.alloc<unsigned long long>(nsub);
+        double *d_rho = lv.alloc<double>(nsub);
         int32_t *any = lv.alloc<int32_t>(nsub);
-        SU_CHECK(hipMemsetAsync(rho_bits, 0, sizeof(unsigned long long) * nsub, s));
         SU_CHECK(hipMemsetAsync(any, 0, sizeof(int32_t) * nsub, s));
-        hipLaunchKernelGGL(k_su_rho, dim3(g), dim3(kSuBlock), 0, s, n, A.ptr, A.col, A.val, strong, d_row_sub, d_cont,
-                           D, hasd, rho_bits, any);
-        const std::vector<unsigned long long> rb = download(rho_bits, nsub, s);
+        hipLaunchKernelGGL(k_su_rho, dim3((unsigned)csubs.size()), dim3(kSuBlock), 0, s, d_csubs, d_row0, d_nrow,
+                           A.ptr, A.col, A.val, strong, D, hasd, d_rho, any);
+        const std::vector<double> rh = download(d_rho, nsub, s);
         const std::vector<int32_t> anyh = download(any, nsub, s);
         std::vector<double> omega(nsub, 0.0);
-        for (int sb = 0; sb < nsub; ++sb) {
-            double rho = 1.0;
-            if (anyh[sb]) std::memcpy(&rho, &rb[sb], sizeof(double));
-            omega[sb] = (4.0 / 3.0) / rho;
-        }
+        for (int sb = 0; sb < nsub; ++sb) omega[sb] = (4.0 / 3.0) / (anyh[sb] ? rh[sb] : 1.0);
         double *d_omega = lv.upload(omega, s);
         DCsr Pm;
         Pm.nrows = n;
@@ -907,9 +1114,11 @@ void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp,
         hipLaunchKernelGGL(k_su_scatter_t, dim3(g), dim3(kSuBlock), 0, s, n, Pm.ptr, Pm.col, Pm.val, R.ptr, rfill,
                            R.col, R.val);
         hipLaunchKernelGGL(k_su_sort_rows, dim3(grid_of(nc)), dim3(kSuBlock), 0, s, nc, R.ptr, R.col, R.val);
-        // 4. R A, the Galerkin product and the restriction operator
+        // 4. R A, the Galerkin product (the next level's operator, kept on the
+        //    device) and the restriction operator
         const DCsr RA = spgemm(lv, R, A, err, s);
-        const DCsr Ac = spgemm(lv, RA, Pm, err, s);
+        std::unique_ptr<Arena> next_mem(new Arena);
+        const DCsr Ac = spgemm(*next_mem, RA, Pm, err, s);
         DCsr Bm;
         Bm.nrows = nc;
         Bm.ncols = n;
@@ -935,12 +1144,8 @@ void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp,
         const std::vector<double> bv = download(Bm.val, Bm.nnz, s);
         const std::vector<int32_t> ap = download(Ac.ptr, nc + 1, s), ac = download(Ac.col, Ac.nnz, s);
         const std::vector<double> av = download(Ac.val, Ac.nnz, s);
-        for (int sb = 0; sb < nsub; ++sb) {
-            if (!alive[sb]) continue;
-            if (!cont[sb]) {
-                alive[sb] = 0;   // this level is the subdomain's coarsest
-                continue;
-            }
+        host_parallel(nsub, [&](int64_t sb) {
+            if (!alive[sb] || !cont[sb]) return;
             Level &L = out[sb].lv.back();
             const int64_t r0 = row0[sb], nr = nrow[sb], c0 = coarse_off[sb], ncs = nagg[sb];
             L.agg.assign(aggh.begin() + r0, aggh.begin() + r0 + nr);
@@ -951,9 +1156,49 @@ void build_hierarchies_device(const std::vector<Csr> &local, const SaParams &sp,
             L.R = local_block(rp, rc, rv, c0, ncs, r0, nr);
             L.B = local_block(bp, bc, bv, c0, ncs, r0, nr);
             curA[sb] = local_block(ap, ac, av, c0, ncs, c0, ncs);
-        }
+        });
+        for (int sb = 0; sb < nsub; ++sb)
+            if (!cont[sb]) alive[sb] = 0;   // this level is the subdomain's coarsest
+        A = Ac;
+        a_mem = std::move(next_mem);
         eps *= 0.5;
     }
+}
+
+void build_az_device(const Csr &A, const std::vector<int32_t> &row_sub, const std::vector<double> &Z, int ndv,
+                     std::vector<double> &AZown, Csr &AZoff, void *stream) {
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ndv > 8) throw Error{DFAMG_EINVAL, "device setup: at most 8 deflation vectors"};
+    const int64_t n = A.nrows;
+    if (A.nnz() > INT32_MAX) throw Error{DFAMG_EINVAL, "device setup: the operator exceeds 2^31 entries"};
+    Arena ar;
+    int32_t *err = ar.alloc<int32_t>(1);
+    SU_CHECK(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+    const DCsr D = upload_csr(ar, A, s);
+    int32_t *d_sub = ar.upload(row_sub, s);
+    double *d_Z = ar.upload(Z, s);
+    double *d_own = ar.alloc<double>((size_t)n * ndv);
+    int32_t *cnt = ar.alloc<int32_t>(n);
+    const unsigned g = grid_of(n);
+    hipLaunchKernelGGL(k_su_az<false>, dim3(g), dim3(kSuBlock), 0, s, n, D.ptr, D.col, D.val, d_sub, d_Z, ndv, d_own,
+                       cnt, nullptr, nullptr, nullptr, err);
+    SU_CHECK(hipGetLastError());
+    check_err(err, s);
+    const std::vector<int32_t> c = download(cnt, n, s);
+    AZoff.nrows = n;
+    AZoff.ptr.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) AZoff.ptr[i + 1] = AZoff.ptr[i] + c[i];
+    const int64_t nz = AZoff.ptr[n];
+    int64_t *d_optr = ar.upload(AZoff.ptr, s);
+    int32_t *d_ocol = ar.alloc<int32_t>(nz);
+    double *d_oval = ar.alloc<double>(nz);
+    hipLaunchKernelGGL(k_su_az<true>, dim3(g), dim3(kSuBlock), 0, s, n, D.ptr, D.col, D.val, d_sub, d_Z, ndv, d_own,
+                       nullptr, d_optr, d_ocol, d_oval, err);
+    SU_CHECK(hipGetLastError());
+    check_err(err, s);
+    AZown = download(d_own, (size_t)n * ndv, s);
+    AZoff.col = download(d_ocol, nz, s);
+    AZoff.val = download(d_oval, nz, s);
 }
 
 }  // namespace dfamg

@@ -6,7 +6,8 @@ The device kernels reproduce the host's operations in the host's order, so
 the bar is equality: aggregates (index work) bit for bit, and the level
 operators A_l, P_l, B_l, the smoother diagonals and omega bit for bit too
 (the host construction itself is pinned to the oracle on the CPU in
-tests/test_host_plan.py).
+tests/test_host_plan.py); AZ, also formed on the device, is compared through
+E = Z^T (AZ).
 """
 import numpy as np
 import pytest
@@ -46,7 +47,13 @@ def _compare(P, sys_row_off=None, subs=None, **kw):
                     assert mh[3] == md[3], (sub, lvl, which)
                     for a, b in zip(mh[:3], md[:3]):
                         assert np.array_equal(a, b), (sub, lvl, which, np.abs(a - b).max() if a.size else 0)
-        print(f"{P.name}: {nlev_total} subdomain levels equal", flush=True)
+        # E = Z^T (AZ) from the AZ each side built (on the device with
+        # setup_device = 1): equal bit for bit as well
+        nsys = 1 if sys_row_off is None else len(sys_row_off) - 1
+        for sy in range(nsys):
+            eh, ed = L.dfamg_plan_coarse_operator(ph, sy), L.dfamg_plan_coarse_operator(pd, sy)
+            assert np.array_equal(eh, ed), (sy, np.abs(eh - ed).max())
+        print(f"{P.name}: {nlev_total} subdomain levels and {nsys} coarse operators equal", flush=True)
     finally:
         L.dfamg_plan_destroy(ph)
         L.dfamg_plan_destroy(pd)
