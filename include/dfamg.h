@@ -75,7 +75,13 @@ enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
  * the b x b block M_i = A_ii^T (A_(i,:) A_(i,:)^T)^{-1} minimising
  * ||I - M A||_F over block-diagonal M; with b = 1 it is SPAI-0). */
 enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1, DFAMG_SMOOTHER_BLOCK_SPAI0 = 2 };
-enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2, DFAMG_FORMAT_CSR_GATHER = 3 };
+/* Sparse layouts: SELL slices, CSR (several lanes per row), CSR staged from
+ * per-tile gather lists, and BSR4: 4 x 4 dense blocks with one column index
+ * per block, for point-block matrices (block_size 4, the velocity-pressure
+ * nodes of the Navier-Stokes problem); explicit zeros of a block are
+ * stored. */
+enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2, DFAMG_FORMAT_CSR_GATHER = 3,
+       DFAMG_FORMAT_BSR4 = 4 };
 /* Preconditioner M: the block-local SA-AMG V-cycle, none (M = I), or the
  * purely local SPAI-0 diagonal m_i = a_ii / sum_j a_ij^2 (the velocity-block
  * preconditioner of the Schur pressure correction, section "Navier-Stokes
@@ -109,11 +115,14 @@ typedef struct {
     int32_t precond;        /* DFAMG_PRECOND_AMG (default), _NONE (M = I) or
                                _SPAI0 (diagonal)                              */
     int32_t spmv_format;    /* DFAMG_FORMAT_*: AUTO lets the setup autotuner
-                               time the candidates on the device; CSR_GATHER
+                               time the candidates on the device (BSR4 among
+                               them when block_size is 4); CSR_GATHER
                                restricts the multigrid operators to CSR that
                                stages each tile's distinct input columns in
                                LDS (a gather list; unstaged CSR where the list
-                               exceeds 64 KiB), the outer operator to CSR     */
+                               exceeds 64 KiB), the outer operator to CSR;
+                               BSR4 (block_size 4 only) stores every operator
+                               in 4 x 4 blocks                                */
     int32_t autotune;       /* 1 (default): time the candidate layouts of every
                                matrix at setup and keep the fastest; 0: one
                                fixed layout (SELL, one row per lane, natural

@@ -129,11 +129,67 @@ void tile_offsets(const std::vector<Tile> &tiles, const std::vector<int32_t> &su
 // Host form of a layout: SELL (rows per lane, row order, column width) or
 // CSR (lanes per row, rows per tile).  A staged and an unstaged candidate of
 // the same structure share one host form.
+// BSR4 host form: tiles of 256 rows, block-row pointers over the whole
+// matrix, block columns (ascending in a block row), 16 values per block.
+struct HostBsr {
+    std::vector<Tile> tiles;
+    std::vector<int32_t> bptr, bcol;
+    std::vector<double> val;
+    int64_t nnz = 0;
+};
+
+// The matrix in 4 x 4 blocks; false when its rows, columns or row ranges do
+// not fall on multiples of 4, or the blocks exceed 32-bit offsets.
+bool make_bsr4(const Csr &M, const std::vector<RowRange> &ranges, HostBsr &B) {
+    if (M.nrows % 4 || M.ncols % 4) return false;
+    for (const RowRange &rg : ranges)
+        if (rg.row0 % 4 || rg.nrows % 4) return false;
+    const int64_t nbr = M.nrows / 4;
+    std::vector<int32_t> cnt(nbr, 0);
+    parallel_for(nbr, 8, [&](int64_t I) {
+        std::vector<int32_t> js;
+        for (int64_t i = 4 * I; i < 4 * I + 4; ++i)
+            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) js.push_back(M.col[k] / 4);
+        std::sort(js.begin(), js.end());
+        cnt[I] = (int32_t)(std::unique(js.begin(), js.end()) - js.begin());
+    });
+    B.bptr.assign(nbr + 1, 0);
+    for (int64_t I = 0; I < nbr; ++I) {
+        if ((int64_t)B.bptr[I] + cnt[I] > INT32_MAX / 16) return false;
+        B.bptr[I + 1] = B.bptr[I] + cnt[I];
+    }
+    B.bcol.assign(B.bptr[nbr], 0);
+    B.val.assign((size_t)B.bptr[nbr] * 16, 0.0);
+    parallel_for(nbr, 8, [&](int64_t I) {
+        std::vector<int32_t> js;
+        for (int64_t i = 4 * I; i < 4 * I + 4; ++i)
+            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) js.push_back(M.col[k] / 4);
+        std::sort(js.begin(), js.end());
+        js.erase(std::unique(js.begin(), js.end()), js.end());
+        const int32_t b0 = B.bptr[I];
+        for (size_t q = 0; q < js.size(); ++q) B.bcol[b0 + q] = js[q];
+        for (int64_t i = 4 * I; i < 4 * I + 4; ++i)
+            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+                const int32_t J = M.col[k] / 4;
+                const int64_t b = b0 + (std::lower_bound(js.begin(), js.end(), J) - js.begin());
+                B.val[(size_t)b * 16 + (i % 4) * 4 + M.col[k] % 4] = M.val[k];
+            }
+    });
+    for (const RowRange &rg : ranges) {
+        int32_t slot = rg.slot0;
+        for (int32_t r0 = 0; r0 < rg.nrows; r0 += kBlock)
+            B.tiles.push_back(Tile{(int32_t)(rg.row0 + r0), std::min(kBlock, rg.nrows - r0), rg.sub, slot++});
+    }
+    B.nnz = M.nnz();
+    return true;
+}
+
 struct HostLayout {
     int fmt = DFAMG_FORMAT_SELL;
-    bool ok = false;          // false: 16-bit columns requested but do not fit
+    bool ok = false;          // false: 16-bit columns requested but do not fit, or no 4 x 4 blocks
     HostSell S;
     HostCsrv C;
+    HostBsr Bs;
 };
 
 struct HostKey {
@@ -146,13 +202,16 @@ struct HostKey {
 inline int csr_tile_rows_of(const Layout &L) { return L.rpg > 0 ? L.rpg * (kBlock / L.par) : kBlock; }
 
 HostKey host_key(const Layout &L) {
+    if (L.fmt == DFAMG_FORMAT_BSR4) return HostKey{L.fmt, 4, 0, 0, kBlock};
     if (L.fmt == DFAMG_FORMAT_SELL) return HostKey{L.fmt, L.par, L.sorted ? 1 : 0, (L.idx16 || L.stage) ? 1 : 0, 0};
     return HostKey{L.fmt, L.par, 0, 0, csr_tile_rows_of(L)};
 }
 
 void build_host_layout(const Csr &M, const std::vector<RowRange> &ranges, const HostKey &k, HostLayout &H) {
     H.fmt = k.fmt;
-    if (k.fmt == DFAMG_FORMAT_SELL) {
+    if (k.fmt == DFAMG_FORMAT_BSR4) {
+        H.ok = make_bsr4(M, ranges, H.Bs);
+    } else if (k.fmt == DFAMG_FORMAT_SELL) {
         H.ok = make_sell(M, ranges, k.par, k.sorted != 0, k.idx16 != 0, H.S);
     } else {
         H.C = make_csrv(M, ranges, k.par, k.tile_rows);
@@ -208,7 +267,17 @@ bool upload_built(DevArena &ar, const HostLayout &H, const Layout &L, hipStream_
     D.fmt = L.fmt;
     D.par = L.par;
     std::vector<Tile> tiles;
-    if (L.fmt == DFAMG_FORMAT_SELL) {
+    if (L.fmt == DFAMG_FORMAT_BSR4) {
+        const HostBsr &B = H.Bs;
+        tiles = B.tiles;
+        D.ptr = ar.upload(B.bptr, s);
+        D.col = ar.upload(B.bcol, s);
+        std::vector<VT> v(B.val.size());
+        for (size_t i = 0; i < v.size(); ++i) v[i] = (VT)B.val[i];
+        D.val = ar.upload(v, s);
+        D.nnz = B.nnz;
+        D.stored = (int64_t)B.val.size();
+    } else if (L.fmt == DFAMG_FORMAT_SELL) {
         const HostSell &S = H.S;
         if (L.stage) {
             const int32_t mx = S.cspan.empty() ? 1 : *std::max_element(S.cspan.begin(), S.cspan.end());
@@ -462,7 +531,8 @@ uint64_t structure_hash(const Csr &M, const std::vector<RowRange> &ranges) {
 template <class VT>
 DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, int format,
                         bool autotune, TuneKind kind, hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys,
-                        int nsub, const std::function<double(const DevMat<VT> &)> &timer = {}, int verbose = 0) {
+                        int nsub, const std::function<double(const DevMat<VT> &)> &timer = {}, int verbose = 0,
+                        bool bsr4 = false) {
     int64_t rows = 0;
     for (auto &r : ranges) rows += r.nrows;
     const double avg_len = rows ? (double)M.nnz() / (double)rows : 0.0;
@@ -472,7 +542,9 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     // gather lists only (the outer operator as plain CSR)
     const bool gather = format == DFAMG_FORMAT_CSR_GATHER;
     const int family = gather ? DFAMG_FORMAT_CSR : format;
-    if (!autotune) {
+    if (family == DFAMG_FORMAT_BSR4) {
+        cand.push_back(Layout{DFAMG_FORMAT_BSR4, 4, false, false, false, 0});
+    } else if (!autotune) {
         if (gather && !outer) {
             Layout c{DFAMG_FORMAT_CSR, 8, false, false, true, 0};
             c.glist = true;
@@ -491,6 +563,8 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
                 }
             }
         }
+        // 4 x 4 blocks for point-block operators
+        if (family == DFAMG_FORMAT_AUTO && bsr4) cand.push_back(Layout{DFAMG_FORMAT_BSR4, 4, false, false, false, 0});
         if ((family == DFAMG_FORMAT_CSR || family == DFAMG_FORMAT_AUTO) &&
             (avg_len >= 10.0 || family == DFAMG_FORMAT_CSR))
             for (int l : outer ? std::vector<int>{8, 16} : std::vector<int>{4, 8, 16})
@@ -704,6 +778,7 @@ OffM upload_off(DevArena &ar, const HostOff &off, const DevMat<double> &D, hipSt
 // Short text of a chosen layout, e.g. "sell2/i16/stage" or "csr8/t64".
 template <class VT>
 std::string describe(const DevMat<VT> &D) {
+    if (D.fmt == DFAMG_FORMAT_BSR4) return "bsr4";
     std::string t = D.fmt == DFAMG_FORMAT_SELL ? "sell" + std::to_string(D.par) : "csr" + std::to_string(D.par);
     if (D.fmt == DFAMG_FORMAT_SELL) {
         t += D.idx16 ? "/i16" : "/i32";
@@ -925,9 +1000,9 @@ struct Hierarchy_dev : PrecondBase {
                 D.z = ar.alloc<VT>(PL.nrows);
                 const auto rr = ranges_of(PL, PL.active_subs);
                 D.A = upload_tuned<VT>(ar, PL.A, rr, format, autotune, TUNE_SMOOTH, s, plan.sub_sys, plan.nsys,
-                                       plan.nsub, {}, verbose);
+                                       plan.nsub, {}, verbose, plan.bs == 4);
                 D.P = upload_tuned<VT>(ar, PL.P, rr, format, autotune, TUNE_PROLONG, s, plan.sub_sys, plan.nsys,
-                                       plan.nsub, {}, verbose);
+                                       plan.nsub, {}, verbose, plan.bs == 4);
                 const PackedLevel &PN = plan.levels[l + 1];
                 std::vector<int32_t> next_subs;
                 for (int sub = 0; sub < plan.nsub; ++sub)
@@ -939,18 +1014,19 @@ struct Hierarchy_dev : PrecondBase {
                     const auto rn = ranges_of(PN, next_subs);
                     DevArena arR, arB;
                     D.R = upload_tuned<VT>(arR, PL.R, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys, plan.nsys,
-                                           plan.nsub, {}, verbose);
+                                           plan.nsub, {}, verbose, plan.bs == 4);
                     // B holds exactly one pre-smoothing sweep from the zero guess
                     bool clustered = false;
                     DevArena arBc;
                     if (autotune && !block && npre == 1) {
                         D.B = upload_tuned<VT>(arB, PL.B, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
-                                               plan.nsys, plan.nsub, {}, verbose);
+                                               plan.nsys, plan.nsub, {}, verbose, plan.bs == 4);
                         // the rows in the clustered order: fewer distinct
                         // columns per tile, but wider column windows
                         if (PL.Bc.nnz() > 0) {
                             DevMat<VT> Bc = upload_tuned<VT>(arBc, PL.Bc, rn, format, autotune, TUNE_RESTRICT, s,
-                                                             plan.sub_sys, plan.nsys, plan.nsub, {}, verbose);
+                                                             plan.sub_sys, plan.nsys, plan.nsub, {}, verbose,
+                                                             plan.bs == 4);
                             if (Bc.tuned_us < D.B.tuned_us) {
                                 D.B = Bc;
                                 clustered = true;
@@ -1449,12 +1525,13 @@ void Handle::setup_device() {
         const bool tune = prm.autotune != 0;
         DevArena arF, arS;
         const DevMat<double> AF = upload_tuned<double>(arF, P.A, rr, prm.spmv_format, tune, TUNE_OUTER, sm,
-                                                       P.sub_sys, nsys, nsub, make_timer(none), prm.verbose);
+                                                       P.sub_sys, nsys, nsub, make_timer(none), prm.verbose,
+                                                       P.bs == 4);
         bool split = false;
         DevMat<double> AS;
         if (tune && !off.col.empty()) {
             AS = upload_tuned<double>(arS, loc, rr, prm.spmv_format, tune, TUNE_OUTER, sm, P.sub_sys, nsys, nsub,
-                                      make_timer(off), prm.verbose);
+                                      make_timer(off), prm.verbose, P.bs == 4);
             split = AS.tuned_us < AF.tuned_us;
         }
         ar.adopt(split ? arS : arF);
@@ -1693,7 +1770,9 @@ void Handle::setup_device() {
         prof.bytes[KID_SPMV] = nnzA * 12.0 + 4.0 * (nd + 1.0) + 16.0 * nd + zbytes;
         {
             const double ib = A.fmt == DFAMG_FORMAT_SELL ? (A.idx16 ? 2.0 : 4.0) : 4.0;
-            double b = (double)A.stored * (8.0 + ib) + 16.0 * nd;
+            double b = A.fmt == DFAMG_FORMAT_BSR4
+                           ? (double)A.stored * 8.0 + (double)A.stored / 16.0 * 4.0 + 4.0 * (nd / 4.0 + 1.0) + 16.0 * nd
+                           : (double)A.stored * (8.0 + ib) + 16.0 * nd;
             if (A.fmt == DFAMG_FORMAT_CSR) b += 4.0 * nd;
             if (A.sorted) b += 2.0 * nd;
             if (outer_split) b += 12.0 * (double)outer_off_nnz + 4.0 * nd;

@@ -25,7 +25,7 @@ struct Layout {
 
 template <class VT>
 struct DevMat {
-    int fmt = DFAMG_FORMAT_SELL;  // DFAMG_FORMAT_SELL or DFAMG_FORMAT_CSR
+    int fmt = DFAMG_FORMAT_SELL;  // DFAMG_FORMAT_SELL, _CSR or _BSR4 (ptr, col: block rows / columns)
     int par = 1;                  // rows per lane (SELL) or lanes per row (CSR)
     bool idx16 = false, sorted = false, stage = false;
     DevTile *tiles = nullptr;
@@ -59,6 +59,10 @@ void with_mat(const DevMat<VT> &M, Fn &&fn) {
     fn(SellM<VT, R, I, S>{M.tiles, M.soff, M.sw, M.col, M.col16, M.cbase, M.cspan, M.ridx, M.val, M.ntiles})
 #define DFAMG_CSR(L, S) \
     fn(CsrM<VT, L, S>{M.tiles, M.ptr, M.col, M.cbase, M.cspan, M.val, M.ntiles, M.uoff, M.ucol, M.col16})
+    if (M.fmt == DFAMG_FORMAT_BSR4) {
+        fn(BsrM<VT>{M.tiles, M.ptr, M.col, M.val, M.ntiles});
+        return;
+    }
     if (M.fmt == DFAMG_FORMAT_SELL) {
         if (!M.stage) {
             if (M.idx16) {

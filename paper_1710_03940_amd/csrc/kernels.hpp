@@ -101,6 +101,19 @@ struct CsrM {
     const uint16_t *col16;
 };
 
+// BSR with 4 x 4 blocks: one column index per block (the block's first
+// scalar column / 4), 16 values per block, row-major within the block;
+// bptr over the block rows of the whole matrix.  Tiles hold 256 rows (64
+// block rows) of one subdomain.
+template <class VT>
+struct BsrM {
+    const DevTile *tiles;
+    const int32_t *bptr;
+    const int32_t *bcol;
+    const VT *val;
+    int32_t ntiles;
+};
+
 __device__ __forceinline__ int tile_of_block(int ntiles) {
     const int per = (ntiles + 7) >> 3;
     return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
@@ -229,6 +242,43 @@ __device__ __forceinline__ void for_rows(const CsrM<VT, L, STAGE> &M, int tile, 
     };
     if (STAGE && M.ucol) rows(M.col16);
     else rows(M.col);
+}
+
+// BSR4: thread t takes row t of the tile; the four threads of a block row
+// read the block's column once and their own row of each block (16 bytes
+// of FP32 or 32 of FP64, one 64- or 128-byte segment per block row), and the
+// four gathered entries the block row shares.
+template <class ACC, class VT, class SRC, class F>
+__device__ __forceinline__ void for_rows(const BsrM<VT> &M, int tile, const DevTile &T, SRC src, F f) {
+    (void)tile;
+    const int lr = threadIdx.x;
+    if (lr >= T.nrows) return;
+    const int row = T.row0 + lr, br = row >> 2, r = row & 3;
+    const int k0 = M.bptr[br], k1 = M.bptr[br + 1];
+    ACC acc = 0;
+    for (int k = k0; k < k1; ++k) {
+        const int c = 4 * stream_load(M.bcol + k);
+        const VT *v = M.val + (int64_t)k * 16 + r * 4;
+        VT a[4];
+        if constexpr (sizeof(VT) == 8) {
+            const f64x2 p0 = stream_load(reinterpret_cast<const f64x2 *>(v));
+            const f64x2 p1 = stream_load(reinterpret_cast<const f64x2 *>(v) + 1);
+            a[0] = p0.x;
+            a[1] = p0.y;
+            a[2] = p1.x;
+            a[3] = p1.y;
+        } else {
+            typedef float f32x4 __attribute__((ext_vector_type(4)));
+            const f32x4 p = stream_load(reinterpret_cast<const f32x4 *>(v));
+            a[0] = p.x;
+            a[1] = p.y;
+            a[2] = p.z;
+            a[3] = p.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += (ACC)a[q] * (ACC)src(c + q);
+    }
+    f(row, acc);
 }
 
 // Rows of a tile for kernels without a matrix: thread t takes rows t, t+256, ..
