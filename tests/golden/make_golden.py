@@ -20,6 +20,27 @@ from oracle import OracleSolver, OracleParams  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 NSAMPLE = 2000
+NSTRATUM = 64
+
+
+def strata(P):
+    """Stratified entries where a layout or tiling mistake would show first:
+    for every subdomain its first and last NSTRATUM unknowns (ascending
+    index, the first and last rows of its tiles) and up to NSTRATUM evenly
+    spaced unknowns coupled to another subdomain."""
+    part = np.asarray(P.part)
+    A = P.A.tocsr()
+    rows = np.repeat(np.arange(P.n), np.diff(A.indptr))
+    coupled = np.zeros(P.n, dtype=bool)
+    coupled[rows[part[rows] != part[A.indices]]] = True
+    pick = []
+    for s in range(P.nsub):
+        r = np.flatnonzero(part == s)
+        pick += [r[:NSTRATUM], r[-NSTRATUM:]]
+        c = r[coupled[r]]
+        if c.size:
+            pick.append(c[np.linspace(0, c.size - 1, min(NSTRATUM, c.size)).astype(np.int64)])
+    return np.unique(np.concatenate(pick))
 
 
 def record(name, P, prm=None):
@@ -38,12 +59,14 @@ def record(name, P, prm=None):
         "x_norm": float(np.linalg.norm(r["x"])),
         "sample_index": [int(i) for i in idx],
         "sample_x": [float(v) for v in r["x"][idx]],
+        "strata_index": [int(i) for i in strata(P)],
+        "strata_x": [float(v) for v in r["x"][strata(P)]],
         "hierarchy_sub0": [list(map(float, lv)) for lv in S.hierarchy_summary()[0]],
         "oracle_setup_s": t1 - t0, "oracle_solve_s": t2 - t1,
         "source": "oracle/ (CPU FP64) via tests/golden/make_golden.py",
     }
     with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
-        json.dump(out, fh, indent=1)
+        json.dump(out, fh)
     print(name, out["iters"], out["relres_true"], f"setup {t1 - t0:.1f}s solve {t2 - t1:.1f}s")
 
 
@@ -79,11 +102,13 @@ def record_batched():
                            "relres_true": float(r["relres_true"]),
                            "x_norm": float(np.linalg.norm(r["x"])),
                            "sample_index": [int(i) for i in idx],
-                           "sample_x": [float(v) for v in r["x"][idx]]}
+                           "sample_x": [float(v) for v in r["x"][idx]],
+                           "strata_index": [int(i) for i in strata(P)],
+                           "strata_x": [float(v) for v in r["x"][strata(P)]]}
         print("batched system", s, P.n, r["iters"])
     with open(os.path.join(HERE, "batched48_sample.json"), "w") as fh:
         json.dump({"workload": "batched48_lognormal1_linear", "systems": systems,
-                   "source": "oracle/ (CPU FP64) via tests/golden/make_golden.py"}, fh, indent=1)
+                   "source": "oracle/ (CPU FP64) via tests/golden/make_golden.py"}, fh)
 
 
 if __name__ == "__main__":

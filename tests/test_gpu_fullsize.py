@@ -2,7 +2,8 @@
 configuration the benchmark times (autotuned layouts, captured graphs).  The
 oracle's result is stored in tests/golden (written by make_golden.py, which
 only calls oracle/): iteration count, residual history and 2000 sampled
-solution entries."""
+solution entries, plus stratified ones per subdomain on the records that
+hold them."""
 import json
 import os
 
@@ -46,6 +47,24 @@ def _golden(name):
         return json.load(fh)
 
 
+def _check_entries(x, g):
+    """x against the oracle's stored entries: the 2000 random samples and,
+    where the record holds them, the stratified ones (each subdomain's first
+    and last unknowns, where its tiles begin and end, and unknowns coupled to
+    another subdomain), which a tiling or boundary mistake reaches first.
+    Each set within 1e-6 of its norm, and the stratified ones entry by entry
+    within 1e-6 of the largest entry stored."""
+    idx = np.array(g["sample_index"])
+    gs = np.array(g["sample_x"])
+    assert np.linalg.norm(x[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+    if "strata_index" in g:
+        si = np.array(g["strata_index"])
+        sx = np.array(g["strata_x"])
+        assert np.linalg.norm(x[si] - sx) <= 1e-6 * np.linalg.norm(sx)
+        worst = np.abs(x[si] - sx).max()
+        assert worst <= 1e-6 * np.abs(sx).max(), worst
+
+
 @pytest.fixture(scope="module")
 def lognormal150():
     from workloads import config_lognormal_poisson
@@ -78,10 +97,7 @@ def test_lognormal150_matches_oracle(lognormal150, precision):
         assert np.allclose(out["history"][:k], g["history"][:k], rtol=1e-5, atol=0)
     else:
         assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
-    idx = np.array(g["sample_index"])
-    xs = x.cpu().numpy()[idx]
-    gs = np.array(g["sample_x"])
-    assert np.linalg.norm(xs - gs) <= 1e-6 * np.linalg.norm(gs)
+    _check_entries(x.cpu().numpy(), g)
     # the whole solution has the oracle's norm
     assert abs(np.linalg.norm(x.cpu().numpy()) - g["x_norm"]) <= 1e-6 * g["x_norm"]
 
@@ -113,9 +129,7 @@ def test_batched48_matches_oracle_on_sampled_systems(precision):
         else:
             assert it <= int(np.floor(1.15 * gs["iters"])) + 1
         seg = xs[off[s]:off[s + 1]]
-        idx = np.array(gs["sample_index"])
-        ref = np.array(gs["sample_x"])
-        assert np.linalg.norm(seg[idx] - ref) <= 1e-6 * np.linalg.norm(ref)
+        _check_entries(seg, gs)
         assert abs(np.linalg.norm(seg) - gs["x_norm"]) <= 1e-6 * gs["x_norm"]
 
 
@@ -143,9 +157,7 @@ def test_oseen64_matches_oracle(precision):
     else:
         assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
     xs = x.cpu().numpy()
-    idx = np.array(g["sample_index"])
-    gs = np.array(g["sample_x"])
-    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+    _check_entries(xs, g)
     assert abs(np.linalg.norm(xs) - g["x_norm"]) <= 1e-6 * g["x_norm"]
 
 
@@ -171,9 +183,7 @@ def test_lognormal150_bicgstab2_matches_oracle(lognormal150, precision):
     else:
         assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
     xs = x.cpu().numpy()
-    idx = np.array(g["sample_index"])
-    gs = np.array(g["sample_x"])
-    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+    _check_entries(xs, g)
 
 
 @pytest.mark.parametrize("coarse,precision", [("exact", "fp64"), ("fp32", "fp64"), ("fp32", "mixed")])
@@ -200,9 +210,7 @@ def test_lognormal150_fgmres_matches_oracle(lognormal150, coarse, precision):
     else:
         assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
     xs = x.cpu().numpy()
-    idx = np.array(g["sample_index"])
-    gs = np.array(g["sample_x"])
-    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+    _check_entries(xs, g)
 
 
 def test_lognormal150_fgmres_cg_coarse_matches_oracle(lognormal150):
@@ -224,9 +232,7 @@ def test_lognormal150_fgmres_cg_coarse_matches_oracle(lognormal150):
     _check_drift(out)
     assert abs(out["iters"] - g["iters"]) <= 2
     xs = x.cpu().numpy()
-    idx = np.array(g["sample_index"])
-    gs = np.array(g["sample_x"])
-    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+    _check_entries(xs, g)
 
 
 def test_oseen64_schur_matches_oracle():
@@ -249,9 +255,7 @@ def test_oseen64_schur_matches_oracle():
     _check_drift(out)
     assert abs(out["iters"] - g["iters"]) <= 2
     xs = x.cpu().numpy()
-    idx = np.array(g["sample_index"])
-    gs = np.array(g["sample_x"])
-    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+    _check_entries(xs, g)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -277,6 +281,4 @@ def test_oseen64_block_spai0_matches_oracle(precision):
     else:
         assert out["iters"] <= int(np.floor(1.15 * g["iters"])) + 1
     xs = x.cpu().numpy()
-    idx = np.array(g["sample_index"])
-    gs = np.array(g["sample_x"])
-    assert np.linalg.norm(xs[idx] - gs) <= 1e-6 * np.linalg.norm(gs)
+    _check_entries(xs, g)
