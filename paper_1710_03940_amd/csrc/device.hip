@@ -184,12 +184,151 @@ bool make_bsr4(const Csr &M, const std::vector<RowRange> &ranges, HostBsr &B) {
     return true;
 }
 
+// Host form of the column-tiled layout (SegM): every range's columns (the
+// columns its rows touch) cut into tiles of `ct` columns; a row's entries in
+// one tile form a segment (a new segment starts wherever the tile of the next
+// entry differs, so the split holds for rows in any column order).
+struct HostSeg {
+    std::vector<Tile> ctiles;       // column tiles (row0 = first column, nrows = width)
+    std::vector<int32_t> slices;    // [ctiles + 1]
+    std::vector<int64_t> soff;      // per slice
+    std::vector<int32_t> sw;        // per slice
+    std::vector<uint16_t> col16;
+    std::vector<double> val;
+    std::vector<int32_t> slot;      // 64 per slice
+    std::vector<int32_t> pp;        // [nrows + 1]: partials of each row
+    std::vector<Tile> rtiles;       // 256-row tiles of the ranges, for the combine step
+    int64_t nnz = 0;
+    int32_t widest = 1;             // widest column tile
+};
+
+bool make_seg(const Csr &M, const std::vector<RowRange> &ranges, int ct, HostSeg &S) {
+    if (ct < 64 || ct > 65536 || M.nrows > INT32_MAX) return false;
+    const int nr = (int)ranges.size();
+    // pass 1: segments per row
+    std::vector<int32_t> cnt(M.nrows, 0);
+    std::vector<int32_t> fmin(nr, 0), ntile(nr, 0);
+    parallel_for(nr, 8, [&](int64_t r) {
+        const RowRange &rg = ranges[r];
+        int32_t lo = INT32_MAX, hi = -1;
+        for (int64_t k = M.ptr[rg.row0]; k < M.ptr[rg.row0 + rg.nrows]; ++k) {
+            lo = std::min(lo, M.col[k]);
+            hi = std::max(hi, M.col[k]);
+        }
+        if (hi < 0) return;
+        fmin[r] = lo;
+        ntile[r] = (hi - lo) / ct + 1;
+        for (int64_t i = rg.row0; i < rg.row0 + rg.nrows; ++i) {
+            int last = -1;
+            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) {
+                const int t = (M.col[k] - lo) / ct;
+                if (t != last) ++cnt[i];
+                last = t;
+            }
+        }
+    });
+    S.pp.assign(M.nrows + 1, 0);
+    for (int64_t i = 0; i < M.nrows; ++i) {
+        if ((int64_t)S.pp[i] + cnt[i] > INT32_MAX) return false;
+        S.pp[i + 1] = S.pp[i] + cnt[i];
+    }
+    // pass 2: every range's tiles and slices (offsets local to the range)
+    struct Part {
+        std::vector<Tile> ct;
+        std::vector<int32_t> first_slice;
+        std::vector<int64_t> soff;
+        std::vector<int32_t> sw, slot;
+        std::vector<uint16_t> col16;
+        std::vector<double> val;
+    };
+    std::vector<Part> parts(nr);
+    parallel_for(nr, 8, [&](int64_t r) {
+        const RowRange &rg = ranges[r];
+        Part &P = parts[r];
+        const int nt = ntile[r];
+        struct Segm {
+            int32_t len, row;
+            int64_t k0;
+            int32_t slot;
+        };
+        std::vector<std::vector<Segm>> per(nt);
+        for (int64_t i = rg.row0; i < rg.row0 + rg.nrows; ++i) {
+            int32_t rank = 0;
+            int64_t k = M.ptr[i];
+            while (k < M.ptr[i + 1]) {
+                const int t = (M.col[k] - fmin[r]) / ct;
+                int64_t e = k;
+                while (e < M.ptr[i + 1] && (M.col[e] - fmin[r]) / ct == t) ++e;
+                per[t].push_back(Segm{(int32_t)(e - k), (int32_t)i, k, S.pp[i] + rank++});
+                k = e;
+            }
+        }
+        int64_t stored = 0;
+        for (int t = 0; t < nt; ++t) {
+            auto &sg = per[t];
+            std::stable_sort(sg.begin(), sg.end(), [](const Segm &a, const Segm &b) { return a.len > b.len; });
+            const int32_t c0 = fmin[r] + t * ct;
+            P.ct.push_back(Tile{c0, 0, rg.sub, 0});
+            P.first_slice.push_back((int32_t)P.sw.size());
+            int32_t cmax = c0;
+            for (size_t s0 = 0; s0 < sg.size(); s0 += 64) {
+                const int32_t w = sg[s0].len;
+                P.soff.push_back(stored);
+                P.sw.push_back(w);
+                P.val.resize((size_t)(stored + (int64_t)w * 64), 0.0);
+                P.col16.resize((size_t)(stored + (int64_t)w * 64), 0);
+                for (int l = 0; l < 64; ++l) {
+                    if (s0 + l >= sg.size()) {
+                        P.slot.push_back(-1);
+                        continue;
+                    }
+                    const Segm &q = sg[s0 + l];
+                    P.slot.push_back(q.slot);
+                    for (int32_t e = 0; e < q.len; ++e) {
+                        const int32_t c = M.col[q.k0 + e];
+                        P.val[(size_t)(stored + (int64_t)e * 64 + l)] = M.val[q.k0 + e];
+                        P.col16[(size_t)(stored + (int64_t)e * 64 + l)] = (uint16_t)(c - c0);
+                        cmax = std::max(cmax, c);
+                    }
+                }
+                stored += (int64_t)w * 64;
+            }
+            P.ct.back().nrows = cmax - c0 + 1;
+        }
+    });
+    // pass 3: concatenation
+    int64_t stored = 0;
+    for (int r = 0; r < nr; ++r) {
+        Part &P = parts[r];
+        const int32_t sbase = (int32_t)S.sw.size();
+        for (size_t t = 0; t < P.ct.size(); ++t) {
+            S.ctiles.push_back(P.ct[t]);
+            S.slices.push_back(sbase + P.first_slice[t]);
+            S.widest = std::max(S.widest, P.ct[t].nrows);
+        }
+        for (int64_t o : P.soff) S.soff.push_back(stored + o);
+        S.sw.insert(S.sw.end(), P.sw.begin(), P.sw.end());
+        S.slot.insert(S.slot.end(), P.slot.begin(), P.slot.end());
+        S.col16.insert(S.col16.end(), P.col16.begin(), P.col16.end());
+        S.val.insert(S.val.end(), P.val.begin(), P.val.end());
+        stored += (int64_t)P.val.size();
+        const RowRange &rg = ranges[r];
+        for (int32_t r0 = 0; r0 < rg.nrows; r0 += kBlock)
+            S.rtiles.push_back(Tile{(int32_t)(rg.row0 + r0), std::min(kBlock, rg.nrows - r0), rg.sub, 0});
+        P = Part{};
+    }
+    S.slices.push_back((int32_t)S.sw.size());
+    S.nnz = M.nnz();
+    return !S.ctiles.empty();
+}
+
 struct HostLayout {
     int fmt = DFAMG_FORMAT_SELL;
     bool ok = false;          // false: 16-bit columns requested but do not fit, or no 4 x 4 blocks
     HostSell S;
     HostCsrv C;
     HostBsr Bs;
+    HostSeg G;
 };
 
 struct HostKey {
@@ -203,6 +342,7 @@ inline int csr_tile_rows_of(const Layout &L) { return L.rpg > 0 ? L.rpg * (kBloc
 
 HostKey host_key(const Layout &L) {
     if (L.fmt == DFAMG_FORMAT_BSR4) return HostKey{L.fmt, 4, 0, 0, kBlock};
+    if (L.fmt == kFormatSeg) return HostKey{L.fmt, L.par, 0, 0, 0};
     if (L.fmt == DFAMG_FORMAT_SELL) return HostKey{L.fmt, L.par, L.sorted ? 1 : 0, (L.idx16 || L.stage) ? 1 : 0, 0};
     return HostKey{L.fmt, L.par, 0, 0, csr_tile_rows_of(L)};
 }
@@ -211,6 +351,8 @@ void build_host_layout(const Csr &M, const std::vector<RowRange> &ranges, const 
     H.fmt = k.fmt;
     if (k.fmt == DFAMG_FORMAT_BSR4) {
         H.ok = make_bsr4(M, ranges, H.Bs);
+    } else if (k.fmt == kFormatSeg) {
+        H.ok = make_seg(M, ranges, k.par, H.G);
     } else if (k.fmt == DFAMG_FORMAT_SELL) {
         H.ok = make_sell(M, ranges, k.par, k.sorted != 0, k.idx16 != 0, H.S);
     } else {
@@ -267,7 +409,28 @@ bool upload_built(DevArena &ar, const HostLayout &H, const Layout &L, hipStream_
     D.fmt = L.fmt;
     D.par = L.par;
     std::vector<Tile> tiles;
-    if (L.fmt == DFAMG_FORMAT_BSR4) {
+    if (L.fmt == kFormatSeg) {
+        const HostSeg &G = H.G;
+        if ((size_t)G.widest * sizeof(VT) > stage_limit) return false;
+        tiles = G.ctiles;
+        D.stage = true;
+        D.max_span = G.widest;
+        D.seg_slices = ar.upload(G.slices, s);
+        D.soff = ar.upload(G.soff, s);
+        D.sw = ar.upload(G.sw, s);
+        D.col16 = ar.upload(G.col16, s);
+        std::vector<VT> v(G.val.size());
+        for (size_t i = 0; i < v.size(); ++i) v[i] = (VT)G.val[i];
+        D.val = ar.upload(v, s);
+        D.seg_slot = ar.upload(G.slot, s);
+        D.seg_pp = ar.upload(G.pp, s);
+        D.seg_rtiles = ar.upload(to_dev_tiles(G.rtiles), s);
+        D.seg_nrt = (int32_t)G.rtiles.size();
+        D.seg_part = ar.alloc<VT>(std::max<int64_t>(1, G.pp.back()));
+        D.seg_nt = L.rpg == 4 ? 1024 : L.rpg == 2 ? 512 : 256;
+        D.nnz = G.nnz;
+        D.stored = (int64_t)G.val.size();
+    } else if (L.fmt == DFAMG_FORMAT_BSR4) {
         const HostBsr &B = H.Bs;
         tiles = B.tiles;
         D.ptr = ar.upload(B.bptr, s);
@@ -565,10 +728,25 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
         }
         // 4 x 4 blocks for point-block operators
         if (family == DFAMG_FORMAT_AUTO && bsr4) cand.push_back(Layout{DFAMG_FORMAT_BSR4, 4, false, false, false, 0});
+        // restrictions split by column tiles of 16, 32 or 64 KB of the input
+        // vector (rows of 16+ entries)
+        if (family == DFAMG_FORMAT_AUTO && kind == TUNE_RESTRICT && avg_len >= 16.0)
+            for (int kb : {16, 32, 64})
+                for (int nt : {1, 2, 4})
+                    cand.push_back(Layout{kFormatSeg, kb * 1024 / (int)sizeof(VT), false, false, true, nt});
+        // lanes per row: 32 and 64 for the long rows of the restrictions
+        // (tens to hundreds of entries) and of the denser coarse operators
+        const std::vector<int> lane_set = outer                    ? std::vector<int>{8, 16}
+                                          : kind == TUNE_RESTRICT ? std::vector<int>{8, 16, 32, 64}
+                                          : avg_len >= 24.0       ? std::vector<int>{4, 8, 16, 32}
+                                                                  : std::vector<int>{4, 8, 16};
         if ((family == DFAMG_FORMAT_CSR || family == DFAMG_FORMAT_AUTO) &&
             (avg_len >= 10.0 || family == DFAMG_FORMAT_CSR))
-            for (int l : outer ? std::vector<int>{8, 16} : std::vector<int>{4, 8, 16})
-                for (int rpg : {0, 1, 4}) {
+            for (int l : lane_set)
+                // 256-row tiles, and tiles of 16/64 rows (32 and 64 lanes) or
+                // of kBlock/l and 4 kBlock/l rows (fewer lanes)
+                for (int rpg : l == 64 ? std::vector<int>{0, 4, 16} : l == 32 ? std::vector<int>{0, 2, 8}
+                                                                                : std::vector<int>{0, 1, 4}) {
                     // smaller tiles where 256-row tiles leave the chip idle, and
                     // for restrictions (long rows gathering from a wide window)
                     if (rpg > 0 && (outer || (rows / 256 >= 2048 && kind != TUNE_RESTRICT))) continue;
@@ -779,6 +957,7 @@ OffM upload_off(DevArena &ar, const HostOff &off, const DevMat<double> &D, hipSt
 template <class VT>
 std::string describe(const DevMat<VT> &D) {
     if (D.fmt == DFAMG_FORMAT_BSR4) return "bsr4";
+    if (D.fmt == kFormatSeg) return "seg" + std::to_string(D.par) + "/b" + std::to_string(D.seg_nt);
     std::string t = D.fmt == DFAMG_FORMAT_SELL ? "sell" + std::to_string(D.par) : "csr" + std::to_string(D.par);
     if (D.fmt == DFAMG_FORMAT_SELL) {
         t += D.idx16 ? "/i16" : "/i32";

@@ -15,7 +15,13 @@
 
 namespace dfamg {
 
-// A layout candidate: SELL (par = rows per lane) or CSR (par = lanes per row)
+// Internal layout of the restrictions, chosen by the tuner only: the
+// operator split by column tiles of `par` columns (see SegM), 256 * rpg
+// threads per block.
+constexpr int kFormatSeg = 16;
+
+// A layout candidate: SELL (par = rows per lane), CSR (par = lanes per row),
+// BSR4, or column-tiled segments (par = columns per tile)
 struct Layout {
     int fmt, par;
     bool sorted, idx16, stage;
@@ -40,6 +46,14 @@ struct DevMat {
     int32_t *uoff = nullptr, *ucol = nullptr;   // gather list of the staged CSR form (null: window)
     VT *val = nullptr;
     int32_t *rowmap = nullptr;    // restriction B: output position of each stored row (null: the row itself)
+    // kFormatSeg: tiles are the column tiles; slices of each tile, per-lane
+    // partial slots, the row -> partials pointer, the row tiles of the
+    // combine step and its partial sums
+    int32_t *seg_slices = nullptr, *seg_slot = nullptr, *seg_pp = nullptr;
+    DevTile *seg_rtiles = nullptr;
+    int32_t seg_nrt = 0;
+    int32_t seg_nt = 256;         // threads per block of the partial-sum kernel
+    VT *seg_part = nullptr;
     int32_t max_span = 0;         // LDS entries of the staged layouts (window or gather list)
     int64_t nnz = 0, stored = 0;
     double tuned_us = 0.0;
@@ -53,6 +67,11 @@ struct DevMat {
 constexpr size_t kMaxStageBytes = 65536;
 
 // Calls fn(view) with the kernel view type of M.
+template <class VT>
+SegM<VT> seg_view(const DevMat<VT> &M) {
+    return SegM<VT>{M.tiles, M.seg_slices, M.soff, M.sw, M.col16, M.val, M.seg_slot, M.ntiles};
+}
+
 template <class VT, class Fn>
 void with_mat(const DevMat<VT> &M, Fn &&fn) {
 #define DFAMG_SELL(R, I, S) \
@@ -90,12 +109,16 @@ void with_mat(const DevMat<VT> &M, Fn &&fn) {
                 case 4: DFAMG_CSR(4, true); return;
                 case 8: DFAMG_CSR(8, true); return;
                 case 16: DFAMG_CSR(16, true); return;
+                case 32: DFAMG_CSR(32, true); return;
+                case 64: DFAMG_CSR(64, true); return;
             }
         } else {
             switch (M.par) {
                 case 4: DFAMG_CSR(4, false); return;
                 case 8: DFAMG_CSR(8, false); return;
                 case 16: DFAMG_CSR(16, false); return;
+                case 32: DFAMG_CSR(32, false); return;
+                case 64: DFAMG_CSR(64, false); return;
             }
         }
     }

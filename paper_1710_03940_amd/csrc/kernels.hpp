@@ -114,6 +114,26 @@ struct BsrM {
     int32_t ntiles;
 };
 
+// A restriction (or any operator whose rows are long and whose columns are
+// a contiguous range per subdomain) split by column tiles: every row's
+// entries in one column tile form a segment; a column tile's segments are
+// stored as SELL-64 slices (segments sorted by length, entry e of lane l at
+// soff[slice] + 64 e + l, 16-bit columns relative to the tile's first
+// column).  One block stages the tile's part of the input vector in LDS once
+// and writes one partial sum per segment to part[slot]; the partials of a
+// row are then added in column-tile order (k_seg_combine).
+template <class VT>
+struct SegM {
+    const DevTile *tiles;      // column tiles: row0 = first column, nrows = width, sub
+    const int32_t *slices;     // [ntiles + 1]: slices of each column tile
+    const int64_t *soff;
+    const int32_t *sw;
+    const uint16_t *col16;
+    const VT *val;
+    const int32_t *slot;       // [64 * slices]: partial of each lane, -1 = padding
+    int32_t ntiles;
+};
+
 __device__ __forceinline__ int tile_of_block(int ntiles) {
     const int per = (ntiles + 7) >> 3;
     return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
@@ -132,26 +152,54 @@ __device__ __forceinline__ T stream_load(const T *p) {
 extern __shared__ double dfamg_stage_lds[];
 
 // Copies src(cb + k), k < span, into LDS; every thread of the block calls it.
-template <class VT, class SRC>
+// Four loads per thread are issued before the first store, so a thread waits
+// for one memory latency per four entries rather than per entry.
+template <class VT, int NT = kBlock, class SRC>
 __device__ __forceinline__ VT *stage_window(int cb, int span, SRC src) {
     VT *lds = reinterpret_cast<VT *>(dfamg_stage_lds);
-    for (int k = threadIdx.x; k < span; k += kBlock) lds[k] = (VT)src(cb + k);
+    int k = threadIdx.x;
+    for (; k + 3 * NT < span; k += 4 * NT) {
+        VT v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (VT)src(cb + k + u * NT);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) lds[k + u * NT] = v[u];
+    }
+    for (; k < span; k += NT) lds[k] = (VT)src(cb + k);
     __syncthreads();
     return lds;
 }
 
 // Copies src(ucol[u0 + k]), k < u1 - u0, into LDS; every thread of the block
-// calls it.
+// calls it.  The list indices of four entries are loaded first, then their
+// four values, then the four stores.
 template <class VT, class SRC>
 __device__ __forceinline__ VT *stage_list(int u0, int u1, const int32_t *__restrict__ ucol, SRC src) {
     VT *lds = reinterpret_cast<VT *>(dfamg_stage_lds);
-    for (int k = threadIdx.x; k < u1 - u0; k += kBlock) lds[k] = (VT)src(ucol[u0 + k]);
+    const int n = u1 - u0;
+    const int32_t *__restrict__ uc = ucol + u0;
+    int k = threadIdx.x;
+    for (; k + 3 * kBlock < n; k += 4 * kBlock) {
+        int c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = uc[k + u * kBlock];
+        VT v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (VT)src(c[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) lds[k + u * kBlock] = v[u];
+    }
+    for (; k < n; k += kBlock) lds[k] = (VT)src(uc[k]);
     __syncthreads();
     return lds;
 }
 
-// sum_j val_j * x(cadd + col_j) over one SELL row (w entries, stride 64),
-// loads issued eight at a time
+// sum_j val_j * x(cadd + col_j) over one SELL row (w entries, stride 64; w
+// is the same for the whole wavefront).  Per chunk of eight entries the
+// column and value loads are issued first, then the eight gathers (entries
+// past w gather x(cadd), a valid position, and are not added), then the
+// sums in entry order: the gathers of a chunk are in flight together
+// instead of one memory round trip each.
 template <class VT, class ACC, class CT, class XF>
 __device__ __forceinline__ ACC sell_dot(const CT *__restrict__ col, int cadd, const VT *__restrict__ val,
                                         int64_t off, int w, XF x) {
@@ -161,14 +209,19 @@ __device__ __forceinline__ ACC sell_dot(const CT *__restrict__ col, int cadd, co
         VT v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
+            c[u] = cadd;
+            v[u] = 0;
             if (j0 + u < w) {
                 c[u] = cadd + (int)stream_load(col + off + (int64_t)(j0 + u) * 64);
                 v[u] = stream_load(val + off + (int64_t)(j0 + u) * 64);
             }
         }
+        ACC xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = (ACC)x(c[u]);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (j0 + u < w) acc += (ACC)v[u] * x(c[u]);
+            if (j0 + u < w) acc += (ACC)v[u] * xv[u];
     }
     return acc;
 }
@@ -180,7 +233,8 @@ template <class ACC, class VT, int RPL, bool I16, bool STAGE, class SRC, class F
 __device__ __forceinline__ void for_rows(const SellM<VT, RPL, I16, STAGE> &M, int tile, const DevTile &T, SRC src,
                                          F f) {
     static_assert(!STAGE || I16, "staged SELL needs 16-bit column offsets");
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    // the wavefront index is uniform: slice offsets and widths become scalar loads
+    const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
     const int cb = I16 ? M.cbase[tile] : 0;
     const VT *lds = nullptr;
     if (STAGE) lds = stage_window<VT>(cb, M.cspan[tile], src);
@@ -221,20 +275,39 @@ __device__ __forceinline__ void for_rows(const CsrM<VT, L, STAGE> &M, int tile, 
         if (STAGE) return lds[c - cb];
         return (VT)src(c);
     };
+    // Each lane keeps four entries of its row in flight (stride L), and the
+    // next row's pointers are loaded before the current row is summed.
     auto rows = [&](const auto *__restrict__ colp) {
-        for (int lr = g; lr < T.nrows; lr += G) {
+        int lr = g;
+        int n0 = 0, n1 = 0;
+        if (lr < T.nrows) {
+            n0 = M.ptr[T.row0 + lr];
+            n1 = M.ptr[T.row0 + lr + 1];
+        }
+        for (; lr < T.nrows; lr += G) {
             const int row = T.row0 + lr;
-            const int k0 = M.ptr[row], k1 = M.ptr[row + 1];
-            ACC a0 = 0, a1 = 0;
-            int k = k0 + lane;
-            for (; k + L < k1; k += 2 * L) {
-                const int c0 = (int)stream_load(colp + k), c1 = (int)stream_load(colp + k + L);
-                const ACC v0 = (ACC)stream_load(M.val + k), v1 = (ACC)stream_load(M.val + k + L);
-                a0 += v0 * x(c0);
-                a1 += v1 * x(c1);
+            const int k0 = n0, k1 = n1;
+            if (lr + G < T.nrows) {
+                n0 = M.ptr[row + G];
+                n1 = M.ptr[row + G + 1];
             }
-            if (k < k1) a0 += (ACC)stream_load(M.val + k) * x((int)stream_load(colp + k));
-            ACC acc = a0 + a1;
+            ACC a[4] = {0, 0, 0, 0};
+            int k = k0 + lane;
+            for (; k + 3 * L < k1; k += 4 * L) {
+                int c[4];
+                ACC v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    c[u] = (int)stream_load(colp + k + u * L);
+                    v[u] = (ACC)stream_load(M.val + k + u * L);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] += v[u] * x(c[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                if (k + u * L < k1) a[u] += (ACC)stream_load(M.val + k + u * L) * x((int)stream_load(colp + k + u * L));
+            ACC acc = (a[0] + a[1]) + (a[2] + a[3]);
 #pragma unroll
             for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
             if (lane == 0) f(row, acc);
@@ -1275,6 +1348,46 @@ __global__ void __launch_bounds__(kBlock) k_restrict(MAT B, const FT *__restrict
     if (st && st[sub_sys[T.sub]].done) return;
     for_rows<VT>(B, tile, T, [&](int c) { return (VT)f[c]; },
                  [&](int row, VT v) { fc[rowmap ? rowmap[row] : row] = v; });
+}
+
+// Partial sums of the segments of a column-tiled operator (see SegM); NT
+// threads per block, one column tile per block, wavefront w taking slices
+// w, w + NT/64, ...
+template <class VT, class FT, int NT>
+__global__ void __launch_bounds__(NT) k_seg_partial(SegM<VT> M, const FT *__restrict__ f, VT *__restrict__ part,
+                                                    const SysState *__restrict__ st,
+                                                    const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(M.ntiles);
+    if (tile >= M.ntiles) return;
+    const DevTile T = M.tiles[tile];
+    if (st && st[sub_sys[T.sub]].done) return;
+    const VT *lds = stage_window<VT, NT>(T.row0, T.nrows, [&](int c) { return (VT)f[c]; });
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int s1 = M.slices[tile + 1];
+    for (int sl = M.slices[tile] + w; sl < s1; sl += NT / 64) {
+        const VT acc = sell_dot<VT, VT>(M.col16, 0, M.val, M.soff[sl] + lane, M.sw[sl], [&](int c) { return lds[c]; });
+        const int q = M.slot[(int64_t)sl * 64 + lane];
+        if (q >= 0) part[q] = acc;
+    }
+}
+
+// y[rowmap ? rowmap[row] : row] = sum of the row's partials part[pp[row] ..
+// pp[row + 1]) in column-tile order; `rt` tiles the rows.
+template <class VT>
+__global__ void __launch_bounds__(kBlock) k_seg_combine(const DevTile *__restrict__ rt, int32_t nrt,
+                                                        const int32_t *__restrict__ pp, const VT *__restrict__ part,
+                                                        VT *__restrict__ y, const int32_t *__restrict__ rowmap,
+                                                        const SysState *__restrict__ st,
+                                                        const int32_t *__restrict__ sub_sys) {
+    const int tile = tile_of_block(nrt);
+    if (tile >= nrt) return;
+    const DevTile T = rt[tile];
+    if (st && st[sub_sys[T.sub]].done) return;
+    for_tile_rows(T, [&](int row) {
+        VT acc = 0;
+        for (int q = pp[row]; q < pp[row + 1]; ++q) acc += part[q];
+        y[rowmap ? rowmap[row] : row] = acc;
+    });
 }
 
 // z = m o f + P xc   (pre-smoothed iterate plus the coarse correction)

@@ -14,9 +14,35 @@ void launch_pre_res(const DevMat<VT> &A, const VT *m, const FT *f, VT *res, cons
     });
 }
 
+// The two launches of a column-tiled operator: partial sums per segment, then
+// their sum per row.
+template <class VT, class FT>
+void launch_seg(const DevMat<VT> &M, const FT *x, VT *y, const SysState *st, const int32_t *sub_sys,
+                hipStream_t s) {
+    switch (M.seg_nt) {
+        case 1024:
+            hipLaunchKernelGGL((k_seg_partial<VT, FT, 1024>), dim3(grid_for_tiles(M.ntiles)), dim3(1024),
+                               M.stage_bytes(), s, seg_view(M), x, M.seg_part, st, sub_sys);
+            break;
+        case 512:
+            hipLaunchKernelGGL((k_seg_partial<VT, FT, 512>), dim3(grid_for_tiles(M.ntiles)), dim3(512),
+                               M.stage_bytes(), s, seg_view(M), x, M.seg_part, st, sub_sys);
+            break;
+        default:
+            hipLaunchKernelGGL((k_seg_partial<VT, FT, 256>), dim3(grid_for_tiles(M.ntiles)), dim3(256),
+                               M.stage_bytes(), s, seg_view(M), x, M.seg_part, st, sub_sys);
+    }
+    hipLaunchKernelGGL((k_seg_combine<VT>), dim3(grid_for_tiles(M.seg_nrt)), dim3(kBlock), 0, s, M.seg_rtiles,
+                       M.seg_nrt, M.seg_pp, M.seg_part, y, M.rowmap, st, sub_sys);
+}
+
 template <class VT>
 void launch_spmv(const DevMat<VT> &M, const VT *x, VT *y, const SysState *st, const int32_t *sub_sys,
                  hipStream_t s) {
+    if (M.fmt == kFormatSeg) {
+        launch_seg<VT, VT>(M, x, y, st, sub_sys, s);
+        return;
+    }
     with_mat(M, [&](auto v) {
         hipLaunchKernelGGL((k_spmv<VT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock), M.stage_bytes(),
                            s, v, x, y, st, sub_sys);
@@ -26,6 +52,10 @@ void launch_spmv(const DevMat<VT> &M, const VT *x, VT *y, const SysState *st, co
 template <class VT, class FT>
 void launch_restrict(const DevMat<VT> &B, const FT *f, VT *fc, const SysState *st, const int32_t *sub_sys,
                      hipStream_t s) {
+    if (B.fmt == kFormatSeg) {
+        launch_seg<VT, FT>(B, f, fc, st, sub_sys, s);
+        return;
+    }
     with_mat(B, [&](auto v) {
         hipLaunchKernelGGL((k_restrict<VT, FT, decltype(v)>), dim3(grid_for_tiles(v.ntiles)), dim3(kBlock),
                            B.stage_bytes(), s, v, f, fc, B.rowmap, st, sub_sys);
