@@ -466,10 +466,21 @@ def load_traffic(span, layouts):
     return e
 
 
-# kernels whose launches the counters isolate: span -> (name prefix, rule);
-# the in-loop instance is the most often dispatched (name, grid) group, and of
-# the restriction groups (one per level) the one with the largest grid
-TRAFFIC_KERNELS = {"spmv": ("k_outer<0,", "most"), "presmooth0": ("k_restrict<double, double,", "largest")}
+# kernels whose launches the counters isolate: span -> (name prefix, rule) of
+# each kernel that one launch of the span dispatches; the in-loop instance is
+# the most often dispatched (name, grid) group, and of the restriction groups
+# (one per level) the one with the largest grid.  The level-0 restriction in
+# the column-tiled layout ("B seg...") is two kernels: the partial sums per
+# column tile and their sum per row.
+def traffic_kernels(span, layout):
+    if span == "spmv":
+        return [("k_outer<0,", "most")]
+    if layout and layout.startswith("B seg"):
+        return [("k_seg_partial<double, double,", "largest"), ("k_seg_combine<double>", "largest")]
+    return [("k_restrict<double, double,", "largest")]
+
+
+TRAFFIC_SPANS = ("spmv", "presmooth0")
 
 
 def _pmc_groups(csv_path, prefix, counter):
@@ -520,21 +531,32 @@ def write_traffic(bench_fetch, bench_write, copy_fetch, copy_write, layouts_file
     out = {"note": "HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch), "
                    "scaled by the counters' reading of a plain copy of known size; only launches that did "
                    "work (above half the group's largest reading) count", "kernels": {}}
-    for span, (prefix, rule) in TRAFFIC_KERNELS.items():
-        fg = _pmc_groups(bench_fetch, prefix, "FETCH_SIZE")
-        wg = _pmc_groups(bench_write, prefix, "WRITE_SIZE")
-        key = _pick_group(fg, rule)
-        if key is None or key not in wg:
+    for span in TRAFFIC_SPANS:
+        names, grids, counted = [], [], []
+        fetch = write = 0.0
+        for prefix, rule in traffic_kernels(span, lay.get(span)):
+            fg = _pmc_groups(bench_fetch, prefix, "FETCH_SIZE")
+            wg = _pmc_groups(bench_write, prefix, "WRITE_SIZE")
+            key = _pick_group(fg, rule)
+            if key is None or key not in wg:
+                names = None
+                break
+            f, w = fg[key], wg[key]
+            fbig = [v for v in f if v > 0.5 * max(f)]
+            wbig = [v for v in w if v > 0.5 * max(w)]
+            fetch += statistics.median(fbig) * fscale * 1024.0
+            write += statistics.median(wbig) * wscale * 1024.0
+            names.append(key[0])
+            grids.append(key[1])
+            counted.append([len(fbig), len(wbig)])
+        if not names:
             continue
-        f, w = fg[key], wg[key]
-        fbig = [v for v in f if v > 0.5 * max(f)]
-        wbig = [v for v in w if v > 0.5 * max(w)]
-        fetch = statistics.median(fbig) * fscale * 1024.0
-        write = statistics.median(wbig) * wscale * 1024.0
-        out["kernels"][span] = {"kernel": key[0], "grid": key[1], "layout": lay.get(span),
+        one = len(names) == 1
+        out["kernels"][span] = {"kernel": names[0] if one else " + ".join(names), "grid": grids[0] if one else grids,
+                                "layout": lay.get(span),
                                 "bytes_per_launch": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
                                 "copy_scale_fetch": fscale, "copy_scale_write": wscale,
-                                "launches_counted": [len(fbig), len(wbig)],
+                                "launches_counted": counted[0] if one else counted,
                                 "kernel_source_hash": kernel_source_hash()}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as fh:

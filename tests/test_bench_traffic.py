@@ -85,6 +85,40 @@ def test_traffic_scaled_by_copy_calibration(tmp_path, monkeypatch):
     assert r["layout"] == "B csr16/t64/glist"
 
 
+def test_column_tiled_restriction_sums_its_two_kernels(tmp_path, monkeypatch):
+    # "B seg...": the level-0 restriction is the partial-sum kernel plus the
+    # per-row combine; each is taken at its largest grid (level 0) and the
+    # two are added; the FP32 instances of the mixed path do not count
+    kib = bench.COPY_BYTES / 1024.0
+    copy_f = _csv(tmp_path / "cf.csv", _rows("at::native::elementwise_kernel", 1, "FETCH_SIZE", kib / 2.0, 3))
+    copy_w = _csv(tmp_path / "cw.csv", _rows("at::native::elementwise_kernel", 1, "WRITE_SIZE", kib, 3))
+    loop = "k_outer<0, 4, dfamg::SellM<double, 1, false, false> >(...)"
+    part = "void dfamg::k_seg_partial<double, double, 1024>(...)"
+    part1 = "void dfamg::k_seg_partial<double, double, 256>(...)"
+    comb = "void dfamg::k_seg_combine<double>(...)"
+    combf = "void dfamg::k_seg_combine<float>(...)"
+    fetch = (_rows(loop, 540000, "FETCH_SIZE", 150000.0, 9) + _rows(part, 425984, "FETCH_SIZE", 160000.0, 9) +
+             _rows(part1, 20480, "FETCH_SIZE", 9000.0, 9) + _rows(comb, 540672, "FETCH_SIZE", 7000.0, 9) +
+             _rows(combf, 540672, "FETCH_SIZE", 99999.0, 9))
+    write = (_rows(loop, 540000, "WRITE_SIZE", 20000.0, 9) + _rows(part, 425984, "WRITE_SIZE", 8000.0, 9) +
+             _rows(part1, 20480, "WRITE_SIZE", 500.0, 9) + _rows(comb, 540672, "WRITE_SIZE", 4200.0, 9) +
+             _rows(combf, 540672, "WRITE_SIZE", 99999.0, 9))
+    sf = _csv(tmp_path / "sf.csv", fetch)
+    sw = _csv(tmp_path / "sw.csv", write)
+    text = LAYOUT_TEXT.replace("L0{A sell2/i16/stage, B csr16/t64/glist", "L0{A sell2/i16/stage, B seg8192/b1024")
+    lay = tmp_path / "layouts.json"
+    lay.write_text(json.dumps({"fp64": bench.parse_layouts(text)}))
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    assert bench.write_traffic(sf, sw, copy_f, copy_w, str(lay)) == 0
+    r = json.load(open(out))["kernels"]["presmooth0"]
+    assert r["layout"] == "B seg8192/b1024"
+    assert r["grid"] == [425984, 540672] and r["launches_counted"] == [[9, 9], [9, 9]]
+    assert abs(r["fetch_bytes"] - (160000.0 + 7000.0) * 2.0 * 1024.0) < 1e-3
+    assert abs(r["write_bytes"] - (8000.0 + 4200.0) * 1024.0) < 1e-3
+    assert "k_seg_partial" in r["kernel"] and "k_seg_combine<double>" in r["kernel"]
+
+
 def test_traffic_dropped_when_layout_differs(tmp_path, monkeypatch):
     _traffic(tmp_path, monkeypatch)
     same = bench.parse_layouts(LAYOUT_TEXT)
