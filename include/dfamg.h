@@ -139,9 +139,13 @@ typedef struct {
                                2 also every autotuning candidate's time       */
     int32_t profile;        /* 1 records HIP events around the outer SpMV and
                                the level-0 restriction (DFAMG_KERNEL_SPMV and
-                               _PRESMOOTH0) of every Krylov iteration, 2
-                               around every kernel span (inside the captured
-                               graph as well); averages in dfamg_stats        */
+                               _PRESMOOTH0) of the Krylov iterations of the
+                               first captured graph of every solve (every
+                               iteration with direct launches or FGMRES;
+                               later chunks replay a graph without event
+                               nodes), 2 around every kernel span of every
+                               iteration (inside the captured graph as well);
+                               averages in dfamg_stats                        */
     int32_t restart;        /* FGMRES: Arnoldi steps per cycle, 1..64 (30);
                                one captured graph runs one cycle              */
     int32_t coarse_solve;   /* DFAMG_COARSE_*; FP32 and CG need solver = FGMRES */

@@ -1048,6 +1048,7 @@ enum KernelId {
 
 struct Prof {
     bool on = false, capturing = false;
+    bool suppress = false;               // capturing the graph without event nodes
     int slot = 0, nslots = 0;
     std::vector<hipEvent_t> ev;          // [slot][kid][2]
     std::vector<char> used;              // [slot][kid] recorded in this chunk / graph
@@ -1063,7 +1064,7 @@ struct Prof {
     }
     int level = 1;                        // 1: outer SpMV and level-0 restriction, 2: every span
     void mark(int kid, int which, hipStream_t st) {
-        if (!on || (level < 2 && kid != KID_SPMV && kid != KID_PRE0)) return;
+        if (!on || suppress || (level < 2 && kid != KID_SPMV && kid != KID_PRE0)) return;
         hipEvent_t e = ev[((size_t)slot * KID_N + kid) * 2 + which];
         if (capturing) HIP_CHECK(record_in_capture(e, st));
         else HIP_CHECK(hipEventRecord(e, st));
@@ -1612,10 +1613,14 @@ struct Handle {
     // correction); it may synchronise the stream, so it runs with direct
     // launches only
     std::function<void(hipStream_t, const double *, double *)> ext_precond;
-    // graph of `graph_iters` iterations
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    // graph of `graph_iters` iterations; with profile = 1 a second graph of the
+    // same iterations without the event nodes, replayed after the first chunk
+    // of every solve (each event node costs a few microseconds in the graph)
+    hipGraph_t graph = nullptr, graph_plain = nullptr;
+    hipGraphExec_t graph_exec = nullptr, graph_exec_plain = nullptr;
     int32_t graph_k = 0;
+    bool want_events = true;     // the next chunk records the profile's events
+    bool chunk_events = false;   // the chunk just launched recorded them
     bool have_rhs = false;
     double setup_device_s = 0.0, solve_s = 0.0;
     double bytes_iter = 0.0;
@@ -1625,6 +1630,8 @@ struct Handle {
     ~Handle() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (graph_exec_plain) (void)hipGraphExecDestroy(graph_exec_plain);
+        if (graph_plain) (void)hipGraphDestroy(graph_plain);
         if (h_states) (void)hipHostFree(h_states);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
@@ -2358,6 +2365,7 @@ void Handle::finish(hipStream_t st) {
 void Handle::launch_iterations(int k) {
     if (fgmres()) {
         // one restart cycle per call (one captured graph per cycle)
+        chunk_events = prof.on;
         if (prm.graph_iters <= 0) {
             prof.clear_used();
             cycle_fgmres(stream);
@@ -2383,10 +2391,12 @@ void Handle::launch_iterations(int k) {
             else if (bicg2()) iteration_bicg2(stream);
             else iteration(stream);
         }
+        chunk_events = prof.on;
         return;
     }
-    if (!graph_exec) {
-        prof.capturing = prof.on;
+    auto capture = [&](bool events, hipGraph_t &g, hipGraphExec_t &ge) {
+        prof.capturing = prof.on && events;
+        prof.suppress = !events;
         HIP_CHECK(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed));
         for (int i = 0; i < prm.graph_iters; ++i) {
             prof.slot = i;
@@ -2394,12 +2404,21 @@ void Handle::launch_iterations(int k) {
             else if (bicg2()) iteration_bicg2(cap_stream);
             else iteration(cap_stream);
         }
-        HIP_CHECK(hipStreamEndCapture(cap_stream, &graph));
-        HIP_CHECK(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
-        graph_k = prm.graph_iters;
+        HIP_CHECK(hipStreamEndCapture(cap_stream, &g));
+        HIP_CHECK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
         prof.capturing = false;
+        prof.suppress = false;
+    };
+    if (!graph_exec) {
+        capture(true, graph, graph_exec);
+        graph_k = prm.graph_iters;
+        if (prof.on && prof.level < 2) capture(false, graph_plain, graph_exec_plain);
     }
-    for (int i = 0; i < k; i += graph_k) HIP_CHECK(hipGraphLaunch(graph_exec, stream));
+    // profile = 1: events in the first chunk of a solve only
+    const bool events = !graph_exec_plain || want_events;
+    for (int i = 0; i < k; i += graph_k) HIP_CHECK(hipGraphLaunch(events ? graph_exec : graph_exec_plain, stream));
+    chunk_events = prof.on && events;
+    want_events = false;
 }
 
 // E = Z^T A Z of every system assembled on the device into Eout (row-major
@@ -2465,12 +2484,14 @@ dfamg_status Handle::run_solve(const double *rhs, double *xio) {
     HIP_CHECK(hipGetLastError());
     const int chunk = fgmres() ? prm.restart : (prm.graph_iters > 0 ? prm.graph_iters : 8);
     int done_iters = 0;
+    want_events = true;
+    chunk_events = false;
     std::vector<int32_t> it_before(nsys, 0);
     bool first = true;
     for (;;) {
         HIP_CHECK(hipMemcpyAsync(h_states, states, sizeof(SysState) * nsys, hipMemcpyDeviceToHost, stream));
         HIP_CHECK(hipStreamSynchronize(stream));
-        if (!first && prof.on) {
+        if (!first && prof.on && chunk_events) {
             // iterations of this chunk that ran to the end, and the one that
             // stopped at the test
             int full = 0, partial = 0;

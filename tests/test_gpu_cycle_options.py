@@ -96,3 +96,36 @@ def test_two_sweeps_reduce_iterations():
         S.close()
     print("iterations V(1,1), V(2,2):", its, flush=True)
     assert its[1] < its[0]
+
+
+@pytest.mark.parametrize("graph_iters", [16, 0])
+def test_cg_profile_events_first_graph_only(graph_iters):
+    # profile = 1 records its events in the first captured graph of every
+    # solve (later chunks replay a graph without event nodes), every
+    # iteration with direct launches; profile = 2 every span of every
+    # iteration.  The iterate is bitwise that of the unprofiled solve.
+    import paper_1710_03940_amd as L
+    P = make_problem("p20", (20, 20, 20), (2, 2, 1), deflation="linear", sigma=2.0, coef_seed=11,
+                     rhs="uniform", rhs_seed=12)
+    kw = dict(coarse_enough=40, autotune=0, graph_iters=graph_iters)
+    xs, its, calls = [], [], {}
+    for prof in (0, 1, 2):
+        S = L.Solver(P.A, P.part, P.nsub, P.Z, profile=prof, **kw)
+        for _ in range(2):
+            x = _t(np.zeros(P.n))
+            out = S.solve(_t(P.b), x)
+        st = S.stats()
+        S.close()
+        assert out["status"] == 0
+        xs.append(x.cpu().numpy())
+        its.append(out["iters"])
+        calls[prof] = st["kernels"]["spmv"]["calls"]
+        if prof:
+            assert st["kernels"]["presmooth0"]["calls"] == calls[prof] and st["kernels"]["spmv"]["ms"] > 0
+    assert its[0] == its[1] == its[2] and its[0] > 16
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    print("iterations", its[0], "spmv spans", calls, flush=True)
+    # the iteration that meets the tolerance may go uncounted once per solve
+    every = range(2 * (its[0] - 1), 2 * its[0] + 1)
+    assert calls[1] == 2 * 16 if graph_iters else calls[1] in every
+    assert calls[2] in every
