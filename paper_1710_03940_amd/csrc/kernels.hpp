@@ -226,6 +226,50 @@ __device__ __forceinline__ ACC sell_dot(const CT *__restrict__ col, int cadd, co
     return acc;
 }
 
+// Two SELL rows of one lane at once (slices with widths w0 and w1, both
+// wave-uniform): per chunk of eight entries, the loads of both rows, then
+// both rows' gathers, then the sums in entry order (each row summed as by
+// sell_dot, so the results are the same to the bit); twice the loads in
+// flight per wavefront.
+template <class VT, class ACC, class CT, class XF>
+__device__ __forceinline__ void sell_dot2(const CT *__restrict__ col, int cadd, const VT *__restrict__ val,
+                                          int64_t off0, int w0, int64_t off1, int w1, XF x, ACC &acc0, ACC &acc1) {
+    acc0 = 0;
+    acc1 = 0;
+    const int wm = w0 > w1 ? w0 : w1;
+    for (int j0 = 0; j0 < wm; j0 += 8) {
+        int c0[8], c1[8];
+        VT v0[8], v1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            c0[u] = cadd;
+            v0[u] = 0;
+            c1[u] = cadd;
+            v1[u] = 0;
+            if (j0 + u < w0) {
+                c0[u] = cadd + (int)stream_load(col + off0 + (int64_t)(j0 + u) * 64);
+                v0[u] = stream_load(val + off0 + (int64_t)(j0 + u) * 64);
+            }
+            if (j0 + u < w1) {
+                c1[u] = cadd + (int)stream_load(col + off1 + (int64_t)(j0 + u) * 64);
+                v1[u] = stream_load(val + off1 + (int64_t)(j0 + u) * 64);
+            }
+        }
+        ACC x0[8], x1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            x0[u] = (ACC)x(c0[u]);
+            x1[u] = (ACC)x(c1[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < w0) acc0 += (ACC)v0[u] * x0[u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < w1) acc1 += (ACC)v1[u] * x1[u];
+    }
+}
+
 // Calls f(row, sum_j a_rj src(c_j)) for every row of the tile owned by this
 // thread (exactly once per row over the block).  Every thread of the block
 // must call it (the staged layouts synchronise the block).
@@ -238,6 +282,34 @@ __device__ __forceinline__ void for_rows(const SellM<VT, RPL, I16, STAGE> &M, in
     const int cb = I16 ? M.cbase[tile] : 0;
     const VT *lds = nullptr;
     if (STAGE) lds = stage_window<VT>(cb, M.cspan[tile], src);
+    if constexpr (RPL % 2 == 0) {
+        // slices in pairs (their padding lanes load zero values at valid
+        // positions; only rows of the tile are passed to f)
+#pragma unroll
+        for (int r = 0; r < RPL; r += 2) {
+            const int sl = w * RPL + r;
+            const int64_t si = (int64_t)tile * 4 * RPL + sl;
+            ACC acc[2];
+            if (STAGE)
+                sell_dot2<VT, ACC>(M.col16, 0, M.val, M.soff[si] + lane, M.sw[si], M.soff[si + 1] + lane, M.sw[si + 1],
+                                   [&](int c) { return lds[c]; }, acc[0], acc[1]);
+            else if (I16)
+                sell_dot2<VT, ACC>(M.col16, cb, M.val, M.soff[si] + lane, M.sw[si], M.soff[si + 1] + lane,
+                                   M.sw[si + 1], src, acc[0], acc[1]);
+            else
+                sell_dot2<VT, ACC>(M.col, 0, M.val, M.soff[si] + lane, M.sw[si], M.soff[si + 1] + lane, M.sw[si + 1],
+                                   src, acc[0], acc[1]);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int lr = (sl + q) * 64 + lane;
+                if (lr < T.nrows) {
+                    const int lrow = M.ridx ? (int)M.ridx[(int64_t)tile * 256 * RPL + lr] : lr;
+                    f(T.row0 + lrow, acc[q]);
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int sl = w * RPL + r;
