@@ -670,23 +670,40 @@ void tune_cache_store(const TuneKey &k, const Layout &L, double us) {
 
 // Hash of the row ranges, row lengths and columns of the rows covered
 // (64-bit multiply-xorshift per word).
+// Hash of a matrix's structure over the row ranges: each range hashed on
+// its own (in parallel), the range hashes then combined in order.
 uint64_t structure_hash(const Csr &M, const std::vector<RowRange> &ranges) {
-    uint64_t h = 1469598103934665603ull;
-    auto mix = [&](uint64_t v) {
+    auto mix = [](uint64_t &h, uint64_t v) {
         h = (h ^ v) * 0x9e3779b97f4a7c15ull;
         h ^= h >> 29;
     };
-    mix((uint64_t)M.nrows);
-    mix((uint64_t)M.ncols);
-    for (const RowRange &r : ranges) {
-        mix((uint64_t)r.row0);
-        mix((uint64_t)r.nrows);
+    std::vector<uint64_t> rh(ranges.size());
+    parallel_for((int64_t)ranges.size(), 8, [&](int64_t j) {
+        const RowRange &r = ranges[j];
+        uint64_t h = 1469598103934665603ull;
+        mix(h, (uint64_t)r.row0);
+        mix(h, (uint64_t)r.nrows);
         for (int64_t i = r.row0; i < r.row0 + r.nrows; ++i) {
-            mix((uint64_t)(M.ptr[i + 1] - M.ptr[i]));
-            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) mix((uint64_t)(uint32_t)M.col[k]);
+            mix(h, (uint64_t)(M.ptr[i + 1] - M.ptr[i]));
+            for (int64_t k = M.ptr[i]; k < M.ptr[i + 1]; ++k) mix(h, (uint64_t)(uint32_t)M.col[k]);
         }
-    }
+        rh[j] = h;
+    });
+    uint64_t h = 1469598103934665603ull;
+    mix(h, (uint64_t)M.nrows);
+    mix(h, (uint64_t)M.ncols);
+    for (uint64_t v : rh) mix(h, v);
     return h;
+}
+
+// The time recorded for a matrix of this kind, value type, family and
+// structure (tuned before in this process, or read from the layout record),
+// or -1.
+template <class VT>
+double recorded_us(int kind, int format, uint64_t hash) {
+    std::lock_guard<std::mutex> g(tune_cache_mutex());
+    auto it = tune_cache().find(TuneKey{kind, (int)sizeof(VT), format, hash});
+    return it == tune_cache().end() ? -1.0 : it->second.second;
 }
 
 // `timer` (optional) replaces the default timing of a candidate; `verbose`
@@ -695,7 +712,7 @@ template <class VT>
 DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> &ranges, int format,
                         bool autotune, TuneKind kind, hipStream_t s, const std::vector<int32_t> &sub_sys, int nsys,
                         int nsub, const std::function<double(const DevMat<VT> &)> &timer = {}, int verbose = 0,
-                        bool bsr4 = false) {
+                        bool bsr4 = false, uint64_t hash = 0) {
     int64_t rows = 0;
     for (auto &r : ranges) rows += r.nrows;
     const double avg_len = rows ? (double)M.nnz() / (double)rows : 0.0;
@@ -735,13 +752,15 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
                 for (int nt : {1, 2, 4})
                     cand.push_back(Layout{kFormatSeg, kb * 1024 / (int)sizeof(VT), false, false, true, nt});
         // lanes per row: 32 and 64 for the long rows of the restrictions
-        // (tens to hundreds of entries) and of the denser coarse operators
-        const std::vector<int> lane_set = outer                    ? std::vector<int>{8, 16}
+        // (tens to hundreds of entries) and of the denser coarse operators,
+        // 1, 2 and 4 for rows of fewer than ten
+        const bool short_rows = avg_len < 10.0;
+        const std::vector<int> lane_set = short_rows              ? std::vector<int>{1, 2, 4}
+                                          : outer                 ? std::vector<int>{8, 16}
                                           : kind == TUNE_RESTRICT ? std::vector<int>{8, 16, 32, 64}
                                           : avg_len >= 24.0       ? std::vector<int>{4, 8, 16, 32}
                                                                   : std::vector<int>{4, 8, 16};
-        if ((family == DFAMG_FORMAT_CSR || family == DFAMG_FORMAT_AUTO) &&
-            (avg_len >= 10.0 || family == DFAMG_FORMAT_CSR))
+        if (family == DFAMG_FORMAT_CSR || family == DFAMG_FORMAT_AUTO)
             for (int l : lane_set)
                 // 256-row tiles, and tiles of 16/64 rows (32 and 64 lanes) or
                 // of kBlock/l and 4 kBlock/l rows (fewer lanes)
@@ -769,7 +788,7 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     }
     // a matrix tuned before in this process (same kind, value type, family and
     // structure) gets the layout chosen then, without timing
-    const TuneKey key{(int)kind, (int)sizeof(VT), format, structure_hash(M, ranges)};
+    const TuneKey key{(int)kind, (int)sizeof(VT), format, hash ? hash : structure_hash(M, ranges)};
     double cached_us = -1.0;
     if (cand.size() > 1) {
         std::lock_guard<std::mutex> g(tune_cache_mutex());
@@ -1192,36 +1211,64 @@ struct Hierarchy_dev : PrecondBase {
                 // the tuner's timings (R without tuning)
                 {
                     const auto rn = ranges_of(PN, next_subs);
-                    DevArena arR, arB;
-                    D.R = upload_tuned<VT>(arR, PL.R, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys, plan.nsys,
-                                           plan.nsub, {}, verbose, plan.bs == 4);
-                    // B holds exactly one pre-smoothing sweep from the zero guess
-                    bool clustered = false;
-                    DevArena arBc;
-                    if (autotune && !block && npre == 1) {
-                        D.B = upload_tuned<VT>(arB, PL.B, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
-                                               plan.nsys, plan.nsub, {}, verbose, plan.bs == 4);
-                        // the rows in the clustered order: fewer distinct
-                        // columns per tile, but wider column windows
-                        if (PL.Bc.nnz() > 0) {
-                            DevMat<VT> Bc = upload_tuned<VT>(arBc, PL.Bc, rn, format, autotune, TUNE_RESTRICT, s,
-                                                             plan.sub_sys, plan.nsys, plan.nsub, {}, verbose,
-                                                             plan.bs == 4);
-                            if (Bc.tuned_us < D.B.tuned_us) {
-                                D.B = Bc;
-                                clustered = true;
-                            }
+                    const bool can_fuse = autotune && !block && npre == 1;
+                    const bool has_bc = can_fuse && PL.Bc.nnz() > 0;
+                    const uint64_t hR = structure_hash(PL.R, rn);
+                    const uint64_t hB = can_fuse ? structure_hash(PL.B, rn) : 0;
+                    const uint64_t hBc = has_bc ? structure_hash(PL.Bc, rn) : 0;
+                    const double uR = autotune ? recorded_us<VT>(TUNE_RESTRICT, format, hR) : -1.0;
+                    const double uB = can_fuse ? recorded_us<VT>(TUNE_RESTRICT, format, hB) : -1.0;
+                    const double uBc = has_bc ? recorded_us<VT>(TUNE_RESTRICT, format, hBc) : -1.0;
+                    if (uR >= 0.0 && (!can_fuse || (uB >= 0.0 && (!has_bc || uBc >= 0.0)))) {
+                        // every candidate's time is recorded: build only the
+                        // operators the comparison below keeps
+                        const bool clustered = has_bc && uBc < uB;
+                        D.fused = can_fuse && (clustered ? uBc : uB) < D.A.tuned_us + uR;
+                        if (D.fused) {
+                            D.B = upload_tuned<VT>(ar, clustered ? PL.Bc : PL.B, rn, format, autotune, TUNE_RESTRICT, s,
+                                                   plan.sub_sys, plan.nsys, plan.nsub, {}, verbose, plan.bs == 4,
+                                                   clustered ? hBc : hB);
+                            if (clustered) D.B.rowmap = ar.upload(PL.B_rowmap, s);
+                        } else {
+                            D.R = upload_tuned<VT>(ar, PL.R, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
+                                                   plan.nsys, plan.nsub, {}, verbose, plan.bs == 4, hR);
+                            D.res = ar.alloc<VT>(PL.nrows);
                         }
-                        D.fused = D.B.tuned_us < D.A.tuned_us + D.R.tuned_us;
-                    }
-                    if (D.fused) {
-                        ar.adopt(clustered ? arBc : arB);
-                        if (clustered) D.B.rowmap = ar.upload(PL.B_rowmap, s);
-                        D.R = DevMat<VT>{};
                     } else {
-                        ar.adopt(arR);
-                        D.B = DevMat<VT>{};
-                        D.res = ar.alloc<VT>(PL.nrows);
+                        // the level's restricted residual either through B in one
+                        // launch or as pre-smoothing residual (A) plus restriction
+                        // (R): the faster by the tuner's timings (R without tuning)
+                        DevArena arR, arB;
+                        D.R = upload_tuned<VT>(arR, PL.R, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
+                                               plan.nsys, plan.nsub, {}, verbose, plan.bs == 4, hR);
+                        // B holds exactly one pre-smoothing sweep from the zero guess
+                        bool clustered = false;
+                        DevArena arBc;
+                        if (can_fuse) {
+                            D.B = upload_tuned<VT>(arB, PL.B, rn, format, autotune, TUNE_RESTRICT, s, plan.sub_sys,
+                                                   plan.nsys, plan.nsub, {}, verbose, plan.bs == 4, hB);
+                            // the rows in the clustered order: fewer distinct
+                            // columns per tile, but wider column windows
+                            if (has_bc) {
+                                DevMat<VT> Bc = upload_tuned<VT>(arBc, PL.Bc, rn, format, autotune, TUNE_RESTRICT, s,
+                                                                 plan.sub_sys, plan.nsys, plan.nsub, {}, verbose,
+                                                                 plan.bs == 4, hBc);
+                                if (Bc.tuned_us < D.B.tuned_us) {
+                                    D.B = Bc;
+                                    clustered = true;
+                                }
+                            }
+                            D.fused = D.B.tuned_us < D.A.tuned_us + D.R.tuned_us;
+                        }
+                        if (D.fused) {
+                            ar.adopt(clustered ? arBc : arB);
+                            if (clustered) D.B.rowmap = ar.upload(PL.B_rowmap, s);
+                            D.R = DevMat<VT>{};
+                        } else {
+                            ar.adopt(arR);
+                            D.B = DevMat<VT>{};
+                            D.res = ar.alloc<VT>(PL.nrows);
+                        }
                     }
                 }
                 if (l < 20) {
@@ -1661,6 +1708,15 @@ struct Handle {
 
 void Handle::setup_device() {
     const double t0 = now_s();
+    // phase times, printed with verbose >= 1
+    double tmark = t0;
+    std::string phases;
+    auto phase = [&](const char *name) {
+        HIP_CHECK(hipStreamSynchronize(stream));
+        const double t = now_s();
+        phases += std::string(phases.empty() ? "" : ", ") + name + " " + std::to_string((int)((t - tmark) * 1e3)) + " ms";
+        tmark = t;
+    };
     hipStream_t sm = stream;
     const Plan &P = plan;
     const int nsys = P.nsys, nsub = P.nsub, ndv = P.ndv;
@@ -1709,24 +1765,36 @@ void Handle::setup_device() {
             });
         };
         const bool tune = prm.autotune != 0;
-        DevArena arF, arS;
-        const DevMat<double> AF = upload_tuned<double>(arF, P.A, rr, prm.spmv_format, tune, TUNE_OUTER, sm,
-                                                       P.sub_sys, nsys, nsub, make_timer(none), prm.verbose,
-                                                       P.bs == 4);
+        const bool try_split = tune && !off.col.empty();
+        const uint64_t hF = structure_hash(P.A, rr), hS = try_split ? structure_hash(loc, rr) : 0;
+        const double uF = tune ? recorded_us<double>(TUNE_OUTER, prm.spmv_format, hF) : -1.0;
+        const double uS = try_split ? recorded_us<double>(TUNE_OUTER, prm.spmv_format, hS) : -1.0;
         bool split = false;
-        DevMat<double> AS;
-        if (tune && !off.col.empty()) {
-            AS = upload_tuned<double>(arS, loc, rr, prm.spmv_format, tune, TUNE_OUTER, sm, P.sub_sys, nsys, nsub,
-                                      make_timer(off), prm.verbose, P.bs == 4);
-            split = AS.tuned_us < AF.tuned_us;
+        if (uF >= 0.0 && (!try_split || uS >= 0.0)) {
+            // both forms' times recorded: build only the faster one
+            split = try_split && uS < uF;
+            A = upload_tuned<double>(ar, split ? loc : P.A, rr, prm.spmv_format, tune, TUNE_OUTER, sm, P.sub_sys, nsys,
+                                     nsub, make_timer(split ? off : none), prm.verbose, P.bs == 4, split ? hS : hF);
+        } else {
+            DevArena arF, arS;
+            const DevMat<double> AF = upload_tuned<double>(arF, P.A, rr, prm.spmv_format, tune, TUNE_OUTER, sm,
+                                                           P.sub_sys, nsys, nsub, make_timer(none), prm.verbose,
+                                                           P.bs == 4, hF);
+            DevMat<double> AS;
+            if (try_split) {
+                AS = upload_tuned<double>(arS, loc, rr, prm.spmv_format, tune, TUNE_OUTER, sm, P.sub_sys, nsys, nsub,
+                                          make_timer(off), prm.verbose, P.bs == 4, hS);
+                split = AS.tuned_us < AF.tuned_us;
+            }
+            ar.adopt(split ? arS : arF);
+            A = split ? AS : AF;
         }
-        ar.adopt(split ? arS : arF);
-        A = split ? AS : AF;
         offA = upload_off(ar, split ? off : none, A, sm);
         outer_split = split;
         outer_off_nnz = split ? (int64_t)off.col.size() : 0;
         HIP_CHECK(hipStreamSynchronize(sm));
     }
+    phase("outer operator");
     d_sto_A = ar.upload(A.sys_tile_off, sm);
     d_subto_A = ar.upload(A.sub_tile_off, sm);
     // row tiles of 256 rows: one row per thread in the vector kernels
@@ -1889,6 +1957,7 @@ void Handle::setup_device() {
                             "E = Z^T A Z of system " + std::to_string(which[bad]) + " is singular"};
         }
     }
+    phase("vectors, AZ and E^-1");
     // the single-precision copy of E^{-1} for the inexact coarse solve
     if (fgmres() && prm.coarse_solve == DFAMG_COARSE_FP32 && ndv > 0) {
         const int64_t ne = P.sys_E_off[nsys];
@@ -1917,6 +1986,7 @@ void Handle::setup_device() {
         part_rs_job = ar.alloc<double>(std::max(1, M->ncjobs0));
         HIP_CHECK(hipMemsetAsync(part_rs_job, 0, sizeof(double) * std::max(1, M->ncjobs0), sm));
         d_sys_cjob_off0 = ar.upload(M->sys_cjob_off0, sm);
+        phase("hierarchy layouts and coarsest inverses");
     } else {
         if (prm.precond == DFAMG_PRECOND_SPAI0) {
             // m_i = a_ii / sum_j a_ij^2 over the rows of the permuted matrix
@@ -2005,7 +2075,9 @@ void Handle::setup_device() {
         }
     }
     HIP_CHECK(hipStreamSynchronize(sm));
+    phase("rest");
     setup_device_s = now_s() - t0;
+    if (prm.verbose >= 1) std::fprintf(stderr, "[dfamg] device setup %.3f s: %s\n", setup_device_s, phases.c_str());
 }
 
 __global__ void k_probe(double *p) {

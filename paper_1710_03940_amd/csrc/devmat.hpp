@@ -106,6 +106,8 @@ void with_mat(const DevMat<VT> &M, Fn &&fn) {
     } else {
         if (M.stage) {
             switch (M.par) {
+                case 1: DFAMG_CSR(1, true); return;
+                case 2: DFAMG_CSR(2, true); return;
                 case 4: DFAMG_CSR(4, true); return;
                 case 8: DFAMG_CSR(8, true); return;
                 case 16: DFAMG_CSR(16, true); return;
@@ -114,6 +116,8 @@ void with_mat(const DevMat<VT> &M, Fn &&fn) {
             }
         } else {
             switch (M.par) {
+                case 1: DFAMG_CSR(1, false); return;
+                case 2: DFAMG_CSR(2, false); return;
                 case 4: DFAMG_CSR(4, false); return;
                 case 8: DFAMG_CSR(8, false); return;
                 case 16: DFAMG_CSR(16, false); return;

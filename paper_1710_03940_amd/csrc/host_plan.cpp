@@ -606,13 +606,15 @@ bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool 
     auto len = [&](int64_t r) { return (int)(M.ptr[r + 1] - M.ptr[r]); };
     // tile-local order of the rows (identity unless sorted)
     std::vector<int16_t> order((size_t)S.tiles.size() * tile_rows, 0);
-    for (size_t ti = 0; ti < S.tiles.size(); ++ti) {
+    const int64_t ntiles = (int64_t)S.tiles.size();
+    // every tile's rows, slices and entries are independent of the others'
+    parallel_for(ntiles, 8, [&](int64_t ti) {
         const Tile &t = S.tiles[ti];
         int16_t *o = &order[ti * tile_rows];
         for (int k = 0; k < t.nrows; ++k) o[k] = (int16_t)k;
         if (sorted)
             std::stable_sort(o, o + t.nrows, [&](int16_t a, int16_t b) { return len(t.row0 + a) > len(t.row0 + b); });
-    }
+    });
     if (sorted) S.ridx = order;
     int64_t off = 0;
     S.slice_off.reserve(S.tiles.size() * nsl);
@@ -635,7 +637,8 @@ bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool 
         S.col16.assign(off, 0);
         S.cbase.assign(S.tiles.size(), 0);
         S.cspan.assign(S.tiles.size(), 1);
-        for (size_t ti = 0; ti < S.tiles.size(); ++ti) {
+        std::atomic<bool> fits{true};
+        parallel_for(ntiles, 8, [&](int64_t ti) {
             const Tile &t = S.tiles[ti];
             int64_t lo = INT64_MAX, hi = -1;
             for (int64_t r = t.row0; r < t.row0 + t.nrows; ++r)
@@ -645,15 +648,17 @@ bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool 
                 }
             if (hi < 0) lo = hi = std::min<int64_t>(t.row0, M.ncols - 1);
             // padding of empty rows uses the base itself
-            if (hi - lo > 65535) return false;
+            if (hi - lo > 65535) fits = false;
             S.cbase[ti] = (int32_t)lo;
             S.cspan[ti] = (int32_t)(hi - lo + 1);
-        }
+        });
+        if (!fits) return false;
     } else {
         S.col.assign(off, 0);
     }
     S.val.assign(off, 0.0);
-    for (size_t ti = 0; ti < S.tiles.size(); ++ti) {
+    std::vector<int64_t> tile_nnz(ntiles, 0);
+    parallel_for(ntiles, 8, [&](int64_t ti) {
         const Tile &t = S.tiles[ti];
         for (int k = 0; k < nsl; ++k) {
             const int64_t base = S.slice_off[ti * nsl + k];
@@ -672,10 +677,11 @@ bool make_sell(const Csr &M, const std::vector<RowRange> &ranges, int rpl, bool 
                     else S.col[d] = c;
                     S.val[d] = j < n ? M.val[M.ptr[r] + j] : 0.0;
                 }
-                S.nnz += n;
+                tile_nnz[ti] += n;
             }
         }
-    }
+    });
+    for (int64_t v : tile_nnz) S.nnz += v;
     return true;
 }
 
