@@ -745,10 +745,10 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
         }
         // 4 x 4 blocks for point-block operators
         if (family == DFAMG_FORMAT_AUTO && bsr4) cand.push_back(Layout{DFAMG_FORMAT_BSR4, 4, false, false, false, 0});
-        // restrictions split by column tiles of 16, 32 or 64 KB of the input
+        // restrictions split by column tiles of 4 to 64 KB of the input
         // vector (rows of 16+ entries)
         if (family == DFAMG_FORMAT_AUTO && kind == TUNE_RESTRICT && avg_len >= 16.0)
-            for (int kb : {16, 32, 64})
+            for (int kb : {4, 8, 16, 32, 64})
                 for (int nt : {1, 2, 4})
                     cand.push_back(Layout{kFormatSeg, kb * 1024 / (int)sizeof(VT), false, false, true, nt});
         // lanes per row: 32 and 64 for the long rows of the restrictions
