@@ -469,15 +469,16 @@ def load_traffic(span, layouts):
 # kernels whose launches the counters isolate: span -> (name prefix, rule) of
 # each kernel that one launch of the span dispatches; the in-loop instance is
 # the most often dispatched (name, grid) group, and of the restriction groups
-# (one per level) the one with the largest grid.  The level-0 restriction in
+# (one per level, dispatched as often as each other) the heaviest, the one
+# whose launches move the most bytes (level 0).  The level-0 restriction in
 # the column-tiled layout ("B seg...") is two kernels: the partial sums per
 # column tile and their sum per row.
 def traffic_kernels(span, layout):
     if span == "spmv":
         return [("k_outer<0,", "most")]
     if layout and layout.startswith("B seg"):
-        return [("k_seg_partial<double, double,", "largest"), ("k_seg_combine<double>", "largest")]
-    return [("k_restrict<double, double,", "largest")]
+        return [("k_seg_partial<double, double,", "heaviest"), ("k_seg_combine<double>", "heaviest")]
+    return [("k_restrict<double, double,", "heaviest")]
 
 
 TRAFFIC_SPANS = ("spmv", "presmooth0")
@@ -497,13 +498,14 @@ def _pmc_groups(csv_path, prefix, counter):
 
 
 def _pick_group(by, rule):
+    import statistics
     if not by:
         return None
     if rule == "most":
         return max(by, key=lambda k: len(by[k]))
     top = max(len(v) for v in by.values())
     busy = [k for k in by if len(by[k]) >= top // 2]
-    return max(busy, key=lambda k: k[1])
+    return max(busy, key=lambda k: statistics.median(by[k]))
 
 
 def _pmc_kib(csv_path, name_part, counter):

@@ -48,8 +48,9 @@ def _traffic(tmp_path, monkeypatch):
     # outer: in-loop launches 150,000 KiB fetched / 20,000 written; skipped
     # launches after convergence read almost nothing; the tuner's candidate
     # launches of another layout are fewer and must not count.
-    # restriction: one instance per level (level 0 has the largest grid);
-    # level 1's launches are as many as level 0's but must not count
+    # restriction: one instance per level (level 0 moves the most bytes);
+    # level 1's launches are as many as level 0's but must not count, nor
+    # the tuner's few launches of another layout
     fetch = (_rows(loop, 540000, "FETCH_SIZE", 150000.0, 9) + _rows(loop, 540000, "FETCH_SIZE", 3.0, 4) +
              _rows(tuned, 270000, "FETCH_SIZE", 999999.0, 2) +
              _rows(restr, 2160000, "FETCH_SIZE", 200000.0, 9) + _rows(restr, 290000, "FETCH_SIZE", 50000.0, 9) +
@@ -87,21 +88,22 @@ def test_traffic_scaled_by_copy_calibration(tmp_path, monkeypatch):
 
 def test_column_tiled_restriction_sums_its_two_kernels(tmp_path, monkeypatch):
     # "B seg...": the level-0 restriction is the partial-sum kernel plus the
-    # per-row combine; each is taken at its largest grid (level 0) and the
-    # two are added; the FP32 instances of the mixed path do not count
+    # per-row combine; each is taken at its heaviest instance (level 0, whose
+    # grid may be smaller than level 1's) and the two are added; the FP32
+    # instances of the mixed path do not count
     kib = bench.COPY_BYTES / 1024.0
     copy_f = _csv(tmp_path / "cf.csv", _rows("at::native::elementwise_kernel", 1, "FETCH_SIZE", kib / 2.0, 3))
     copy_w = _csv(tmp_path / "cw.csv", _rows("at::native::elementwise_kernel", 1, "WRITE_SIZE", kib, 3))
     loop = "k_outer<0, 4, dfamg::SellM<double, 1, false, false> >(...)"
     part = "void dfamg::k_seg_partial<double, double, 1024>(...)"
-    part1 = "void dfamg::k_seg_partial<double, double, 256>(...)"
+    part1 = "void dfamg::k_seg_partial<double, double, 512>(...)"
     comb = "void dfamg::k_seg_combine<double>(...)"
     combf = "void dfamg::k_seg_combine<float>(...)"
     fetch = (_rows(loop, 540000, "FETCH_SIZE", 150000.0, 9) + _rows(part, 425984, "FETCH_SIZE", 160000.0, 9) +
-             _rows(part1, 20480, "FETCH_SIZE", 9000.0, 9) + _rows(comb, 540672, "FETCH_SIZE", 7000.0, 9) +
+             _rows(part1, 557056, "FETCH_SIZE", 9000.0, 9) + _rows(comb, 540672, "FETCH_SIZE", 7000.0, 9) +
              _rows(combf, 540672, "FETCH_SIZE", 99999.0, 9))
     write = (_rows(loop, 540000, "WRITE_SIZE", 20000.0, 9) + _rows(part, 425984, "WRITE_SIZE", 8000.0, 9) +
-             _rows(part1, 20480, "WRITE_SIZE", 500.0, 9) + _rows(comb, 540672, "WRITE_SIZE", 4200.0, 9) +
+             _rows(part1, 557056, "WRITE_SIZE", 500.0, 9) + _rows(comb, 540672, "WRITE_SIZE", 4200.0, 9) +
              _rows(combf, 540672, "WRITE_SIZE", 99999.0, 9))
     sf = _csv(tmp_path / "sf.csv", fetch)
     sw = _csv(tmp_path / "sw.csv", write)
