@@ -76,12 +76,15 @@ enum { DFAMG_PREC_FP64 = 0, DFAMG_PREC_MIXED = 1 };
  * ||I - M A||_F over block-diagonal M; with b = 1 it is SPAI-0). */
 enum { DFAMG_SMOOTHER_SPAI0 = 0, DFAMG_SMOOTHER_JACOBI = 1, DFAMG_SMOOTHER_BLOCK_SPAI0 = 2 };
 /* Sparse layouts: SELL slices, CSR (several lanes per row), CSR staged from
- * per-tile gather lists, and BSR4: 4 x 4 dense blocks with one column index
- * per block, for point-block matrices (block_size 4, the velocity-pressure
- * nodes of the Navier-Stokes problem); explicit zeros of a block are
- * stored. */
+ * per-tile gather lists, BSR4: 4 x 4 dense blocks with one column index per
+ * block, for point-block matrices (block_size 4, the velocity-pressure nodes
+ * of the Navier-Stokes problem; explicit zeros of a block are stored), and
+ * COLUMN_TILED: the restriction operators split by column tiles of the
+ * finer vector (each tile staged once in LDS, one partial sum per row
+ * segment, the partials added per row in tile order), every other operator
+ * in SELL. */
 enum { DFAMG_FORMAT_AUTO = 0, DFAMG_FORMAT_CSR = 1, DFAMG_FORMAT_SELL = 2, DFAMG_FORMAT_CSR_GATHER = 3,
-       DFAMG_FORMAT_BSR4 = 4 };
+       DFAMG_FORMAT_BSR4 = 4, DFAMG_FORMAT_COLUMN_TILED = 5 };
 /* Preconditioner M: the block-local SA-AMG V-cycle, none (M = I), or the
  * purely local SPAI-0 diagonal m_i = a_ii / sum_j a_ij^2 (the velocity-block
  * preconditioner of the Schur pressure correction, section "Navier-Stokes
@@ -122,7 +125,10 @@ typedef struct {
                                LDS (a gather list; unstaged CSR where the list
                                exceeds 64 KiB), the outer operator to CSR;
                                BSR4 (block_size 4 only) stores every operator
-                               in 4 x 4 blocks                                */
+                               in 4 x 4 blocks; COLUMN_TILED stores the
+                               restrictions (the fused operator B with one
+                               pre-smoothing sweep) in column tiles of 512
+                               unknowns and the rest in SELL, untimed     */
     int32_t autotune;       /* 1 (default): time the candidate layouts of every
                                matrix at setup and keep the fastest; 0: one
                                fixed layout (SELL, one row per lane, natural

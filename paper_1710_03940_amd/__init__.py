@@ -28,7 +28,8 @@ _ENUMS = {
     "smoother": {"spai0": _lib.SMOOTHER_SPAI0, "jacobi": _lib.SMOOTHER_JACOBI,
                  "block_spai0": _lib.SMOOTHER_BLOCK_SPAI0},
     "spmv_format": {"auto": _lib.FORMAT_AUTO, "csr": _lib.FORMAT_CSR, "sell": _lib.FORMAT_SELL,
-                    "csr_gather": _lib.FORMAT_CSR_GATHER, "bsr4": _lib.FORMAT_BSR4},
+                    "csr_gather": _lib.FORMAT_CSR_GATHER, "bsr4": _lib.FORMAT_BSR4,
+                    "column_tiled": _lib.FORMAT_COLUMN_TILED},
     "precond": {"amg": _lib.PRECOND_AMG, "none": _lib.PRECOND_NONE, "spai0": _lib.PRECOND_SPAI0},
 }
 

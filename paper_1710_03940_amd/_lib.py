@@ -20,7 +20,7 @@ SOLVER_CG, SOLVER_BICGSTAB, SOLVER_BICGSTAB2, SOLVER_FGMRES = 0, 1, 2, 3
 COARSE_EXACT, COARSE_FP32, COARSE_CG = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 SMOOTHER_SPAI0, SMOOTHER_JACOBI, SMOOTHER_BLOCK_SPAI0 = 0, 1, 2
-FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL, FORMAT_CSR_GATHER, FORMAT_BSR4 = 0, 1, 2, 3, 4
+FORMAT_AUTO, FORMAT_CSR, FORMAT_SELL, FORMAT_CSR_GATHER, FORMAT_BSR4, FORMAT_COLUMN_TILED = 0, 1, 2, 3, 4, 5
 PRECOND_AMG, PRECOND_NONE, PRECOND_SPAI0 = 0, 1, 2
 OP_SPMV, OP_PROJECT, OP_PRECOND, OP_RECOVER = 0, 1, 2, 3
 NOALLOC_MAX_N = 512

@@ -724,6 +724,11 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     const int family = gather ? DFAMG_FORMAT_CSR : format;
     if (family == DFAMG_FORMAT_BSR4) {
         cand.push_back(Layout{DFAMG_FORMAT_BSR4, 4, false, false, false, 0});
+    } else if (family == DFAMG_FORMAT_COLUMN_TILED) {
+        // restrictions in column tiles of 512 unknowns (256 threads), the
+        // other operators in SELL; nothing timed
+        cand.push_back(kind == TUNE_RESTRICT ? Layout{kFormatSeg, 512, false, false, true, 1}
+                                             : Layout{DFAMG_FORMAT_SELL, 1, false, false, false, 0});
     } else if (!autotune) {
         if (gather && !outer) {
             Layout c{DFAMG_FORMAT_CSR, 8, false, false, true, 0};
@@ -849,6 +854,9 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
             // unstaged form
             if (c.fmt == DFAMG_FORMAT_SELL && !c.stage && c.idx16) {
                 c.idx16 = false;
+            } else if (c.fmt == kFormatSeg && family == DFAMG_FORMAT_COLUMN_TILED) {
+                // an operator with no entries to tile: SELL
+                c = Layout{DFAMG_FORMAT_SELL, 1, false, false, false, 0};
             } else if (gather && c.glist) {
                 c.stage = false;
                 c.glist = false;
@@ -1211,7 +1219,8 @@ struct Hierarchy_dev : PrecondBase {
                 // the tuner's timings (R without tuning)
                 {
                     const auto rn = ranges_of(PN, next_subs);
-                    const bool can_fuse = autotune && !block && npre == 1;
+                    const bool column_tiled = format == DFAMG_FORMAT_COLUMN_TILED;
+                    const bool can_fuse = (autotune || column_tiled) && !block && npre == 1;
                     const bool has_bc = can_fuse && PL.Bc.nnz() > 0;
                     const uint64_t hR = structure_hash(PL.R, rn);
                     const uint64_t hB = can_fuse ? structure_hash(PL.B, rn) : 0;
@@ -1258,7 +1267,7 @@ struct Hierarchy_dev : PrecondBase {
                                     clustered = true;
                                 }
                             }
-                            D.fused = D.B.tuned_us < D.A.tuned_us + D.R.tuned_us;
+                            D.fused = column_tiled || D.B.tuned_us < D.A.tuned_us + D.R.tuned_us;
                         }
                         if (D.fused) {
                             ar.adopt(clustered ? arBc : arB);

@@ -842,7 +842,8 @@ void validate_params(const dfamg_params &p) {
     if (p.block_size < 1 || p.block_size > 8) fail(DFAMG_EINVAL, "block_size must be in [1, 8]");
     if (p.precond != DFAMG_PRECOND_AMG && p.precond != DFAMG_PRECOND_NONE && p.precond != DFAMG_PRECOND_SPAI0)
         fail(DFAMG_EINVAL, "unknown precond");
-    if (p.spmv_format < DFAMG_FORMAT_AUTO || p.spmv_format > DFAMG_FORMAT_BSR4) fail(DFAMG_EINVAL, "unknown spmv_format");
+    if (p.spmv_format < DFAMG_FORMAT_AUTO || p.spmv_format > DFAMG_FORMAT_COLUMN_TILED)
+        fail(DFAMG_EINVAL, "unknown spmv_format");
     if (p.spmv_format == DFAMG_FORMAT_BSR4 && p.block_size != 4)
         fail(DFAMG_EINVAL, "spmv_format BSR4 needs block_size 4");
     if (p.graph_iters < 0) fail(DFAMG_EINVAL, "graph_iters must be >= 0");

@@ -356,7 +356,8 @@ def test_cycle_options_validated_on_the_host():
     for kw in (dict(flexible_cg=1, solver=_lib.SOLVER_BICGSTAB), dict(npre=5), dict(npost=0), dict(npre=-1),
                dict(flexible_cg=2), dict(npre=2, npost=2, smoother=_lib.SMOOTHER_BLOCK_SPAI0),
                dict(setup_device=2), dict(setup_device=1, smoother=_lib.SMOOTHER_BLOCK_SPAI0),
-               dict(setup_device=1, block_size=2), dict(spmv_format=_lib.FORMAT_BSR4)):
+               dict(setup_device=1, block_size=2), dict(spmv_format=_lib.FORMAT_BSR4),
+               dict(spmv_format=_lib.FORMAT_COLUMN_TILED + 1)):
         with pytest.raises(L.DfamgError) as ei:
             L.dfamg_setup(L.make_params(**kw), P.A, P.part, P.nsub, P.Z)
         assert ei.value.status == _lib.EINVAL, kw
