@@ -767,10 +767,10 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
                                                                   : std::vector<int>{4, 8, 16};
         if (family == DFAMG_FORMAT_CSR || family == DFAMG_FORMAT_AUTO)
             for (int l : lane_set)
-                // 256-row tiles, and tiles of 16/64 rows (32 and 64 lanes) or
-                // of kBlock/l and 4 kBlock/l rows (fewer lanes)
-                for (int rpg : l == 64 ? std::vector<int>{0, 4, 16} : l == 32 ? std::vector<int>{0, 2, 8}
-                                                                                : std::vector<int>{0, 1, 4}) {
+                // 256-row tiles, and tiles of 4/16/64 rows (64 lanes), 8/16/64
+                // rows (32 lanes) or of kBlock/l and 4 kBlock/l rows (fewer lanes)
+                for (int rpg : l == 64 ? std::vector<int>{0, 1, 4, 16} : l == 32 ? std::vector<int>{0, 1, 2, 8}
+                                                                                   : std::vector<int>{0, 1, 4}) {
                     // smaller tiles where 256-row tiles leave the chip idle, and
                     // for restrictions (long rows gathering from a wide window)
                     if (rpg > 0 && (outer || (rows / 256 >= 2048 && kind != TUNE_RESTRICT))) continue;

@@ -347,8 +347,13 @@ __device__ __forceinline__ void for_rows(const CsrM<VT, L, STAGE> &M, int tile, 
         if (STAGE) return lds[c - cb];
         return (VT)src(c);
     };
-    // Each lane keeps four entries of its row in flight (stride L), and the
-    // next row's pointers are loaded before the current row is summed.
+    // A row is read in chunks of 8 L entries: per chunk every lane issues
+    // its (up to) eight column and value loads, then the eight gathers
+    // (entries past the row's end gather x at the window base, a valid
+    // position, and are not added), then sums them in entry order, so a
+    // row of up to 8 L entries costs one load round trip and one gather
+    // round trip.  The next row's pointers are loaded before the current
+    // row is summed.
     auto rows = [&](const auto *__restrict__ colp) {
         int lr = g;
         int n0 = 0, n1 = 0;
@@ -363,23 +368,26 @@ __device__ __forceinline__ void for_rows(const CsrM<VT, L, STAGE> &M, int tile, 
                 n0 = M.ptr[row + G];
                 n1 = M.ptr[row + G + 1];
             }
-            ACC a[4] = {0, 0, 0, 0};
-            int k = k0 + lane;
-            for (; k + 3 * L < k1; k += 4 * L) {
-                int c[4];
-                ACC v[4];
+            ACC acc = 0;
+            for (int kc = k0 + lane; kc - lane < k1; kc += 8 * L) {
+                int c[8];
+                VT v[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    c[u] = (int)stream_load(colp + k + u * L);
-                    v[u] = (ACC)stream_load(M.val + k + u * L);
+                for (int u = 0; u < 8; ++u) {
+                    c[u] = cb;
+                    v[u] = 0;
+                    if (kc + u * L < k1) {
+                        c[u] = (int)stream_load(colp + kc + u * L);
+                        v[u] = stream_load(M.val + kc + u * L);
+                    }
                 }
+                ACC xv[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) a[u] += v[u] * x(c[u]);
+                for (int u = 0; u < 8; ++u) xv[u] = (ACC)x(c[u]);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (kc + u * L < k1) acc += (ACC)v[u] * xv[u];
             }
-#pragma unroll
-            for (int u = 0; u < 3; ++u)
-                if (k + u * L < k1) a[u] += (ACC)stream_load(M.val + k + u * L) * x((int)stream_load(colp + k + u * L));
-            ACC acc = (a[0] + a[1]) + (a[2] + a[3]);
 #pragma unroll
             for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
             if (lane == 0) f(row, acc);
