@@ -795,7 +795,8 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     // structure) gets the layout chosen then, without timing
     const TuneKey key{(int)kind, (int)sizeof(VT), format, hash ? hash : structure_hash(M, ranges)};
     double cached_us = -1.0;
-    if (cand.size() > 1) {
+    // (DFAMG_TUNE_VERIFY, below, times and checks every candidate anew)
+    if (cand.size() > 1 && std::getenv("DFAMG_TUNE_VERIFY") == nullptr) {
         std::lock_guard<std::mutex> g(tune_cache_mutex());
         auto it = tune_cache().find(key);
         if (it != tune_cache().end()) {
@@ -806,11 +807,59 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
     DevArena scratch;
     VT *x = scratch.alloc<VT>(std::max<int64_t>(1, std::max(M.ncols, M.nrows)));
     VT *y = scratch.alloc<VT>(std::max<int64_t>(1, std::max(M.ncols, M.nrows)));
+    // With the environment variable DFAMG_TUNE_VERIFY set, every candidate
+    // is first applied once to the same varied input (entries in [1, 2)) and
+    // its output compared with the first candidate's: a layout that differs
+    // by more than rounding is an error, not a slower choice.  The bound is
+    // relative to the largest row sum of |entries| times the input's bound.
+    const bool verify = cand.size() > 1 && cached_us < 0.0 && std::getenv("DFAMG_TUNE_VERIFY") != nullptr;
+    std::vector<VT> yref;
+    std::string ref_name;
+    double vbound = 0.0;
     if (cand.size() > 1) {
-        std::vector<VT> ones(std::max<int64_t>(1, std::max(M.ncols, M.nrows)), (VT)1);
-        HIP_CHECK(hipMemcpyAsync(x, ones.data(), ones.size() * sizeof(VT), hipMemcpyHostToDevice, s));
+        std::vector<VT> xin(std::max<int64_t>(1, std::max(M.ncols, M.nrows)), (VT)1);
+        if (verify) {
+            for (size_t i = 0; i < xin.size(); ++i) xin[i] = (VT)(1.0 + (double)((i * 7919) % 1013) / 1013.0);
+            // smoothing: f - A (m o f) with m = f = x, so |entries| x 4 plus 2
+            for (int64_t r = 0; r < M.nrows; ++r) {
+                double a = 0.0;
+                for (int64_t k = M.ptr[r]; k < M.ptr[r + 1]; ++k) a += std::fabs(M.val[k]);
+                vbound = std::max(vbound, 4.0 * a + 2.0);
+            }
+        }
+        HIP_CHECK(hipMemcpyAsync(x, xin.data(), xin.size() * sizeof(VT), hipMemcpyHostToDevice, s));
         HIP_CHECK(hipStreamSynchronize(s));
     }
+    auto check_candidate = [&](const DevMat<VT> &D) {
+        const int64_t ny = std::max<int64_t>(1, M.nrows);
+        // the prolongation kernel adds to its output: start from zero
+        HIP_CHECK(hipMemsetAsync(y, 0, (size_t)ny * sizeof(VT), s));
+        launch_for_tuning(kind, D, x, y, s);
+        HIP_CHECK(hipGetLastError());
+        std::vector<VT> yh(ny);
+        HIP_CHECK(hipMemcpyAsync(yh.data(), y, (size_t)ny * sizeof(VT), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (yref.empty()) {
+            yref = std::move(yh);
+            ref_name = describe(D);
+            return;
+        }
+        const double tol = (sizeof(VT) == 8 ? 1e-12 : 1e-4) * vbound;
+        double dmax = 0.0;
+        for (int64_t i = 0; i < ny; ++i) {
+            const double d = std::fabs((double)yh[i] - (double)yref[i]);
+            if (!(d <= tol)) {   // also catches NaN
+                char msg[256];
+                std::snprintf(msg, sizeof msg, "layout check: %s differs from %s by %.3g at row %lld (bound %.3g)",
+                              describe(D).c_str(), ref_name.c_str(), d, (long long)i, tol);
+                throw Error{DFAMG_EINVAL, msg};
+            }
+            dmax = std::max(dmax, d);
+        }
+        if (verbose > 1)
+            std::fprintf(stderr, "[dfamg] layout check %s against %s: max difference %.3g (bound %.3g)\n",
+                         describe(D).c_str(), ref_name.c_str(), dmax, tol);
+    };
     double best = 1e30;
     DevMat<VT> bestM;
     Layout bestL{};
@@ -866,6 +915,7 @@ DevMat<VT> upload_tuned(DevArena &ar, const Csr &M, const std::vector<RowRange> 
             A = std::make_unique<DevArena>();
             if (!upload_built<VT>(*A, *form_of(c), c, s, sub_sys, nsys, nsub, D, stage_limit, &gl_cache)) continue;
         }
+        if (verify) check_candidate(D);
         const double t = cached_us >= 0.0 ? cached_us
                          : cand.size() > 1 ? (timer ? timer(D) : time_layout(kind, D, x, y, s))
                                            : 0.0;
