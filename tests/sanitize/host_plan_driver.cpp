@@ -13,13 +13,15 @@
 // otherwise, per user subdomain, "S <user> <nlevels>" followed by the rows,
 // nnz(A), nnz(P) and omega of each level; per system "E <sys> <m> <sum of E>";
 // per packed level the sparse layouts built from it (SELL with every row
-// order and column width, CSR with several lane counts and tile heights) as
+// order and column width, CSR with lane counts 1 to 64 and tile heights 4 to
+// 1024 rows, with the rows the tiles cover) as
 // "L <level> <rows> <nnz A> <nnz B> <layout entries ...>", which exercises the
 // layout builders on every operator of the hierarchy.
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "host_plan.hpp"
@@ -76,11 +78,16 @@ static void layouts(const Csr &M, const std::vector<RowRange> &rg, std::string &
                 out += " sell" + std::to_string(rpl) + (sorted ? "s" : "") + (i16 ? "i" : "") + "=" +
                        (ok ? std::to_string(S.nnz) : std::string("no"));
             }
-    for (int lanes : {4, 16})
-        for (int rows : {64, 256}) {
-            HostCsrv C = make_csrv(M, rg, lanes, rows);
-            out += " csr" + std::to_string(lanes) + "t" + std::to_string(rows) + "=" + std::to_string(C.nnz);
-        }
+    // lane counts with their tile heights: one row per 64- or 32-lane group
+    // (4 and 8 rows), the usual 64- and 256-row tiles, 1024 rows of 1 lane
+    const std::pair<int, int> forms[] = {{4, 64}, {4, 256}, {16, 64}, {16, 256}, {64, 4}, {32, 8}, {1, 1024}};
+    for (const auto &fr : forms) {
+        HostCsrv C = make_csrv(M, rg, fr.first, fr.second);
+        int64_t rows = 0;
+        for (const Tile &t : C.tiles) rows += t.nrows;
+        out += " csr" + std::to_string(fr.first) + "t" + std::to_string(fr.second) + "=" + std::to_string(C.nnz) + "/" +
+               std::to_string(rows);
+    }
 }
 
 int main(int argc, char **argv) {
