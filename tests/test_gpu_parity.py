@@ -234,11 +234,13 @@ def test_graph_and_direct_launch_agree():
         assert np.array_equal(xv, res[0][1])
 
 
-@pytest.mark.parametrize("ndv", [2, 6])
+@pytest.mark.parametrize("ndv", [2, 6, 8])
 def test_other_deflation_counts(ndv):
-    # Z with ndv columns per subdomain: linear vectors plus bilinear ones
+    # Z with ndv columns per subdomain: linear vectors plus bilinear and
+    # trilinear ones (8, the most the library takes)
     P = tiny_problem(N=12, pieces=(2, 2, 1), deflation="linear", sigma=1.0, seed=ndv)
-    Zx = np.column_stack([P.Z, P.Z[:, 1] * P.Z[:, 2], P.Z[:, 2] * P.Z[:, 3]])[:, :ndv]
+    Zx = np.column_stack([P.Z, P.Z[:, 1] * P.Z[:, 2], P.Z[:, 2] * P.Z[:, 3], P.Z[:, 1] * P.Z[:, 3],
+                          P.Z[:, 1] * P.Z[:, 2] * P.Z[:, 3]])[:, :ndv]
     P2 = P.__class__(P.name, P.A, P.part, P.nsub, np.ascontiguousarray(Zx), P.b, P.x0)
     ref, out = _solve_pair(P2, dict(coarse_enough=30), dict(coarse_enough=30))
     _assert_parity(ref, out)

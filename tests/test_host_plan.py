@@ -227,7 +227,10 @@ def test_validation_errors():
     _expect(_lib.EINVAL, P, maxiter=-1)
     _expect(_lib.EINVAL, P, solver=L.make_params().solver + 7)        # unknown solver
     _expect(_lib.EINVAL, P, solver=_lib.SOLVER_FGMRES, restart=0)
-    _expect(_lib.EINVAL, P, spmv_format=_lib.FORMAT_CSR_GATHER + 1)   # unknown layout family
+    _expect(_lib.EINVAL, P, spmv_format=_lib.FORMAT_COLUMN_TILED + 1)  # unknown layout family
+    _expect(_lib.EINVAL, P, spmv_format=_lib.FORMAT_BSR4)              # BSR4 needs 4 x 4 blocks
+    # at most 8 deflation vectors per subdomain
+    assert "ndv" in _expect(_lib.EINVAL, P, Z=np.column_stack([P.Z, P.Z, P.Z[:, :1]]))
     _expect(_lib.EINVAL, P, spmv_format=-1)
     _expect(_lib.EINVAL, P, solver=_lib.SOLVER_FGMRES, restart=65)
     _expect(_lib.EINVAL, P, coarse_solve=2)
