@@ -586,12 +586,39 @@ __global__ void __launch_bounds__(kBlock) k_outer(MAT A, OffM off, const double 
     const int nq = (MODE == 2) ? 1 : ndv + 1;
     d0 = wave_sum(d0);
     if ((t & 63) == 0) lds[w] = d0;
+    auto zq_one_by_one = [&] {
 #pragma unroll
-    for (int k = 0; k < NDV; ++k) {
-        if (k < ndv && MODE != 2) {
-            const double s = wave_sum(zq[k]);
-            if ((t & 63) == 0) lds[4 * (k + 1) + w] = s;
+        for (int k = 0; k < NDV; ++k) {
+            if (k < ndv && MODE != 2) {
+                const double s = wave_sum(zq[k]);
+                if ((t & 63) == 0) lds[4 * (k + 1) + w] = s;
+            }
         }
+    };
+    if constexpr (NDV == 4) {
+        if (ndv == 4 && MODE != 2) {
+            // the four Z^T q sums of the wavefront together: seven exchanges
+            // instead of four times six.  Across lane halves each lane keeps
+            // two of the four values and adds its partner's, then one of the
+            // two across quarters, then the usual butterfly over the 16-lane
+            // group; lane 16 q ends with the sum of value q (the same sums,
+            // in the same order, as the butterfly of each value alone).
+            const int lane = t & 63;
+            const bool hi = (lane & 32) != 0, mid = (lane & 16) != 0;
+            double k0 = hi ? zq[2] : zq[0], k1 = hi ? zq[3] : zq[1];
+            const double g0 = hi ? zq[0] : zq[2], g1 = hi ? zq[1] : zq[3];
+            k0 += __shfl_xor(g0, 32, kWave);
+            k1 += __shfl_xor(g1, 32, kWave);
+            double v = mid ? k1 : k0;
+            v += __shfl_xor(mid ? k0 : k1, 16, kWave);
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+            if ((lane & 15) == 0) lds[4 * (1 + (lane >> 4)) + w] = v;
+        } else {
+            zq_one_by_one();
+        }
+    } else {
+        zq_one_by_one();
     }
     __syncthreads();
     if (t < nq && (MODE != 3 || t > 0)) {
@@ -696,6 +723,40 @@ __global__ void __launch_bounds__(kBlock) k_update(
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
     const DevTile T = tiles[tile];
+    const int ndv = ndv_rt;   // <= NDV, the unroll bound
+    // A row's operands do not depend on the system's state or on alpha, so
+    // they are loaded before those (row tiles hold at most kBlock rows: one
+    // row per thread) and their memory round trip overlaps the state and
+    // curvature reads instead of following them.
+    struct RowIn {
+        double q, p, y, r, s;
+        int e, e1;
+        f64x2 a01, a23;   // the row of the own AZ block (ndv == 4)
+    };
+    auto load_row = [&](int row) {
+        RowIn o{};
+        o.q = stream_load(q + row);
+        if (CG) {
+            o.p = stream_load(p + row);
+            o.y = y[row];
+            o.r = r[row];
+        }
+        if (MODE == 3) o.s = stream_load(s_prev + row);
+        if (ndv > 0) {
+            o.e = offp[row];
+            o.e1 = offp[row + 1];
+        }
+        if (NDV == 4 && ndv == 4) {
+            // one row of the own AZ block is 32 contiguous bytes
+            const f64x2 *az = reinterpret_cast<const f64x2 *>(AZown + (int64_t)row * 4);
+            o.a01 = stream_load(az);
+            o.a23 = stream_load(az + 1);
+        }
+        return o;
+    };
+    const bool own = (int)threadIdx.x < T.nrows;
+    RowIn first{};
+    if (own) first = load_row(T.row0 + (int)threadIdx.x);
     const int sys = sub_sys[T.sub];
     SysState &S = st[sys];
     if (CG && S.done) return;
@@ -708,38 +769,21 @@ __global__ void __launch_bounds__(kBlock) k_update(
     }
     const double a = CG ? alpha_s : 0.0;
     double rr = 0.0, rs = 0.0;
-    const int ndv = ndv_rt;   // <= NDV, the unroll bound
     double t2s[NDV > 0 ? NDV : 1];
 #pragma unroll
     for (int k = 0; k < NDV; ++k) t2s[k] = k < ndv ? t2[(int64_t)T.sub * ndv + k] : 0.0;
-    for_tile_rows(T, [&](int row) {
-        // every load that does not depend on another is issued first
-        const double qv = stream_load(q + row);
-        double pv = 0.0, yv = 0.0, rv = 0.0, sv = 0.0;
-        if (CG) {
-            pv = stream_load(p + row);
-            yv = y[row];
-            rv = r[row];
-        }
-        if (MODE == 3) sv = stream_load(s_prev + row);
-        int e = 0, e1 = 0;
-        if (ndv > 0) {
-            e = offp[row];
-            e1 = offp[row + 1];
-        }
+    auto finish_row = [&](int row, const RowIn &o) {
         double corr = 0.0;
         if (NDV == 4 && ndv == 4) {
-            // one row of the own AZ block is 32 contiguous bytes
-            const f64x2 *az = reinterpret_cast<const f64x2 *>(AZown + (int64_t)row * 4);
-            const f64x2 a01 = stream_load(az), a23 = stream_load(az + 1);
-            corr = ((a01.x * t2s[0] + a01.y * t2s[1]) + a23.x * t2s[2]) + a23.y * t2s[3];
+            corr = ((o.a01.x * t2s[0] + o.a01.y * t2s[1]) + o.a23.x * t2s[2]) + o.a23.y * t2s[3];
         } else {
 #pragma unroll
             for (int k = 0; k < NDV; ++k)
                 if (k < ndv) corr += stream_load(AZown + (int64_t)row * ndv + k) * t2s[k];
         }
         // couplings to other subdomains: groups of four independent gathers
-        for (; e + 4 <= e1; e += 4) {
+        int e = o.e;
+        for (; e + 4 <= o.e1; e += 4) {
             int c[4];
             double v[4];
 #pragma unroll
@@ -750,21 +794,23 @@ __global__ void __launch_bounds__(kBlock) k_update(
 #pragma unroll
             for (int u = 0; u < 4; ++u) corr += v[u] * t2[c[u]];
         }
-        for (; e < e1; ++e) corr += offv[e] * t2[offc[e]];
-        const double wv = qv - corr;
+        for (; e < o.e1; ++e) corr += offv[e] * t2[offc[e]];
+        const double wv = o.q - corr;
         if (CG) {
-            y[row] = yv + a * pv;
-            const double rn = rv - a * wv;
+            y[row] = o.y + a * o.p;
+            const double rn = o.r - a * wv;
             r[row] = rn;
             rr += rn * rn;
-            if (MODE == 3) rs += rn * sv;
+            if (MODE == 3) rs += rn * o.s;
         } else if (MODE == 1) {
             r[row] = wv;
             rr += wv * wv;
         } else {
             r[row] = wv;
         }
-    });
+    };
+    if (own) finish_row(T.row0 + (int)threadIdx.x, first);
+    for (int lr = (int)threadIdx.x + kBlock; lr < T.nrows; lr += kBlock) finish_row(T.row0 + lr, load_row(T.row0 + lr));
     if (MODE == 2) return;
     const double s = block_sum(rr, lds, kBlock);
     if (threadIdx.x == 0) part[T.slot] = s;
@@ -902,10 +948,23 @@ __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restri
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
     const DevTile T = tiles[tile];
+    // the row's s and p are loaded before the system's state (row tiles hold
+    // at most kBlock rows: one row per thread), so the two reads overlap
+    const bool own = (int)threadIdx.x < T.nrows;
+    const int row = T.row0 + (int)threadIdx.x;
+    double sv = 0.0, pv = 0.0;
+    if (own) {
+        sv = s[row];
+        if (!INIT) pv = p[row];
+    }
     const SysState &S = st[sub_sys[T.sub]];
     if (!INIT && S.done) return;
     const double beta = S.beta;
-    for_tile_rows(T, [&](int row) { p[row] = INIT ? s[row] : s[row] + beta * p[row]; });
+    if (own) p[row] = INIT ? sv : sv + beta * pv;
+    for (int lr = (int)threadIdx.x + kBlock; lr < T.nrows; lr += kBlock) {
+        const int rw = T.row0 + lr;
+        p[rw] = INIT ? s[rw] : s[rw] + beta * p[rw];
+    }
 }
 
 // ---------------------------------------------------------------------------
