@@ -724,10 +724,11 @@ __global__ void __launch_bounds__(kBlock) k_update(
     if (tile >= ntiles) return;
     const DevTile T = tiles[tile];
     const int ndv = ndv_rt;   // <= NDV, the unroll bound
-    // A row's operands do not depend on the system's state or on alpha, so
-    // they are loaded before those (row tiles hold at most kBlock rows: one
-    // row per thread) and their memory round trip overlaps the state and
-    // curvature reads instead of following them.
+    // A row's operands do not depend on alpha, so they are loaded before it
+    // (row tiles hold at most kBlock rows: one row per thread) and their
+    // memory round trip overlaps the curvature reads and the block's
+    // synchronisation instead of following them; a stopped system's rows are
+    // not read at all (batched systems stop at different iterations).
     struct RowIn {
         double q, p, y, r, s;
         int e, e1;
@@ -754,12 +755,12 @@ __global__ void __launch_bounds__(kBlock) k_update(
         }
         return o;
     };
-    const bool own = (int)threadIdx.x < T.nrows;
-    RowIn first{};
-    if (own) first = load_row(T.row0 + (int)threadIdx.x);
     const int sys = sub_sys[T.sub];
     SysState &S = st[sys];
     if (CG && S.done) return;
+    const bool own = (int)threadIdx.x < T.nrows;
+    RowIn first{};
+    if (own) first = load_row(T.row0 + (int)threadIdx.x);
     if (CG) {
         if (threadIdx.x < 64) {
             const double pq = cg_curvature(psub, tt_part, R, sys);
@@ -948,23 +949,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restri
     const int tile = tile_of_block(ntiles);
     if (tile >= ntiles) return;
     const DevTile T = tiles[tile];
-    // the row's s and p are loaded before the system's state (row tiles hold
-    // at most kBlock rows: one row per thread), so the two reads overlap
-    const bool own = (int)threadIdx.x < T.nrows;
-    const int row = T.row0 + (int)threadIdx.x;
-    double sv = 0.0, pv = 0.0;
-    if (own) {
-        sv = s[row];
-        if (!INIT) pv = p[row];
-    }
     const SysState &S = st[sub_sys[T.sub]];
     if (!INIT && S.done) return;
     const double beta = S.beta;
-    if (own) p[row] = INIT ? sv : sv + beta * pv;
-    for (int lr = (int)threadIdx.x + kBlock; lr < T.nrows; lr += kBlock) {
-        const int rw = T.row0 + lr;
-        p[rw] = INIT ? s[rw] : s[rw] + beta * p[rw];
-    }
+    for_tile_rows(T, [&](int row) { p[row] = INIT ? s[row] : s[row] + beta * p[row]; });
 }
 
 // ---------------------------------------------------------------------------
