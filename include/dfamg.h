@@ -137,7 +137,15 @@ typedef struct {
                                the multigrid operators when CSR_GATHER), so
                                that two handles built
                                from the same subdomains sum every dot product
-                               in the same order (bitwise-equal results)       */
+                               in the same order (bitwise-equal results).
+                               Environment: DFAMG_TUNE_CACHE names a file that
+                               records the chosen layouts by matrix structure
+                               across processes (read, then appended to);
+                               DFAMG_TUNE_VERIFY (any value) applies every
+                               candidate once to a varied input and fails the
+                               setup with DFAMG_EINVAL, the message naming both
+                               layouts, if one differs from the operator's
+                               first candidate beyond rounding               */
     int32_t graph_iters;    /* Krylov iterations per captured HIP graph;
                                0 launches kernels directly (default 16)       */
     int32_t host_threads;   /* setup worker threads, 0 = hardware concurrency  */
