@@ -609,6 +609,16 @@ def kernel_breakdown(P, b, x, log, precision):
     st = S.stats()
     S.close()
     out = span_rates(st)
+    # the coarser span encloses the event nodes of its three sub-spans (six
+    # per iteration, a few us each): report it as the sum of the sub-spans
+    subs = ("restrict1", "deep", "up1")
+    if "coarser" in out and all(k in out for k in subs):
+        c = out["coarser"]
+        a = sum(out[k]["avg_us"] for k in subs) * 1e-6
+        gbps = c["bytes_per_launch"] / a / 1e9 if c["bytes_per_launch"] and a > 0 else None
+        out["coarser"] = {"avg_us": a * 1e6, "bytes_per_launch": c["bytes_per_launch"], "GBps": gbps,
+                          "frac": gbps / HBM_PEAK_GBS if gbps else None, "avg_us_enclosing_span": c["avg_us"],
+                          "note": "sum of restrict1, deep and up1"}
     log(f"  per-kernel spans {precision} (us): " + ", ".join(f"{k} {v['avg_us']:.1f}" for k, v in out.items()))
     return out
 
