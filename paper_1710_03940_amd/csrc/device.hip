@@ -2244,7 +2244,8 @@ void Handle::iteration(hipStream_t st) {
     else
         hipLaunchKernelGGL(k_rho<0>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
                            d_sys_cjob_off0, states);
-    hipLaunchKernelGGL(k_cg_direction<false>, gr, bl, 0, st, rows, nrow_tiles, s, p, states, d_sub_sys);
+    hipLaunchKernelGGL(k_cg_direction<false>, dim3(grid_for_tiles((nrow_tiles + 1) / 2)), bl, 0, st, rows, nrow_tiles, s,
+                       p, states, d_sub_sys);
     prof.mark(KID_DIR, 1, st);
 }
 
@@ -2468,7 +2469,8 @@ void Handle::initial(hipStream_t st) {
     precond(st, r, s);
     hipLaunchKernelGGL(k_rho<1>, dim3(nsys()), dim3(kWideBlock), 0, st, part_rs, d_sto0, part_rs_job,
                        d_sys_cjob_off0, states);
-    hipLaunchKernelGGL(k_cg_direction<true>, gr, bl, 0, st, rows, nrow_tiles, s, p, states, d_sub_sys);
+    hipLaunchKernelGGL(k_cg_direction<true>, dim3(grid_for_tiles((nrow_tiles + 1) / 2)), bl, 0, st, rows, nrow_tiles, s,
+                       p, states, d_sub_sys);
 }
 
 // x = y + Z E^{-1} Z^T (b - A y), then ||b - A x|| / ||b||

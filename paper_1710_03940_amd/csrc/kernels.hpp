@@ -946,13 +946,40 @@ __global__ void __launch_bounds__(kBlock) k_cg_direction(const DevTile *__restri
                                                          const double *__restrict__ s, double *__restrict__ p,
                                                          const SysState *__restrict__ st,
                                                          const int32_t *__restrict__ sub_sys) {
-    const int tile = tile_of_block(ntiles);
-    if (tile >= ntiles) return;
-    const DevTile T = tiles[tile];
-    const SysState &S = st[sub_sys[T.sub]];
-    if (!INIT && S.done) return;
-    const double beta = S.beta;
-    for_tile_rows(T, [&](int row) { p[row] = INIT ? s[row] : s[row] + beta * p[row]; });
+    // two row tiles per block (launched on grid_for_tiles((ntiles + 1) / 2)):
+    // both tiles' descriptors and states are read first and then both rows'
+    // s and p, so each block pays its chain of dependent reads (tile,
+    // system, state, data) once per two tiles
+    const int pairs = (ntiles + 1) >> 1;
+    const int pair = tile_of_block(pairs);
+    if (pair >= pairs) return;
+    const int t0 = 2 * pair;
+    const bool has1 = t0 + 1 < ntiles;
+    const DevTile T0 = tiles[t0];
+    const DevTile T1 = tiles[has1 ? t0 + 1 : t0];
+    const SysState &S0 = st[sub_sys[T0.sub]];
+    const SysState &S1 = st[sub_sys[T1.sub]];
+    const bool go0 = INIT || !S0.done, go1 = has1 && (INIT || !S1.done);
+    const double b0 = S0.beta, b1 = S1.beta;
+    // row tiles hold at most kBlock rows: one row of each tile per thread
+    const int lr = (int)threadIdx.x;
+    const bool own0 = go0 && lr < T0.nrows, own1 = go1 && lr < T1.nrows;
+    const int r0 = T0.row0 + lr, r1 = T1.row0 + lr;
+    double s0 = 0.0, p0 = 0.0, s1 = 0.0, p1 = 0.0;
+    if (own0) {
+        s0 = s[r0];
+        if (!INIT) p0 = p[r0];
+    }
+    if (own1) {
+        s1 = s[r1];
+        if (!INIT) p1 = p[r1];
+    }
+    if (own0) p[r0] = INIT ? s0 : s0 + b0 * p0;
+    if (own1) p[r1] = INIT ? s1 : s1 + b1 * p1;
+    for (int l = lr + kBlock; l < T0.nrows; l += kBlock)
+        if (go0) p[T0.row0 + l] = INIT ? s[T0.row0 + l] : s[T0.row0 + l] + b0 * p[T0.row0 + l];
+    for (int l = lr + kBlock; l < T1.nrows; l += kBlock)
+        if (go1) p[T1.row0 + l] = INIT ? s[T1.row0 + l] : s[T1.row0 + l] + b1 * p[T1.row0 + l];
 }
 
 // ---------------------------------------------------------------------------
